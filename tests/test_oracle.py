@@ -1,0 +1,270 @@
+"""Pins of the CPU oracle against what the paper and plain combinatorics fix.
+
+Each check is independent of the oracle's own formulas:
+  * Figure 1's worked butterflies (tests/golden/fig1_butterflies.json);
+  * all 16 signings of K_{2,2} (balanced iff an even number of negatives);
+  * brute force over vertex quadruples (O0) on many random tiny graphs, against
+    the pair enumeration of both sides (O1) and the Gram closed form (O2);
+  * closed forms on complete bipartite graphs and butterfly-free graphs;
+  * invariances of the definition (switching, negation, transpose, relabelling,
+    disjoint union);
+  * the priority-filtered wedge count W against a per-vertex degree formula;
+  * per-vertex counts against a pure-Python brute force and their sum rule.
+"""
+import itertools
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+from gen import SignedBipartiteGraph
+from oracle.gram import gram_count
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def graph_from_edges(n_u, n_v, edges, name="g"):
+    e = np.asarray(edges, dtype=np.int64).reshape(-1, 3)
+    return SignedBipartiteGraph(n_u, n_v, e[:, 0].astype(np.int32), e[:, 1].astype(np.int32),
+                                e[:, 2].astype(np.int8), name)
+
+
+def c2(k):
+    return k * (k - 1) // 2
+
+
+def all_counts_agree(g):
+    b0, t0 = oracle.brute_force(g)
+    bu, uu = oracle.pair_count(g, 0, threads=2)
+    bv, uv = oracle.pair_count(g, 1, threads=3)
+    bg, ug = gram_count(g)
+    assert (bu, uu) == (bv, uv) == (bg, ug), (g.name, (bu, uu), (bv, uv), (bg, ug))
+    assert bu == b0 and bu + uu == t0, (g.name, b0, t0, bu, uu)
+    return b0, t0
+
+
+def test_figure1_patterns():
+    fx = json.load(open(os.path.join(GOLDEN, "fig1_butterflies.json")))
+    for pat in fx["patterns"] + fx["derived"]:
+        g = graph_from_edges(2, 2, pat["edges"], pat["name"])
+        b, t = all_counts_agree(g)
+        assert (b, t) == (pat["balanced"], pat["total"]), pat["name"]
+
+
+def test_all_signings_of_k22():
+    n_bal = 0
+    for signs in itertools.product([1, -1], repeat=4):
+        edges = [[0, 0, signs[0]], [0, 1, signs[1]], [1, 0, signs[2]], [1, 1, signs[3]]]
+        b, t = all_counts_agree(graph_from_edges(2, 2, edges))
+        assert t == 1
+        assert b == (1 if signs.count(-1) % 2 == 0 else 0)
+        n_bal += b
+    assert n_bal == 8
+
+
+def test_random_tiny_graphs_against_brute_force():
+    rng = np.random.default_rng(12345)
+    nonzero = 0
+    for _ in range(1200):
+        nu = int(rng.integers(0, 11))
+        nv = int(rng.integers(0, 11))
+        g = gen.random_graph(rng, nu, nv, float(rng.uniform(0.2, 1.0)), float(rng.uniform(0, 1)))
+        b, t = all_counts_agree(g)
+        nonzero += t > 0
+    assert nonzero > 600
+
+
+def test_complete_bipartite_closed_forms():
+    rng = np.random.default_rng(7)
+    for a, b in [(2, 2), (3, 5), (6, 4), (9, 9), (1, 7), (12, 3)]:
+        expect = c2(a) * c2(b)
+        g = gen.complete_graph(a, b)
+        assert oracle.count(g) == (expect, 0)
+        assert gram_count(g) == (expect, 0)
+        # sign(u, v) = s_u * t_v is a switching of the all-positive graph: every
+        # butterfly keeps an even number of negative edges.
+        su = rng.choice([1, -1], size=a)
+        sv = rng.choice([1, -1], size=b)
+        g = gen.complete_graph(a, b, su, sv)
+        assert oracle.count(g) == (expect, 0)
+        assert oracle.brute_force(g) == (expect, expect)
+        # all negative: four negatives, balanced
+        g = gen.complete_graph(a, b, -np.ones(a), np.ones(b))
+        assert oracle.count(g)[0] == expect
+
+
+def test_k_a2_closed_form():
+    # K_{a,2}: butterflies are the pairs of U vertices; the pair {u1,u2} is
+    # balanced iff sign(u1,v1)sign(u1,v2) == sign(u2,v1)sign(u2,v2).
+    rng = np.random.default_rng(3)
+    for a in [2, 3, 5, 10, 31]:
+        s = rng.choice([1, -1], size=(a, 2))
+        edges = [[u, v, int(s[u, v])] for u in range(a) for v in range(2)]
+        g = graph_from_edges(a, 2, edges)
+        same = int(np.sum(s[:, 0] == s[:, 1]))
+        expect = c2(same) + c2(a - same)
+        assert oracle.count(g) == (expect, same * (a - same))
+
+
+def test_butterfly_free_graphs():
+    rng = np.random.default_rng(11)
+    # star, path, random forest: no 4-cycle
+    star = graph_from_edges(1, 30, [[0, v, int(rng.choice([1, -1]))] for v in range(30)])
+    path = graph_from_edges(20, 20, [[i, i, 1] for i in range(20)] + [[i + 1, i, -1] for i in range(19)])
+    forest = []
+    for v in range(40):  # each V vertex attaches to one new U vertex and one older one
+        forest.append([v, v, 1])
+        if v:
+            forest.append([int(rng.integers(0, v)), v, -1])
+    forest = graph_from_edges(40, 40, forest)
+    for g in (star, path, forest):
+        assert oracle.brute_force(g) == (0, 0)
+        assert oracle.count(g) == (0, 0)
+
+
+def _switch(g, vertex, side):
+    s = g.sign.copy()
+    m = (g.eu == vertex) if side == 0 else (g.ev == vertex)
+    s[m] = -s[m]
+    return g._replace(sign=s)
+
+
+def test_invariances():
+    rng = np.random.default_rng(99)
+    for trial in range(40):
+        g = gen.random_graph(rng, int(rng.integers(3, 14)), int(rng.integers(3, 14)),
+                             float(rng.uniform(0.3, 0.9)), 0.4)
+        base = oracle.count(g, threads=1)
+        # switching at one vertex: a butterfly through it uses exactly two of its edges
+        side = int(rng.integers(0, 2))
+        x = int(rng.integers(0, g.n_u if side == 0 else g.n_v))
+        assert oracle.count(_switch(g, x, side), threads=1) == base
+        # global negation: four sign flips per butterfly
+        assert oracle.count(g._replace(sign=(-g.sign).astype(np.int8)), threads=1) == base
+        # transpose U <-> V
+        gt = SignedBipartiteGraph(g.n_v, g.n_u, g.ev, g.eu, g.sign)
+        assert oracle.count(gt, threads=1) == base
+        # relabel vertices and shuffle the edge list
+        pu = rng.permutation(g.n_u).astype(np.int32)
+        pv = rng.permutation(g.n_v).astype(np.int32)
+        o = rng.permutation(g.n_edges)
+        gp = g._replace(eu=pu[g.eu][o], ev=pv[g.ev][o], sign=g.sign[o])
+        assert oracle.count(gp, threads=1) == base
+    # disjoint union is additive
+    g1 = gen.random_graph(rng, 9, 7, 0.7, 0.3)
+    g2 = gen.random_graph(rng, 5, 8, 0.8, 0.6)
+    gu = SignedBipartiteGraph(g1.n_u + g2.n_u, g1.n_v + g2.n_v,
+                              np.concatenate([g1.eu, g2.eu + g1.n_u]).astype(np.int32),
+                              np.concatenate([g1.ev, g2.ev + g1.n_v]).astype(np.int32),
+                              np.concatenate([g1.sign, g2.sign]))
+    b1, u1 = oracle.count(g1)
+    b2, u2 = oracle.count(g2)
+    assert oracle.count(gu) == (b1 + b2, u1 + u2)
+
+
+def _priority_rank(g):
+    """Global ids (U first, then V) ordered by (degree, id) -- Definition 4."""
+    n = g.n_u + g.n_v
+    deg = np.bincount(np.concatenate([g.eu, g.ev + g.n_u]), minlength=n)
+    order = np.lexsort((np.arange(n), deg))
+    rank = np.empty(n, np.int64)
+    rank[order] = np.arange(n)
+    return rank, deg
+
+
+def wedge_count_by_degrees(g):
+    """W from vertex data alone: an unordered path a-b-c (a != c) is counted by
+    the bucket algorithm exactly when its top-priority vertex is an end, i.e.
+    W = sum_b [ C(deg b, 2) - C(lo_b, 2) ], lo_b = neighbours of b below b."""
+    rank, deg = _priority_rank(g)
+    a = g.eu.astype(np.int64)
+    b = g.ev.astype(np.int64) + g.n_u
+    lo = np.zeros(g.n_u + g.n_v, np.int64)
+    np.add.at(lo, b, rank[a] < rank[b])
+    np.add.at(lo, a, rank[b] < rank[a])
+    return int(np.sum(deg * (deg - 1) // 2 - lo * (lo - 1) // 2))
+
+
+def test_wedge_count_pins():
+    rng = np.random.default_rng(5)
+    for _ in range(300):
+        g = gen.random_graph(rng, int(rng.integers(0, 12)), int(rng.integers(0, 12)),
+                             float(rng.uniform(0.05, 1.0)))
+        assert oracle.wedges(g, threads=2) == wedge_count_by_degrees(g)
+    # K_{a,b}: the larger-degree side outranks the other (ties: V ids are
+    # larger); each start u_i has every vertex of the other side as middle and
+    # the i lower-ranked vertices of its own side as ends.
+    for a, b in [(3, 5), (5, 3), (4, 4), (1, 6), (7, 1), (10, 2)]:
+        g = gen.complete_graph(a, b)
+        if b > a:
+            expect = b * c2(a)   # starts in U (degree b), middles V
+        else:
+            expect = a * c2(b)   # starts in V
+        assert oracle.wedges(g) == expect
+    # star: no wedge has its top-priority vertex at an end
+    star = graph_from_edges(1, 9, [[0, v, 1] for v in range(9)])
+    assert oracle.wedges(star) == 0
+    g = gen.uniform_graph()
+    assert oracle.wedges(g) == wedge_count_by_degrees(g)
+
+
+def per_vertex_python(g):
+    n_u, n_v = g.n_u, g.n_v
+    s = np.zeros((n_u, n_v), np.int64)
+    s[g.eu, g.ev] = g.sign
+    out = np.zeros(n_u + n_v, np.int64)
+    for u1, u2 in itertools.combinations(range(n_u), 2):
+        for v1, v2 in itertools.combinations(range(n_v), 2):
+            p = s[u1, v1] * s[u1, v2] * s[u2, v1] * s[u2, v2]
+            if p > 0:
+                for x in (u1, u2):
+                    out[x] += 1
+                for y in (v1, v2):
+                    out[n_u + y] += 1
+    return out
+
+
+def test_per_vertex_counts():
+    rng = np.random.default_rng(21)
+    for _ in range(60):
+        g = gen.random_graph(rng, int(rng.integers(0, 8)), int(rng.integers(0, 8)),
+                             float(rng.uniform(0.3, 1.0)), 0.4)
+        pv = oracle.per_vertex(g, threads=2).astype(np.int64)
+        assert np.array_equal(pv, per_vertex_python(g))
+    g = gen.uniform_graph()
+    pv = oracle.per_vertex(g)
+    b, _ = oracle.count(g)
+    assert int(pv[: g.n_u].sum()) == 2 * b and int(pv[g.n_u:].sum()) == 2 * b
+
+
+def test_input_validation():
+    g = graph_from_edges(2, 2, [[0, 0, 1], [1, 1, -1]])
+    bad_range = g._replace(ev=np.array([0, 2], np.int32))
+    bad_sign = g._replace(sign=np.array([1, 0], np.int8))
+    dup = graph_from_edges(2, 2, [[0, 0, 1], [0, 0, -1]])
+    for gg, code in [(bad_range, -2), (bad_sign, -3), (dup, -4)]:
+        with pytest.raises(oracle.OracleError) as ei:
+            oracle.pair_count(gg)
+        assert ei.value.code == code
+    empty = graph_from_edges(0, 0, [])
+    assert oracle.count(empty) == (0, 0) and oracle.wedges(empty) == 0
+
+
+def test_workload_sizes_and_closed_form():
+    g = gen.uniform_graph()
+    assert (g.n_u, g.n_v, g.n_edges) == (2000, 1000, 20000)
+    assert oracle.count(g) == gram_count(g, 0) == gram_count(g, 1)
+    g = gen.voting_graph()
+    assert g.n_u == 100 and g.n_v == 10000
+    b, u = gram_count(g, 0)
+    assert oracle.pair_count(g, 0) == (b, u)
+    # iid-sign sanity (statistical, not a pin): with P(neg)=p the expected
+    # balanced fraction is (1 + (1-2p)^4) / 2 = 0.5128 at p = 0.3.
+    g = gen.uniform_graph()
+    b, u = oracle.count(g)
+    assert abs(b / (b + u) - 0.5128) < 0.03
+    assert math.isfinite(b)
