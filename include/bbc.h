@@ -1,0 +1,134 @@
+/*
+ * bbc.h -- balanced-butterfly counting on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of libbbc.so.  Plain pointers and sizes only.
+ *
+ * The operation (Das, Abidi, Shingane, Kiran, "Balanced Butterfly Counting in
+ * Bipartite-Network", Section 2): G = (U, V, E) is a signed bipartite graph,
+ * E a set of pairs (u, v) in U x V, each labelled + or -.  A butterfly is a
+ * 4-cycle u1-v1-u2-v2 (u1 != u2 in U, v1 != v2 in V, all four edges in E;
+ * Definition 1); it is balanced when it holds an even number of negative edges
+ * (Definition 2).  bbc_count returns the number of balanced butterflies (the
+ * problem statement of Section 2), together with the number of unbalanced ones
+ * and the number W of wedges the bucket method enumerates: wedges (u, v, w)
+ * whose start u has a higher priority than the middle v and the end w, the
+ * priority being (degree, id) with ids 0..|U|-1 for U and |U|..|U|+|V|-1 for V
+ * (Definition 4, Algorithm 2).  All results are exact integers.
+ *
+ * Errors: every call returns a bbc_status.  On any status other than BBC_OK
+ * nothing is written to the caller's output buffers, and bbc_last_error()
+ * gives a one-line description.  After BBC_ERR_DEVICE the context must be
+ * destroyed.
+ *
+ * Threading: a context is not thread safe; distinct contexts may be used from
+ * distinct threads at once.
+ */
+#ifndef BBC_H
+#define BBC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum bbc_status {
+    BBC_OK = 0,
+    BBC_ERR_INVALID_ARG = -1,     /* negative size, NULL pointer with n_edges > 0, bad flag */
+    BBC_ERR_VERTEX_RANGE = -2,    /* an edge names u >= n_u, v >= n_v or a negative id */
+    BBC_ERR_BAD_SIGN = -3,        /* an edge sign other than +1 or -1 */
+    BBC_ERR_DUPLICATE_EDGE = -4,  /* the same (u, v) pair twice, whatever the signs */
+    BBC_ERR_TOO_LARGE = -5,       /* n_u + n_v >= 2^30 or n_edges >= 2^31 */
+    BBC_ERR_OVERFLOW = -6,        /* a count does not fit in int64_t */
+    BBC_ERR_OUT_OF_MEMORY = -7,   /* device workspace could not be allocated or exceeds
+                                     the BBC_MAX_DEVICE_BYTES budget */
+    BBC_ERR_DEVICE = -8,          /* a HIP runtime call failed; the context is unusable */
+    BBC_ERR_NOT_IMPLEMENTED = -9, /* a requested feature is not built */
+    BBC_ERR_INTERNAL = -10        /* an internal capacity was exceeded (see bbc_last_error) */
+} bbc_status;
+
+typedef struct bbc_context bbc_context; /* opaque: device, stream, workspace arena */
+
+typedef struct bbc_result {
+    int64_t balanced;   /* balanced butterflies (even number of negative edges) */
+    int64_t unbalanced; /* butterflies with an odd number of negative edges */
+    int64_t wedges;     /* W: wedges kept by the vertex-priority filter */
+} bbc_result;
+
+/* flags for bbc_count */
+enum {
+    BBC_INPUT_ON_DEVICE = 1u, /* edge_u/edge_v/edge_sign are device pointers on the
+                                 context's device, ordered on its stream */
+    BBC_PER_VERTEX = 4u       /* also fill per_vertex (see bbc_count) */
+};
+
+/*
+ * Create a context on HIP device `device`.  `hip_stream` is a hipStream_t the
+ * library launches all work on (borrowed, not destroyed by bbc_destroy); NULL
+ * makes the library create and own a stream.  *out receives the context.
+ * Returns BBC_ERR_INVALID_ARG for out == NULL, BBC_ERR_DEVICE if the device or
+ * stream cannot be used.
+ */
+bbc_status bbc_create(int device, void* hip_stream, bbc_context** out);
+
+/* Release the context's workspace and stream (if owned).  NULL is a no-op. */
+void bbc_destroy(bbc_context* ctx);
+
+/*
+ * Count the balanced butterflies of the signed bipartite graph with vertex
+ * sets U = {0..n_u-1}, V = {0..n_v-1} and edges i = 0..n_edges-1 given by
+ * (edge_u[i], edge_v[i]) with sign edge_sign[i] in {+1, -1}.
+ *
+ * Inputs (int32 ids, int8 signs, all length n_edges) are host pointers, or
+ * device pointers when flags has BBC_INPUT_ON_DEVICE; they are only read, and
+ * only for the duration of the call.  The edge order is arbitrary.
+ * `out` (host) receives the counts.  With BBC_PER_VERTEX, `per_vertex` (host,
+ * n_u + n_v entries, U first then V) receives for every vertex the number of
+ * balanced butterflies that contain it (Section 5.1); otherwise it may be NULL.
+ *
+ * The call is synchronous: it returns when the counts are on the host.
+ * An empty graph, or one with fewer than two vertices on a side, gives zeros.
+ */
+bbc_status bbc_count(bbc_context* ctx, int32_t n_u, int32_t n_v, int64_t n_edges,
+                     const int32_t* edge_u, const int32_t* edge_v, const int8_t* edge_sign,
+                     uint32_t flags, bbc_result* out, int64_t* per_vertex);
+
+/* Static description of a status code (never NULL). */
+const char* bbc_status_string(bbc_status status);
+
+/* Detail of the context's last failure ("" if none; never NULL for a valid ctx). */
+const char* bbc_last_error(const bbc_context* ctx);
+
+/* Library version: major * 10000 + minor * 100 + patch. */
+int bbc_version(void);
+
+/*
+ * Phase timing of the context's last bbc_count, measured with HIP events on the
+ * context's stream when timing is enabled (bbc_set_timing(ctx, 1)).
+ * phase: 0 = whole device pipeline (first kernel to last),
+ *        1 = preprocessing (validation, degrees, priority relabel, CSR build),
+ *        2 = wedge enumeration and bucket counting (the wedge kernel alone),
+ *        3 = planning (work estimate and work-item construction).
+ * *ms receives milliseconds.  BBC_ERR_INVALID_ARG for an unknown phase or when
+ * timing was off during the last call.
+ */
+bbc_status bbc_set_timing(bbc_context* ctx, int enabled);
+bbc_status bbc_last_phase_ms(const bbc_context* ctx, int phase, double* ms);
+
+/*
+ * Work statistics of the last successful bbc_count (for throughput and
+ * roofline accounting): stats[0] = number of vertices with at least one
+ * edge, [1] = edges, [2] = W, [3] = middle records (oriented edges used as
+ * u->v with v below u), [4] = work items run by the wedge kernel,
+ * [5] = hashed work pieces whose on-chip table overflowed and that were
+ * redone in smaller parts, [6] = start vertices with at least one wedge,
+ * [7] = work items that cover part of one heavy start.  `n` is the capacity
+ * of `stats`; up to 8 values are written.
+ */
+bbc_status bbc_last_stats(const bbc_context* ctx, int64_t* stats, int n);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BBC_H */

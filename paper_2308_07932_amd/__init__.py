@@ -1,0 +1,246 @@
+"""Balanced-butterfly counting on AMD MI355X: Python binding of libbbc.so.
+
+Argument marshalling only; every step of the count runs in the HIP library.
+There is no CPU fallback: if the library is missing, importing works but any
+call raises :class:`LibraryNotBuilt`.
+
+    >>> import paper_2308_07932_amd as bbc
+    >>> r = bbc.count(eu, ev, sign, n_u, n_v)     # numpy (host) or torch (device)
+    >>> r.balanced, r.unbalanced, r.wedges
+
+Tensors on a GPU are passed as device pointers; the call is ordered after the
+work already queued on torch's current stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from typing import NamedTuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbbc.so")
+HEADER_PATH = os.path.join(_HERE, "..", "include", "bbc.h")
+
+OK = 0
+INVALID_ARG = -1
+VERTEX_RANGE = -2
+BAD_SIGN = -3
+DUPLICATE_EDGE = -4
+TOO_LARGE = -5
+OVERFLOW = -6
+OUT_OF_MEMORY = -7
+DEVICE = -8
+NOT_IMPLEMENTED = -9
+INTERNAL = -10
+
+INPUT_ON_DEVICE = 1
+PER_VERTEX = 4
+
+PHASE_TOTAL, PHASE_PREP, PHASE_WEDGE, PHASE_PLAN = 0, 1, 2, 3
+
+
+class LibraryNotBuilt(ImportError):
+    pass
+
+
+class BBCError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"bbc error {code}: {message}")
+        self.code = code
+        self.message = message
+
+
+class Result(NamedTuple):
+    balanced: int
+    unbalanced: int
+    wedges: int
+
+
+class _CResult(ctypes.Structure):
+    _fields_ = [("balanced", ctypes.c_int64), ("unbalanced", ctypes.c_int64),
+                ("wedges", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return LIB_PATH
+
+
+def load_library():
+    """Load libbbc.so (built in-tree by ``python -m paper_2308_07932_amd._build``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise LibraryNotBuilt(f"{LIB_PATH} is missing; build it with "
+                              "`python -m paper_2308_07932_amd._build` (hipcc, gfx950)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, U32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+    lib.bbc_create.argtypes = [ctypes.c_int, P, ctypes.POINTER(P)]
+    lib.bbc_create.restype = ctypes.c_int
+    lib.bbc_destroy.argtypes = [P]
+    lib.bbc_destroy.restype = None
+    lib.bbc_count.argtypes = [P, I32, I32, I64, P, P, P, U32, ctypes.POINTER(_CResult), P]
+    lib.bbc_count.restype = ctypes.c_int
+    lib.bbc_status_string.argtypes = [ctypes.c_int]
+    lib.bbc_status_string.restype = ctypes.c_char_p
+    lib.bbc_last_error.argtypes = [P]
+    lib.bbc_last_error.restype = ctypes.c_char_p
+    lib.bbc_version.argtypes = []
+    lib.bbc_version.restype = ctypes.c_int
+    lib.bbc_set_timing.argtypes = [P, ctypes.c_int]
+    lib.bbc_set_timing.restype = ctypes.c_int
+    lib.bbc_last_phase_ms.argtypes = [P, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+    lib.bbc_last_phase_ms.restype = ctypes.c_int
+    lib.bbc_last_stats.argtypes = [P, ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
+    lib.bbc_last_stats.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def declared_symbols() -> list[str]:
+    """Function names declared in include/bbc.h."""
+    text = open(HEADER_PATH).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(bbc_[a-z_]+)\s*\(", text)))
+
+
+def status_string(code: int) -> str:
+    return load_library().bbc_status_string(int(code)).decode()
+
+
+def _is_torch(x) -> bool:
+    return type(x).__module__.startswith("torch")
+
+
+def _prepare(eu, ev, sign):
+    """Return (pointers, keepalive, on_device, n_edges)."""
+    if _is_torch(eu):
+        import torch  # noqa: F401  (only needed for tensors)
+        ts = (eu, ev, sign)
+        if not all(_is_torch(t) for t in ts):
+            raise TypeError("eu, ev and sign must all be torch tensors or all be arrays")
+        dev = {t.device.type for t in ts}
+        if len(dev) != 1:
+            raise ValueError("eu, ev and sign must live on the same device")
+        want = ("int32", "int32", "int8")
+        ts = tuple(t.contiguous() for t in ts)
+        for t, w in zip(ts, want):
+            if str(t.dtype) != f"torch.{w}":
+                raise TypeError(f"expected torch.{w}, got {t.dtype}")
+        n = int(ts[0].numel())
+        if int(ts[1].numel()) != n or int(ts[2].numel()) != n:
+            raise ValueError("eu, ev and sign must have the same length")
+        on_dev = ts[0].is_cuda
+        return tuple(t.data_ptr() for t in ts), ts, on_dev, n
+    arrs = (np.ascontiguousarray(eu, dtype=np.int32), np.ascontiguousarray(ev, dtype=np.int32),
+            np.ascontiguousarray(sign, dtype=np.int8))
+    n = int(arrs[0].shape[0])
+    if arrs[1].shape[0] != n or arrs[2].shape[0] != n:
+        raise ValueError("eu, ev and sign must have the same length")
+    return tuple(a.ctypes.data for a in arrs), arrs, False, n
+
+
+class Context:
+    """A libbbc context: device, stream and a reusable device workspace."""
+
+    def __init__(self, device: int = 0, stream: int | None = None):
+        lib = load_library()
+        h = ctypes.c_void_p()
+        rc = lib.bbc_create(int(device), ctypes.c_void_p(stream) if stream else None,
+                            ctypes.byref(h))
+        if rc != OK:
+            raise BBCError(rc, f"bbc_create(device={device}): {status_string(rc)}")
+        self._lib = lib
+        self._h = h
+        self.device = int(device)
+        self.stream = stream
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.bbc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def set_timing(self, on: bool = True):
+        self._lib.bbc_set_timing(self._h, 1 if on else 0)
+
+    def phase_ms(self, phase: int) -> float:
+        v = ctypes.c_double()
+        rc = self._lib.bbc_last_phase_ms(self._h, int(phase), ctypes.byref(v))
+        if rc != OK:
+            raise BBCError(rc, "no phase timing for the last call (enable set_timing)")
+        return float(v.value)
+
+    def stats(self) -> list[int]:
+        a = (ctypes.c_int64 * 8)()
+        self._lib.bbc_last_stats(self._h, a, 8)
+        return list(a)
+
+    def last_error(self) -> str:
+        return self._lib.bbc_last_error(self._h).decode()
+
+    def count_raw(self, n_u: int, n_v: int, n_edges: int, p_u: int, p_v: int, p_s: int,
+                  flags: int = 0, per_vertex_ptr: int | None = None) -> Result:
+        """Pointer-level entry (ints are addresses); raises BBCError on failure."""
+        out = _CResult()
+        rc = self._lib.bbc_count(self._h, int(n_u), int(n_v), int(n_edges), p_u, p_v, p_s,
+                                 int(flags), ctypes.byref(out), per_vertex_ptr)
+        if rc != OK:
+            raise BBCError(rc, self.last_error() or status_string(rc))
+        return Result(int(out.balanced), int(out.unbalanced), int(out.wedges))
+
+    def count(self, eu, ev, sign, n_u: int, n_v: int, per_vertex: bool = False):
+        """Count the balanced butterflies of the signed bipartite graph given by
+        edges (eu[i], ev[i]) with sign[i] in {+1, -1}.  Returns a Result, or
+        (Result, per-vertex int64 array) when per_vertex is set."""
+        ptrs, keep, on_dev, n = _prepare(eu, ev, sign)
+        flags = INPUT_ON_DEVICE if on_dev else 0
+        pv = None
+        pv_ptr = None
+        if per_vertex:
+            flags |= PER_VERTEX
+            pv = np.zeros(int(n_u) + int(n_v), dtype=np.int64)
+            pv_ptr = pv.ctypes.data
+        if on_dev:
+            import torch
+            cur = torch.cuda.current_stream(keep[0].device)
+            if self.stream is None or int(cur.cuda_stream) != int(self.stream):
+                cur.synchronize()
+        r = self.count_raw(n_u, n_v, n, *ptrs, flags=flags, per_vertex_ptr=pv_ptr)
+        del keep
+        return (r, pv) if per_vertex else r
+
+
+_default: dict[int, Context] = {}
+
+
+def default_context(device: int = 0) -> Context:
+    if device not in _default:
+        _default[device] = Context(device)
+    return _default[device]
+
+
+def count(eu, ev, sign, n_u: int, n_v: int, per_vertex: bool = False, device: int = 0):
+    """Module-level convenience: count on the default context of `device`."""
+    return default_context(device).count(eu, ev, sign, n_u, n_v, per_vertex=per_vertex)
+
+
+def version() -> int:
+    return int(load_library().bbc_version())

@@ -1,0 +1,514 @@
+// Host side of the C ABI declared in include/bbc.h: argument checks, the
+// device workspace, and the launch sequence of the counting pipeline.
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+
+#include "../../include/bbc.h"
+#include "bbc_internal.h"
+
+namespace bbc {
+// launchers defined in prep.hip / plan.hip / wedge.hip
+hipError_t launch_degree(const int32_t*, const int32_t*, const int8_t*, uint64_t, uint32_t, uint32_t,
+                         uint32_t*, Control*, hipStream_t);
+size_t radix_tmp_bytes(uint32_t n);
+hipError_t radix_sort_by_key(const uint32_t*, uint32_t, uint32_t, uint32_t*, uint32_t*, uint32_t*,
+                             uint32_t*, void*, size_t, uint32_t**, hipStream_t);
+hipError_t launch_sides(const uint32_t*, uint32_t, uint32_t, uint32_t*, hipStream_t);
+hipError_t launch_assign(const uint32_t*, const uint32_t*, const uint32_t*, uint32_t, uint32_t,
+                         uint32_t*, uint32_t*, uint32_t*, hipStream_t);
+hipError_t launch_scatter(const int32_t*, const int32_t*, const int8_t*, uint64_t, uint32_t,
+                          uint32_t, const uint32_t*, uint32_t*, uint32_t*, hipStream_t);
+hipError_t launch_row_sort(const uint32_t*, const uint32_t*, const uint32_t*, uint32_t*, Dims,
+                           Control*, uint32_t, hipStream_t);
+hipError_t launch_lowcount(const uint32_t*, const uint32_t*, const uint32_t*, uint32_t, uint32_t*,
+                           hipStream_t);
+hipError_t launch_records(const uint32_t*, const uint32_t*, const uint32_t*, const uint32_t*, Dims,
+                          const Control*, uint4*, u64*, uint32_t, hipStream_t);
+hipError_t launch_tile_table(const uint32_t*, const uint32_t*, Dims, const Control*, uint32_t*,
+                             uint32_t, hipStream_t);
+hipError_t launch_plan_count(const u64*, const uint32_t*, const uint32_t*, Dims, uint32_t*, u64*,
+                             uint32_t*, uint32_t*, u64*, u64*, hipStream_t);
+hipError_t launch_gather_totals(const uint32_t*, const u64*, const uint32_t*, const uint32_t*,
+                                uint32_t, Control*, hipStream_t);
+hipError_t launch_plan_write(const u64*, const uint32_t*, const uint32_t*, const uint32_t*,
+                             const uint32_t*,
+                             const uint32_t*, const u64*, const u64*, const uint32_t*,
+                             const uint32_t*, Dims, uint32_t, Piece*, u64*, uint32_t, uint32_t,
+                             uint32_t*, hipStream_t);
+hipError_t launch_wedge(const Piece*, const uint32_t*, uint32_t, uint32_t, const uint4*,
+                        const uint32_t*, const uint32_t*, Dims, const uint32_t[2], u64*, Control*,
+                        uint32_t, hipStream_t);
+}  // namespace bbc
+
+using namespace bbc;
+
+// ---------------------------------------------------------------------------
+// Device workspace: one growing buffer carved into 256-byte aligned slices.
+struct Arena {
+    char* base = nullptr;
+    size_t cap = 0;
+    size_t used = 0;
+};
+
+enum { kEvStart, kEvPrepEnd, kEvPlanA, kEvPlanB, kEvPlanC, kEvWedgeA, kEvWedgeB, kEvEnd, kNumEv };
+
+struct bbc_context {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    uint32_t num_cus = 0;
+    size_t budget = 0;  // 0 = unlimited
+    Arena prep, plan;
+    Control* host_ctl = nullptr;  // pinned
+    hipEvent_t ev[kNumEv] = {};
+    bool timing = false;
+    bool timing_valid = false;
+    float phase_ms[4] = {0, 0, 0, 0};
+    int64_t stats[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    char err[512] = {0};
+};
+
+static bbc_status fail(bbc_context* c, bbc_status s, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(c->err, sizeof(c->err), fmt, ap);
+    va_end(ap);
+    return s;
+}
+
+#define HIPCHECK(ctx, call)                                                                     \
+    do {                                                                                        \
+        hipError_t e_ = (call);                                                                 \
+        if (e_ != hipSuccess)                                                                   \
+            return fail((ctx), BBC_ERR_DEVICE, "%s failed: %s", #call, hipGetErrorString(e_));  \
+    } while (0)
+
+static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static size_t total_reserved(const bbc_context* c) { return c->prep.cap + c->plan.cap; }
+
+static bbc_status arena_reserve(bbc_context* c, Arena& a, size_t bytes) {
+    if (bytes <= a.cap) return BBC_OK;
+    size_t want = bytes + bytes / 4;
+    if (c->budget && total_reserved(c) - a.cap + want > c->budget) {
+        want = bytes;
+        if (total_reserved(c) - a.cap + want > c->budget)
+            return fail(c, BBC_ERR_OUT_OF_MEMORY,
+                        "device workspace of %zu bytes exceeds BBC_MAX_DEVICE_BYTES=%zu", bytes,
+                        c->budget);
+    }
+    if (a.base) {
+        hipError_t e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) return fail(c, BBC_ERR_DEVICE, "hipStreamSynchronize: %s", hipGetErrorString(e));
+        hipFree(a.base);
+        a.base = nullptr;
+        a.cap = 0;
+    }
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, want);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        e = hipMalloc(&p, bytes);
+        want = bytes;
+    }
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(c, BBC_ERR_OUT_OF_MEMORY, "hipMalloc(%zu) failed", bytes);
+    }
+    a.base = (char*)p;
+    a.cap = want;
+    return BBC_OK;
+}
+
+// Two-pass layout helper: first pass measures, second pass hands out pointers.
+struct Carver {
+    char* base;
+    size_t off = 0;
+    explicit Carver(char* b) : base(b) {}
+    template <typename T>
+    T* take(size_t count) {
+        T* p = base ? (T*)(base + off) : nullptr;
+        off += align_up(count * sizeof(T) + 1);
+        return p;
+    }
+};
+
+struct PrepBufs {
+    int32_t* eu;
+    int32_t* ev;
+    int8_t* sg;
+    uint32_t *deg, *k0, *v0, *k1, *v1, *flag, *cnt_u, *sidx_of, *rowdeg, *rowcross, *row_ptr,
+        *cursor, *col_in, *col, *lowcnt, *mptr, *tb, *hp, *hp_off, *lf, *lf_off, *gs, *gs_off;
+    u64 *lr, *lr_off, *wu;
+    uint4* recs;
+    void* rtmp;
+    void* stmp;
+    size_t rtmp_bytes, stmp_bytes;
+    Control* ctl;
+};
+
+static size_t carve_prep(Carver& cv, PrepBufs& b, uint32_t n, uint64_t m, bool copy_in,
+                         uint64_t tb_total) {
+    b.ctl = cv.take<Control>(1);
+    if (copy_in) {
+        b.eu = cv.take<int32_t>(m);
+        b.ev = cv.take<int32_t>(m);
+        b.sg = cv.take<int8_t>(m);
+    }
+    b.deg = cv.take<uint32_t>(n);
+    b.k0 = cv.take<uint32_t>(n);
+    b.v0 = cv.take<uint32_t>(n);
+    b.k1 = cv.take<uint32_t>(n);
+    b.v1 = cv.take<uint32_t>(n);
+    b.flag = cv.take<uint32_t>(n);
+    b.cnt_u = cv.take<uint32_t>(n + 1);
+    b.sidx_of = cv.take<uint32_t>(n);
+    b.rowdeg = cv.take<uint32_t>(n);
+    b.rowcross = cv.take<uint32_t>(n);
+    b.row_ptr = cv.take<uint32_t>(n + 1);
+    b.cursor = cv.take<uint32_t>(n);
+    b.col_in = cv.take<uint32_t>(2 * m);
+    b.col = cv.take<uint32_t>(2 * m);
+    b.lowcnt = cv.take<uint32_t>(n);
+    b.mptr = cv.take<uint32_t>(n + 1);
+    b.recs = cv.take<uint4>(m);
+    b.wu = cv.take<u64>(n);
+    b.tb = cv.take<uint32_t>(tb_total);
+    b.hp = cv.take<uint32_t>(n);
+    b.hp_off = cv.take<uint32_t>(n + 1);
+    b.lr = cv.take<u64>(n);
+    b.lr_off = cv.take<u64>(n + 1);
+    b.lf = cv.take<uint32_t>(n);
+    b.lf_off = cv.take<uint32_t>(n + 1);
+    b.gs = cv.take<uint32_t>(n);
+    b.gs_off = cv.take<uint32_t>(n + 1);
+    b.rtmp_bytes = radix_tmp_bytes(n);
+    b.rtmp = cv.take<char>(b.rtmp_bytes);
+    b.stmp_bytes = scan_tmp_bytes(n + 1);
+    b.stmp = cv.take<char>(b.stmp_bytes);
+    return cv.off;
+}
+
+static uint32_t bitlen(uint64_t x) {
+    uint32_t b = 0;
+    while (x) {
+        b++;
+        x >>= 1;
+    }
+    return b;
+}
+
+static float ev_ms(bbc_context* c, int a, int b) {
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, c->ev[a], c->ev[b]) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return ms;
+}
+
+// ---------------------------------------------------------------------------
+extern "C" {
+
+int bbc_version(void) { return 10000; }
+
+const char* bbc_status_string(bbc_status s) {
+    switch (s) {
+        case BBC_OK: return "ok";
+        case BBC_ERR_INVALID_ARG: return "invalid argument";
+        case BBC_ERR_VERTEX_RANGE: return "vertex id out of range";
+        case BBC_ERR_BAD_SIGN: return "edge sign not +1/-1";
+        case BBC_ERR_DUPLICATE_EDGE: return "duplicate edge";
+        case BBC_ERR_TOO_LARGE: return "graph too large";
+        case BBC_ERR_OVERFLOW: return "count overflows int64";
+        case BBC_ERR_OUT_OF_MEMORY: return "out of device memory";
+        case BBC_ERR_DEVICE: return "HIP device error";
+        case BBC_ERR_NOT_IMPLEMENTED: return "not implemented";
+        case BBC_ERR_INTERNAL: return "internal capacity exceeded";
+    }
+    return "unknown status";
+}
+
+const char* bbc_last_error(const bbc_context* ctx) { return ctx ? ctx->err : ""; }
+
+bbc_status bbc_create(int device, void* hip_stream, bbc_context** out) {
+    if (!out) return BBC_ERR_INVALID_ARG;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+        (void)hipGetLastError();
+        return BBC_ERR_DEVICE;
+    }
+    bbc_context* c = new bbc_context();
+    c->device = device;
+    if (hipSetDevice(device) != hipSuccess) {
+        delete c;
+        return BBC_ERR_DEVICE;
+    }
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+        cus <= 0)
+        cus = 256;
+    c->num_cus = (uint32_t)cus;
+    if (hip_stream) {
+        c->stream = (hipStream_t)hip_stream;
+    } else {
+        if (hipStreamCreate(&c->stream) != hipSuccess) {
+            delete c;
+            return BBC_ERR_DEVICE;
+        }
+        c->own_stream = true;
+    }
+    const char* b = getenv("BBC_MAX_DEVICE_BYTES");
+    if (b && *b) c->budget = (size_t)strtoull(b, nullptr, 10);
+    void* h = nullptr;
+    if (hipHostMalloc(&h, sizeof(Control), hipHostMallocDefault) != hipSuccess) {
+        bbc_destroy(c);
+        return BBC_ERR_DEVICE;
+    }
+    c->host_ctl = (Control*)h;
+    for (int i = 0; i < kNumEv; ++i)
+        if (hipEventCreate(&c->ev[i]) != hipSuccess) {
+            bbc_destroy(c);
+            return BBC_ERR_DEVICE;
+        }
+    *out = c;
+    return BBC_OK;
+}
+
+void bbc_destroy(bbc_context* c) {
+    if (!c) return;
+    hipSetDevice(c->device);
+    if (c->stream) hipStreamSynchronize(c->stream);
+    if (c->prep.base) hipFree(c->prep.base);
+    if (c->plan.base) hipFree(c->plan.base);
+    if (c->host_ctl) hipHostFree(c->host_ctl);
+    for (int i = 0; i < kNumEv; ++i)
+        if (c->ev[i]) hipEventDestroy(c->ev[i]);
+    if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
+    (void)hipGetLastError();
+    delete c;
+}
+
+bbc_status bbc_set_timing(bbc_context* c, int enabled) {
+    if (!c) return BBC_ERR_INVALID_ARG;
+    c->timing = enabled != 0;
+    return BBC_OK;
+}
+
+bbc_status bbc_last_phase_ms(const bbc_context* c, int phase, double* ms) {
+    if (!c || !ms || phase < 0 || phase > 3 || !c->timing_valid) return BBC_ERR_INVALID_ARG;
+    *ms = c->phase_ms[phase];
+    return BBC_OK;
+}
+
+bbc_status bbc_last_stats(const bbc_context* c, int64_t* stats, int n) {
+    if (!c || !stats || n < 0) return BBC_ERR_INVALID_ARG;
+    for (int i = 0; i < n && i < 8; ++i) stats[i] = c->stats[i];
+    return BBC_OK;
+}
+
+bbc_status bbc_count(bbc_context* c, int32_t n_u, int32_t n_v, int64_t n_edges,
+                     const int32_t* edge_u, const int32_t* edge_v, const int8_t* edge_sign,
+                     uint32_t flags, bbc_result* out, int64_t* per_vertex) {
+    if (!c) return BBC_ERR_INVALID_ARG;
+    c->err[0] = 0;
+    c->timing_valid = false;
+    if (!out) return fail(c, BBC_ERR_INVALID_ARG, "out is NULL");
+    if (n_u < 0 || n_v < 0 || n_edges < 0)
+        return fail(c, BBC_ERR_INVALID_ARG, "negative size (n_u=%d n_v=%d n_edges=%lld)", n_u, n_v,
+                    (long long)n_edges);
+    if (flags & ~(uint32_t)(BBC_INPUT_ON_DEVICE | BBC_PER_VERTEX))
+        return fail(c, BBC_ERR_INVALID_ARG, "unknown flag bits 0x%x", flags);
+    if (n_edges > 0 && (!edge_u || !edge_v || !edge_sign))
+        return fail(c, BBC_ERR_INVALID_ARG, "NULL edge array with n_edges=%lld", (long long)n_edges);
+    if (flags & BBC_PER_VERTEX) {
+        if (!per_vertex) return fail(c, BBC_ERR_INVALID_ARG, "BBC_PER_VERTEX without per_vertex buffer");
+        return fail(c, BBC_ERR_NOT_IMPLEMENTED, "per-vertex counts are not built");
+    }
+    const uint64_t n64 = (uint64_t)n_u + (uint64_t)n_v;
+    if (n64 >= (1ull << 30)) return fail(c, BBC_ERR_TOO_LARGE, "n_u + n_v = %llu >= 2^30", (unsigned long long)n64);
+    if ((uint64_t)n_edges >= (1ull << 31))
+        return fail(c, BBC_ERR_TOO_LARGE, "n_edges = %lld >= 2^31", (long long)n_edges);
+    if (n_edges == 0) {
+        out->balanced = out->unbalanced = out->wedges = 0;
+        memset(c->stats, 0, sizeof(c->stats));
+        return BBC_OK;
+    }
+    HIPCHECK(c, hipSetDevice(c->device));
+    hipStream_t st = c->stream;
+    const uint32_t n = (uint32_t)n64, nu = (uint32_t)n_u, nv = (uint32_t)n_v;
+    const uint64_t m = (uint64_t)n_edges;
+    const bool copy_in = !(flags & BBC_INPUT_ON_DEVICE);
+
+    Dims d;
+    d.n_u = nu;
+    d.n_v = nv;
+    d.n = n;
+    d.base[0] = 0;
+    d.base[1] = nu;
+    d.size[0] = nu;
+    d.size[1] = nv;
+    d.ntile[0] = (nu + kTile - 1) / kTile;
+    d.ntile[1] = (nv + kTile - 1) / kTile;
+    // rows of side Y with more than kLongDeg entries: at most m / (kLongDeg + 1) per side
+    uint64_t maxlong0 = std::min<uint64_t>(nu, m / (kLongDeg + 1));
+    uint64_t maxlong1 = std::min<uint64_t>(nv, m / (kLongDeg + 1));
+    d.tb_off[0] = 0;
+    d.tb_off[1] = maxlong0 * (d.ntile[1] + 1);
+    uint64_t tb_total = d.tb_off[1] + maxlong1 * (d.ntile[0] + 1);
+
+    // ---- workspace
+    PrepBufs b;
+    {
+        Carver probe(nullptr);
+        size_t need = carve_prep(probe, b, n, m, copy_in, tb_total);
+        bbc_status s = arena_reserve(c, c->prep, need);
+        if (s) return s;
+        Carver cv(c->prep.base);
+        carve_prep(cv, b, n, m, copy_in, tb_total);
+    }
+    const int32_t* eu = edge_u;
+    const int32_t* ev = edge_v;
+    const int8_t* sg = edge_sign;
+    if (copy_in) {
+        HIPCHECK(c, hipMemcpyAsync(b.eu, edge_u, m * 4, hipMemcpyHostToDevice, st));
+        HIPCHECK(c, hipMemcpyAsync(b.ev, edge_v, m * 4, hipMemcpyHostToDevice, st));
+        HIPCHECK(c, hipMemcpyAsync(b.sg, edge_sign, m, hipMemcpyHostToDevice, st));
+        eu = b.eu;
+        ev = b.ev;
+        sg = b.sg;
+    }
+    const bool tm = c->timing;
+    if (tm) HIPCHECK(c, hipEventRecord(c->ev[kEvStart], st));
+
+    // ---- control block
+    {
+        Control z;
+        memset(&z, 0, sizeof(z));
+        z.edge_err = ~0ull;
+        *c->host_ctl = z;
+        HIPCHECK(c, hipMemcpyAsync(b.ctl, c->host_ctl, sizeof(Control), hipMemcpyHostToDevice, st));
+    }
+
+    // ---- 1. degrees + validation
+    HIPCHECK(c, fill_u32(b.deg, 0, n, st));
+    HIPCHECK(c, launch_degree(eu, ev, sg, m, nu, nv, b.deg, b.ctl, st));
+    // ---- 2. priority order: stable sort of vertex ids by degree
+    uint32_t* inv = nullptr;
+    uint32_t maxdeg_bound = (uint32_t)std::min<uint64_t>(m, std::max(nu, nv));
+    HIPCHECK(c, radix_sort_by_key(b.deg, n, bitlen(maxdeg_bound), b.k0, b.v0, b.k1, b.v1, b.rtmp,
+                                  b.rtmp_bytes, &inv, st));
+    // ---- 3. per-side index and cross counts
+    HIPCHECK(c, launch_sides(inv, n, nu, b.flag, st));
+    HIPCHECK(c, scan_excl_u32(b.flag, b.cnt_u, n, b.stmp, b.stmp_bytes, st));
+    HIPCHECK(c, launch_assign(inv, b.cnt_u, b.deg, n, nu, b.sidx_of, b.rowdeg, b.rowcross, st));
+    // ---- 4. CSR: offsets, scatter, per-row sort
+    HIPCHECK(c, scan_excl_u32(b.rowdeg, b.row_ptr, n, b.stmp, b.stmp_bytes, st));
+    HIPCHECK(c, copy_u32(b.row_ptr, b.cursor, n, st));
+    HIPCHECK(c, launch_scatter(eu, ev, sg, m, nu, nv, b.sidx_of, b.cursor, b.col_in, st));
+    HIPCHECK(c, launch_row_sort(b.rowdeg, b.row_ptr, b.col_in, b.col, d, b.ctl, c->num_cus, st));
+    // ---- 5. middle counts, 6. records and W_u, 7. tile tables
+    HIPCHECK(c, launch_lowcount(b.row_ptr, b.col, b.rowcross, n, b.lowcnt, st));
+    HIPCHECK(c, scan_excl_u32(b.lowcnt, b.mptr, n, b.stmp, b.stmp_bytes, st));
+    HIPCHECK(c, launch_records(b.row_ptr, b.col, b.lowcnt, b.mptr, d, b.ctl, b.recs, b.wu,
+                               c->num_cus, st));
+    HIPCHECK(c, launch_tile_table(b.row_ptr, b.col, d, b.ctl, b.tb, c->num_cus, st));
+    if (tm) HIPCHECK(c, hipEventRecord(c->ev[kEvPrepEnd], st));
+
+    // ---- planning: piece counts, offsets, totals
+    HIPCHECK(c, launch_plan_count(b.wu, b.lowcnt, b.row_ptr, d, b.hp, b.lr, b.lf, b.gs, &b.ctl->wedges,
+                                  &b.ctl->active_starts, st));
+    HIPCHECK(c, scan_excl_u32(b.hp, b.hp_off, n, b.stmp, b.stmp_bytes, st));
+    HIPCHECK(c, scan_excl_u64(b.lr, b.lr_off, n, b.stmp, b.stmp_bytes, st));
+    HIPCHECK(c, scan_excl_u32(b.lf, b.lf_off, n, b.stmp, b.stmp_bytes, st));
+    HIPCHECK(c, scan_excl_u32(b.gs, b.gs_off, n, b.stmp, b.stmp_bytes, st));
+    HIPCHECK(c, launch_gather_totals(b.hp_off, b.lr_off, b.lf_off, b.gs_off, n, b.ctl, st));
+    if (tm) HIPCHECK(c, hipEventRecord(c->ev[kEvPlanA], st));
+    HIPCHECK(c, hipMemcpyAsync(c->host_ctl, b.ctl, sizeof(Control), hipMemcpyDeviceToHost, st));
+    HIPCHECK(c, hipStreamSynchronize(st));
+    Control h = *c->host_ctl;
+    if (h.edge_err != ~0ull) {
+        unsigned long long idx = h.edge_err >> 4;
+        if ((h.edge_err & 15ull) == kErrRange)
+            return fail(c, BBC_ERR_VERTEX_RANGE, "edge %llu: (u=%d, v=%d) outside |U|=%d, |V|=%d", idx,
+                        copy_in ? edge_u[idx] : -1, copy_in ? edge_v[idx] : -1, n_u, n_v);
+        return fail(c, BBC_ERR_BAD_SIGN, "edge %llu: sign %d is not +1/-1", idx,
+                    copy_in ? (int)edge_sign[idx] : 0);
+    }
+    if (h.dup) return fail(c, BBC_ERR_DUPLICATE_EDGE, "a (u, v) pair occurs more than once");
+
+    // ---- planning: write the pieces and the light items
+    if (h.tot_heavy + h.tot_light >= (1ull << 31))
+        return fail(c, BBC_ERR_INTERNAL, "too many work pieces (%llu)",
+                    (unsigned long long)(h.tot_heavy + h.tot_light));
+    const uint32_t n_heavy = (uint32_t)h.tot_heavy, n_light = (uint32_t)h.tot_light;
+    const uint64_t n_light_items64 = (h.tot_light_region + kLightWindow - 1) / kLightWindow;
+    const uint32_t n_light_items = (uint32_t)n_light_items64;
+    const uint32_t n_items = n_heavy + n_light_items;
+    uint32_t first_long[2] = {h.cls[0][4] - d.base[0], h.cls[1][4] - d.base[1]};
+    Piece* pieces;
+    u64* light_off;
+    uint32_t* items_first;
+    u64* G;
+    {
+        auto carve_plan = [&](Carver& cv) {
+            pieces = cv.take<Piece>((size_t)n_heavy + n_light);
+            light_off = cv.take<u64>((size_t)n_light + 1);
+            items_first = cv.take<uint32_t>((size_t)n_light_items + 2);
+            G = cv.take<u64>((size_t)h.tot_g + 1);
+            return cv.off;
+        };
+        Carver probe(nullptr);
+        size_t need = carve_plan(probe);
+        bbc_status s = arena_reserve(c, c->plan, need);
+        if (s) return s;
+        Carver cv(c->plan.base);
+        carve_plan(cv);
+    }
+    if (tm) HIPCHECK(c, hipEventRecord(c->ev[kEvPlanB], st));
+    HIPCHECK(c, fill_u64(G, 0, (size_t)h.tot_g, st));
+    HIPCHECK(c, launch_plan_write(b.wu, b.lowcnt, b.row_ptr, b.mptr, b.hp, b.hp_off, b.lr, b.lr_off, b.lf_off,
+                                  b.gs_off, d, n_heavy, pieces, light_off, n_light, n_light_items,
+                                  items_first, st));
+    if (tm) HIPCHECK(c, hipEventRecord(c->ev[kEvPlanC], st));
+
+    // ---- wedge enumeration and bucket counting
+    if (tm) HIPCHECK(c, hipEventRecord(c->ev[kEvWedgeA], st));
+    HIPCHECK(c, launch_wedge(pieces, items_first, n_heavy, n_items, b.recs, b.col, b.tb, d,
+                             first_long, G, b.ctl, c->num_cus, st));
+    if (tm) HIPCHECK(c, hipEventRecord(c->ev[kEvWedgeB], st));
+    if (tm) HIPCHECK(c, hipEventRecord(c->ev[kEvEnd], st));
+    HIPCHECK(c, hipMemcpyAsync(c->host_ctl, b.ctl, sizeof(Control), hipMemcpyDeviceToHost, st));
+    HIPCHECK(c, hipStreamSynchronize(st));
+    h = *c->host_ctl;
+    if (h.internal_err)
+        return fail(c, BBC_ERR_INTERNAL, "a hashed work piece could not be split further");
+    if (h.balanced > (u64)INT64_MAX || h.unbalanced > (u64)INT64_MAX || h.wedges > (u64)INT64_MAX)
+        return fail(c, BBC_ERR_OVERFLOW, "a count exceeds INT64_MAX");
+    if (tm) {
+        c->phase_ms[0] = ev_ms(c, kEvStart, kEvEnd);
+        c->phase_ms[1] = ev_ms(c, kEvStart, kEvPrepEnd);
+        c->phase_ms[2] = ev_ms(c, kEvWedgeA, kEvWedgeB);
+        c->phase_ms[3] = ev_ms(c, kEvPrepEnd, kEvPlanA) + ev_ms(c, kEvPlanB, kEvPlanC);
+        c->timing_valid = true;
+    }
+    c->stats[0] = (int64_t)n;
+    c->stats[1] = (int64_t)m;
+    c->stats[2] = (int64_t)h.wedges;
+    c->stats[3] = (int64_t)m;
+    c->stats[4] = (int64_t)n_items;
+    c->stats[5] = (int64_t)h.resplits;
+    c->stats[6] = (int64_t)h.active_starts;
+    c->stats[7] = (int64_t)n_heavy;
+    out->balanced = (int64_t)h.balanced;
+    out->unbalanced = (int64_t)h.unbalanced;
+    out->wedges = (int64_t)h.wedges;
+    return BBC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,148 @@
+// Internal definitions shared by the HIP sources of libbbc (not installed).
+//
+// Vocabulary (paper: Sections 2-4):
+//   * side 0 is U, side 1 is V; a vertex's "sidx" is its position among the
+//     vertices of its own side in ascending priority order, the priority being
+//     (degree, global id) with global ids U = 0..n_u-1, V = n_u..n-1
+//     (Definition 4).  Within one side sidx order equals priority order.
+//   * the CSR holds one row per vertex: rows 0..n_u-1 are U vertices by sidx,
+//     rows n_u..n-1 are V vertices by sidx.  An entry is (sidx(nbr) << 1) | neg,
+//     neg = 1 for a negative edge; every row is sorted ascending, i.e. by the
+//     neighbour's priority (the sorted adjacency of Algorithm 2).
+//   * cross(x) = number of vertices of the other side with lower priority than
+//     x: a neighbour y of x is a valid middle vertex (p(y) < p(x)) iff
+//     sidx(y) < cross(x).  A same-side end vertex w is valid (p(w) < p(x)) iff
+//     sidx(w) < sidx(x).
+//   * a "record" is an edge oriented from its higher-priority end u (the wedge
+//     start) to its lower one v (the middle): it stores where row v starts and
+//     pos = |{w in Gamma(v) : p(w) < p(u)}|, so the wedges (u, v, .) are the
+//     first pos entries of row v.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bbc {
+
+typedef unsigned long long u64;
+
+constexpr uint32_t kEmpty = 0xFFFFFFFFu;
+constexpr u64 kEmpty64 = ~0ull;
+constexpr uint32_t kNoTile = 0xFFFFFFFFu;
+
+// ---- degree classes used by the row sort and the record builder ----------
+// thresholds on row length; class c holds rows with kClassHi[c-1] < len <= kClassHi[c]
+constexpr int kNumClassBounds = 6;
+__host__ __device__ constexpr uint32_t class_hi(int c) {
+    return c == 0 ? 1u : c == 1 ? 8u : c == 2 ? 16u : c == 3 ? 32u : c == 4 ? 64u : 4096u;
+}
+constexpr uint32_t kLongDeg = 64;            // rows longer than this carry a tile table
+constexpr uint32_t kBitmapChunk = 1u << 18;  // sidx span handled per block by the big-row sort
+
+// ---- wedge kernel geometry -------------------------------------------------
+constexpr int kWedgeThreads = 1024;
+constexpr uint32_t kDenseW = 16384;           // dense counters per item (u64 each, 128 KiB)
+constexpr uint32_t kHashSlots = 8192;         // hash slots (u32 key + u64 counters)
+constexpr uint32_t kLightWindow = kHashSlots / 2;  // H: light regions start inside [iH, iH+H)
+constexpr uint32_t kLightMax = kHashSlots / 4;     // max wedges of a batched (light) start
+constexpr uint32_t kMinRegion = 32;
+constexpr uint32_t kMaxItemPieces = (2 * kLightWindow) / kMinRegion + 1;
+constexpr uint32_t kTile = 16384;             // end-vertex tile width (sidx units)
+constexpr u64 kRecordChunkWedges = 65536;     // wedges per record chunk of a small-side start
+constexpr double kHashTarget = 4096.0;       // expected wedges per hashed run of tiles
+
+// piece flags
+constexpr uint32_t kPieceDense = 1u;    // counters addressed by w - lo (else hashed)
+constexpr uint32_t kPieceMerge = 2u;    // partial counts: merge exactly through G
+constexpr uint32_t kPiecePartial = 4u;  // w-range is a tile range: look up sub-intervals
+constexpr uint32_t kPieceSideV = 8u;    // the start vertex lies on side V
+
+// One unit of counting: records [rec0, rec0 + nrec) of one start vertex,
+// restricted to end vertices with sidx in [lo, hi).
+struct Piece {
+    uint32_t rec0, nrec;
+    uint32_t lo, hi;
+    uint32_t t0, t1;      // tile range [t0, t1) when kPiecePartial
+    uint32_t region;      // hash region: base | log2(size) << 16
+    uint32_t flags;
+    uint32_t gbase;       // merge array offset (kPieceMerge)
+    uint32_t start_row;   // row of the start vertex
+};
+
+// Error word bits (device -> host); edge errors keep the first offending edge.
+constexpr u64 kErrRange = 1;
+constexpr u64 kErrSign = 2;
+
+// Layout of the small device "control" block.
+struct Control {
+    u64 edge_err;        // min over bad edges of (index << 4 | code), ~0 if none
+    u64 balanced;
+    u64 unbalanced;
+    u64 wedges;
+    u64 resplits;        // hashed pieces abandoned and redone in halves
+    uint32_t internal_err;
+    uint32_t pad0;
+    uint32_t dup;        // duplicate edge seen
+    uint32_t queue;      // wedge-kernel work counter
+    uint32_t cls[2][kNumClassBounds];  // first row (absolute) with len > class_hi(c), per side
+    uint32_t nbig_pairs; // (big row, chunk) pairs for the bitmap sort
+    uint32_t pad;
+    u64 tot_heavy, tot_light_region, tot_light, tot_g;  // planner totals
+    u64 active_starts;   // vertices with W_u > 0
+};
+
+struct Dims {
+    uint32_t n_u, n_v, n;
+    uint32_t base[2];   // first row of each side
+    uint32_t size[2];   // vertices per side
+    uint32_t ntile[2];  // ceil(size[s] / kTile): tiles over side s's sidx space
+    uint64_t tb_off[2]; // tile-table offset for rows of side s (entries index the other side)
+};
+
+// ---- small device helpers ---------------------------------------------------
+__device__ inline uint32_t lane_id() { return threadIdx.x & 63u; }
+
+__device__ inline uint32_t lower_bound_u32(const uint32_t* a, uint32_t n, uint32_t key) {
+    uint32_t lo = 0, hi = n;
+    while (lo < hi) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (a[mid] < key)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+template <typename T>
+__device__ inline T wave_reduce_sum(T v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// inclusive scan across the 64 lanes of a wave
+template <typename T>
+__device__ inline T wave_incl_scan(T v) {
+    const uint32_t lane = lane_id();
+    for (int off = 1; off < 64; off <<= 1) {
+        T o = __shfl_up(v, off, 64);
+        if (lane >= (uint32_t)off) v += o;
+    }
+    return v;
+}
+
+__device__ inline u64 choose2(u64 k) { return k < 2 ? 0 : k * (k - 1) / 2; }
+
+}  // namespace bbc
+
+// ---- host-side launchers (defined in the .hip files) ------------------------
+namespace bbc {
+hipError_t scan_excl_u32(const uint32_t* in, uint32_t* out, uint32_t n, void* tmp, size_t tmp_bytes,
+                         hipStream_t st);
+hipError_t scan_excl_u64(const u64* in, u64* out, uint32_t n, void* tmp, size_t tmp_bytes,
+                         hipStream_t st);
+size_t scan_tmp_bytes(uint32_t n);
+hipError_t fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t st);
+hipError_t fill_u64(u64* p, u64 v, size_t n, hipStream_t st);
+hipError_t copy_u32(const uint32_t* src, uint32_t* dst, size_t n, hipStream_t st);
+}  // namespace bbc

@@ -1,0 +1,637 @@
+// Preprocessing of the bucket method (paper: Section 4.1, Algorithm 2, lines
+// "compute p(u)" and "rearrange Gamma(u) in ascending order"; Section 4.2 notes
+// the O(n) binning sort of the vertices):
+//   1. validate edges and count degrees;
+//   2. order all vertices by priority (degree, id) with a stable LSD radix sort
+//      on the degree (ids enter in ascending order, so ties keep id order);
+//   3. per-side index (sidx) and cross counts from a scan of side flags;
+//   4. signed CSR: row offsets by scan, scatter, then a segmented sort of every
+//      row by neighbour priority (size classes: registers, lane groups, LDS
+//      bitonic, LDS bitmaps);
+//   5. per row the number k of lower-priority neighbours (middle vertices);
+//   6. one record per edge, oriented from its higher-priority end, holding the
+//      middle row and the prefix length pos; W_u = sum of pos over u's records;
+//   7. tile boundary tables for long rows.
+#include "bbc_internal.h"
+
+namespace bbc {
+
+// ---------------------------------------------------------------- degrees ----
+__global__ void k_degree(const int32_t* __restrict__ eu, const int32_t* __restrict__ ev,
+                         const int8_t* __restrict__ sg, uint64_t m, uint32_t n_u, uint32_t n_v,
+                         uint32_t* __restrict__ deg, Control* ctl) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        int32_t u = eu[i], v = ev[i];
+        int8_t s = sg[i];
+        if (u < 0 || (uint32_t)u >= n_u || v < 0 || (uint32_t)v >= n_v) {
+            atomicMin(&ctl->edge_err, (i << 4) | kErrRange);
+            continue;
+        }
+        if (s != 1 && s != -1) {
+            atomicMin(&ctl->edge_err, (i << 4) | kErrSign);
+            continue;
+        }
+        atomicAdd(&deg[u], 1u);
+        atomicAdd(&deg[n_u + (uint32_t)v], 1u);
+    }
+}
+
+// ------------------------------------------------------------- radix sort ----
+// Stable LSD radix sort of (key, value) pairs, 8-bit digits.  Tiles of 2048
+// elements per workgroup; per-tile digit histograms are scanned digit-major so
+// that each tile writes its elements of digit d after all earlier tiles'.
+constexpr int kRsThreads = 256;
+constexpr int kRsItems = 8;
+constexpr uint32_t kRsTile = kRsThreads * kRsItems;
+
+__global__ __launch_bounds__(kRsThreads) void k_rs_hist(const uint32_t* __restrict__ keys,
+                                                        uint32_t n, uint32_t shift,
+                                                        uint32_t* __restrict__ hist) {
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const uint64_t base = (uint64_t)blockIdx.x * kRsTile;
+    for (int i = 0; i < kRsItems; ++i) {
+        uint64_t idx = base + (uint64_t)i * kRsThreads + threadIdx.x;
+        if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(uint64_t)threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
+}
+
+// vals == nullptr means value = element index
+__global__ __launch_bounds__(kRsThreads) void k_rs_scatter(
+    const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals, uint32_t n,
+    uint32_t shift, const uint32_t* __restrict__ offs, uint32_t* __restrict__ keys_out,
+    uint32_t* __restrict__ vals_out) {
+    __shared__ uint32_t cnt[256];
+    __shared__ uint32_t wh[kRsThreads / 64][256];
+    const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
+    cnt[tid] = offs[(uint64_t)tid * gridDim.x + blockIdx.x];
+    for (int w = 0; w < kRsThreads / 64; ++w) wh[w][tid] = 0;
+    __syncthreads();
+    const uint64_t base = (uint64_t)blockIdx.x * kRsTile;
+    const u64 lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int r = 0; r < kRsItems; ++r) {
+        uint64_t idx = base + (uint64_t)r * kRsThreads + tid;
+        bool valid = idx < n;
+        uint32_t key = valid ? keys[idx] : 0u;
+        uint32_t val = valid ? (vals ? vals[idx] : (uint32_t)idx) : 0u;
+        uint32_t d = (key >> shift) & 255u;
+        u64 peers = __ballot(valid);
+        for (int b = 0; b < 8; ++b) {
+            u64 bb = __ballot((d >> b) & 1u);
+            peers &= ((d >> b) & 1u) ? bb : ~bb;
+        }
+        uint32_t lrank = __popcll(peers & lt_mask);
+        if (valid && lrank == 0) wh[wave][d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        {
+            uint32_t run = cnt[tid];
+            for (int w = 0; w < kRsThreads / 64; ++w) {
+                uint32_t c = wh[w][tid];
+                wh[w][tid] = run;
+                run += c;
+            }
+            cnt[tid] = run;
+        }
+        __syncthreads();
+        if (valid) {
+            uint32_t dst = wh[wave][d] + lrank;
+            keys_out[dst] = key;
+            vals_out[dst] = val;
+        }
+        __syncthreads();
+        for (int w = 0; w < kRsThreads / 64; ++w) wh[w][tid] = 0;
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------ sides and rows -------
+__global__ void k_side_flags(const uint32_t* __restrict__ inv, uint32_t n, uint32_t n_u,
+                             uint32_t* __restrict__ flag) {
+    for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x)
+        flag[r] = inv[r] < n_u ? 1u : 0u;
+}
+
+// rank r -> sidx of its vertex, its row, the row's length and cross threshold
+__global__ void k_assign(const uint32_t* __restrict__ inv, const uint32_t* __restrict__ cnt_u,
+                         const uint32_t* __restrict__ deg, uint32_t n, uint32_t n_u,
+                         uint32_t* __restrict__ sidx_of, uint32_t* __restrict__ rowdeg,
+                         uint32_t* __restrict__ rowcross) {
+    for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
+        uint32_t g = inv[r], cu = cnt_u[r];
+        uint32_t sidx, cross, row;
+        if (g < n_u) {
+            sidx = cu;
+            cross = r - cu;  // V vertices below r
+            row = sidx;
+        } else {
+            sidx = r - cu;
+            cross = cu;      // U vertices below r
+            row = n_u + sidx;
+        }
+        sidx_of[g] = sidx;
+        rowdeg[row] = deg[g];
+        rowcross[row] = cross;
+    }
+}
+
+__global__ void k_scatter(const int32_t* __restrict__ eu, const int32_t* __restrict__ ev,
+                          const int8_t* __restrict__ sg, uint64_t m, uint32_t n_u, uint32_t n_v,
+                          const uint32_t* __restrict__ sidx_of, uint32_t* __restrict__ cursor,
+                          uint32_t* __restrict__ col) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        int32_t u = eu[i], v = ev[i];
+        int8_t s = sg[i];
+        if (u < 0 || (uint32_t)u >= n_u || v < 0 || (uint32_t)v >= n_v || (s != 1 && s != -1))
+            continue;
+        uint32_t su = sidx_of[u], sv = sidx_of[n_u + (uint32_t)v];
+        uint32_t neg = s < 0 ? 1u : 0u;
+        uint32_t pu = atomicAdd(&cursor[su], 1u);
+        col[pu] = (sv << 1) | neg;
+        uint32_t pv = atomicAdd(&cursor[n_u + sv], 1u);
+        col[pv] = (su << 1) | neg;
+    }
+}
+
+// Row lengths are non-decreasing inside each side (sidx order is degree
+// order), so each size class is a contiguous row range per side.
+__global__ void k_classes(const uint32_t* __restrict__ rowdeg, Dims d, Control* ctl) {
+    uint32_t t = threadIdx.x;
+    if (t >= 2 * kNumClassBounds) return;
+    uint32_t side = t / kNumClassBounds, c = t % kNumClassBounds;
+    uint32_t lo = d.base[side], hi = d.base[side] + d.size[side];
+    uint32_t th = class_hi((int)c);
+    while (lo < hi) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (rowdeg[mid] <= th)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    ctl->cls[side][c] = lo;
+}
+
+// ---------------------------------------------------------- row sorting ------
+// Class ranges, per side: c0 [base, cls0): len <= 1, c1 [cls0, cls1): <= 8,
+// c2 <= 16, c3 <= 32, c4 <= 64, c5 (64, 4096], c6 > 4096.
+__device__ inline void class_range(const Control* ctl, const Dims& d, int side, int c0, int c1,
+                                   uint32_t* lo, uint32_t* hi) {
+    *lo = c0 == 0 ? d.base[side] : ctl->cls[side][c0 - 1];
+    *hi = c1 >= kNumClassBounds ? d.base[side] + d.size[side] : ctl->cls[side][c1];
+}
+
+__device__ inline void cswap(uint32_t& a, uint32_t& b) {
+    uint32_t x = min(a, b), y = max(a, b);
+    a = x;
+    b = y;
+}
+
+// rows with len <= 8: one thread per row, 8-input sorting network in registers
+__global__ void k_sort_tiny(const uint32_t* __restrict__ row_ptr, const uint32_t* __restrict__ in,
+                            uint32_t* __restrict__ out, Dims d, Control* ctl) {
+    uint32_t lo0, hi0, lo1, hi1;
+    class_range(ctl, d, 0, 0, 1, &lo0, &hi0);
+    class_range(ctl, d, 1, 0, 1, &lo1, &hi1);
+    uint32_t n0 = hi0 - lo0, tot = n0 + (hi1 - lo1);
+    bool dup = false;
+    for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < tot; q += gridDim.x * blockDim.x) {
+        uint32_t r = q < n0 ? lo0 + q : lo1 + (q - n0);
+        uint32_t a = row_ptr[r], L = row_ptr[r + 1] - a;
+        uint32_t x[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) x[i] = (uint32_t)i < L ? in[a + i] : kEmpty;
+        // Batcher odd-even merge sort network for 8 inputs (19 comparators)
+        cswap(x[0], x[1]); cswap(x[2], x[3]); cswap(x[4], x[5]); cswap(x[6], x[7]);
+        cswap(x[0], x[2]); cswap(x[1], x[3]); cswap(x[4], x[6]); cswap(x[5], x[7]);
+        cswap(x[1], x[2]); cswap(x[5], x[6]);
+        cswap(x[0], x[4]); cswap(x[1], x[5]); cswap(x[2], x[6]); cswap(x[3], x[7]);
+        cswap(x[2], x[4]); cswap(x[3], x[5]);
+        cswap(x[1], x[2]); cswap(x[3], x[4]); cswap(x[5], x[6]);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            if ((uint32_t)i < L) {
+                out[a + i] = x[i];
+                if (i > 0 && (x[i] >> 1) == (x[i - 1] >> 1)) dup = true;
+            }
+        }
+    }
+    if (dup) atomicOr(&ctl->dup, 1u);
+}
+
+// rows with G/2 < len <= G (G = 16, 32, 64): G lanes per row, bitonic sort
+// across the lanes with shuffles.
+template <int G>
+__global__ __launch_bounds__(256) void k_sort_group(const uint32_t* __restrict__ row_ptr,
+                                                    const uint32_t* __restrict__ in,
+                                                    uint32_t* __restrict__ out, Dims d,
+                                                    Control* ctl) {
+    constexpr int cls = G == 16 ? 2 : (G == 32 ? 3 : 4);
+    uint32_t lo0, hi0, lo1, hi1;
+    class_range(ctl, d, 0, cls, cls, &lo0, &hi0);
+    class_range(ctl, d, 1, cls, cls, &lo1, &hi1);
+    uint32_t n0 = hi0 - lo0, tot = n0 + (hi1 - lo1);
+    const uint32_t gl = threadIdx.x & (G - 1);
+    const uint32_t groups_per_block = blockDim.x / G;
+    const uint32_t gid = blockIdx.x * groups_per_block + threadIdx.x / G;
+    const uint32_t gstride = gridDim.x * groups_per_block;
+    bool dup = false;
+    // every lane of a wave runs the same number of iterations (uniform bound)
+    const uint32_t iters = (tot + gstride - 1) / gstride;
+    for (uint32_t it = 0; it < iters; ++it) {
+        uint32_t q = gid + it * gstride;
+        bool act = q < tot;
+        uint32_t r = act ? (q < n0 ? lo0 + q : lo1 + (q - n0)) : 0;
+        uint32_t a = act ? row_ptr[r] : 0, L = act ? row_ptr[r + 1] - a : 0;
+        uint32_t v = gl < L ? in[a + gl] : kEmpty;
+#pragma unroll
+        for (int k = 2; k <= G; k <<= 1) {
+#pragma unroll
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                uint32_t o = __shfl_xor(v, j, 64);
+                bool asc = (gl & k) == 0;
+                bool low = (gl & j) == 0;
+                v = (low == asc) ? min(v, o) : max(v, o);
+            }
+        }
+        uint32_t prev = __shfl_up(v, 1, 64);
+        if (gl < L) {
+            out[a + gl] = v;
+            if (gl > 0 && (prev >> 1) == (v >> 1)) dup = true;
+        }
+    }
+    if (dup) atomicOr(&ctl->dup, 1u);
+}
+
+// rows with 64 < len <= 4096: one workgroup per row, bitonic sort in LDS
+__global__ __launch_bounds__(256) void k_sort_block(const uint32_t* __restrict__ row_ptr,
+                                                   const uint32_t* __restrict__ in,
+                                                   uint32_t* __restrict__ out, Dims d,
+                                                   Control* ctl) {
+    __shared__ uint32_t s[4096];
+    uint32_t lo0, hi0, lo1, hi1;
+    class_range(ctl, d, 0, 5, 5, &lo0, &hi0);
+    class_range(ctl, d, 1, 5, 5, &lo1, &hi1);
+    uint32_t n0 = hi0 - lo0, tot = n0 + (hi1 - lo1);
+    bool dup = false;
+    for (uint32_t q = blockIdx.x; q < tot; q += gridDim.x) {
+        uint32_t r = q < n0 ? lo0 + q : lo1 + (q - n0);
+        uint32_t a = row_ptr[r], L = row_ptr[r + 1] - a;
+        uint32_t P = 1;
+        while (P < L) P <<= 1;
+        for (uint32_t i = threadIdx.x; i < P; i += blockDim.x) s[i] = i < L ? in[a + i] : kEmpty;
+        __syncthreads();
+        for (uint32_t k = 2; k <= P; k <<= 1) {
+            for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+                for (uint32_t i = threadIdx.x; i < P; i += blockDim.x) {
+                    uint32_t ij = i ^ j;
+                    if (ij > i) {
+                        uint32_t x = s[i], y = s[ij];
+                        bool asc = (i & k) == 0;
+                        if ((x > y) == asc) {
+                            s[i] = y;
+                            s[ij] = x;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        for (uint32_t i = threadIdx.x; i < L; i += blockDim.x) {
+            uint32_t x = s[i];
+            out[a + i] = x;
+            if (i > 0 && (s[i - 1] >> 1) == (x >> 1)) dup = true;
+        }
+        __syncthreads();
+    }
+    if (dup) atomicOr(&ctl->dup, 1u);
+}
+
+// rows with len > 4096: one workgroup per (row, sidx chunk of 2^18): mark the
+// row's entries of the chunk in an LDS bitmap (plus a sign bitmap), then emit
+// the set bits in order.  Entries are distinct unless an edge is repeated,
+// which the bitmap detects.
+constexpr int kBigThreads = 512;
+constexpr uint32_t kBigWords = kBitmapChunk / 32;
+
+__device__ inline void big_pair(const Control* ctl, const Dims& d, uint32_t q, uint32_t* row,
+                                uint32_t* chunk, uint32_t* ok) {
+    // side 0 big rows (entries index side 1), then side 1 big rows
+    uint32_t b0 = ctl->cls[0][5], e0 = d.base[0] + d.size[0];
+    uint32_t b1 = ctl->cls[1][5], e1 = d.base[1] + d.size[1];
+    uint32_t ch0 = (d.size[1] + kBitmapChunk - 1) / kBitmapChunk;
+    uint32_t ch1 = (d.size[0] + kBitmapChunk - 1) / kBitmapChunk;
+    uint32_t np0 = (e0 - b0) * ch0, np1 = (e1 - b1) * ch1;
+    *ok = 1;
+    if (q < np0) {
+        *row = b0 + q / ch0;
+        *chunk = q % ch0;
+    } else if (q - np0 < np1) {
+        q -= np0;
+        *row = b1 + q / ch1;
+        *chunk = q % ch1;
+    } else {
+        *ok = 0;
+    }
+}
+
+__global__ __launch_bounds__(kBigThreads) void k_sort_big(const uint32_t* __restrict__ row_ptr,
+                                                          const uint32_t* __restrict__ in,
+                                                          uint32_t* __restrict__ out, Dims d,
+                                                          Control* ctl) {
+    __shared__ uint32_t bm[kBigWords];
+    __shared__ uint32_t sgn[kBigWords];
+    __shared__ uint32_t s_wave[kBigThreads / 64];
+    __shared__ uint32_t s_before;
+    const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
+    bool dup = false;
+    for (uint32_t q = blockIdx.x;; q += gridDim.x) {
+        uint32_t r, c, ok;
+        big_pair(ctl, d, q, &r, &c, &ok);
+        if (!ok) break;
+        for (uint32_t i = tid; i < kBigWords; i += kBigThreads) {
+            bm[i] = 0;
+            sgn[i] = 0;
+        }
+        if (tid == 0) s_before = 0;
+        __syncthreads();
+        const uint32_t a = row_ptr[r], L = row_ptr[r + 1] - a;
+        const uint32_t c0 = c * kBitmapChunk;
+        uint32_t before = 0;
+        for (uint32_t e = tid; e < L; e += kBigThreads) {
+            uint32_t x = in[a + e];
+            uint32_t y = x >> 1;
+            if (y < c0) {
+                before++;
+            } else if (y - c0 < kBitmapChunk) {
+                uint32_t bit = y - c0;
+                uint32_t m = 1u << (bit & 31);
+                uint32_t old = atomicOr(&bm[bit >> 5], m);
+                if (old & m) dup = true;
+                if (x & 1u) atomicOr(&sgn[bit >> 5], m);
+            }
+        }
+        before = wave_reduce_sum(before);
+        if (lane == 0) atomicAdd(&s_before, before);
+        __syncthreads();
+        // compaction: each thread owns kBigWords / kBigThreads consecutive words
+        constexpr uint32_t kPer = kBigWords / kBigThreads;
+        uint32_t cnt = 0;
+        for (uint32_t i = 0; i < kPer; ++i) cnt += __popc(bm[tid * kPer + i]);
+        uint32_t incl = wave_incl_scan(cnt);
+        if (lane == 63) s_wave[wave] = incl;
+        __syncthreads();
+        uint32_t off = 0;
+        for (uint32_t w = 0; w < wave; ++w) off += s_wave[w];
+        uint32_t pos = a + s_before + off + incl - cnt;
+        for (uint32_t i = 0; i < kPer; ++i) {
+            uint32_t wi = tid * kPer + i;
+            uint32_t bits = bm[wi], sb = sgn[wi];
+            while (bits) {
+                uint32_t b = __ffs(bits) - 1;
+                uint32_t y = c0 + wi * 32 + b;
+                if (pos < a + L) out[pos] = (y << 1) | ((sb >> b) & 1u);
+                pos++;
+                bits &= bits - 1;
+            }
+        }
+        __syncthreads();
+    }
+    if (dup) atomicOr(&ctl->dup, 1u);
+}
+
+// --------------------------------------------------- lower neighbour counts --
+__global__ void k_lowcount(const uint32_t* __restrict__ row_ptr, const uint32_t* __restrict__ col,
+                           const uint32_t* __restrict__ rowcross, uint32_t n,
+                           uint32_t* __restrict__ lowcnt) {
+    for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
+        uint32_t a = row_ptr[r], L = row_ptr[r + 1] - a;
+        lowcnt[r] = lower_bound_u32(col + a, L, rowcross[r] << 1);
+    }
+}
+
+// ------------------------------------------------------------- records ------
+// Record of middle entry j of row r (start x, side X; middle v, side Y):
+//   .x = first entry of row v, .y = pos << 1 | neg(x, v), .z = sidx(v)
+// with pos = |{w in Gamma(v): sidx(w) < sidx(x)}| (row v holds X-side sidx).
+__device__ inline uint32_t make_record(const uint32_t* __restrict__ row_ptr,
+                                       const uint32_t* __restrict__ col, const Dims& d,
+                                       uint32_t side, uint32_t my_sidx, uint32_t e,
+                                       uint4* rec) {
+    uint32_t vs = e >> 1;
+    uint32_t oth = side ^ 1u;
+    if (vs >= d.size[oth]) {  // only possible when a repeated edge left a hole
+        *rec = make_uint4(0, 0, 0, 0);
+        return 0;
+    }
+    uint32_t vrow = d.base[oth] + vs;
+    uint32_t va = row_ptr[vrow], vl = row_ptr[vrow + 1] - va;
+    uint32_t pos = lower_bound_u32(col + va, vl, my_sidx << 1);
+    *rec = make_uint4(va, (pos << 1) | (e & 1u), vs, 0u);
+    return pos;
+}
+
+// rows with len <= 64: one thread per row
+__global__ void k_records_small(const uint32_t* __restrict__ row_ptr,
+                                const uint32_t* __restrict__ col,
+                                const uint32_t* __restrict__ lowcnt,
+                                const uint32_t* __restrict__ mptr, Dims d, const Control* ctl,
+                                uint4* __restrict__ recs, u64* __restrict__ wu) {
+    uint32_t lo0 = d.base[0], hi0 = ctl->cls[0][4];
+    uint32_t lo1 = d.base[1], hi1 = ctl->cls[1][4];
+    uint32_t n0 = hi0 - lo0, tot = n0 + (hi1 - lo1);
+    for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < tot; q += gridDim.x * blockDim.x) {
+        uint32_t side = q < n0 ? 0u : 1u;
+        uint32_t r = side == 0 ? lo0 + q : lo1 + (q - n0);
+        uint32_t my = r - d.base[side];
+        uint32_t a = row_ptr[r], k = lowcnt[r], mp = mptr[r];
+        u64 w = 0;
+        for (uint32_t j = 0; j < k; ++j) {
+            uint4 rc;
+            w += make_record(row_ptr, col, d, side, my, col[a + j], &rc);
+            recs[mp + j] = rc;
+        }
+        wu[r] = w;
+    }
+}
+
+// rows with len > 64: one wave per row
+__global__ __launch_bounds__(256) void k_records_wave(const uint32_t* __restrict__ row_ptr,
+                                                      const uint32_t* __restrict__ col,
+                                                      const uint32_t* __restrict__ lowcnt,
+                                                      const uint32_t* __restrict__ mptr, Dims d,
+                                                      const Control* ctl,
+                                                      uint4* __restrict__ recs,
+                                                      u64* __restrict__ wu) {
+    uint32_t lo0 = ctl->cls[0][4], hi0 = d.base[0] + d.size[0];
+    uint32_t lo1 = ctl->cls[1][4], hi1 = d.base[1] + d.size[1];
+    uint32_t n0 = hi0 - lo0, tot = n0 + (hi1 - lo1);
+    const uint32_t lane = lane_id();
+    const uint32_t wid = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t wstride = (gridDim.x * blockDim.x) >> 6;
+    for (uint32_t q = wid; q < tot; q += wstride) {
+        uint32_t side = q < n0 ? 0u : 1u;
+        uint32_t r = side == 0 ? lo0 + q : lo1 + (q - n0);
+        uint32_t my = r - d.base[side];
+        uint32_t a = row_ptr[r], k = lowcnt[r], mp = mptr[r];
+        u64 w = 0;
+        for (uint32_t j = lane; j < k; j += 64) {
+            uint4 rc;
+            w += make_record(row_ptr, col, d, side, my, col[a + j], &rc);
+            recs[mp + j] = rc;
+        }
+        w = wave_reduce_sum(w);
+        if (lane == 0) wu[r] = w;
+    }
+}
+
+// ------------------------------------------------------- tile boundaries ----
+// For a long row of side Y (entries: X-side sidx), tb[t] = number of entries
+// with sidx < t * kTile, t = 0..ntile[X]; one wave per row.
+__global__ __launch_bounds__(256) void k_tile_table(const uint32_t* __restrict__ row_ptr,
+                                                    const uint32_t* __restrict__ col, Dims d,
+                                                    const Control* ctl, uint32_t* __restrict__ tb) {
+    uint32_t lo0 = ctl->cls[0][4], hi0 = d.base[0] + d.size[0];
+    uint32_t lo1 = ctl->cls[1][4], hi1 = d.base[1] + d.size[1];
+    uint32_t n0 = hi0 - lo0, tot = n0 + (hi1 - lo1);
+    const uint32_t lane = lane_id();
+    const uint32_t wid = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t wstride = (gridDim.x * blockDim.x) >> 6;
+    for (uint32_t q = wid; q < tot; q += wstride) {
+        uint32_t side = q < n0 ? 0u : 1u;     // side Y of the row
+        uint32_t r = side == 0 ? lo0 + q : lo1 + (q - n0);
+        uint32_t rel = side == 0 ? q : q - n0;
+        uint32_t nt = d.ntile[side ^ 1u];
+        uint32_t a = row_ptr[r], L = row_ptr[r + 1] - a;
+        uint32_t* out = tb + d.tb_off[side] + (uint64_t)rel * (nt + 1);
+        for (uint32_t t = lane; t <= nt; t += 64) {
+            uint64_t key = (uint64_t)t * kTile;
+            out[t] = key >= d.size[side ^ 1u] ? L : lower_bound_u32(col + a, L, (uint32_t)key << 1);
+        }
+    }
+}
+
+// ------------------------------------------------------------- launchers -----
+static dim3 grid_n(uint64_t n, uint32_t threads, uint32_t cap = 16384) {
+    uint64_t b = (n + threads - 1) / threads;
+    if (b > cap) b = cap;
+    if (b == 0) b = 1;
+    return dim3((unsigned)b);
+}
+
+hipError_t launch_degree(const int32_t* eu, const int32_t* ev, const int8_t* sg, uint64_t m,
+                         uint32_t n_u, uint32_t n_v, uint32_t* deg, Control* ctl, hipStream_t st) {
+    hipLaunchKernelGGL(k_degree, grid_n(m, 256), dim3(256), 0, st, eu, ev, sg, m, n_u, n_v, deg, ctl);
+    return hipGetLastError();
+}
+
+size_t radix_tmp_bytes(uint32_t n) {
+    uint32_t nb = (n + kRsTile - 1) / kRsTile;
+    if (nb == 0) nb = 1;
+    size_t h = (size_t)256 * nb;
+    return (2 * h + 1) * sizeof(uint32_t) + scan_tmp_bytes((uint32_t)h) + 1024;
+}
+
+// Sorts (keys, index) by key over the low `bits` bits.  Result values (the
+// element indices in sorted order) end in *vals_result.
+hipError_t radix_sort_by_key(const uint32_t* keys_in, uint32_t n, uint32_t bits, uint32_t* k0,
+                             uint32_t* v0, uint32_t* k1, uint32_t* v1, void* tmp, size_t tmp_bytes,
+                             uint32_t** vals_result, hipStream_t st) {
+    uint32_t nb = (n + kRsTile - 1) / kRsTile;
+    if (nb == 0) nb = 1;
+    uint32_t h = 256 * nb;
+    uint32_t* hist = (uint32_t*)tmp;
+    uint32_t* offs = hist + h;
+    void* stmp = (void*)(offs + h + 1);
+    size_t stmp_bytes = tmp_bytes - (2 * (size_t)h + 1) * sizeof(uint32_t);
+    uint32_t passes = (bits + 7) / 8;
+    if (passes == 0) passes = 1;
+    const uint32_t* kin = keys_in;
+    const uint32_t* vin = nullptr;
+    uint32_t *ko = k0, *vo = v0;
+    for (uint32_t p = 0; p < passes; ++p) {
+        uint32_t shift = 8 * p;
+        hipLaunchKernelGGL(k_rs_hist, dim3(nb), dim3(kRsThreads), 0, st, kin, n, shift, hist);
+        hipError_t e = scan_excl_u32(hist, offs, h, stmp, stmp_bytes, st);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_rs_scatter, dim3(nb), dim3(kRsThreads), 0, st, kin, vin, n, shift,
+                           (const uint32_t*)offs, ko, vo);
+        kin = ko;
+        vin = vo;
+        *vals_result = vo;
+        if (ko == k0) {
+            ko = k1;
+            vo = v1;
+        } else {
+            ko = k0;
+            vo = v0;
+        }
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_sides(const uint32_t* inv, uint32_t n, uint32_t n_u, uint32_t* flag,
+                        hipStream_t st) {
+    hipLaunchKernelGGL(k_side_flags, grid_n(n, 256), dim3(256), 0, st, inv, n, n_u, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_assign(const uint32_t* inv, const uint32_t* cnt_u, const uint32_t* deg,
+                         uint32_t n, uint32_t n_u, uint32_t* sidx_of, uint32_t* rowdeg,
+                         uint32_t* rowcross, hipStream_t st) {
+    hipLaunchKernelGGL(k_assign, grid_n(n, 256), dim3(256), 0, st, inv, cnt_u, deg, n, n_u, sidx_of,
+                       rowdeg, rowcross);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter(const int32_t* eu, const int32_t* ev, const int8_t* sg, uint64_t m,
+                          uint32_t n_u, uint32_t n_v, const uint32_t* sidx_of, uint32_t* cursor,
+                          uint32_t* col, hipStream_t st) {
+    hipLaunchKernelGGL(k_scatter, grid_n(m, 256), dim3(256), 0, st, eu, ev, sg, m, n_u, n_v,
+                       sidx_of, cursor, col);
+    return hipGetLastError();
+}
+
+hipError_t launch_row_sort(const uint32_t* rowdeg, const uint32_t* row_ptr, const uint32_t* in,
+                           uint32_t* out, Dims d, Control* ctl, uint32_t num_cus, hipStream_t st) {
+    hipLaunchKernelGGL(k_classes, dim3(1), dim3(64), 0, st, rowdeg, d, ctl);
+    hipLaunchKernelGGL(k_sort_tiny, grid_n(d.n, 256), dim3(256), 0, st, row_ptr, in, out, d, ctl);
+    hipLaunchKernelGGL(k_sort_group<16>, grid_n((uint64_t)d.n * 16, 256), dim3(256), 0, st,
+                       row_ptr, in, out, d, ctl);
+    hipLaunchKernelGGL(k_sort_group<32>, grid_n((uint64_t)d.n * 32, 256, 8192), dim3(256), 0, st,
+                       row_ptr, in, out, d, ctl);
+    hipLaunchKernelGGL(k_sort_group<64>, grid_n((uint64_t)d.n * 64, 256, 8192), dim3(256), 0, st,
+                       row_ptr, in, out, d, ctl);
+    hipLaunchKernelGGL(k_sort_block, dim3(num_cus * 8), dim3(256), 0, st, row_ptr, in, out, d, ctl);
+    hipLaunchKernelGGL(k_sort_big, dim3(num_cus * 2), dim3(kBigThreads), 0, st, row_ptr, in, out, d,
+                       ctl);
+    return hipGetLastError();
+}
+
+hipError_t launch_lowcount(const uint32_t* row_ptr, const uint32_t* col, const uint32_t* rowcross,
+                           uint32_t n, uint32_t* lowcnt, hipStream_t st) {
+    hipLaunchKernelGGL(k_lowcount, grid_n(n, 256), dim3(256), 0, st, row_ptr, col, rowcross, n,
+                       lowcnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_records(const uint32_t* row_ptr, const uint32_t* col, const uint32_t* lowcnt,
+                          const uint32_t* mptr, Dims d, const Control* ctl, uint4* recs, u64* wu,
+                          uint32_t num_cus, hipStream_t st) {
+    hipLaunchKernelGGL(k_records_small, grid_n(d.n, 256), dim3(256), 0, st, row_ptr, col, lowcnt,
+                       mptr, d, ctl, recs, wu);
+    hipLaunchKernelGGL(k_records_wave, dim3(num_cus * 16), dim3(256), 0, st, row_ptr, col, lowcnt,
+                       mptr, d, ctl, recs, wu);
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_table(const uint32_t* row_ptr, const uint32_t* col, Dims d,
+                             const Control* ctl, uint32_t* tb, uint32_t num_cus, hipStream_t st) {
+    hipLaunchKernelGGL(k_tile_table, dim3(num_cus * 8), dim3(256), 0, st, row_ptr, col, d, ctl, tb);
+    return hipGetLastError();
+}
+
+}  // namespace bbc

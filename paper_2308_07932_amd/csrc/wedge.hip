@@ -1,0 +1,322 @@
+// Wedge enumeration and bucket counting: the counting stage of Algorithm 2
+// (Section 4.1), run as in Algorithm 4 (Section 5.2) with a parallel loop over
+// start vertices and per-start buckets.
+//
+// For a start u and a middle v (p(v) < p(u)), the end vertices w with
+// p(w) < p(u) are the first pos entries of row v.  A wedge u-v-w is symmetric
+// when sign(u,v) == sign(v,w) and asymmetric otherwise (Definitions 5, 6); the
+// start's bucket for w counts both kinds (l, m), packed as l + (m << 32) in one
+// 64-bit word so that each wedge is one LDS atomic.  By Lemmas 1 and 2 the
+// pair (u, w) contributes C(l,2) + C(m,2) balanced butterflies and l*m
+// unbalanced ones, each butterfly being counted once, at its top-priority
+// vertex (Theorem 1).
+//
+// One persistent workgroup per CU takes work items from a global counter.  An
+// item is a list of pieces (see plan.hip); the workgroup keeps the item's
+// buckets in LDS (dense counters addressed by w - lo, or a hash table), then
+// sums C(.,2) over them and adds to the 64-bit totals.  Pieces that split a
+// start along the middle vertices merge their partial counts exactly through a
+// global array G with returning atomics: with old = counts already merged,
+// C(old + c, 2) = C(old, 2) + C(c, 2) + old * c, so adding C(c,2) + old*c is
+// exact in any arrival order.  A hashed piece of a heavy start whose table
+// fills up is abandoned (its counts are never added) and redone as two halves
+// of its tile run; a single tile is redone with dense counters, which always
+// fit, so every piece ends exact.
+#include "bbc_internal.h"
+
+namespace bbc {
+
+struct WedgeArgs {
+    const Piece* pieces;
+    const uint32_t* items_first;
+    uint32_t n_heavy, n_items;
+    const uint4* recs;
+    const uint32_t* col;
+    const uint32_t* tb;
+    Dims d;
+    uint32_t first_long[2];  // sidx of the first row longer than kLongDeg, per side
+    u64* G;
+    Control* ctl;
+};
+
+constexpr uint32_t kShort = 16;       // sub-intervals up to this length are walked by one lane
+constexpr uint32_t kWaves = kWedgeThreads / 64;
+constexpr uint32_t kProbeLimit = 256; // heavy hashed pieces give up after this many probes
+constexpr uint32_t kStack = 16;       // pending halves of an abandoned piece
+
+__device__ inline uint32_t hash32(uint32_t w) { return w * 0x9E3779B1u; }
+
+// Add one wedge to the bucket of end vertex w.  Returns false if the hashed
+// region has no room for w within `lim` probes.
+__device__ inline bool bucket_add(u64* s_tab, uint32_t* keys, u64* hvals, bool dense,
+                                  uint32_t dlo, uint32_t region, uint32_t lim, uint32_t w,
+                                  u64 inc) {
+    if (dense) {
+        atomicAdd(&s_tab[w - dlo], inc);
+        return true;
+    }
+    const uint32_t rb = region & 0xFFFFu, lg = (region >> 16) & 31u;
+    const uint32_t msk = (1u << lg) - 1u;
+    const uint32_t h = hash32(w) >> (32 - lg);
+    for (uint32_t i = 0; i < lim; ++i) {
+        const uint32_t s = rb + ((h + i) & msk);
+        uint32_t k = keys[s];
+        if (k == kEmpty) {
+            k = atomicCAS(&keys[s], kEmpty, w);
+            if (k == kEmpty) k = w;  // inserted here
+        }
+        if (k == w) {
+            atomicAdd(&hvals[s], inc);
+            return true;
+        }
+    }
+    return false;
+}
+
+__global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
+    // on-chip buckets: dense mode uses s_tab[0 .. kDenseW); hash mode uses
+    // keys = (uint32_t*)s_tab [0 .. kHashSlots) and vals = s_tab + kHashSlots/2.
+    __shared__ u64 s_tab[kDenseW];
+    __shared__ Piece s_pc[kMaxItemPieces];
+    __shared__ uint32_t s_pre[kMaxItemPieces + 1];
+    __shared__ Piece s_stack[kStack];
+    __shared__ uint32_t s_sp;
+    __shared__ uint32_t s_item;
+    __shared__ uint32_t s_abort;
+    __shared__ u64 s_red[2][kWaves];
+    uint32_t* keys = (uint32_t*)s_tab;
+    u64* hvals = s_tab + kHashSlots / 2;
+
+    const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
+    const uint32_t* __restrict__ col = a.col;
+
+    for (;;) {
+        __syncthreads();  // every thread is done with the previous item and s_item
+        if (tid == 0) s_item = atomicAdd(&a.ctl->queue, 1u);
+        __syncthreads();
+        const uint32_t item = s_item;
+        if (item >= a.n_items) break;
+        uint32_t p0, p1;
+        if (item < a.n_heavy) {
+            p0 = item;
+            p1 = item + 1;
+        } else {
+            uint32_t li = item - a.n_heavy;
+            p0 = a.n_heavy + a.items_first[li];
+            p1 = a.n_heavy + a.items_first[li + 1];
+        }
+        const uint32_t np = p1 - p0;
+        if (np == 0 || np > kMaxItemPieces) continue;  // never planned; uniform across the block
+        if (tid < np) s_pc[tid] = a.pieces[p0 + tid];
+        if (tid == 0) s_sp = 0;
+        const bool heavy = item < a.n_heavy;
+
+        for (;;) {  // the item's pieces, then any re-split halves (heavy items only)
+            __syncthreads();
+            // prefix of record counts over the pieces (wave 0)
+            if (wave == 0) {
+                uint32_t carry = 0;
+                for (uint32_t c = 0; c < np; c += 64) {
+                    uint32_t i = c + lane;
+                    uint32_t v = i < np ? s_pc[i].nrec : 0u;
+                    uint32_t incl = wave_incl_scan(v);
+                    if (i < np) s_pre[i] = carry + incl - v;
+                    carry += __shfl(incl, 63, 64);
+                }
+                if (lane == 0) s_pre[np] = carry;
+            }
+            if (tid == 0) s_abort = 0;
+            const bool dense = (s_pc[0].flags & kPieceDense) != 0;
+            const uint32_t dlo = s_pc[0].lo;
+            const uint32_t dwidth = s_pc[0].hi - s_pc[0].lo;
+            const uint32_t lim0 = heavy ? kProbeLimit : kHashSlots;
+            if (dense) {
+                for (uint32_t i = tid; i < dwidth; i += kWedgeThreads) s_tab[i] = 0;
+            } else {
+                for (uint32_t i = tid; i < kHashSlots; i += kWedgeThreads) {
+                    keys[i] = kEmpty;
+                    hvals[i] = 0;
+                }
+            }
+            __syncthreads();
+            const uint32_t total = s_pre[np];
+
+            for (uint32_t base = wave * 64; base < total; base += kWedgeThreads) {
+                if (s_abort) break;  // the piece will be redone; stop early
+                const uint32_t f = base + lane;
+                const bool act = f < total;
+                uint32_t p = 0;
+                if (np > 1 && act) {
+                    uint32_t lo = 0, hi = np;  // last piece with s_pre[p] <= f
+                    while (hi - lo > 1) {
+                        uint32_t mid = (lo + hi) >> 1;
+                        if (s_pre[mid] <= f)
+                            lo = mid;
+                        else
+                            hi = mid;
+                    }
+                    p = lo;
+                }
+                uint32_t rs = 0, s1 = 0, ia = 0, ib = 0;
+                if (act) {
+                    const Piece& P = s_pc[p];
+                    const uint4 rc = a.recs[P.rec0 + (f - s_pre[p])];
+                    rs = rc.x;
+                    const uint32_t pos = rc.y >> 1;
+                    s1 = rc.y & 1u;
+                    ia = 0;
+                    ib = pos;
+                    if (P.flags & kPiecePartial) {
+                        const uint32_t ys = (P.flags & kPieceSideV) ? 0u : 1u;  // side of v
+                        const uint32_t vs = rc.z;
+                        if (vs >= a.first_long[ys]) {
+                            const uint32_t* t = a.tb + a.d.tb_off[ys] +
+                                                (uint64_t)(vs - a.first_long[ys]) *
+                                                    (a.d.ntile[ys ^ 1u] + 1);
+                            ia = min(t[P.t0], pos);
+                            ib = min(t[P.t1], pos);
+                        } else {
+                            ia = lower_bound_u32(col + rs, pos, P.lo << 1);
+                            ib = ia + lower_bound_u32(col + rs + ia, pos - ia, P.hi << 1);
+                        }
+                    }
+                }
+                const uint32_t len = ib - ia;
+                bool ok = true;
+
+                // -- one lane per short sub-interval
+                if (len > 0 && len <= kShort) {
+                    const uint32_t region = s_pc[p].region;
+                    const uint32_t lim = min(lim0, 1u << ((region >> 16) & 31u));
+                    for (uint32_t e = ia; e < ib && ok; ++e) {
+                        const uint32_t x = col[rs + e];
+                        ok = bucket_add(s_tab, keys, hvals, dense, dlo, region, lim, x >> 1,
+                                        ((x ^ s1) & 1u) ? (1ull << 32) : 1ull);
+                    }
+                }
+                // -- whole wave per long sub-interval
+                u64 longmask = __ballot(len > kShort);
+                while (longmask) {
+                    const uint32_t L = __ffsll((unsigned long long)longmask) - 1;
+                    longmask &= longmask - 1;
+                    const uint32_t lrs = __shfl(rs, L, 64);
+                    const uint32_t la = __shfl(ia, L, 64);
+                    const uint32_t lb = __shfl(ib, L, 64);
+                    const uint32_t ls1 = __shfl(s1, L, 64);
+                    const uint32_t lp = __shfl(p, L, 64);
+                    const uint32_t region = s_pc[lp].region;
+                    const uint32_t lim = min(lim0, 1u << ((region >> 16) & 31u));
+                    for (uint32_t e = la + lane; e < lb && ok; e += 64) {
+                        const uint32_t x = col[lrs + e];
+                        ok = bucket_add(s_tab, keys, hvals, dense, dlo, region, lim, x >> 1,
+                                        ((x ^ ls1) & 1u) ? (1ull << 32) : 1ull);
+                    }
+                }
+                if (!ok) s_abort = 1;
+            }
+            __syncthreads();
+
+            if (s_abort) {
+                // Abandon this piece's counts; redo it as two halves of its tile
+                // run, or, for a single tile, with dense counters.
+                if (tid == 0) {
+                    atomicAdd(&a.ctl->resplits, 1ull);
+                    Piece P = s_pc[0];
+                    if (!heavy || np != 1 || !(P.flags & kPiecePartial) || s_sp + 1 >= kStack) {
+                        atomicOr(&a.ctl->internal_err, 1u);  // cannot happen by construction
+                        s_sp = kStack + 1;
+                    } else if (P.t1 - P.t0 > 1) {
+                        const uint32_t tm = (P.t0 + P.t1) >> 1;
+                        Piece hi = P;
+                        hi.t0 = tm;
+                        hi.lo = tm * kTile;
+                        s_stack[s_sp++] = hi;
+                        P.t1 = tm;
+                        P.hi = min(P.hi, tm * kTile);
+                        s_pc[0] = P;
+                    } else {
+                        P.flags |= kPieceDense;
+                        s_pc[0] = P;
+                    }
+                }
+                __syncthreads();
+                if (s_sp > kStack) break;
+                continue;
+            }
+
+            // -- finalize: C(l,2) + C(m,2) and l*m over the buckets
+            u64 bal = 0, unb = 0;
+            if (dense) {
+                const bool merge = (s_pc[0].flags & kPieceMerge) != 0;
+                const uint32_t gb = s_pc[0].gbase;
+                for (uint32_t i = tid; i < dwidth; i += kWedgeThreads) {
+                    const u64 v = s_tab[i];
+                    if (v == 0) continue;
+                    const u64 l = v & 0xFFFFFFFFull, m = v >> 32;
+                    bal += choose2(l) + choose2(m);
+                    unb += l * m;
+                    if (merge) {
+                        const u64 old = atomicAdd(&a.G[(uint64_t)gb + dlo + i], v);
+                        const u64 ol = old & 0xFFFFFFFFull, om = old >> 32;
+                        bal += ol * l + om * m;
+                        unb += ol * m + om * l;
+                    }
+                }
+            } else {
+                for (uint32_t i = tid; i < kHashSlots; i += kWedgeThreads) {
+                    if (keys[i] == kEmpty) continue;
+                    const u64 v = hvals[i];
+                    const u64 l = v & 0xFFFFFFFFull, m = v >> 32;
+                    bal += choose2(l) + choose2(m);
+                    unb += l * m;
+                }
+            }
+            bal = wave_reduce_sum(bal);
+            unb = wave_reduce_sum(unb);
+            if (lane == 0) {
+                s_red[0][wave] = bal;
+                s_red[1][wave] = unb;
+            }
+            __syncthreads();
+            if (tid == 0) {
+                u64 b = 0, u = 0;
+                for (uint32_t w = 0; w < kWaves; ++w) {
+                    b += s_red[0][w];
+                    u += s_red[1][w];
+                }
+                if (b) atomicAdd(&a.ctl->balanced, b);
+                if (u) atomicAdd(&a.ctl->unbalanced, u);
+                if (s_sp > 0) s_pc[0] = s_stack[--s_sp];
+                else s_sp = kStack + 2;  // done with this item
+            }
+            __syncthreads();
+            if (s_sp > kStack) break;
+        }
+    }
+}
+
+hipError_t launch_wedge(const Piece* pieces, const uint32_t* items_first, uint32_t n_heavy,
+                        uint32_t n_items, const uint4* recs, const uint32_t* col, const uint32_t* tb,
+                        Dims d, const uint32_t first_long[2], u64* G, Control* ctl,
+                        uint32_t num_cus, hipStream_t st) {
+    WedgeArgs a;
+    a.pieces = pieces;
+    a.items_first = items_first;
+    a.n_heavy = n_heavy;
+    a.n_items = n_items;
+    a.recs = recs;
+    a.col = col;
+    a.tb = tb;
+    a.d = d;
+    a.first_long[0] = first_long[0];
+    a.first_long[1] = first_long[1];
+    a.G = G;
+    a.ctl = ctl;
+    uint32_t grid = num_cus;
+    if (grid > n_items) grid = n_items;
+    if (grid == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_wedge, dim3(grid), dim3(kWedgeThreads), 0, st, a);
+    return hipGetLastError();
+}
+
+}  // namespace bbc

@@ -1,0 +1,68 @@
+"""Host-side checks of the C ABI library (no GPU work is launched here)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import paper_2308_07932_amd as bbc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(bbc.LIB_PATH):
+        from paper_2308_07932_amd import _build
+        _build.build()
+    return bbc.load_library()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = bbc.declared_symbols()
+    assert {"bbc_create", "bbc_destroy", "bbc_count", "bbc_status_string",
+            "bbc_last_error"} <= set(names)
+    out = subprocess.run(["nm", "-D", "--defined-only", bbc.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\sT\s(bbc_\w+)", out))
+    for n in names:
+        assert n in exported, n
+        assert hasattr(lib, n)
+
+
+def test_status_strings_and_version(lib):
+    for code in range(0, -11, -1):
+        s = bbc.status_string(code)
+        assert s and s != "unknown status"
+    assert bbc.status_string(5) == "unknown status"
+    assert bbc.version() >= 10000
+
+
+def test_create_argument_checks(lib):
+    # NULL out pointer is rejected before any device query
+    assert lib.bbc_create(0, None, None) == bbc.INVALID_ARG
+    lib.bbc_destroy(None)  # NULL-safe
+
+
+def test_no_device_reports_device_error(lib):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("GPU present")
+    h = ctypes.c_void_p()
+    assert lib.bbc_create(0, None, ctypes.byref(h)) == bbc.DEVICE
+
+
+def test_binding_rejects_mismatched_lengths():
+    with pytest.raises(ValueError):
+        bbc._prepare(np.zeros(3, np.int32), np.zeros(2, np.int32), np.ones(3, np.int8))
+
+
+def test_product_never_touches_the_oracle():
+    pkg = os.path.join(ROOT, "paper_2308_07932_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert not re.search(r"\bimport oracle\b|from oracle\b|liboracle|bbo_", text), f
