@@ -26,8 +26,8 @@ hipError_t launch_row_sort(const uint32_t*, const uint32_t*, const uint32_t*, ui
                            Control*, uint32_t, hipStream_t);
 hipError_t launch_lowcount(const uint32_t*, const uint32_t*, const uint32_t*, uint32_t, uint32_t*,
                            hipStream_t);
-hipError_t launch_records(const uint32_t*, const uint32_t*, const uint32_t*, const uint32_t*, Dims,
-                          const Control*, uint4*, u64*, uint32_t, hipStream_t);
+hipError_t launch_records(const uint32_t*, const uint32_t*, const uint32_t*, Dims, uint64_t,
+                          uint32_t*, uint4*, u64*, hipStream_t);
 hipError_t launch_tile_table(const uint32_t*, const uint32_t*, Dims, const Control*, uint32_t*,
                              uint32_t, hipStream_t);
 hipError_t launch_plan_count(const u64*, const uint32_t*, const uint32_t*, Dims, uint32_t*, u64*,
@@ -37,9 +37,10 @@ hipError_t launch_gather_totals(const uint32_t*, const u64*, const uint32_t*, co
 hipError_t launch_plan_write(const u64*, const uint32_t*, const uint32_t*, const uint32_t*,
                              const uint32_t*,
                              const uint32_t*, const u64*, const u64*, const uint32_t*,
-                             const uint32_t*, Dims, uint32_t, Piece*, u64*, uint32_t, uint32_t,
-                             uint32_t*, hipStream_t);
-hipError_t launch_wedge(const Piece*, const uint32_t*, uint32_t, uint32_t, const uint4*,
+                             const uint32_t*, Dims, uint32_t, Piece*, u64*, uint32_t*, uint32_t,
+                             uint32_t, uint32_t*, hipStream_t);
+hipError_t launch_wedge(const Piece*, const uint32_t*, const uint32_t*, uint32_t, uint32_t,
+                        const uint4*,
                         const uint32_t*, const uint32_t*, Dims, const uint32_t[2], u64*, Control*,
                         uint32_t, hipStream_t);
 }  // namespace bbc
@@ -415,8 +416,9 @@ bbc_status bbc_count(bbc_context* c, int32_t n_u, int32_t n_v, int64_t n_edges,
     // ---- 5. middle counts, 6. records and W_u, 7. tile tables
     HIPCHECK(c, launch_lowcount(b.row_ptr, b.col, b.rowcross, n, b.lowcnt, st));
     HIPCHECK(c, scan_excl_u32(b.lowcnt, b.mptr, n, b.stmp, b.stmp_bytes, st));
-    HIPCHECK(c, launch_records(b.row_ptr, b.col, b.lowcnt, b.mptr, d, b.ctl, b.recs, b.wu,
-                               c->num_cus, st));
+    HIPCHECK(c, copy_u32(b.mptr, b.cursor, n, st));  // cursor now: next free record slot
+    HIPCHECK(c, fill_u64(b.wu, 0, n, st));
+    HIPCHECK(c, launch_records(b.row_ptr, b.col, b.lowcnt, d, 2 * m, b.cursor, b.recs, b.wu, st));
     HIPCHECK(c, launch_tile_table(b.row_ptr, b.col, d, b.ctl, b.tb, c->num_cus, st));
     if (tm) HIPCHECK(c, hipEventRecord(c->ev[kEvPrepEnd], st));
 
@@ -455,12 +457,21 @@ bbc_status bbc_count(bbc_context* c, int32_t n_u, int32_t n_v, int64_t n_edges,
     u64* light_off;
     uint32_t* items_first;
     u64* G;
+    uint32_t *hkey, *ok0, *ov0, *ok1, *ov1;
+    void* ortmp;
+    const size_t ortmp_bytes = radix_tmp_bytes(n_heavy + 1);
     {
         auto carve_plan = [&](Carver& cv) {
             pieces = cv.take<Piece>((size_t)n_heavy + n_light);
             light_off = cv.take<u64>((size_t)n_light + 1);
             items_first = cv.take<uint32_t>((size_t)n_light_items + 2);
             G = cv.take<u64>((size_t)h.tot_g + 1);
+            hkey = cv.take<uint32_t>((size_t)n_heavy + 1);
+            ok0 = cv.take<uint32_t>((size_t)n_heavy + 1);
+            ov0 = cv.take<uint32_t>((size_t)n_heavy + 1);
+            ok1 = cv.take<uint32_t>((size_t)n_heavy + 1);
+            ov1 = cv.take<uint32_t>((size_t)n_heavy + 1);
+            ortmp = cv.take<char>(ortmp_bytes);
             return cv.off;
         };
         Carver probe(nullptr);
@@ -473,13 +484,17 @@ bbc_status bbc_count(bbc_context* c, int32_t n_u, int32_t n_v, int64_t n_edges,
     if (tm) HIPCHECK(c, hipEventRecord(c->ev[kEvPlanB], st));
     HIPCHECK(c, fill_u64(G, 0, (size_t)h.tot_g, st));
     HIPCHECK(c, launch_plan_write(b.wu, b.lowcnt, b.row_ptr, b.mptr, b.hp, b.hp_off, b.lr, b.lr_off, b.lf_off,
-                                  b.gs_off, d, n_heavy, pieces, light_off, n_light, n_light_items,
-                                  items_first, st));
+                                  b.gs_off, d, n_heavy, pieces, light_off, hkey, n_light,
+                                  n_light_items, items_first, st));
+    uint32_t* order = nullptr;
+    if (n_heavy > 0)  // heavy pieces, most expensive first
+        HIPCHECK(c, radix_sort_by_key(hkey, n_heavy, 16, ok0, ov0, ok1, ov1, ortmp, ortmp_bytes,
+                                      &order, st));
     if (tm) HIPCHECK(c, hipEventRecord(c->ev[kEvPlanC], st));
 
     // ---- wedge enumeration and bucket counting
     if (tm) HIPCHECK(c, hipEventRecord(c->ev[kEvWedgeA], st));
-    HIPCHECK(c, launch_wedge(pieces, items_first, n_heavy, n_items, b.recs, b.col, b.tb, d,
+    HIPCHECK(c, launch_wedge(pieces, order, items_first, n_heavy, n_items, b.recs, b.col, b.tb, d,
                              first_long, G, b.ctl, c->num_cus, st));
     if (tm) HIPCHECK(c, hipEventRecord(c->ev[kEvWedgeB], st));
     if (tm) HIPCHECK(c, hipEventRecord(c->ev[kEvEnd], st));

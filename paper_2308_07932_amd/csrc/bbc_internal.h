@@ -133,6 +133,27 @@ __device__ inline T wave_incl_scan(T v) {
 
 __device__ inline u64 choose2(u64 k) { return k < 2 ? 0 : k * (k - 1) / 2; }
 
+// Workgroup-local aggregation of global atomics on hot keys (hub vertices):
+// the slot of `key` in an open-addressing LDS table of SLOTS keys, or -1 when
+// no slot is found within a few probes (the caller then goes to global memory
+// directly).  Keys are never removed, so a key that found no slot never finds
+// one later in the same round.
+template <uint32_t LOG2_SLOTS>
+__device__ inline int agg_slot(uint32_t* keys, uint32_t key) {
+    constexpr uint32_t kMask = (1u << LOG2_SLOTS) - 1u;
+    const uint32_t h = (key * 0x9E3779B1u) >> (32 - LOG2_SLOTS);
+    for (uint32_t i = 0; i < 8; ++i) {
+        const uint32_t s = (h + i) & kMask;
+        uint32_t k = keys[s];
+        if (k == kEmpty) {
+            k = atomicCAS(&keys[s], kEmpty, key);
+            if (k == kEmpty) return (int)s;
+        }
+        if (k == key) return (int)s;
+    }
+    return -1;
+}
+
 }  // namespace bbc
 
 // ---- host-side launchers (defined in the .hip files) ------------------------

@@ -35,8 +35,18 @@ __device__ inline uint32_t next_pow2(uint32_t x) {
 
 __device__ inline uint32_t log2_pow2(uint32_t x) { return 31u - __clz(x); }
 
+// Sort key putting the most expensive pieces first (ascending key): a 16-bit
+// log-scale of the estimated cost, 4 units per record visited plus the
+// expected wedges.
+__device__ inline uint32_t cost_key(double wedges, uint32_t nrec) {
+    const double c = wedges + 4.0 * nrec;
+    const double q = log2(1.0 + c) * 2048.0;
+    return 65535u - (uint32_t)fmin(q, 65535.0);
+}
+
 // Tile runs of a start with end-vertex space [0, S) on the side whose rows start
-// at `base`; calls emit(t0, t1, dense) per run and returns the number of runs.
+// at `base`; calls emit(t0, t1, dense, expected wedges) per run and returns the
+// number of runs.
 template <typename F>
 __device__ uint32_t plan_runs(const uint32_t* __restrict__ row_ptr, uint32_t base, uint32_t S,
                               u64 W, F emit) {
@@ -50,14 +60,14 @@ __device__ uint32_t plan_runs(const uint32_t* __restrict__ row_ptr, uint32_t bas
         const double e = (double)(row_ptr[base + hi] - row_ptr[base + lo]) * scale;
         if (e > kHashTarget) {
             if (rs != kNoTile) {
-                emit(rs, t, false);
+                emit(rs, t, false, re);
                 ++n;
                 rs = kNoTile;
             }
-            emit(t, t + 1, true);
+            emit(t, t + 1, true, e);
             ++n;
         } else if (rs != kNoTile && re + e > kHashTarget) {
-            emit(rs, t, false);
+            emit(rs, t, false, re);
             ++n;
             rs = t;
             re = e;
@@ -70,7 +80,7 @@ __device__ uint32_t plan_runs(const uint32_t* __restrict__ row_ptr, uint32_t bas
         }
     }
     if (rs != kNoTile) {
-        emit(rs, T, false);
+        emit(rs, T, false, re);
         ++n;
     }
     return n;
@@ -95,7 +105,7 @@ __global__ void k_plan_count(const u64* __restrict__ wu, const uint32_t* __restr
             h = (uint32_t)np;
             g = np > 1 ? S : 0;
         } else {
-            h = plan_runs(row_ptr, d.base[side], S, W, [](uint32_t, uint32_t, bool) {});
+            h = plan_runs(row_ptr, d.base[side], S, W, [](uint32_t, uint32_t, bool, double) {});
         }
         hp[r] = h;
         lr[r] = l;
@@ -110,7 +120,8 @@ __global__ void k_plan_write(const u64* __restrict__ wu, const uint32_t* __restr
                              const uint32_t* __restrict__ hp_off, const u64* __restrict__ lr,
                              const u64* __restrict__ lr_off, const uint32_t* __restrict__ lf_off,
                              const uint32_t* __restrict__ gs_off, Dims d, uint32_t n_heavy,
-                             Piece* __restrict__ pieces, u64* __restrict__ light_off) {
+                             Piece* __restrict__ pieces, u64* __restrict__ light_off,
+                             uint32_t* __restrict__ hkey) {
     for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < d.n; r += gridDim.x * blockDim.x) {
         u64 W = wu[r];
         if (W == 0) continue;
@@ -121,6 +132,7 @@ __global__ void k_plan_write(const u64* __restrict__ wu, const uint32_t* __restr
         uint32_t h = hp[r];
         if (h > 0) {
             Piece* out = pieces + hp_off[r];
+            uint32_t* key = hkey + hp_off[r];
             if (S <= kDenseW) {
                 for (uint32_t i = 0; i < h; ++i) {
                     uint32_t c0 = (uint32_t)((u64)k * i / h), c1 = (uint32_t)((u64)k * (i + 1) / h);
@@ -136,11 +148,13 @@ __global__ void k_plan_write(const u64* __restrict__ wu, const uint32_t* __restr
                     p.gbase = gs_off[r];
                     p.start_row = r;
                     out[i] = p;
+                    key[i] = cost_key((double)W * (c1 - c0) / k, c1 - c0);
                 }
             } else {
                 const uint32_t T = (S + kTile - 1) / kTile;
                 uint32_t i = 0;
-                plan_runs(row_ptr, d.base[side], S, W, [&](uint32_t t0, uint32_t t1, bool dense) {
+                plan_runs(row_ptr, d.base[side], S, W,
+                          [&](uint32_t t0, uint32_t t1, bool dense, double est) {
                     Piece p;
                     p.rec0 = m0;
                     p.nrec = k;
@@ -153,7 +167,10 @@ __global__ void k_plan_write(const u64* __restrict__ wu, const uint32_t* __restr
                               (dense ? kPieceDense : 0u) | sideflag;
                     p.gbase = kEmpty;
                     p.start_row = r;
-                    if (i < h) out[i] = p;
+                    if (i < h) {
+                        out[i] = p;
+                        key[i] = cost_key(est, k);
+                    }
                     ++i;
                 });
             }
@@ -199,8 +216,9 @@ __global__ void k_items_first(const u64* __restrict__ light_off, uint32_t n_ligh
 }
 
 // W = sum of W_u, and the number of starts with W_u > 0
-__global__ void k_sum_u64(const u64* __restrict__ a, uint32_t n, u64* __restrict__ out,
-                          u64* __restrict__ nonzero) {
+__global__ __launch_bounds__(256) void k_sum_u64(const u64* __restrict__ a, uint32_t n,
+                                                 u64* __restrict__ out, u64* __restrict__ nonzero) {
+    __shared__ u64 s_s[4], s_c[4];
     u64 s = 0, c = 0;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         s += a[i];
@@ -208,8 +226,17 @@ __global__ void k_sum_u64(const u64* __restrict__ a, uint32_t n, u64* __restrict
     }
     s = wave_reduce_sum(s);
     c = wave_reduce_sum(c);
-    if (lane_id() == 0 && s) atomicAdd(out, s);
-    if (lane_id() == 0 && c) atomicAdd(nonzero, c);
+    if (lane_id() == 0) {
+        s_s[threadIdx.x >> 6] = s;
+        s_c[threadIdx.x >> 6] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        s = s_s[0] + s_s[1] + s_s[2] + s_s[3];
+        c = s_c[0] + s_c[1] + s_c[2] + s_c[3];
+        if (s) atomicAdd(out, s);
+        if (c) atomicAdd(nonzero, c);
+    }
 }
 
 __global__ void k_gather_totals(const uint32_t* __restrict__ hp_off, const u64* __restrict__ lr_off,
@@ -243,7 +270,7 @@ hipError_t launch_plan_count(const u64* wu, const uint32_t* lowcnt, const uint32
                              hipStream_t st) {
     hipLaunchKernelGGL(k_plan_count, grid_n(d.n, 256), dim3(256), 0, st, wu, lowcnt, row_ptr, d, hp,
                        lr, lf, gs);
-    hipLaunchKernelGGL(k_sum_u64, grid_n(d.n, 256, 2048), dim3(256), 0, st, wu, d.n, wsum, nonzero);
+    hipLaunchKernelGGL(k_sum_u64, grid_n(d.n, 256, 512), dim3(256), 0, st, wu, d.n, wsum, nonzero);
     return hipGetLastError();
 }
 
@@ -252,10 +279,10 @@ hipError_t launch_plan_write(const u64* wu, const uint32_t* lowcnt, const uint32
                              const uint32_t* hp, const uint32_t* hp_off, const u64* lr,
                              const u64* lr_off, const uint32_t* lf_off, const uint32_t* gs_off,
                              Dims d, uint32_t n_heavy, Piece* pieces, u64* light_off,
-                             uint32_t n_light, uint32_t n_light_items, uint32_t* items_first,
-                             hipStream_t st) {
+                             uint32_t* hkey, uint32_t n_light, uint32_t n_light_items,
+                             uint32_t* items_first, hipStream_t st) {
     hipLaunchKernelGGL(k_plan_write, grid_n(d.n, 256), dim3(256), 0, st, wu, lowcnt, row_ptr, mptr, hp,
-                       hp_off, lr, lr_off, lf_off, gs_off, d, n_heavy, pieces, light_off);
+                       hp_off, lr, lr_off, lf_off, gs_off, d, n_heavy, pieces, light_off, hkey);
     hipLaunchKernelGGL(k_items_first, grid_n((uint64_t)n_light_items + 1, 256), dim3(256), 0, st,
                        (const u64*)light_off, n_light, n_light_items, items_first);
     return hipGetLastError();

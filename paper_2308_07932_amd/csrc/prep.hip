@@ -17,23 +17,56 @@
 namespace bbc {
 
 // ---------------------------------------------------------------- degrees ----
-__global__ void k_degree(const int32_t* __restrict__ eu, const int32_t* __restrict__ ev,
-                         const int8_t* __restrict__ sg, uint64_t m, uint32_t n_u, uint32_t n_v,
-                         uint32_t* __restrict__ deg, Control* ctl) {
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
-         i += (uint64_t)gridDim.x * blockDim.x) {
-        int32_t u = eu[i], v = ev[i];
-        int8_t s = sg[i];
-        if (u < 0 || (uint32_t)u >= n_u || v < 0 || (uint32_t)v >= n_v) {
-            atomicMin(&ctl->edge_err, (i << 4) | kErrRange);
-            continue;
+// Each workgroup takes chunks of kAggChunk edges and counts endpoint degrees in
+// an LDS table first, so a hub endpoint costs one global atomic per chunk
+// instead of one per edge.
+constexpr int kAggThreads = 256;
+constexpr int kAggPer = 8;  // edges per thread per chunk
+constexpr uint32_t kAggChunk = kAggThreads * kAggPer;
+constexpr uint32_t kAggLog2 = 12;
+constexpr uint32_t kAggSlots = 1u << kAggLog2;
+
+__device__ inline bool edge_ok(int32_t u, int32_t v, int8_t s, uint32_t n_u, uint32_t n_v) {
+    return u >= 0 && (uint32_t)u < n_u && v >= 0 && (uint32_t)v < n_v && (s == 1 || s == -1);
+}
+
+__global__ __launch_bounds__(kAggThreads) void k_degree(const int32_t* __restrict__ eu,
+                                                        const int32_t* __restrict__ ev,
+                                                        const int8_t* __restrict__ sg, uint64_t m,
+                                                        uint32_t n_u, uint32_t n_v,
+                                                        uint32_t* __restrict__ deg, Control* ctl) {
+    __shared__ uint32_t keys[kAggSlots];
+    __shared__ uint32_t cnt[kAggSlots];
+    const uint32_t tid = threadIdx.x;
+    for (uint64_t c0 = (uint64_t)blockIdx.x * kAggChunk; c0 < m; c0 += (uint64_t)gridDim.x * kAggChunk) {
+        for (uint32_t i = tid; i < kAggSlots; i += kAggThreads) {
+            keys[i] = kEmpty;
+            cnt[i] = 0;
         }
-        if (s != 1 && s != -1) {
-            atomicMin(&ctl->edge_err, (i << 4) | kErrSign);
-            continue;
+        __syncthreads();
+        for (int k = 0; k < kAggPer; ++k) {
+            const uint64_t e = c0 + (uint64_t)k * kAggThreads + tid;
+            if (e >= m) break;
+            const int32_t u = eu[e], v = ev[e];
+            const int8_t s = sg[e];
+            if (!edge_ok(u, v, s, n_u, n_v)) {
+                const bool range = u < 0 || (uint32_t)u >= n_u || v < 0 || (uint32_t)v >= n_v;
+                atomicMin(&ctl->edge_err, (e << 4) | (range ? kErrRange : kErrSign));
+                continue;
+            }
+            const uint32_t x[2] = {(uint32_t)u, n_u + (uint32_t)v};
+            for (int t = 0; t < 2; ++t) {
+                const int sl = agg_slot<kAggLog2>(keys, x[t]);
+                if (sl >= 0)
+                    atomicAdd(&cnt[sl], 1u);
+                else
+                    atomicAdd(&deg[x[t]], 1u);
+            }
         }
-        atomicAdd(&deg[u], 1u);
-        atomicAdd(&deg[n_u + (uint32_t)v], 1u);
+        __syncthreads();
+        for (uint32_t i = tid; i < kAggSlots; i += kAggThreads)
+            if (keys[i] != kEmpty) atomicAdd(&deg[keys[i]], cnt[i]);
+        __syncthreads();
     }
 }
 
@@ -138,22 +171,59 @@ __global__ void k_assign(const uint32_t* __restrict__ inv, const uint32_t* __res
     }
 }
 
-__global__ void k_scatter(const int32_t* __restrict__ eu, const int32_t* __restrict__ ev,
-                          const int8_t* __restrict__ sg, uint64_t m, uint32_t n_u, uint32_t n_v,
-                          const uint32_t* __restrict__ sidx_of, uint32_t* __restrict__ cursor,
-                          uint32_t* __restrict__ col) {
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
-         i += (uint64_t)gridDim.x * blockDim.x) {
-        int32_t u = eu[i], v = ev[i];
-        int8_t s = sg[i];
-        if (u < 0 || (uint32_t)u >= n_u || v < 0 || (uint32_t)v >= n_v || (s != 1 && s != -1))
-            continue;
-        uint32_t su = sidx_of[u], sv = sidx_of[n_u + (uint32_t)v];
-        uint32_t neg = s < 0 ? 1u : 0u;
-        uint32_t pu = atomicAdd(&cursor[su], 1u);
-        col[pu] = (sv << 1) | neg;
-        uint32_t pv = atomicAdd(&cursor[n_u + sv], 1u);
-        col[pv] = (su << 1) | neg;
+// Each edge lands in row u (entry sidx(v)) and row v (entry sidx(u)).  Slots
+// inside a row are reserved with one global atomic per (workgroup chunk, row)
+// through an LDS table; the order inside a row is fixed later by the sort.
+__global__ __launch_bounds__(kAggThreads) void k_scatter(
+    const int32_t* __restrict__ eu, const int32_t* __restrict__ ev, const int8_t* __restrict__ sg,
+    uint64_t m, uint32_t n_u, uint32_t n_v, const uint32_t* __restrict__ sidx_of,
+    uint32_t* __restrict__ cursor, uint32_t* __restrict__ col) {
+    __shared__ uint32_t keys[kAggSlots];
+    __shared__ uint32_t cnt[kAggSlots];
+    __shared__ uint32_t base[kAggSlots];
+    const uint32_t tid = threadIdx.x;
+    for (uint64_t c0 = (uint64_t)blockIdx.x * kAggChunk; c0 < m; c0 += (uint64_t)gridDim.x * kAggChunk) {
+        for (uint32_t i = tid; i < kAggSlots; i += kAggThreads) {
+            keys[i] = kEmpty;
+            cnt[i] = 0;
+        }
+        __syncthreads();
+        uint32_t slot[kAggPer][2], rank[kAggPer][2], val[kAggPer][2];
+        for (int k = 0; k < kAggPer; ++k) {
+            slot[k][0] = slot[k][1] = kEmpty - 1;  // marks an edge to skip
+            const uint64_t e = c0 + (uint64_t)k * kAggThreads + tid;
+            if (e >= m) continue;
+            const int32_t u = eu[e], v = ev[e];
+            const int8_t s = sg[e];
+            if (!edge_ok(u, v, s, n_u, n_v)) continue;
+            const uint32_t su = sidx_of[u], sv = sidx_of[n_u + (uint32_t)v];
+            const uint32_t neg = s < 0 ? 1u : 0u;
+            const uint32_t row[2] = {su, n_u + sv};
+            val[k][0] = (sv << 1) | neg;
+            val[k][1] = (su << 1) | neg;
+            for (int t = 0; t < 2; ++t) {
+                const int sl = agg_slot<kAggLog2>(keys, row[t]);
+                if (sl >= 0) {
+                    slot[k][t] = (uint32_t)sl;
+                    rank[k][t] = atomicAdd(&cnt[sl], 1u);
+                } else {
+                    slot[k][t] = kEmpty;  // position reserved directly
+                    rank[k][t] = atomicAdd(&cursor[row[t]], 1u);
+                }
+            }
+        }
+        __syncthreads();
+        for (uint32_t i = tid; i < kAggSlots; i += kAggThreads)
+            if (keys[i] != kEmpty) base[i] = atomicAdd(&cursor[keys[i]], cnt[i]);
+        __syncthreads();
+        for (int k = 0; k < kAggPer; ++k)
+            for (int t = 0; t < 2; ++t) {
+                const uint32_t sl = slot[k][t];
+                if (sl == kEmpty - 1) continue;
+                const uint32_t p = sl == kEmpty ? rank[k][t] : base[sl] + rank[k][t];
+                col[p] = val[k][t];
+            }
+        __syncthreads();
     }
 }
 
@@ -414,77 +484,85 @@ __global__ void k_lowcount(const uint32_t* __restrict__ row_ptr, const uint32_t*
 }
 
 // ------------------------------------------------------------- records ------
-// Record of middle entry j of row r (start x, side X; middle v, side Y):
-//   .x = first entry of row v, .y = pos << 1 | neg(x, v), .z = sidx(v)
-// with pos = |{w in Gamma(v): sidx(w) < sidx(x)}| (row v holds X-side sidx).
-__device__ inline uint32_t make_record(const uint32_t* __restrict__ row_ptr,
-                                       const uint32_t* __restrict__ col, const Dims& d,
-                                       uint32_t side, uint32_t my_sidx, uint32_t e,
-                                       uint4* rec) {
-    uint32_t vs = e >> 1;
-    uint32_t oth = side ^ 1u;
-    if (vs >= d.size[oth]) {  // only possible when a repeated edge left a hole
-        *rec = make_uint4(0, 0, 0, 0);
-        return 0;
-    }
-    uint32_t vrow = d.base[oth] + vs;
-    uint32_t va = row_ptr[vrow], vl = row_ptr[vrow + 1] - va;
-    uint32_t pos = lower_bound_u32(col + va, vl, my_sidx << 1);
-    *rec = make_uint4(va, (pos << 1) | (e & 1u), vs, 0u);
-    return pos;
-}
+// Records come from the upper part of every row: in the sorted row of v, the
+// entry at index i >= k_v names a neighbour u of higher priority, and exactly
+// i entries precede it, all of lower priority than u -- so pos_v(u) = i with
+// no search.  The record (row v, i, sign, sidx(v)) is appended to u's record
+// list (slots reserved through an LDS table as in the scatter), and i is added
+// to W_u.  The order of a start's records is irrelevant to the count.
+//   .x = first entry of row v, .y = pos << 1 | neg(u, v), .z = sidx(v)
+constexpr int kRecPer = 8;  // consecutive CSR entries per thread
+constexpr uint32_t kRecChunk = kAggThreads * kRecPer;
 
-// rows with len <= 64: one thread per row
-__global__ void k_records_small(const uint32_t* __restrict__ row_ptr,
-                                const uint32_t* __restrict__ col,
-                                const uint32_t* __restrict__ lowcnt,
-                                const uint32_t* __restrict__ mptr, Dims d, const Control* ctl,
-                                uint4* __restrict__ recs, u64* __restrict__ wu) {
-    uint32_t lo0 = d.base[0], hi0 = ctl->cls[0][4];
-    uint32_t lo1 = d.base[1], hi1 = ctl->cls[1][4];
-    uint32_t n0 = hi0 - lo0, tot = n0 + (hi1 - lo1);
-    for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < tot; q += gridDim.x * blockDim.x) {
-        uint32_t side = q < n0 ? 0u : 1u;
-        uint32_t r = side == 0 ? lo0 + q : lo1 + (q - n0);
-        uint32_t my = r - d.base[side];
-        uint32_t a = row_ptr[r], k = lowcnt[r], mp = mptr[r];
-        u64 w = 0;
-        for (uint32_t j = 0; j < k; ++j) {
-            uint4 rc;
-            w += make_record(row_ptr, col, d, side, my, col[a + j], &rc);
-            recs[mp + j] = rc;
+__global__ __launch_bounds__(kAggThreads) void k_records(
+    const uint32_t* __restrict__ row_ptr, const uint32_t* __restrict__ col,
+    const uint32_t* __restrict__ lowcnt, Dims d, uint32_t* __restrict__ rcur,
+    uint4* __restrict__ recs, u64* __restrict__ wu) {
+    __shared__ uint32_t keys[kAggSlots];
+    __shared__ uint32_t cnt[kAggSlots];
+    __shared__ uint32_t base[kAggSlots];
+    __shared__ u64 wsum[kAggSlots];
+    const uint32_t tid = threadIdx.x;
+    const uint64_t nnz = row_ptr[d.n];  // entries actually placed (invalid edges are not)
+    for (uint64_t c0 = (uint64_t)blockIdx.x * kRecChunk; c0 < nnz; c0 += (uint64_t)gridDim.x * kRecChunk) {
+        for (uint32_t i = tid; i < kAggSlots; i += kAggThreads) {
+            keys[i] = kEmpty;
+            cnt[i] = 0;
+            wsum[i] = 0;
         }
-        wu[r] = w;
-    }
-}
-
-// rows with len > 64: one wave per row
-__global__ __launch_bounds__(256) void k_records_wave(const uint32_t* __restrict__ row_ptr,
-                                                      const uint32_t* __restrict__ col,
-                                                      const uint32_t* __restrict__ lowcnt,
-                                                      const uint32_t* __restrict__ mptr, Dims d,
-                                                      const Control* ctl,
-                                                      uint4* __restrict__ recs,
-                                                      u64* __restrict__ wu) {
-    uint32_t lo0 = ctl->cls[0][4], hi0 = d.base[0] + d.size[0];
-    uint32_t lo1 = ctl->cls[1][4], hi1 = d.base[1] + d.size[1];
-    uint32_t n0 = hi0 - lo0, tot = n0 + (hi1 - lo1);
-    const uint32_t lane = lane_id();
-    const uint32_t wid = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const uint32_t wstride = (gridDim.x * blockDim.x) >> 6;
-    for (uint32_t q = wid; q < tot; q += wstride) {
-        uint32_t side = q < n0 ? 0u : 1u;
-        uint32_t r = side == 0 ? lo0 + q : lo1 + (q - n0);
-        uint32_t my = r - d.base[side];
-        uint32_t a = row_ptr[r], k = lowcnt[r], mp = mptr[r];
-        u64 w = 0;
-        for (uint32_t j = lane; j < k; j += 64) {
-            uint4 rc;
-            w += make_record(row_ptr, col, d, side, my, col[a + j], &rc);
-            recs[mp + j] = rc;
+        __syncthreads();
+        const uint64_t e0 = c0 + (uint64_t)tid * kRecPer;
+        uint32_t slot[kRecPer], rank[kRecPer];
+        uint4 rec[kRecPer];
+        uint32_t r = 0;
+        if (e0 < nnz) {  // row holding entry e0: last r with row_ptr[r] <= e0
+            uint32_t lo = 0, hi = d.n;
+            while (hi - lo > 1) {
+                uint32_t mid = (lo + hi) >> 1;
+                if (row_ptr[mid] <= e0)
+                    lo = mid;
+                else
+                    hi = mid;
+            }
+            r = lo;
         }
-        w = wave_reduce_sum(w);
-        if (lane == 0) wu[r] = w;
+        for (int k = 0; k < kRecPer; ++k) {
+            slot[k] = kEmpty - 1;
+            const uint64_t e = e0 + k;
+            if (e >= nnz) continue;
+            while (row_ptr[r + 1] <= e) ++r;
+            const uint32_t rs = row_ptr[r];
+            const uint32_t i = (uint32_t)(e - rs);
+            if (i < lowcnt[r]) continue;  // lower entry: v's own middle, not a record here
+            const uint32_t side = r >= d.n_u ? 1u : 0u;
+            const uint32_t x = col[e];
+            if ((x >> 1) >= d.size[side ^ 1u]) continue;  // hole left by a repeated edge
+            const uint32_t urow = d.base[side ^ 1u] + (x >> 1);
+            rec[k] = make_uint4(rs, (i << 1) | (x & 1u), r - d.base[side], 0u);
+            const int sl = agg_slot<kAggLog2>(keys, urow);
+            if (sl >= 0) {
+                slot[k] = (uint32_t)sl;
+                rank[k] = atomicAdd(&cnt[sl], 1u);
+                atomicAdd(&wsum[sl], (u64)i);
+            } else {
+                slot[k] = kEmpty;
+                rank[k] = atomicAdd(&rcur[urow], 1u);
+                atomicAdd(&wu[urow], (u64)i);
+            }
+        }
+        __syncthreads();
+        for (uint32_t i = tid; i < kAggSlots; i += kAggThreads)
+            if (keys[i] != kEmpty) {
+                base[i] = atomicAdd(&rcur[keys[i]], cnt[i]);
+                atomicAdd(&wu[keys[i]], wsum[i]);
+            }
+        __syncthreads();
+        for (int k = 0; k < kRecPer; ++k) {
+            const uint32_t sl = slot[k];
+            if (sl == kEmpty - 1) continue;
+            recs[sl == kEmpty ? rank[k] : base[sl] + rank[k]] = rec[k];
+        }
+        __syncthreads();
     }
 }
 
@@ -524,7 +602,8 @@ static dim3 grid_n(uint64_t n, uint32_t threads, uint32_t cap = 16384) {
 
 hipError_t launch_degree(const int32_t* eu, const int32_t* ev, const int8_t* sg, uint64_t m,
                          uint32_t n_u, uint32_t n_v, uint32_t* deg, Control* ctl, hipStream_t st) {
-    hipLaunchKernelGGL(k_degree, grid_n(m, 256), dim3(256), 0, st, eu, ev, sg, m, n_u, n_v, deg, ctl);
+    hipLaunchKernelGGL(k_degree, grid_n(m, kAggChunk, 2048), dim3(kAggThreads), 0, st, eu, ev, sg, m,
+                       n_u, n_v, deg, ctl);
     return hipGetLastError();
 }
 
@@ -590,8 +669,8 @@ hipError_t launch_assign(const uint32_t* inv, const uint32_t* cnt_u, const uint3
 hipError_t launch_scatter(const int32_t* eu, const int32_t* ev, const int8_t* sg, uint64_t m,
                           uint32_t n_u, uint32_t n_v, const uint32_t* sidx_of, uint32_t* cursor,
                           uint32_t* col, hipStream_t st) {
-    hipLaunchKernelGGL(k_scatter, grid_n(m, 256), dim3(256), 0, st, eu, ev, sg, m, n_u, n_v,
-                       sidx_of, cursor, col);
+    hipLaunchKernelGGL(k_scatter, grid_n(m, kAggChunk, 2048), dim3(kAggThreads), 0, st, eu, ev, sg,
+                       m, n_u, n_v, sidx_of, cursor, col);
     return hipGetLastError();
 }
 
@@ -619,12 +698,10 @@ hipError_t launch_lowcount(const uint32_t* row_ptr, const uint32_t* col, const u
 }
 
 hipError_t launch_records(const uint32_t* row_ptr, const uint32_t* col, const uint32_t* lowcnt,
-                          const uint32_t* mptr, Dims d, const Control* ctl, uint4* recs, u64* wu,
-                          uint32_t num_cus, hipStream_t st) {
-    hipLaunchKernelGGL(k_records_small, grid_n(d.n, 256), dim3(256), 0, st, row_ptr, col, lowcnt,
-                       mptr, d, ctl, recs, wu);
-    hipLaunchKernelGGL(k_records_wave, dim3(num_cus * 16), dim3(256), 0, st, row_ptr, col, lowcnt,
-                       mptr, d, ctl, recs, wu);
+                          Dims d, uint64_t nnz_bound, uint32_t* rcur, uint4* recs, u64* wu,
+                          hipStream_t st) {
+    hipLaunchKernelGGL(k_records, grid_n(nnz_bound, kRecChunk, 2048), dim3(kAggThreads), 0, st,
+                       row_ptr, col, lowcnt, d, rcur, recs, wu);
     return hipGetLastError();
 }
 

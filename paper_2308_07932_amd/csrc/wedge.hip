@@ -28,6 +28,7 @@ namespace bbc {
 
 struct WedgeArgs {
     const Piece* pieces;
+    const uint32_t* order;  // heavy item i runs piece order[i] (largest first)
     const uint32_t* items_first;
     uint32_t n_heavy, n_items;
     const uint4* recs;
@@ -98,8 +99,8 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
         if (item >= a.n_items) break;
         uint32_t p0, p1;
         if (item < a.n_heavy) {
-            p0 = item;
-            p1 = item + 1;
+            p0 = a.order[item];
+            p1 = p0 + 1;
         } else {
             uint32_t li = item - a.n_heavy;
             p0 = a.n_heavy + a.items_first[li];
@@ -295,12 +296,14 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
     }
 }
 
-hipError_t launch_wedge(const Piece* pieces, const uint32_t* items_first, uint32_t n_heavy,
+hipError_t launch_wedge(const Piece* pieces, const uint32_t* order, const uint32_t* items_first,
+                        uint32_t n_heavy,
                         uint32_t n_items, const uint4* recs, const uint32_t* col, const uint32_t* tb,
                         Dims d, const uint32_t first_long[2], u64* G, Control* ctl,
                         uint32_t num_cus, hipStream_t st) {
     WedgeArgs a;
     a.pieces = pieces;
+    a.order = order;
     a.items_first = items_first;
     a.n_heavy = n_heavy;
     a.n_items = n_items;
