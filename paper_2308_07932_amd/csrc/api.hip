@@ -7,7 +7,7 @@
 
 #include <algorithm>
 
-#include "../../include/bbc.h"
+#include "bbc.h"
 #include "bbc_internal.h"
 
 namespace bbc {
@@ -26,23 +26,25 @@ hipError_t launch_row_sort(const uint32_t*, const uint32_t*, const uint32_t*, ui
                            Control*, uint32_t, hipStream_t);
 hipError_t launch_lowcount(const uint32_t*, const uint32_t*, const uint32_t*, uint32_t, uint32_t*,
                            hipStream_t);
-hipError_t launch_records(const uint32_t*, const uint32_t*, const uint32_t*, Dims, uint64_t,
-                          uint32_t*, uint4*, u64*, hipStream_t);
+hipError_t launch_records(const uint32_t*, const uint32_t*, const uint32_t*, Dims, const Control*,
+                          uint64_t, uint32_t*, uint32_t*, uint4*, u64*, u64*, hipStream_t);
 hipError_t launch_tile_table(const uint32_t*, const uint32_t*, Dims, const Control*, uint32_t*,
                              uint32_t, hipStream_t);
-hipError_t launch_plan_count(const u64*, const uint32_t*, const uint32_t*, Dims, uint32_t*, u64*,
-                             uint32_t*, uint32_t*, u64*, u64*, hipStream_t);
+hipError_t launch_plan_count(const u64*, const u64*, const uint32_t*, const uint32_t*, Dims,
+                             uint32_t*, u64*, uint32_t*, uint32_t*, uint32_t*, u64*, u64*, u64*,
+                             hipStream_t);
 hipError_t launch_gather_totals(const uint32_t*, const u64*, const uint32_t*, const uint32_t*,
-                                uint32_t, Control*, hipStream_t);
+                                const uint32_t*, const u64*, uint32_t, Control*, hipStream_t);
 hipError_t launch_plan_write(const u64*, const uint32_t*, const uint32_t*, const uint32_t*,
-                             const uint32_t*,
-                             const uint32_t*, const u64*, const u64*, const uint32_t*,
-                             const uint32_t*, Dims, uint32_t, Piece*, u64*, uint32_t*, uint32_t,
-                             uint32_t, uint32_t*, hipStream_t);
+                             const uint32_t*, const uint32_t*, const u64*, const uint32_t*,
+                             const uint32_t*, const uint32_t*, Dims, uint32_t, Piece*, u64*,
+                             uint32_t*, uint32_t*, uint32_t, uint32_t, uint32_t*, hipStream_t);
+hipError_t launch_short_wedges(const uint4*, uint32_t, const uint32_t*, const uint32_t*,
+                               const uint32_t*, const uint32_t*, const uint32_t*, const uint32_t*,
+                               const uint32_t*, uint32_t*, uint32_t*, uint32_t*, bool, hipStream_t);
 hipError_t launch_wedge(const Piece*, const uint32_t*, const uint32_t*, uint32_t, uint32_t,
-                        const uint4*,
-                        const uint32_t*, const uint32_t*, Dims, const uint32_t[2], u64*, Control*,
-                        uint32_t, hipStream_t);
+                        const uint4*, const uint32_t*, const uint32_t*, Dims, const uint32_t[2], u64*,
+                        const uint32_t*, const uint32_t*, Control*, uint32_t, hipStream_t);
 }  // namespace bbc
 
 using namespace bbc;
@@ -143,8 +145,9 @@ struct PrepBufs {
     int32_t* ev;
     int8_t* sg;
     uint32_t *deg, *k0, *v0, *k1, *v1, *flag, *cnt_u, *sidx_of, *rowdeg, *rowcross, *row_ptr,
-        *cursor, *col_in, *col, *lowcnt, *mptr, *tb, *hp, *hp_off, *lf, *lf_off, *gs, *gs_off;
-    u64 *lr, *lr_off, *wu;
+        *cursor, *col_in, *col, *lowcnt, *mptr, *tb, *hp, *hp_off, *lf, *lf_off, *gs, *gs_off,
+        *back, *tc, *tc_off;
+    u64 *lr, *lr_off, *wu, *wsu, *swc, *swc_off;
     uint4* recs;
     void* rtmp;
     void* stmp;
@@ -187,6 +190,12 @@ static size_t carve_prep(Carver& cv, PrepBufs& b, uint32_t n, uint64_t m, bool c
     b.lf_off = cv.take<uint32_t>(n + 1);
     b.gs = cv.take<uint32_t>(n);
     b.gs_off = cv.take<uint32_t>(n + 1);
+    b.back = cv.take<uint32_t>(n);
+    b.tc = cv.take<uint32_t>(n);
+    b.tc_off = cv.take<uint32_t>(n + 1);
+    b.wsu = cv.take<u64>(n);
+    b.swc = cv.take<u64>(n);
+    b.swc_off = cv.take<u64>(n + 1);
     b.rtmp_bytes = radix_tmp_bytes(n);
     b.rtmp = cv.take<char>(b.rtmp_bytes);
     b.stmp_bytes = scan_tmp_bytes(n + 1);
@@ -416,20 +425,28 @@ bbc_status bbc_count(bbc_context* c, int32_t n_u, int32_t n_v, int64_t n_edges,
     // ---- 5. middle counts, 6. records and W_u, 7. tile tables
     HIPCHECK(c, launch_lowcount(b.row_ptr, b.col, b.rowcross, n, b.lowcnt, st));
     HIPCHECK(c, scan_excl_u32(b.lowcnt, b.mptr, n, b.stmp, b.stmp_bytes, st));
-    HIPCHECK(c, copy_u32(b.mptr, b.cursor, n, st));  // cursor now: next free record slot
+    // record slots of start u: long-middle records fill [mptr[u], ...) from the
+    // front (cursor), short-middle ones fill [..., mptr[u+1]) from the back
+    HIPCHECK(c, copy_u32(b.mptr, b.cursor, n, st));
+    HIPCHECK(c, copy_u32(b.mptr + 1, b.back, n, st));
     HIPCHECK(c, fill_u64(b.wu, 0, n, st));
-    HIPCHECK(c, launch_records(b.row_ptr, b.col, b.lowcnt, d, 2 * m, b.cursor, b.recs, b.wu, st));
+    HIPCHECK(c, fill_u64(b.wsu, 0, n, st));
+    HIPCHECK(c, launch_records(b.row_ptr, b.col, b.lowcnt, d, b.ctl, 2 * m, b.cursor, b.back, b.recs,
+                               b.wu, b.wsu, st));
     HIPCHECK(c, launch_tile_table(b.row_ptr, b.col, d, b.ctl, b.tb, c->num_cus, st));
     if (tm) HIPCHECK(c, hipEventRecord(c->ev[kEvPrepEnd], st));
 
     // ---- planning: piece counts, offsets, totals
-    HIPCHECK(c, launch_plan_count(b.wu, b.lowcnt, b.row_ptr, d, b.hp, b.lr, b.lf, b.gs, &b.ctl->wedges,
-                                  &b.ctl->active_starts, st));
+    HIPCHECK(c, launch_plan_count(b.wu, b.wsu, b.lowcnt, b.row_ptr, d, b.hp, b.lr, b.lf, b.gs, b.tc,
+                                  b.swc, &b.ctl->wedges, &b.ctl->active_starts, st));
     HIPCHECK(c, scan_excl_u32(b.hp, b.hp_off, n, b.stmp, b.stmp_bytes, st));
     HIPCHECK(c, scan_excl_u64(b.lr, b.lr_off, n, b.stmp, b.stmp_bytes, st));
     HIPCHECK(c, scan_excl_u32(b.lf, b.lf_off, n, b.stmp, b.stmp_bytes, st));
     HIPCHECK(c, scan_excl_u32(b.gs, b.gs_off, n, b.stmp, b.stmp_bytes, st));
-    HIPCHECK(c, launch_gather_totals(b.hp_off, b.lr_off, b.lf_off, b.gs_off, n, b.ctl, st));
+    HIPCHECK(c, scan_excl_u32(b.tc, b.tc_off, n, b.stmp, b.stmp_bytes, st));
+    HIPCHECK(c, scan_excl_u64(b.swc, b.swc_off, n, b.stmp, b.stmp_bytes, st));
+    HIPCHECK(c, launch_gather_totals(b.hp_off, b.lr_off, b.lf_off, b.gs_off, b.tc_off, b.swc_off, n,
+                                     b.ctl, st));
     if (tm) HIPCHECK(c, hipEventRecord(c->ev[kEvPlanA], st));
     HIPCHECK(c, hipMemcpyAsync(c->host_ctl, b.ctl, sizeof(Control), hipMemcpyDeviceToHost, st));
     HIPCHECK(c, hipStreamSynchronize(st));
@@ -448,6 +465,9 @@ bbc_status bbc_count(bbc_context* c, int32_t n_u, int32_t n_v, int64_t n_edges,
     if (h.tot_heavy + h.tot_light >= (1ull << 31))
         return fail(c, BBC_ERR_INTERNAL, "too many work pieces (%llu)",
                     (unsigned long long)(h.tot_heavy + h.tot_light));
+    if (h.tot_sw >= (1ull << 32) || h.tot_tiles >= (1ull << 32))
+        return fail(c, BBC_ERR_INTERNAL, "too many bucketed short-middle wedges (%llu)",
+                    (unsigned long long)h.tot_sw);
     const uint32_t n_heavy = (uint32_t)h.tot_heavy, n_light = (uint32_t)h.tot_light;
     const uint64_t n_light_items64 = (h.tot_light_region + kLightWindow - 1) / kLightWindow;
     const uint32_t n_light_items = (uint32_t)n_light_items64;
@@ -457,7 +477,7 @@ bbc_status bbc_count(bbc_context* c, int32_t n_u, int32_t n_v, int64_t n_edges,
     u64* light_off;
     uint32_t* items_first;
     u64* G;
-    uint32_t *hkey, *ok0, *ov0, *ok1, *ov1;
+    uint32_t *hkey, *ok0, *ov0, *ok1, *ov1, *tile_piece, *sw_cnt, *sw_off, *sw_cur, *sw_list;
     void* ortmp;
     const size_t ortmp_bytes = radix_tmp_bytes(n_heavy + 1);
     {
@@ -472,6 +492,11 @@ bbc_status bbc_count(bbc_context* c, int32_t n_u, int32_t n_v, int64_t n_edges,
             ok1 = cv.take<uint32_t>((size_t)n_heavy + 1);
             ov1 = cv.take<uint32_t>((size_t)n_heavy + 1);
             ortmp = cv.take<char>(ortmp_bytes);
+            tile_piece = cv.take<uint32_t>((size_t)h.tot_tiles + 1);
+            sw_cnt = cv.take<uint32_t>((size_t)n_heavy + 1);
+            sw_off = cv.take<uint32_t>((size_t)n_heavy + 1);
+            sw_cur = cv.take<uint32_t>((size_t)n_heavy + 1);
+            sw_list = cv.take<uint32_t>((size_t)h.tot_sw + 1);
             return cv.off;
         };
         Carver probe(nullptr);
@@ -483,9 +508,21 @@ bbc_status bbc_count(bbc_context* c, int32_t n_u, int32_t n_v, int64_t n_edges,
     }
     if (tm) HIPCHECK(c, hipEventRecord(c->ev[kEvPlanB], st));
     HIPCHECK(c, fill_u64(G, 0, (size_t)h.tot_g, st));
-    HIPCHECK(c, launch_plan_write(b.wu, b.lowcnt, b.row_ptr, b.mptr, b.hp, b.hp_off, b.lr, b.lr_off, b.lf_off,
-                                  b.gs_off, d, n_heavy, pieces, light_off, hkey, n_light,
-                                  n_light_items, items_first, st));
+    HIPCHECK(c, launch_plan_write(b.wu, b.lowcnt, b.row_ptr, b.mptr, b.cursor, b.hp_off, b.lr_off,
+                                  b.lf_off, b.gs_off, b.tc_off, d, n_heavy, pieces, light_off, hkey,
+                                  tile_piece, n_light, n_light_items, items_first, st));
+    // bucket the short-middle wedges of split starts by piece
+    HIPCHECK(c, fill_u32(sw_cnt, 0, (size_t)n_heavy + 1, st));
+    if (h.tot_sw > 0) {
+        HIPCHECK(c, launch_short_wedges(b.recs, (uint32_t)m, b.col, b.mptr, b.cursor, b.tc, b.tc_off,
+                                        b.hp_off, tile_piece, sw_cnt, sw_cur, sw_list, false, st));
+    }
+    HIPCHECK(c, scan_excl_u32(sw_cnt, sw_off, n_heavy, ortmp, ortmp_bytes, st));
+    if (h.tot_sw > 0) {
+        HIPCHECK(c, copy_u32(sw_off, sw_cur, n_heavy, st));
+        HIPCHECK(c, launch_short_wedges(b.recs, (uint32_t)m, b.col, b.mptr, b.cursor, b.tc, b.tc_off,
+                                        b.hp_off, tile_piece, sw_cnt, sw_cur, sw_list, true, st));
+    }
     uint32_t* order = nullptr;
     if (n_heavy > 0)  // heavy pieces, most expensive first
         HIPCHECK(c, radix_sort_by_key(hkey, n_heavy, 16, ok0, ov0, ok1, ov1, ortmp, ortmp_bytes,
@@ -495,7 +532,7 @@ bbc_status bbc_count(bbc_context* c, int32_t n_u, int32_t n_v, int64_t n_edges,
     // ---- wedge enumeration and bucket counting
     if (tm) HIPCHECK(c, hipEventRecord(c->ev[kEvWedgeA], st));
     HIPCHECK(c, launch_wedge(pieces, order, items_first, n_heavy, n_items, b.recs, b.col, b.tb, d,
-                             first_long, G, b.ctl, c->num_cus, st));
+                             first_long, G, sw_off, sw_list, b.ctl, c->num_cus, st));
     if (tm) HIPCHECK(c, hipEventRecord(c->ev[kEvWedgeB], st));
     if (tm) HIPCHECK(c, hipEventRecord(c->ev[kEvEnd], st));
     HIPCHECK(c, hipMemcpyAsync(c->host_ctl, b.ctl, sizeof(Control), hipMemcpyDeviceToHost, st));

@@ -16,7 +16,8 @@
 //   * a "record" is an edge oriented from its higher-priority end u (the wedge
 //     start) to its lower one v (the middle): it stores where row v starts and
 //     pos = |{w in Gamma(v) : p(w) < p(u)}|, so the wedges (u, v, .) are the
-//     first pos entries of row v.
+//     first pos entries of row v.  A start's records with a long middle row
+//     (more than kLongDeg entries) come first, those with a short one last.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -67,6 +68,7 @@ struct Piece {
     uint32_t flags;
     uint32_t gbase;       // merge array offset (kPieceMerge)
     uint32_t start_row;   // row of the start vertex
+    uint32_t list;        // kPiecePartial: heavy piece owning the bucketed short wedges
 };
 
 // Error word bits (device -> host); edge errors keep the first offending edge.
@@ -89,6 +91,8 @@ struct Control {
     uint32_t pad;
     u64 tot_heavy, tot_light_region, tot_light, tot_g;  // planner totals
     u64 active_starts;   // vertices with W_u > 0
+    u64 tot_tiles;       // tile-to-piece map entries of split starts
+    u64 tot_sw;          // bucketed short-middle wedges of split starts
 };
 
 struct Dims {

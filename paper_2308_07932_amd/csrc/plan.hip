@@ -23,6 +23,12 @@
 //             into hashed pieces of at most kHashTarget expected wedges.  A
 //             hashed piece that overflows anyway is redone by the wedge kernel
 //             in halves.
+//
+// A start cut into tile pieces ("split start") visits its records once per
+// piece.  Records through a long middle row find their sub-interval of a tile
+// in O(1) from the row's tile table; the wedges through short middle rows are
+// instead bucketed once, per piece, into a packed list (w << 1 | asymmetric)
+// that the piece reads contiguously.
 #include "bbc_internal.h"
 
 namespace bbc {
@@ -86,99 +92,81 @@ __device__ uint32_t plan_runs(const uint32_t* __restrict__ row_ptr, uint32_t bas
     return n;
 }
 
-__global__ void k_plan_count(const u64* __restrict__ wu, const uint32_t* __restrict__ lowcnt,
-                             const uint32_t* __restrict__ row_ptr, Dims d, uint32_t* __restrict__ hp, u64* __restrict__ lr,
-                             uint32_t* __restrict__ lf, uint32_t* __restrict__ gs) {
+enum : uint32_t { kClassNone = 0, kClassLight, kClassSmallSide, kClassTiles };
+
+struct StartPlan {
+    uint32_t cls, pieces, region, tiles;  // tiles > 0: a split start with T tiles
+};
+
+__device__ inline StartPlan plan_start(const uint32_t* __restrict__ row_ptr, const Dims& d,
+                                       uint32_t r, u64 W, uint32_t k) {
+    StartPlan sp = {kClassNone, 0, 0, 0};
+    const uint32_t side = r >= d.n_u ? 1u : 0u;
+    const uint32_t S = r - d.base[side];
+    if (W == 0) return sp;
+    if (W <= kLightMax) {
+        sp.cls = kClassLight;
+        sp.region = max(kMinRegion, next_pow2((uint32_t)(2 * W)));
+        return sp;
+    }
+    if (S <= kDenseW) {
+        u64 np = (W + kRecordChunkWedges - 1) / kRecordChunkWedges;
+        if (np > k) np = k;
+        sp.cls = kClassSmallSide;
+        sp.pieces = (uint32_t)np;
+        return sp;
+    }
+    const uint32_t T = (S + kTile - 1) / kTile;
+    bool whole = false;
+    sp.cls = kClassTiles;
+    sp.pieces = plan_runs(row_ptr, d.base[side], S, W,
+                          [&](uint32_t t0, uint32_t t1, bool dense, double) {
+                              whole = whole || (t0 == 0 && t1 == T && !dense);
+                          });
+    sp.tiles = whole ? 0u : T;  // one hashed run over everything: not split
+    return sp;
+}
+
+__global__ void k_plan_count(const u64* __restrict__ wu, const u64* __restrict__ wsu,
+                             const uint32_t* __restrict__ lowcnt,
+                             const uint32_t* __restrict__ row_ptr, Dims d,
+                             uint32_t* __restrict__ hp, u64* __restrict__ lr,
+                             uint32_t* __restrict__ lf, uint32_t* __restrict__ gs,
+                             uint32_t* __restrict__ tc, u64* __restrict__ swc) {
     for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < d.n; r += gridDim.x * blockDim.x) {
-        uint32_t side = r >= d.n_u ? 1u : 0u;
-        uint32_t S = r - d.base[side];
-        u64 W = wu[r];
-        uint32_t k = lowcnt[r];
-        uint32_t h = 0, l = 0, f = 0, g = 0;
-        if (W == 0) {
-        } else if (W <= kLightMax) {
-            l = max(kMinRegion, next_pow2((uint32_t)(2 * W)));
-            f = 1;
-        } else if (S <= kDenseW) {
-            u64 np = (W + kRecordChunkWedges - 1) / kRecordChunkWedges;
-            if (np > k) np = k;
-            h = (uint32_t)np;
-            g = np > 1 ? S : 0;
-        } else {
-            h = plan_runs(row_ptr, d.base[side], S, W, [](uint32_t, uint32_t, bool, double) {});
-        }
-        hp[r] = h;
-        lr[r] = l;
-        lf[r] = f;
-        gs[r] = g;
+        const u64 W = wu[r];
+        const StartPlan sp = plan_start(row_ptr, d, r, W, lowcnt[r]);
+        const uint32_t side = r >= d.n_u ? 1u : 0u;
+        hp[r] = sp.pieces;
+        lr[r] = sp.cls == kClassLight ? sp.region : 0u;
+        lf[r] = sp.cls == kClassLight ? 1u : 0u;
+        gs[r] = (sp.cls == kClassSmallSide && sp.pieces > 1) ? r - d.base[side] : 0u;
+        tc[r] = sp.tiles;
+        swc[r] = sp.tiles ? wsu[r] : 0ull;
     }
 }
 
 __global__ void k_plan_write(const u64* __restrict__ wu, const uint32_t* __restrict__ lowcnt,
                              const uint32_t* __restrict__ row_ptr,
-                             const uint32_t* __restrict__ mptr, const uint32_t* __restrict__ hp,
-                             const uint32_t* __restrict__ hp_off, const u64* __restrict__ lr,
-                             const u64* __restrict__ lr_off, const uint32_t* __restrict__ lf_off,
-                             const uint32_t* __restrict__ gs_off, Dims d, uint32_t n_heavy,
+                             const uint32_t* __restrict__ mptr, const uint32_t* __restrict__ front,
+                             const uint32_t* __restrict__ hp_off, const u64* __restrict__ lr_off,
+                             const uint32_t* __restrict__ lf_off,
+                             const uint32_t* __restrict__ gs_off,
+                             const uint32_t* __restrict__ tc_off, Dims d, uint32_t n_heavy,
                              Piece* __restrict__ pieces, u64* __restrict__ light_off,
-                             uint32_t* __restrict__ hkey) {
+                             uint32_t* __restrict__ hkey, uint32_t* __restrict__ tile_piece) {
     for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < d.n; r += gridDim.x * blockDim.x) {
-        u64 W = wu[r];
+        const u64 W = wu[r];
         if (W == 0) continue;
-        uint32_t side = r >= d.n_u ? 1u : 0u;
-        uint32_t S = r - d.base[side];
-        uint32_t k = lowcnt[r], m0 = mptr[r];
-        uint32_t sideflag = side ? kPieceSideV : 0u;
-        uint32_t h = hp[r];
-        if (h > 0) {
-            Piece* out = pieces + hp_off[r];
-            uint32_t* key = hkey + hp_off[r];
-            if (S <= kDenseW) {
-                for (uint32_t i = 0; i < h; ++i) {
-                    uint32_t c0 = (uint32_t)((u64)k * i / h), c1 = (uint32_t)((u64)k * (i + 1) / h);
-                    Piece p;
-                    p.rec0 = m0 + c0;
-                    p.nrec = c1 - c0;
-                    p.lo = 0;
-                    p.hi = S;
-                    p.t0 = kNoTile;
-                    p.t1 = kNoTile;
-                    p.region = 0;
-                    p.flags = kPieceDense | (h > 1 ? kPieceMerge : 0u) | sideflag;
-                    p.gbase = gs_off[r];
-                    p.start_row = r;
-                    out[i] = p;
-                    key[i] = cost_key((double)W * (c1 - c0) / k, c1 - c0);
-                }
-            } else {
-                const uint32_t T = (S + kTile - 1) / kTile;
-                uint32_t i = 0;
-                plan_runs(row_ptr, d.base[side], S, W,
-                          [&](uint32_t t0, uint32_t t1, bool dense, double est) {
-                    Piece p;
-                    p.rec0 = m0;
-                    p.nrec = k;
-                    p.lo = t0 * kTile;
-                    p.hi = min(S, t1 * kTile);
-                    p.t0 = t0;
-                    p.t1 = t1;
-                    p.region = log2_pow2(kHashSlots) << 16;
-                    p.flags = ((t0 == 0 && t1 == T) ? 0u : kPiecePartial) |
-                              (dense ? kPieceDense : 0u) | sideflag;
-                    p.gbase = kEmpty;
-                    p.start_row = r;
-                    if (i < h) {
-                        out[i] = p;
-                        key[i] = cost_key(est, k);
-                    }
-                    ++i;
-                });
-            }
-                } else if (lr[r] > 0) {
-            uint32_t idx = lf_off[r];
-            u64 off = lr_off[r];
-            u64 item = off / kLightWindow;
-            uint32_t base = (uint32_t)(off - item * kLightWindow);
+        const uint32_t k = lowcnt[r], m0 = mptr[r];
+        const StartPlan sp = plan_start(row_ptr, d, r, W, k);
+        const uint32_t side = r >= d.n_u ? 1u : 0u;
+        const uint32_t S = r - d.base[side];
+        const uint32_t sideflag = side ? kPieceSideV : 0u;
+        if (sp.cls == kClassLight) {
+            const uint32_t idx = lf_off[r];
+            const u64 off = lr_off[r];
+            const u64 item = off / kLightWindow;
             Piece p;
             p.rec0 = m0;
             p.nrec = k;
@@ -186,32 +174,140 @@ __global__ void k_plan_write(const u64* __restrict__ wu, const uint32_t* __restr
             p.hi = S;
             p.t0 = kNoTile;
             p.t1 = kNoTile;
-            p.region = base | (log2_pow2((uint32_t)lr[r]) << 16);
+            p.region = (uint32_t)(off - item * kLightWindow) | (log2_pow2(sp.region) << 16);
             p.flags = sideflag;
             p.gbase = kEmpty;
             p.start_row = r;
+            p.list = kEmpty;
             pieces[n_heavy + idx] = p;
             light_off[idx] = off;
+            continue;
         }
+        const uint32_t h = sp.pieces;
+        const uint32_t b = hp_off[r];
+        if (sp.cls == kClassSmallSide) {
+            for (uint32_t i = 0; i < h; ++i) {
+                const uint32_t c0 = (uint32_t)((u64)k * i / h), c1 = (uint32_t)((u64)k * (i + 1) / h);
+                Piece p;
+                p.rec0 = m0 + c0;
+                p.nrec = c1 - c0;
+                p.lo = 0;
+                p.hi = S;
+                p.t0 = kNoTile;
+                p.t1 = kNoTile;
+                p.region = 0;
+                p.flags = kPieceDense | (h > 1 ? kPieceMerge : 0u) | sideflag;
+                p.gbase = gs_off[r];
+                p.start_row = r;
+                p.list = kEmpty;
+                pieces[b + i] = p;
+                hkey[b + i] = cost_key((double)W * (c1 - c0) / k, c1 - c0);
+            }
+            continue;
+        }
+        // tile runs; a split start keeps only its long-middle records, the
+        // short-middle wedges come from the bucketed list of each piece
+        const uint32_t T = (S + kTile - 1) / kTile;
+        const bool split = sp.tiles > 0;
+        const uint32_t nlong = front[r] - m0;
+        uint32_t i = 0;
+        plan_runs(row_ptr, d.base[side], S, W, [&](uint32_t t0, uint32_t t1, bool dense, double est) {
+            if (i >= h) return;
+            Piece p;
+            p.rec0 = m0;
+            p.nrec = split ? nlong : k;
+            p.lo = t0 * kTile;
+            p.hi = min(S, t1 * kTile);
+            p.t0 = t0;
+            p.t1 = t1;
+            p.region = log2_pow2(kHashSlots) << 16;
+            p.flags = (split ? kPiecePartial : 0u) | (dense ? kPieceDense : 0u) | sideflag;
+            p.gbase = kEmpty;
+            p.start_row = r;
+            p.list = split ? b + i : kEmpty;
+            pieces[b + i] = p;
+            hkey[b + i] = cost_key(est, p.nrec);
+            if (split)
+                for (uint32_t t = t0; t < t1; ++t) tile_piece[tc_off[r] + t] = i;
+            ++i;
+        });
     }
 }
 
-// first light piece of each light item: item i holds the pieces whose region
-// offset lies in [i H, (i+1) H)
-__global__ void k_items_first(const u64* __restrict__ light_off, uint32_t n_light,
-                              uint32_t n_items, uint32_t* __restrict__ first) {
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i <= n_items;
-         i += gridDim.x * blockDim.x) {
-        u64 key = (u64)i * kLightWindow;
-        uint32_t lo = 0, hi = n_light;
-        while (lo < hi) {
-            uint32_t mid = (lo + hi) >> 1;
-            if (light_off[mid] < key)
-                lo = mid + 1;
-            else
-                hi = mid;
+// -- bucketing of the short-middle wedges of split starts, two passes over
+// their short records: count per piece, then place.  Counts and reservations
+// go through an LDS table keyed by piece, one global atomic per (chunk, piece).
+constexpr int kSwThreads = 256;
+constexpr uint32_t kSwLog2 = 11;
+constexpr uint32_t kSwSlots = 1u << kSwLog2;
+
+template <bool kFill>
+__global__ __launch_bounds__(kSwThreads) void k_short_wedges(
+    const uint4* __restrict__ recs, uint32_t m, const uint32_t* __restrict__ col,
+    const uint32_t* __restrict__ mptr, const uint32_t* __restrict__ front,
+    const uint32_t* __restrict__ tc, const uint32_t* __restrict__ tc_off,
+    const uint32_t* __restrict__ hp_off, const uint32_t* __restrict__ tile_piece,
+    uint32_t* __restrict__ counts, uint32_t* __restrict__ cursor, uint32_t* __restrict__ list) {
+    __shared__ uint32_t keys[kSwSlots];
+    __shared__ uint32_t cnt[kSwSlots];
+    __shared__ uint32_t base[kSwSlots];
+    const uint32_t tid = threadIdx.x;
+    for (uint32_t c0 = blockIdx.x * kSwThreads; c0 < m; c0 += gridDim.x * kSwThreads) {
+        for (uint32_t i = tid; i < kSwSlots; i += kSwThreads) {
+            keys[i] = kEmpty;
+            cnt[i] = 0;
         }
-        first[i] = lo;
+        __syncthreads();
+        const uint32_t j = c0 + tid;
+        uint4 rc = make_uint4(0, 0, 0, 0);
+        bool mine = false;
+        if (j < m) {
+            rc = recs[j];
+            const uint32_t u = rc.w;
+            mine = tc[u] > 0 && j >= front[u];  // short record of a split start
+        }
+        const uint32_t pos = mine ? rc.y >> 1 : 0u;
+        const uint32_t s1 = rc.y & 1u;
+        uint32_t tb0 = 0, pb = 0;
+        if (mine) {
+            tb0 = tc_off[rc.w];
+            pb = hp_off[rc.w];
+        }
+        // pass over the prefix: per entry, the piece of its tile
+        for (uint32_t e = 0; e < pos; ++e) {
+            const uint32_t x = col[rc.x + e];
+            const uint32_t gp = pb + tile_piece[tb0 + (x >> 1) / kTile];
+            const int sl = agg_slot<kSwLog2>(keys, gp);
+            if (!kFill) {
+                if (sl >= 0)
+                    atomicAdd(&cnt[sl], 1u);
+                else
+                    atomicAdd(&counts[gp], 1u);
+            } else if (sl >= 0) {
+                atomicAdd(&cnt[sl], 1u);
+            }
+        }
+        __syncthreads();
+        for (uint32_t i = tid; i < kSwSlots; i += kSwThreads)
+            if (keys[i] != kEmpty) {
+                if (!kFill)
+                    atomicAdd(&counts[keys[i]], cnt[i]);
+                else
+                    base[i] = atomicAdd(&cursor[keys[i]], cnt[i]);
+                cnt[i] = 0;
+            }
+        __syncthreads();
+        if (kFill) {
+            for (uint32_t e = 0; e < pos; ++e) {
+                const uint32_t x = col[rc.x + e];
+                const uint32_t gp = pb + tile_piece[tb0 + (x >> 1) / kTile];
+                const int sl = agg_slot<kSwLog2>(keys, gp);  // finds the slot taken above
+                const uint32_t at = sl >= 0 ? base[sl] + atomicAdd(&cnt[sl], 1u)
+                                            : atomicAdd(&cursor[gp], 1u);
+                list[at] = (x & ~1u) | ((x ^ s1) & 1u);
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -241,20 +337,36 @@ __global__ __launch_bounds__(256) void k_sum_u64(const u64* __restrict__ a, uint
 
 __global__ void k_gather_totals(const uint32_t* __restrict__ hp_off, const u64* __restrict__ lr_off,
                                 const uint32_t* __restrict__ lf_off,
-                                const uint32_t* __restrict__ gs_off, uint32_t n, Control* ctl) {
+                                const uint32_t* __restrict__ gs_off,
+                                const uint32_t* __restrict__ tc_off, const u64* __restrict__ sw_off,
+                                uint32_t n, Control* ctl) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         ctl->tot_heavy = hp_off[n];
         ctl->tot_light_region = lr_off[n];
         ctl->tot_light = lf_off[n];
         ctl->tot_g = gs_off[n];
+        ctl->tot_tiles = tc_off[n];
+        ctl->tot_sw = sw_off[n];
     }
 }
 
-hipError_t launch_gather_totals(const uint32_t* hp_off, const u64* lr_off, const uint32_t* lf_off,
-                                const uint32_t* gs_off, uint32_t n, Control* ctl, hipStream_t st) {
-    hipLaunchKernelGGL(k_gather_totals, dim3(1), dim3(64), 0, st, hp_off, lr_off, lf_off, gs_off, n,
-                       ctl);
-    return hipGetLastError();
+// first light piece of each light item: item i holds the pieces whose region
+// offset lies in [i H, (i+1) H)
+__global__ void k_items_first(const u64* __restrict__ light_off, uint32_t n_light,
+                              uint32_t n_items, uint32_t* __restrict__ first) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i <= n_items;
+         i += gridDim.x * blockDim.x) {
+        u64 key = (u64)i * kLightWindow;
+        uint32_t lo = 0, hi = n_light;
+        while (lo < hi) {
+            uint32_t mid = (lo + hi) >> 1;
+            if (light_off[mid] < key)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        first[i] = lo;
+    }
 }
 
 static dim3 grid_n(uint64_t n, uint32_t threads, uint32_t cap = 16384) {
@@ -264,27 +376,51 @@ static dim3 grid_n(uint64_t n, uint32_t threads, uint32_t cap = 16384) {
     return dim3((unsigned)b);
 }
 
-hipError_t launch_plan_count(const u64* wu, const uint32_t* lowcnt, const uint32_t* row_ptr, Dims d,
-                             uint32_t* hp,
-                             u64* lr, uint32_t* lf, uint32_t* gs, u64* wsum, u64* nonzero,
+hipError_t launch_plan_count(const u64* wu, const u64* wsu, const uint32_t* lowcnt,
+                             const uint32_t* row_ptr, Dims d, uint32_t* hp, u64* lr, uint32_t* lf,
+                             uint32_t* gs, uint32_t* tc, u64* swc, u64* wsum, u64* nonzero,
                              hipStream_t st) {
-    hipLaunchKernelGGL(k_plan_count, grid_n(d.n, 256), dim3(256), 0, st, wu, lowcnt, row_ptr, d, hp,
-                       lr, lf, gs);
+    hipLaunchKernelGGL(k_plan_count, grid_n(d.n, 256), dim3(256), 0, st, wu, wsu, lowcnt, row_ptr, d,
+                       hp, lr, lf, gs, tc, swc);
     hipLaunchKernelGGL(k_sum_u64, grid_n(d.n, 256, 512), dim3(256), 0, st, wu, d.n, wsum, nonzero);
     return hipGetLastError();
 }
 
+hipError_t launch_gather_totals(const uint32_t* hp_off, const u64* lr_off, const uint32_t* lf_off,
+                                const uint32_t* gs_off, const uint32_t* tc_off, const u64* sw_off,
+                                uint32_t n, Control* ctl, hipStream_t st) {
+    hipLaunchKernelGGL(k_gather_totals, dim3(1), dim3(64), 0, st, hp_off, lr_off, lf_off, gs_off,
+                       tc_off, sw_off, n, ctl);
+    return hipGetLastError();
+}
+
 hipError_t launch_plan_write(const u64* wu, const uint32_t* lowcnt, const uint32_t* row_ptr,
-                             const uint32_t* mptr,
-                             const uint32_t* hp, const uint32_t* hp_off, const u64* lr,
+                             const uint32_t* mptr, const uint32_t* front, const uint32_t* hp_off,
                              const u64* lr_off, const uint32_t* lf_off, const uint32_t* gs_off,
-                             Dims d, uint32_t n_heavy, Piece* pieces, u64* light_off,
-                             uint32_t* hkey, uint32_t n_light, uint32_t n_light_items,
-                             uint32_t* items_first, hipStream_t st) {
-    hipLaunchKernelGGL(k_plan_write, grid_n(d.n, 256), dim3(256), 0, st, wu, lowcnt, row_ptr, mptr, hp,
-                       hp_off, lr, lr_off, lf_off, gs_off, d, n_heavy, pieces, light_off, hkey);
+                             const uint32_t* tc_off, Dims d, uint32_t n_heavy, Piece* pieces,
+                             u64* light_off, uint32_t* hkey, uint32_t* tile_piece, uint32_t n_light,
+                             uint32_t n_light_items, uint32_t* items_first, hipStream_t st) {
+    hipLaunchKernelGGL(k_plan_write, grid_n(d.n, 256), dim3(256), 0, st, wu, lowcnt, row_ptr, mptr,
+                       front, hp_off, lr_off, lf_off, gs_off, tc_off, d, n_heavy, pieces, light_off,
+                       hkey, tile_piece);
     hipLaunchKernelGGL(k_items_first, grid_n((uint64_t)n_light_items + 1, 256), dim3(256), 0, st,
                        (const u64*)light_off, n_light, n_light_items, items_first);
+    return hipGetLastError();
+}
+
+hipError_t launch_short_wedges(const uint4* recs, uint32_t m, const uint32_t* col,
+                               const uint32_t* mptr, const uint32_t* front, const uint32_t* tc,
+                               const uint32_t* tc_off, const uint32_t* hp_off,
+                               const uint32_t* tile_piece, uint32_t* counts, uint32_t* cursor,
+                               uint32_t* list, bool fill, hipStream_t st) {
+    if (fill)
+        hipLaunchKernelGGL(k_short_wedges<true>, grid_n(m, kSwThreads, 8192), dim3(kSwThreads), 0, st,
+                           recs, m, col, mptr, front, tc, tc_off, hp_off, tile_piece, counts, cursor,
+                           list);
+    else
+        hipLaunchKernelGGL(k_short_wedges<false>, grid_n(m, kSwThreads, 8192), dim3(kSwThreads), 0,
+                           st, recs, m, col, mptr, front, tc, tc_off, hp_off, tile_piece, counts,
+                           cursor, list);
     return hipGetLastError();
 }
 

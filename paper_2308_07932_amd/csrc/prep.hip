@@ -487,28 +487,35 @@ __global__ void k_lowcount(const uint32_t* __restrict__ row_ptr, const uint32_t*
 // Records come from the upper part of every row: in the sorted row of v, the
 // entry at index i >= k_v names a neighbour u of higher priority, and exactly
 // i entries precede it, all of lower priority than u -- so pos_v(u) = i with
-// no search.  The record (row v, i, sign, sidx(v)) is appended to u's record
-// list (slots reserved through an LDS table as in the scatter), and i is added
-// to W_u.  The order of a start's records is irrelevant to the count.
-//   .x = first entry of row v, .y = pos << 1 | neg(u, v), .z = sidx(v)
-constexpr int kRecPer = 8;  // consecutive CSR entries per thread
+// no search.  The record is appended to u's record list: records whose middle
+// row v is long fill u's slots from the front, the others from the back (slots
+// reserved through an LDS table as in the scatter).  i is added to W_u, and to
+// Ws_u (the wedges through short middle rows) for the short ones.  The order of
+// a start's records is otherwise irrelevant to the count.
+//   .x = first entry of row v, .y = pos << 1 | neg(u, v), .z = sidx(v), .w = row u
+constexpr int kRecPer = 4;  // consecutive CSR entries per thread
 constexpr uint32_t kRecChunk = kAggThreads * kRecPer;
+constexpr uint32_t kRecLog2 = 11;
+constexpr uint32_t kRecSlots = 1u << kRecLog2;
 
 __global__ __launch_bounds__(kAggThreads) void k_records(
     const uint32_t* __restrict__ row_ptr, const uint32_t* __restrict__ col,
-    const uint32_t* __restrict__ lowcnt, Dims d, uint32_t* __restrict__ rcur,
-    uint4* __restrict__ recs, u64* __restrict__ wu) {
-    __shared__ uint32_t keys[kAggSlots];
-    __shared__ uint32_t cnt[kAggSlots];
-    __shared__ uint32_t base[kAggSlots];
-    __shared__ u64 wsum[kAggSlots];
+    const uint32_t* __restrict__ lowcnt, Dims d, const Control* ctl,
+    uint32_t* __restrict__ front, uint32_t* __restrict__ back, uint4* __restrict__ recs,
+    u64* __restrict__ wu, u64* __restrict__ wsu) {
+    __shared__ uint32_t keys[kRecSlots];
+    __shared__ uint32_t cnt[kRecSlots];  // long count | short count << 16
+    __shared__ uint32_t baseL[kRecSlots], baseS[kRecSlots];
+    __shared__ u64 wsum[kRecSlots], wsumS[kRecSlots];
     const uint32_t tid = threadIdx.x;
     const uint64_t nnz = row_ptr[d.n];  // entries actually placed (invalid edges are not)
+    const uint32_t long0 = ctl->cls[0][4], long1 = ctl->cls[1][4];
     for (uint64_t c0 = (uint64_t)blockIdx.x * kRecChunk; c0 < nnz; c0 += (uint64_t)gridDim.x * kRecChunk) {
-        for (uint32_t i = tid; i < kAggSlots; i += kAggThreads) {
+        for (uint32_t i = tid; i < kRecSlots; i += kAggThreads) {
             keys[i] = kEmpty;
             cnt[i] = 0;
             wsum[i] = 0;
+            wsumS[i] = 0;
         }
         __syncthreads();
         const uint64_t e0 = c0 + (uint64_t)tid * kRecPer;
@@ -538,29 +545,43 @@ __global__ __launch_bounds__(kAggThreads) void k_records(
             const uint32_t x = col[e];
             if ((x >> 1) >= d.size[side ^ 1u]) continue;  // hole left by a repeated edge
             const uint32_t urow = d.base[side ^ 1u] + (x >> 1);
-            rec[k] = make_uint4(rs, (i << 1) | (x & 1u), r - d.base[side], 0u);
-            const int sl = agg_slot<kAggLog2>(keys, urow);
+            const bool is_long = r >= (side ? long1 : long0);
+            rec[k] = make_uint4(rs, (i << 1) | (x & 1u), r - d.base[side], urow);
+            const int sl = agg_slot<kRecLog2>(keys, urow);
             if (sl >= 0) {
-                slot[k] = (uint32_t)sl;
-                rank[k] = atomicAdd(&cnt[sl], 1u);
+                slot[k] = (uint32_t)sl | (is_long ? 0u : 0x80000000u);
+                const uint32_t old = atomicAdd(&cnt[sl], is_long ? 1u : 0x10000u);
+                rank[k] = is_long ? (old & 0xFFFFu) : (old >> 16);
                 atomicAdd(&wsum[sl], (u64)i);
+                if (!is_long) atomicAdd(&wsumS[sl], (u64)i);
             } else {
-                slot[k] = kEmpty;
-                rank[k] = atomicAdd(&rcur[urow], 1u);
+                slot[k] = kEmpty;  // position reserved directly
+                rank[k] = is_long ? atomicAdd(&front[urow], 1u) : atomicSub(&back[urow], 1u) - 1u;
                 atomicAdd(&wu[urow], (u64)i);
+                if (!is_long) atomicAdd(&wsu[urow], (u64)i);
             }
         }
         __syncthreads();
-        for (uint32_t i = tid; i < kAggSlots; i += kAggThreads)
+        for (uint32_t i = tid; i < kRecSlots; i += kAggThreads)
             if (keys[i] != kEmpty) {
-                base[i] = atomicAdd(&rcur[keys[i]], cnt[i]);
+                const uint32_t cl = cnt[i] & 0xFFFFu, cs = cnt[i] >> 16;
+                if (cl) baseL[i] = atomicAdd(&front[keys[i]], cl);
+                if (cs) baseS[i] = atomicSub(&back[keys[i]], cs) - cs;
                 atomicAdd(&wu[keys[i]], wsum[i]);
+                if (wsumS[i]) atomicAdd(&wsu[keys[i]], wsumS[i]);
             }
         __syncthreads();
         for (int k = 0; k < kRecPer; ++k) {
             const uint32_t sl = slot[k];
             if (sl == kEmpty - 1) continue;
-            recs[sl == kEmpty ? rank[k] : base[sl] + rank[k]] = rec[k];
+            uint32_t at;
+            if (sl == kEmpty)
+                at = rank[k];
+            else if (sl & 0x80000000u)
+                at = baseS[sl & 0x7FFFFFFFu] + rank[k];
+            else
+                at = baseL[sl] + rank[k];
+            recs[at] = rec[k];
         }
         __syncthreads();
     }
@@ -698,10 +719,10 @@ hipError_t launch_lowcount(const uint32_t* row_ptr, const uint32_t* col, const u
 }
 
 hipError_t launch_records(const uint32_t* row_ptr, const uint32_t* col, const uint32_t* lowcnt,
-                          Dims d, uint64_t nnz_bound, uint32_t* rcur, uint4* recs, u64* wu,
-                          hipStream_t st) {
-    hipLaunchKernelGGL(k_records, grid_n(nnz_bound, kRecChunk, 2048), dim3(kAggThreads), 0, st,
-                       row_ptr, col, lowcnt, d, rcur, recs, wu);
+                          Dims d, const Control* ctl, uint64_t nnz_bound, uint32_t* front,
+                          uint32_t* back, uint4* recs, u64* wu, u64* wsu, hipStream_t st) {
+    hipLaunchKernelGGL(k_records, grid_n(nnz_bound, kRecChunk, 4096), dim3(kAggThreads), 0, st,
+                       row_ptr, col, lowcnt, d, ctl, front, back, recs, wu, wsu);
     return hipGetLastError();
 }
 

@@ -37,10 +37,13 @@ struct WedgeArgs {
     Dims d;
     uint32_t first_long[2];  // sidx of the first row longer than kLongDeg, per side
     u64* G;
+    const uint32_t* sw_off;   // short-middle wedge list of heavy piece p: [sw_off[p], sw_off[p+1])
+    const uint32_t* sw_list;  // packed w << 1 | asymmetric
     Control* ctl;
 };
 
-constexpr uint32_t kShort = 16;       // sub-intervals up to this length are walked by one lane
+constexpr uint32_t kScanMax = 16;     // short middle prefixes are read whole and filtered
+constexpr uint32_t kUnroll = 4;       // independent CSR loads in flight per lane
 constexpr uint32_t kWaves = kWedgeThreads / 64;
 constexpr uint32_t kProbeLimit = 256; // heavy hashed pieces give up after this many probes
 constexpr uint32_t kStack = 16;       // pending halves of an abandoned piece
@@ -84,6 +87,10 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
     __shared__ uint32_t s_sp;
     __shared__ uint32_t s_item;
     __shared__ uint32_t s_abort;
+    __shared__ uint32_t s_batch;
+    __shared__ uint32_t s_wbase[kWaves][64];  // per wave: compacted sub-interval starts,
+    __shared__ uint32_t s_wpre[kWaves][64];   // exclusive prefix of their lengths,
+    __shared__ uint32_t s_waux[kWaves][64];   // sign(u,v) | filter << 1 | piece << 2
     __shared__ u64 s_red[2][kWaves];
     uint32_t* keys = (uint32_t*)s_tab;
     u64* hvals = s_tab + kHashSlots / 2;
@@ -91,12 +98,14 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
     const uint32_t* __restrict__ col = a.col;
 
+    u64 acc_bal = 0, acc_unb = 0;  // this workgroup's totals (thread 0)
+    if (tid == 0) s_item = atomicAdd(&a.ctl->queue, 1u);
     for (;;) {
-        __syncthreads();  // every thread is done with the previous item and s_item
-        if (tid == 0) s_item = atomicAdd(&a.ctl->queue, 1u);
-        __syncthreads();
+        __syncthreads();  // every thread is done with the previous item; s_item is set
         const uint32_t item = s_item;
         if (item >= a.n_items) break;
+        uint32_t next = 0;
+        if (tid == 0) next = atomicAdd(&a.ctl->queue, 1u);  // in flight while this item runs
         uint32_t p0, p1;
         if (item < a.n_heavy) {
             p0 = a.order[item];
@@ -107,7 +116,10 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
             p1 = a.n_heavy + a.items_first[li + 1];
         }
         const uint32_t np = p1 - p0;
-        if (np == 0 || np > kMaxItemPieces) continue;  // never planned; uniform across the block
+        if (np == 0 || np > kMaxItemPieces) {  // never planned; uniform across the block
+            if (tid == 0) s_item = next;
+            continue;
+        }
         if (tid < np) s_pc[tid] = a.pieces[p0 + tid];
         if (tid == 0) s_sp = 0;
         const bool heavy = item < a.n_heavy;
@@ -126,7 +138,10 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
                 }
                 if (lane == 0) s_pre[np] = carry;
             }
-            if (tid == 0) s_abort = 0;
+            if (tid == 0) {
+                s_abort = 0;
+                s_batch = 0;
+            }
             const bool dense = (s_pc[0].flags & kPieceDense) != 0;
             const uint32_t dlo = s_pc[0].lo;
             const uint32_t dwidth = s_pc[0].hi - s_pc[0].lo;
@@ -142,8 +157,11 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
             __syncthreads();
             const uint32_t total = s_pre[np];
 
-            for (uint32_t base = wave * 64; base < total; base += kWedgeThreads) {
-                if (s_abort) break;  // the piece will be redone; stop early
+            for (;;) {
+                uint32_t base = 0;
+                if (lane == 0) base = atomicAdd(&s_batch, 64u);  // next 64 records for this wave
+                base = __shfl(base, 0, 64);
+                if (base >= total || s_abort) break;  // s_abort: the piece will be redone
                 const uint32_t f = base + lane;
                 const bool act = f < total;
                 uint32_t p = 0;
@@ -158,14 +176,14 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
                     }
                     p = lo;
                 }
-                uint32_t rs = 0, s1 = 0, ia = 0, ib = 0;
+                // -- 1. this lane's record and its sub-interval [ia, ib) of row v
+                uint32_t rs = 0, s1 = 0, ia = 0, ib = 0, filt = 0;
                 if (act) {
                     const Piece& P = s_pc[p];
                     const uint4 rc = a.recs[P.rec0 + (f - s_pre[p])];
                     rs = rc.x;
                     const uint32_t pos = rc.y >> 1;
                     s1 = rc.y & 1u;
-                    ia = 0;
                     ib = pos;
                     if (P.flags & kPiecePartial) {
                         const uint32_t ys = (P.flags & kPieceSideV) ? 0u : 1u;  // side of v
@@ -176,6 +194,8 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
                                                     (a.d.ntile[ys ^ 1u] + 1);
                             ia = min(t[P.t0], pos);
                             ib = min(t[P.t1], pos);
+                        } else if (pos <= kScanMax) {
+                            filt = 1;  // short prefix: read it all, keep entries in [lo, hi)
                         } else {
                             ia = lower_bound_u32(col + rs, pos, P.lo << 1);
                             ib = ia + lower_bound_u32(col + rs + ia, pos - ia, P.hi << 1);
@@ -183,34 +203,74 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
                     }
                 }
                 const uint32_t len = ib - ia;
+                // -- 2. compact the non-empty sub-intervals of the wave into LDS
+                const u64 nz = __ballot(len > 0);
+                const uint32_t cnt = (uint32_t)__popcll(nz);
+                const uint32_t excl = wave_incl_scan(len) - len;
+                const uint32_t T = __shfl(excl + len, 63, 64);
+                if (len > 0) {
+                    const uint32_t ci = (uint32_t)__popcll(nz & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
+                    s_wbase[wave][ci] = rs + ia;
+                    s_wpre[wave][ci] = excl;
+                    s_waux[wave][ci] = s1 | (filt << 1) | (p << 2);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                // -- 3. all lanes over the concatenated wedges, kUnroll loads in flight
                 bool ok = true;
-
-                // -- one lane per short sub-interval
-                if (len > 0 && len <= kShort) {
-                    const uint32_t region = s_pc[p].region;
-                    const uint32_t lim = min(lim0, 1u << ((region >> 16) & 31u));
-                    for (uint32_t e = ia; e < ib && ok; ++e) {
-                        const uint32_t x = col[rs + e];
-                        ok = bucket_add(s_tab, keys, hvals, dense, dlo, region, lim, x >> 1,
-                                        ((x ^ s1) & 1u) ? (1ull << 32) : 1ull);
+                for (uint32_t j = 0; j < T && ok; j += 64 * kUnroll) {
+                    uint32_t x[kUnroll], aux[kUnroll];
+#pragma unroll
+                    for (uint32_t u = 0; u < kUnroll; ++u) {
+                        const uint32_t q = j + u * 64 + lane;
+                        aux[u] = kEmpty;
+                        x[u] = 0;
+                        if (q < T) {
+                            uint32_t lo = 0, hi = cnt;  // last compacted interval with pre <= q
+                            while (hi - lo > 1) {
+                                const uint32_t mid = (lo + hi) >> 1;
+                                if (s_wpre[wave][mid] <= q)
+                                    lo = mid;
+                                else
+                                    hi = mid;
+                            }
+                            aux[u] = s_waux[wave][lo];
+                            x[u] = col[s_wbase[wave][lo] + (q - s_wpre[wave][lo])];
+                        }
+                    }
+#pragma unroll
+                    for (uint32_t u = 0; u < kUnroll; ++u) {
+                        if (aux[u] == kEmpty || !ok) continue;
+                        const uint32_t w = x[u] >> 1;
+                        const Piece& P = s_pc[aux[u] >> 2];
+                        if ((aux[u] & 2u) && (w < P.lo || w >= P.hi)) continue;
+                        const uint32_t lim = min(lim0, 1u << ((P.region >> 16) & 31u));
+                        ok = bucket_add(s_tab, keys, hvals, dense, dlo, P.region, lim, w,
+                                        ((x[u] ^ aux[u]) & 1u) ? (1ull << 32) : 1ull);
                     }
                 }
-                // -- whole wave per long sub-interval
-                u64 longmask = __ballot(len > kShort);
-                while (longmask) {
-                    const uint32_t L = __ffsll((unsigned long long)longmask) - 1;
-                    longmask &= longmask - 1;
-                    const uint32_t lrs = __shfl(rs, L, 64);
-                    const uint32_t la = __shfl(ia, L, 64);
-                    const uint32_t lb = __shfl(ib, L, 64);
-                    const uint32_t ls1 = __shfl(s1, L, 64);
-                    const uint32_t lp = __shfl(p, L, 64);
-                    const uint32_t region = s_pc[lp].region;
-                    const uint32_t lim = min(lim0, 1u << ((region >> 16) & 31u));
-                    for (uint32_t e = la + lane; e < lb && ok; e += 64) {
-                        const uint32_t x = col[lrs + e];
-                        ok = bucket_add(s_tab, keys, hvals, dense, dlo, region, lim, x >> 1,
-                                        ((x ^ ls1) & 1u) ? (1ull << 32) : 1ull);
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                if (!ok) s_abort = 1;
+            }
+            // -- bucketed wedges through short middle rows (split starts)
+            if (heavy && (s_pc[0].flags & kPiecePartial) && s_pc[0].list != kEmpty) {
+                const uint32_t L = s_pc[0].list;
+                const uint32_t b0 = a.sw_off[L], b1 = a.sw_off[L + 1];
+                const uint32_t plo = s_pc[0].lo, phi = s_pc[0].hi, region = s_pc[0].region;
+                bool ok = true;
+                for (uint32_t q0 = b0 + tid; q0 < b1 && ok && !s_abort; q0 += kWedgeThreads * kUnroll) {
+                    uint32_t x[kUnroll];
+#pragma unroll
+                    for (uint32_t u = 0; u < kUnroll; ++u) {
+                        const uint32_t q = q0 + u * kWedgeThreads;
+                        x[u] = q < b1 ? a.sw_list[q] : kEmpty;
+                    }
+#pragma unroll
+                    for (uint32_t u = 0; u < kUnroll; ++u) {
+                        if (x[u] == kEmpty || !ok) continue;
+                        const uint32_t w = x[u] >> 1;
+                        if (w < plo || w >= phi) continue;  // a re-split half keeps its share
+                        ok = bucket_add(s_tab, keys, hvals, dense, dlo, region, lim0, w,
+                                        (x[u] & 1u) ? (1ull << 32) : 1ull);
                     }
                 }
                 if (!ok) s_abort = 1;
@@ -280,27 +340,29 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
             }
             __syncthreads();
             if (tid == 0) {
-                u64 b = 0, u = 0;
                 for (uint32_t w = 0; w < kWaves; ++w) {
-                    b += s_red[0][w];
-                    u += s_red[1][w];
+                    acc_bal += s_red[0][w];
+                    acc_unb += s_red[1][w];
                 }
-                if (b) atomicAdd(&a.ctl->balanced, b);
-                if (u) atomicAdd(&a.ctl->unbalanced, u);
                 if (s_sp > 0) s_pc[0] = s_stack[--s_sp];
                 else s_sp = kStack + 2;  // done with this item
             }
             __syncthreads();
             if (s_sp > kStack) break;
         }
+        if (tid == 0) s_item = next;
+    }
+    if (tid == 0) {
+        if (acc_bal) atomicAdd(&a.ctl->balanced, acc_bal);
+        if (acc_unb) atomicAdd(&a.ctl->unbalanced, acc_unb);
     }
 }
 
 hipError_t launch_wedge(const Piece* pieces, const uint32_t* order, const uint32_t* items_first,
                         uint32_t n_heavy,
                         uint32_t n_items, const uint4* recs, const uint32_t* col, const uint32_t* tb,
-                        Dims d, const uint32_t first_long[2], u64* G, Control* ctl,
-                        uint32_t num_cus, hipStream_t st) {
+                        Dims d, const uint32_t first_long[2], u64* G, const uint32_t* sw_off,
+                        const uint32_t* sw_list, Control* ctl, uint32_t num_cus, hipStream_t st) {
     WedgeArgs a;
     a.pieces = pieces;
     a.order = order;
@@ -314,6 +376,8 @@ hipError_t launch_wedge(const Piece* pieces, const uint32_t* order, const uint32
     a.first_long[0] = first_long[0];
     a.first_long[1] = first_long[1];
     a.G = G;
+    a.sw_off = sw_off;
+    a.sw_list = sw_list;
     a.ctl = ctl;
     uint32_t grid = num_cus;
     if (grid > n_items) grid = n_items;
