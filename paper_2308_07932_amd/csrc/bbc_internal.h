@@ -46,7 +46,7 @@ constexpr uint32_t kDenseW = 16384;           // dense counters per item (u64 ea
 constexpr uint32_t kHashSlots = 8192;         // hash slots (u32 key + u64 counters)
 constexpr uint32_t kLightWindow = kHashSlots / 2;  // H: light regions start inside [iH, iH+H)
 constexpr uint32_t kLightMax = kHashSlots / 4;     // max wedges of a batched (light) start
-constexpr uint32_t kMinRegion = 32;
+constexpr uint32_t kMinRegion = 64;
 constexpr uint32_t kMaxItemPieces = (2 * kLightWindow) / kMinRegion + 1;
 constexpr uint32_t kTile = 16384;             // end-vertex tile width (sidx units)
 constexpr u64 kRecordChunkWedges = 65536;     // wedges per record chunk of a small-side start

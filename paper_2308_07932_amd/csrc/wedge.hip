@@ -47,6 +47,8 @@ constexpr uint32_t kUnroll = 4;       // independent CSR loads in flight per lan
 constexpr uint32_t kWaves = kWedgeThreads / 64;
 constexpr uint32_t kProbeLimit = 256; // heavy hashed pieces give up after this many probes
 constexpr uint32_t kStack = 16;       // pending halves of an abandoned piece
+constexpr uint32_t kChunk = 2048;     // longer sub-intervals are cut; the tail chunks are
+constexpr uint32_t kQueue = 256;      // queued in LDS and shared by all waves afterwards
 
 __device__ inline uint32_t hash32(uint32_t w) { return w * 0x9E3779B1u; }
 
@@ -88,17 +90,22 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
     __shared__ uint32_t s_item;
     __shared__ uint32_t s_abort;
     __shared__ uint32_t s_batch;
-    __shared__ uint32_t s_wbase[kWaves][64];  // per wave: compacted sub-interval starts,
-    __shared__ uint32_t s_wpre[kWaves][64];   // exclusive prefix of their lengths,
-    __shared__ uint32_t s_waux[kWaves][64];   // sign(u,v) | filter << 1 | piece << 2
+    __shared__ uint32_t s_wadj[kWaves][64];   // per wave: compacted sub-intervals' address - start,
+    __shared__ uint32_t s_waux[kWaves][64];   // sign(u,v) | filter << 1 | piece << 2,
+    __shared__ uint8_t s_head[kWaves][64 * kUnroll];  // head flags of the current windows
+    __shared__ uint32_t s_qadj[kQueue], s_qlen[kQueue], s_qaux[kQueue];  // queued long chunks
+    __shared__ uint32_t s_qn, s_qtake;
     __shared__ u64 s_red[2][kWaves];
     uint32_t* keys = (uint32_t*)s_tab;
     u64* hvals = s_tab + kHashSlots / 2;
 
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
     const uint32_t* __restrict__ col = a.col;
+    for (uint32_t u = 0; u < kUnroll; ++u) s_head[wave][u * 64 + lane] = 0;
 
     u64 acc_bal = 0, acc_unb = 0;  // this workgroup's totals (thread 0)
+    Piece pf;                      // thread 0: the next heavy item's piece, fetched ahead
+    uint32_t pf_item = kEmpty;
     if (tid == 0) s_item = atomicAdd(&a.ctl->queue, 1u);
     for (;;) {
         __syncthreads();  // every thread is done with the previous item; s_item is set
@@ -106,21 +113,19 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
         if (item >= a.n_items) break;
         uint32_t next = 0;
         if (tid == 0) next = atomicAdd(&a.ctl->queue, 1u);  // in flight while this item runs
-        uint32_t p0, p1;
+        uint32_t np = 1;
         if (item < a.n_heavy) {
-            p0 = a.order[item];
-            p1 = p0 + 1;
+            if (tid == 0) s_pc[0] = (pf_item == item) ? pf : a.pieces[a.order[item]];
         } else {
-            uint32_t li = item - a.n_heavy;
-            p0 = a.n_heavy + a.items_first[li];
-            p1 = a.n_heavy + a.items_first[li + 1];
+            const uint32_t li = item - a.n_heavy;
+            const uint32_t p0 = a.n_heavy + a.items_first[li];
+            np = a.n_heavy + a.items_first[li + 1] - p0;
+            if (np == 0 || np > kMaxItemPieces) {  // never planned; uniform across the block
+                if (tid == 0) s_item = next;
+                continue;
+            }
+            if (tid < np) s_pc[tid] = a.pieces[p0 + tid];
         }
-        const uint32_t np = p1 - p0;
-        if (np == 0 || np > kMaxItemPieces) {  // never planned; uniform across the block
-            if (tid == 0) s_item = next;
-            continue;
-        }
-        if (tid < np) s_pc[tid] = a.pieces[p0 + tid];
         if (tid == 0) s_sp = 0;
         const bool heavy = item < a.n_heavy;
 
@@ -141,11 +146,14 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
             if (tid == 0) {
                 s_abort = 0;
                 s_batch = 0;
+                s_qn = 0;
+                s_qtake = 0;
             }
             const bool dense = (s_pc[0].flags & kPieceDense) != 0;
             const uint32_t dlo = s_pc[0].lo;
             const uint32_t dwidth = s_pc[0].hi - s_pc[0].lo;
             const uint32_t lim0 = heavy ? kProbeLimit : kHashSlots;
+            const uint32_t plo0 = s_pc[0].lo, phi0 = s_pc[0].hi, region0 = s_pc[0].region;
             if (dense) {
                 for (uint32_t i = tid; i < dwidth; i += kWedgeThreads) s_tab[i] = 0;
             } else {
@@ -154,16 +162,22 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
                     hvals[i] = 0;
                 }
             }
+            if (tid == 0 && next < a.n_heavy && pf_item != next) {
+                pf = a.pieces[a.order[next]];
+                pf_item = next;
+            }
             __syncthreads();
             const uint32_t total = s_pre[np];
+            // records per grab: small items are shared by all waves, large ones in 64s
+            const uint32_t bsz = min(64u, max(8u, (total + 63) / 64));
 
             for (;;) {
                 uint32_t base = 0;
-                if (lane == 0) base = atomicAdd(&s_batch, 64u);  // next 64 records for this wave
+                if (lane == 0) base = atomicAdd(&s_batch, bsz);  // this wave's next records
                 base = __shfl(base, 0, 64);
                 if (base >= total || s_abort) break;  // s_abort: the piece will be redone
                 const uint32_t f = base + lane;
-                const bool act = f < total;
+                const bool act = lane < bsz && f < total;
                 uint32_t p = 0;
                 if (np > 1 && act) {
                     uint32_t lo = 0, hi = np;  // last piece with s_pre[p] <= f
@@ -202,53 +216,130 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
                         }
                     }
                 }
+                // -- a long sub-interval keeps its first kChunk entries; the rest goes
+                // to the LDS queue in chunks of kChunk (as many as fit)
+                if (ib - ia > kChunk) {
+                    const uint32_t want = (ib - ia - 1) / kChunk;  // chunks beyond the first
+                    uint32_t old = s_qn, got = 0;
+                    for (;;) {
+                        got = min(want, kQueue - min(old, kQueue));
+                        if (got == 0) break;
+                        const uint32_t seen = atomicCAS(&s_qn, old, old + got);
+                        if (seen == old) break;
+                        old = seen;
+                    }
+                    if (got > 0) {
+                        const uint32_t keep_end = max(ia + kChunk, ib - got * kChunk);
+                        for (uint32_t c = 0; c < got; ++c) {
+                            const uint32_t c0 = keep_end + c * kChunk;
+                            s_qadj[old + c] = rs + c0;
+                            s_qlen[old + c] = min(kChunk, ib - c0);
+                            s_qaux[old + c] = s1 | (filt << 1) | (p << 2);
+                        }
+                        ib = keep_end;
+                    }
+                }
                 const uint32_t len = ib - ia;
-                // -- 2. compact the non-empty sub-intervals of the wave into LDS
+                // -- 2. compact the non-empty sub-intervals of the wave into LDS.  Entry
+                // q of the concatenation (q in [excl, excl + len) of its interval) is
+                // col[adj + q] with adj = rs + ia - excl.
                 const u64 nz = __ballot(len > 0);
-                const uint32_t cnt = (uint32_t)__popcll(nz);
                 const uint32_t excl = wave_incl_scan(len) - len;
                 const uint32_t T = __shfl(excl + len, 63, 64);
                 if (len > 0) {
                     const uint32_t ci = (uint32_t)__popcll(nz & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
-                    s_wbase[wave][ci] = rs + ia;
-                    s_wpre[wave][ci] = excl;
+                    s_wadj[wave][ci] = rs + ia - excl;
                     s_waux[wave][ci] = s1 | (filt << 1) | (p << 2);
                 }
-                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                // -- 3. all lanes over the concatenated wedges, kUnroll loads in flight
+                // -- 3. all lanes over the concatenated wedges, kUnroll windows of 64 at a
+                // time.  The owner of position q is found from head flags: each interval
+                // marks its first position, a ballot gives the window's heads, and the
+                // owner index is (heads before the window) + (heads at or before q) - 1.
                 bool ok = true;
+                uint32_t before = 0;
+                const u64 le_mask = ~0ull >> (63 - lane);  // lanes 0..lane
                 for (uint32_t j = 0; j < T && ok; j += 64 * kUnroll) {
+                    if (len > 0 && excl >= j && excl < j + 64 * kUnroll) s_head[wave][excl - j] = 1;
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
                     uint32_t x[kUnroll], aux[kUnroll];
 #pragma unroll
                     for (uint32_t u = 0; u < kUnroll; ++u) {
+                        const uint32_t hd = s_head[wave][u * 64 + lane];
+                        const u64 M = __ballot(hd != 0);
+                        const uint32_t idx = before + (uint32_t)__popcll(M & le_mask) - 1u;
+                        before += (uint32_t)__popcll(M);
                         const uint32_t q = j + u * 64 + lane;
                         aux[u] = kEmpty;
                         x[u] = 0;
                         if (q < T) {
-                            uint32_t lo = 0, hi = cnt;  // last compacted interval with pre <= q
-                            while (hi - lo > 1) {
-                                const uint32_t mid = (lo + hi) >> 1;
-                                if (s_wpre[wave][mid] <= q)
-                                    lo = mid;
-                                else
-                                    hi = mid;
-                            }
-                            aux[u] = s_waux[wave][lo];
-                            x[u] = col[s_wbase[wave][lo] + (q - s_wpre[wave][lo])];
+                            aux[u] = s_waux[wave][idx];
+                            x[u] = col[s_wadj[wave][idx] + q];
                         }
                     }
 #pragma unroll
-                    for (uint32_t u = 0; u < kUnroll; ++u) {
-                        if (aux[u] == kEmpty || !ok) continue;
-                        const uint32_t w = x[u] >> 1;
-                        const Piece& P = s_pc[aux[u] >> 2];
-                        if ((aux[u] & 2u) && (w < P.lo || w >= P.hi)) continue;
-                        const uint32_t lim = min(lim0, 1u << ((P.region >> 16) & 31u));
-                        ok = bucket_add(s_tab, keys, hvals, dense, dlo, P.region, lim, w,
-                                        ((x[u] ^ aux[u]) & 1u) ? (1ull << 32) : 1ull);
+                    for (uint32_t u = 0; u < kUnroll; ++u) s_head[wave][u * 64 + lane] = 0;
+                    if (np == 1 && dense) {
+                        // one dense piece: counters addressed by w - lo, never full
+#pragma unroll
+                        for (uint32_t u = 0; u < kUnroll; ++u) {
+                            if (aux[u] == kEmpty) continue;
+                            const uint32_t w = x[u] >> 1;
+                            if ((aux[u] & 2u) && (w < plo0 || w >= phi0)) continue;
+                            atomicAdd(&s_tab[w - dlo], ((x[u] ^ aux[u]) & 1u) ? (1ull << 32) : 1ull);
+                        }
+                    } else if (np == 1) {
+#pragma unroll 1
+                        for (uint32_t u = 0; u < kUnroll; ++u) {
+                            if (aux[u] == kEmpty || !ok) continue;
+                            const uint32_t w = x[u] >> 1;
+                            if ((aux[u] & 2u) && (w < plo0 || w >= phi0)) continue;
+                            ok = bucket_add(s_tab, keys, hvals, false, 0, region0, lim0, w,
+                                            ((x[u] ^ aux[u]) & 1u) ? (1ull << 32) : 1ull);
+                        }
+                    } else {
+#pragma unroll 1
+                        for (uint32_t u = 0; u < kUnroll; ++u) {
+                            if (aux[u] == kEmpty || !ok) continue;
+                            const uint32_t region = s_pc[aux[u] >> 2].region;
+                            const uint32_t lim = 1u << ((region >> 16) & 31u);
+                            ok = bucket_add(s_tab, keys, hvals, false, 0, region, lim, x[u] >> 1,
+                                            ((x[u] ^ aux[u]) & 1u) ? (1ull << 32) : 1ull);
+                        }
                     }
                 }
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                if (!ok) s_abort = 1;
+            }
+            __syncthreads();
+            // -- queued chunks of long sub-intervals: one wave per chunk, coalesced
+            if (np == 1) {
+                bool ok = true;
+                for (;;) {
+                    uint32_t c = 0;
+                    if (lane == 0) c = atomicAdd(&s_qtake, 1u);
+                    c = __shfl(c, 0, 64);
+                    if (c >= s_qn || s_abort || !ok) break;
+                    const uint32_t adj = s_qadj[c], qlen = s_qlen[c], aux = s_qaux[c];
+                    for (uint32_t e0 = 0; e0 < qlen && ok; e0 += 64 * kUnroll) {
+                        uint32_t x[kUnroll];
+#pragma unroll
+                        for (uint32_t u = 0; u < kUnroll; ++u) {
+                            const uint32_t e = e0 + u * 64 + lane;
+                            x[u] = e < qlen ? col[adj + e] : kEmpty;
+                        }
+#pragma unroll
+                        for (uint32_t u = 0; u < kUnroll; ++u) {
+                            if (x[u] == kEmpty || !ok) continue;
+                            const uint32_t w = x[u] >> 1;
+                            if ((aux & 2u) && (w < plo0 || w >= phi0)) continue;
+                            const u64 inc = ((x[u] ^ aux) & 1u) ? (1ull << 32) : 1ull;
+                            if (dense)
+                                atomicAdd(&s_tab[w - dlo], inc);
+                            else
+                                ok = bucket_add(s_tab, keys, hvals, false, 0, region0, lim0, w, inc);
+                        }
+                    }
+                }
                 if (!ok) s_abort = 1;
             }
             // -- bucketed wedges through short middle rows (split starts)
