@@ -127,6 +127,25 @@ bbc_status bbc_last_phase_ms(const bbc_context* ctx, int phase, double* ms);
  */
 bbc_status bbc_last_stats(const bbc_context* ctx, int64_t* stats, int n);
 
+/*
+ * Tunable work-split thresholds of a context.  They change how the work is
+ * cut into pieces, never the result: every setting in range counts exactly.
+ *   BBC_PARAM_HASH_TARGET  expected wedges per hashed run of end-vertex tiles
+ *                          of a heavy start (Section 5.2's per-start buckets,
+ *                          split along the end-vertex axis); tiles expected to
+ *                          hold more get dense counters.  Default 4096, range
+ *                          [64, 1048576].
+ *   BBC_PARAM_PROBE_LIMIT  hash probes a heavy start's hashed piece tries
+ *                          before it gives up; the piece is then redone in
+ *                          halves (or densely).  Default 256, range [1, 8192].
+ * bbc_set_param returns BBC_ERR_INVALID_ARG for a NULL context, an unknown
+ * parameter or a value out of range (the setting is then unchanged);
+ * bbc_get_param writes the current value to *value.
+ */
+enum { BBC_PARAM_HASH_TARGET = 1, BBC_PARAM_PROBE_LIMIT = 2 };
+bbc_status bbc_set_param(bbc_context* ctx, int param, int64_t value);
+bbc_status bbc_get_param(const bbc_context* ctx, int param, int64_t* value);
+
 #ifdef __cplusplus
 }
 #endif

@@ -38,6 +38,8 @@ INTERNAL = -10
 
 INPUT_ON_DEVICE = 1
 PER_VERTEX = 4
+PARAM_HASH_TARGET = 1
+PARAM_PROBE_LIMIT = 2
 
 PHASE_TOTAL, PHASE_PREP, PHASE_WEDGE, PHASE_PLAN = 0, 1, 2, 3
 
@@ -99,6 +101,10 @@ def load_library():
     lib.bbc_last_phase_ms.restype = ctypes.c_int
     lib.bbc_last_stats.argtypes = [P, ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
     lib.bbc_last_stats.restype = ctypes.c_int
+    lib.bbc_set_param.argtypes = [P, ctypes.c_int, I64]
+    lib.bbc_set_param.restype = ctypes.c_int
+    lib.bbc_get_param.argtypes = [P, ctypes.c_int, ctypes.POINTER(ctypes.c_int64)]
+    lib.bbc_get_param.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -177,6 +183,18 @@ class Context:
 
     def __exit__(self, *exc):
         self.close()
+
+    def set_param(self, param: int, value: int):
+        rc = self._lib.bbc_set_param(self._h, int(param), int(value))
+        if rc != OK:
+            raise BBCError(rc, f"parameter {param} = {value} rejected")
+
+    def get_param(self, param: int) -> int:
+        v = ctypes.c_int64()
+        rc = self._lib.bbc_get_param(self._h, int(param), ctypes.byref(v))
+        if rc != OK:
+            raise BBCError(rc, f"unknown parameter {param}")
+        return int(v.value)
 
     def set_timing(self, on: bool = True):
         self._lib.bbc_set_timing(self._h, 1 if on else 0)

@@ -72,6 +72,8 @@ struct bbc_context {
     bool timing_valid = false;
     float phase_ms[4] = {0, 0, 0, 0};
     int64_t stats[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    uint32_t hash_target = bbc::kDefaultHashTarget;
+    uint32_t probe_limit = bbc::kDefaultProbeLimit;
     char err[512] = {0};
 };
 
@@ -310,6 +312,31 @@ bbc_status bbc_set_timing(bbc_context* c, int enabled) {
     return BBC_OK;
 }
 
+bbc_status bbc_set_param(bbc_context* c, int param, int64_t value) {
+    if (!c) return BBC_ERR_INVALID_ARG;
+    switch (param) {
+    case BBC_PARAM_HASH_TARGET:
+        if (value < 64 || value > (1 << 20)) return BBC_ERR_INVALID_ARG;
+        c->hash_target = (uint32_t)value;
+        return BBC_OK;
+    case BBC_PARAM_PROBE_LIMIT:
+        if (value < 1 || value > (int64_t)bbc::kHashSlots) return BBC_ERR_INVALID_ARG;
+        c->probe_limit = (uint32_t)value;
+        return BBC_OK;
+    default:
+        return BBC_ERR_INVALID_ARG;
+    }
+}
+
+bbc_status bbc_get_param(const bbc_context* c, int param, int64_t* value) {
+    if (!c || !value) return BBC_ERR_INVALID_ARG;
+    switch (param) {
+    case BBC_PARAM_HASH_TARGET: *value = c->hash_target; return BBC_OK;
+    case BBC_PARAM_PROBE_LIMIT: *value = c->probe_limit; return BBC_OK;
+    default: return BBC_ERR_INVALID_ARG;
+    }
+}
+
 bbc_status bbc_last_phase_ms(const bbc_context* c, int phase, double* ms) {
     if (!c || !ms || phase < 0 || phase > 3 || !c->timing_valid) return BBC_ERR_INVALID_ARG;
     *ms = c->phase_ms[phase];
@@ -368,6 +395,8 @@ bbc_status bbc_count(bbc_context* c, int32_t n_u, int32_t n_v, int64_t n_edges,
     // rows of side Y with more than kLongDeg entries: at most m / (kLongDeg + 1) per side
     uint64_t maxlong0 = std::min<uint64_t>(nu, m / (kLongDeg + 1));
     uint64_t maxlong1 = std::min<uint64_t>(nv, m / (kLongDeg + 1));
+    d.hash_target = c->hash_target;
+    d.probe_limit = c->probe_limit;
     d.tb_off[0] = 0;
     d.tb_off[1] = maxlong0 * (d.ntile[1] + 1);
     uint64_t tb_total = d.tb_off[1] + maxlong1 * (d.ntile[0] + 1);

@@ -50,7 +50,8 @@ constexpr uint32_t kMinRegion = 64;
 constexpr uint32_t kMaxItemPieces = (2 * kLightWindow) / kMinRegion + 1;
 constexpr uint32_t kTile = 16384;             // end-vertex tile width (sidx units)
 constexpr u64 kRecordChunkWedges = 65536;     // wedges per record chunk of a small-side start
-constexpr double kHashTarget = 4096.0;       // expected wedges per hashed run of tiles
+constexpr uint32_t kDefaultHashTarget = 4096;   // expected wedges per hashed run of tiles
+constexpr uint32_t kDefaultProbeLimit = 256;    // probes before a split hashed piece gives up
 
 // piece flags
 constexpr uint32_t kPieceDense = 1u;    // counters addressed by w - lo (else hashed)
@@ -101,6 +102,8 @@ struct Dims {
     uint32_t size[2];   // vertices per side
     uint32_t ntile[2];  // ceil(size[s] / kTile): tiles over side s's sidx space
     uint64_t tb_off[2]; // tile-table offset for rows of side s (entries index the other side)
+    uint32_t hash_target;  // planner: expected wedges per hashed tile run
+    uint32_t probe_limit;  // wedge kernel: probes before a split hashed piece is halved
 };
 
 // ---- small device helpers ---------------------------------------------------

@@ -18,11 +18,13 @@
 //   * else:   the end-vertex space is cut into tiles of kTile.  The wedges of u
 //             are estimated per tile in proportion to the tile's degree mass
 //             (an end vertex is reached through its edges).  A tile expected to
-//             hold more than kHashTarget wedges becomes one dense piece (its
-//             counters always fit); runs of lighter tiles are packed greedily
-//             into hashed pieces of at most kHashTarget expected wedges.  A
-//             hashed piece that overflows anyway is redone by the wedge kernel
-//             in halves.
+//             hold more than the hash target (a tunable, default 4096) wedges
+//             becomes one dense piece (its counters always fit); runs of
+//             lighter tiles are packed greedily into hashed pieces of at most
+//             that many expected wedges.  A hashed piece that overflows anyway
+//             is redone by the wedge kernel in halves.  The decisions use exact
+//             integer arithmetic so that the counting and the writing pass
+//             plan identically.
 //
 // A start cut into tile pieces ("split start") visits its records once per
 // piece.  Records through a long middle row find their sub-interval of a tile
@@ -52,41 +54,44 @@ __device__ inline uint32_t cost_key(double wedges, uint32_t nrec) {
 
 // Tile runs of a start with end-vertex space [0, S) on the side whose rows start
 // at `base`; calls emit(t0, t1, dense, expected wedges) per run and returns the
-// number of runs.
+// number of runs.  A tile of degree mass x is expected to hold W * x / tot
+// wedges; "more than target" is tested exactly as x * W > target * tot.
 template <typename F>
 __device__ uint32_t plan_runs(const uint32_t* __restrict__ row_ptr, uint32_t base, uint32_t S,
-                              u64 W, F emit) {
+                              u64 W, uint32_t target, F emit) {
+    using u128 = unsigned __int128;
     const uint32_t T = (S + kTile - 1) / kTile;
-    const double tot = (double)(row_ptr[base + S] - row_ptr[base]);
-    const double scale = tot > 0 ? (double)W / tot : 0.0;
+    const u64 tot = row_ptr[base + S] - row_ptr[base];
+    const u128 lim = (u128)target * tot;
+    auto est = [&](u64 x) { return tot > 0 ? (double)x * (double)W / (double)tot : 0.0; };
     uint32_t n = 0, rs = kNoTile;
-    double re = 0;
+    u64 rx = 0;  // degree mass of the open run
     for (uint32_t t = 0; t < T; ++t) {
         const uint32_t lo = t * kTile, hi = min(S, lo + kTile);
-        const double e = (double)(row_ptr[base + hi] - row_ptr[base + lo]) * scale;
-        if (e > kHashTarget) {
+        const u64 x = row_ptr[base + hi] - row_ptr[base + lo];
+        if ((u128)x * W > lim) {
             if (rs != kNoTile) {
-                emit(rs, t, false, re);
+                emit(rs, t, false, est(rx));
                 ++n;
                 rs = kNoTile;
             }
-            emit(t, t + 1, true, e);
+            emit(t, t + 1, true, est(x));
             ++n;
-        } else if (rs != kNoTile && re + e > kHashTarget) {
-            emit(rs, t, false, re);
+        } else if (rs != kNoTile && (u128)(rx + x) * W > lim) {
+            emit(rs, t, false, est(rx));
             ++n;
             rs = t;
-            re = e;
+            rx = x;
         } else {
             if (rs == kNoTile) {
                 rs = t;
-                re = 0;
+                rx = 0;
             }
-            re += e;
+            rx += x;
         }
     }
     if (rs != kNoTile) {
-        emit(rs, T, false, re);
+        emit(rs, T, false, est(rx));
         ++n;
     }
     return n;
@@ -119,11 +124,15 @@ __device__ inline StartPlan plan_start(const uint32_t* __restrict__ row_ptr, con
     const uint32_t T = (S + kTile - 1) / kTile;
     bool whole = false;
     sp.cls = kClassTiles;
-    sp.pieces = plan_runs(row_ptr, d.base[side], S, W,
+    sp.pieces = plan_runs(row_ptr, d.base[side], S, W, d.hash_target,
                           [&](uint32_t t0, uint32_t t1, bool dense, double) {
                               whole = whole || (t0 == 0 && t1 == T && !dense);
                           });
-    sp.tiles = whole ? 0u : T;  // one hashed run over everything: not split
+    // One hashed run over everything is left unsplit only when its W wedges
+    // cannot fill the table (at most W distinct ends); otherwise it keeps its
+    // tiles so that an overflowing run can be halved.
+    whole = whole && W <= kHashSlots / 2;
+    sp.tiles = whole ? 0u : T;
     return sp;
 }
 
@@ -211,7 +220,7 @@ __global__ void k_plan_write(const u64* __restrict__ wu, const uint32_t* __restr
         const bool split = sp.tiles > 0;
         const uint32_t nlong = front[r] - m0;
         uint32_t i = 0;
-        plan_runs(row_ptr, d.base[side], S, W, [&](uint32_t t0, uint32_t t1, bool dense, double est) {
+        plan_runs(row_ptr, d.base[side], S, W, d.hash_target, [&](uint32_t t0, uint32_t t1, bool dense, double est) {
             if (i >= h) return;
             Piece p;
             p.rec0 = m0;

@@ -45,7 +45,6 @@ struct WedgeArgs {
 constexpr uint32_t kScanMax = 16;     // short middle prefixes are read whole and filtered
 constexpr uint32_t kUnroll = 4;       // independent CSR loads in flight per lane
 constexpr uint32_t kWaves = kWedgeThreads / 64;
-constexpr uint32_t kProbeLimit = 256; // heavy hashed pieces give up after this many probes
 constexpr uint32_t kStack = 16;       // pending halves of an abandoned piece
 constexpr uint32_t kChunk = 2048;     // longer sub-intervals are cut; the tail chunks are
 constexpr uint32_t kQueue = 256;      // queued in LDS and shared by all waves afterwards
@@ -152,7 +151,10 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
             const bool dense = (s_pc[0].flags & kPieceDense) != 0;
             const uint32_t dlo = s_pc[0].lo;
             const uint32_t dwidth = s_pc[0].hi - s_pc[0].lo;
-            const uint32_t lim0 = heavy ? kProbeLimit : kHashSlots;
+            // a split piece may give up early (it is halved and redone); an
+            // unsplit one holds at most kHashSlots/2 distinct ends and probes on
+            const uint32_t lim0 =
+                (heavy && (s_pc[0].flags & kPiecePartial)) ? a.d.probe_limit : kHashSlots;
             const uint32_t plo0 = s_pc[0].lo, phi0 = s_pc[0].hi, region0 = s_pc[0].region;
             if (dense) {
                 for (uint32_t i = tid; i < dwidth; i += kWedgeThreads) s_tab[i] = 0;
@@ -288,23 +290,27 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
                             atomicAdd(&s_tab[w - dlo], ((x[u] ^ aux[u]) & 1u) ? (1ull << 32) : 1ull);
                         }
                     } else if (np == 1) {
+                        bool lok = true;
 #pragma unroll 1
                         for (uint32_t u = 0; u < kUnroll; ++u) {
-                            if (aux[u] == kEmpty || !ok) continue;
+                            if (aux[u] == kEmpty || !lok) continue;
                             const uint32_t w = x[u] >> 1;
                             if ((aux[u] & 2u) && (w < plo0 || w >= phi0)) continue;
-                            ok = bucket_add(s_tab, keys, hvals, false, 0, region0, lim0, w,
-                                            ((x[u] ^ aux[u]) & 1u) ? (1ull << 32) : 1ull);
+                            lok = bucket_add(s_tab, keys, hvals, false, 0, region0, lim0, w,
+                                             ((x[u] ^ aux[u]) & 1u) ? (1ull << 32) : 1ull);
                         }
+                        ok = __ballot(!lok) == 0;  // the whole wave leaves together
                     } else {
+                        bool lok = true;
 #pragma unroll 1
                         for (uint32_t u = 0; u < kUnroll; ++u) {
-                            if (aux[u] == kEmpty || !ok) continue;
+                            if (aux[u] == kEmpty || !lok) continue;
                             const uint32_t region = s_pc[aux[u] >> 2].region;
                             const uint32_t lim = 1u << ((region >> 16) & 31u);
-                            ok = bucket_add(s_tab, keys, hvals, false, 0, region, lim, x[u] >> 1,
-                                            ((x[u] ^ aux[u]) & 1u) ? (1ull << 32) : 1ull);
+                            lok = bucket_add(s_tab, keys, hvals, false, 0, region, lim, x[u] >> 1,
+                                             ((x[u] ^ aux[u]) & 1u) ? (1ull << 32) : 1ull);
                         }
+                        ok = __ballot(!lok) == 0;
                     }
                 }
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -327,17 +333,19 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
                             const uint32_t e = e0 + u * 64 + lane;
                             x[u] = e < qlen ? col[adj + e] : kEmpty;
                         }
+                        bool lok = true;
 #pragma unroll
                         for (uint32_t u = 0; u < kUnroll; ++u) {
-                            if (x[u] == kEmpty || !ok) continue;
+                            if (x[u] == kEmpty || !lok) continue;
                             const uint32_t w = x[u] >> 1;
                             if ((aux & 2u) && (w < plo0 || w >= phi0)) continue;
                             const u64 inc = ((x[u] ^ aux) & 1u) ? (1ull << 32) : 1ull;
                             if (dense)
                                 atomicAdd(&s_tab[w - dlo], inc);
                             else
-                                ok = bucket_add(s_tab, keys, hvals, false, 0, region0, lim0, w, inc);
+                                lok = bucket_add(s_tab, keys, hvals, false, 0, region0, lim0, w, inc);
                         }
+                        ok = __ballot(!lok) == 0;  // wave-uniform: lane 0 keeps taking chunks
                     }
                 }
                 if (!ok) s_abort = 1;

@@ -46,6 +46,12 @@ def test_create_argument_checks(lib):
     lib.bbc_destroy(None)  # NULL-safe
 
 
+def test_param_calls_reject_null_context(lib):
+    v = ctypes.c_int64()
+    assert lib.bbc_set_param(None, 1, 4096) == bbc.INVALID_ARG
+    assert lib.bbc_get_param(None, 1, ctypes.byref(v)) == bbc.INVALID_ARG
+
+
 def test_no_device_reports_device_error(lib):
     import torch
     if torch.cuda.is_available():

@@ -154,6 +154,41 @@ def test_resplit_path(ctx):
     assert ctx.stats()[5] > 0, "expected a hashed piece to be redone"
 
 
+def test_forced_resplits_stay_exact(ctx):
+    # A probe limit of a few slots makes nearly every hashed piece of a heavy
+    # start overflow, so the halving and dense-redo paths run thousands of
+    # times, interleaved with normal pieces on the same workgroups.  A smaller
+    # and a larger hash target change the piece layout itself.
+    g = gen.chung_lu_graph(seed=21, n_u=200000, n_v=60000, n_edges=1500000, alpha=2.1, p_neg=0.2)
+    want = expect(g)
+    base = run(ctx, g)
+    assert base == want
+    try:
+        for target, probes in ((4096, 4), (8192, 4), (512, 2), (65536, 256)):
+            ctx.set_param(bbc.PARAM_HASH_TARGET, target)
+            ctx.set_param(bbc.PARAM_PROBE_LIMIT, probes)
+            for _ in range(2):
+                got = run(ctx, g)
+                assert got == want, (target, probes, got, want)
+            if probes <= 4:
+                assert ctx.stats()[5] > 100, (target, probes, ctx.stats())
+    finally:
+        ctx.set_param(bbc.PARAM_HASH_TARGET, 4096)
+        ctx.set_param(bbc.PARAM_PROBE_LIMIT, 256)
+
+
+def test_param_checks(ctx):
+    assert ctx.get_param(bbc.PARAM_HASH_TARGET) == 4096
+    assert ctx.get_param(bbc.PARAM_PROBE_LIMIT) == 256
+    for p, v in ((bbc.PARAM_HASH_TARGET, 63), (bbc.PARAM_HASH_TARGET, (1 << 20) + 1),
+                 (bbc.PARAM_PROBE_LIMIT, 0), (bbc.PARAM_PROBE_LIMIT, 8193), (99, 1)):
+        with pytest.raises(bbc.BBCError):
+            ctx.set_param(p, v)
+    assert ctx.get_param(bbc.PARAM_HASH_TARGET) == 4096
+    with pytest.raises(bbc.BBCError):
+        ctx.get_param(99)
+
+
 def test_full_workloads_match_golden(ctx):
     gold = json.load(open(os.path.join(GOLDEN, "workloads.json")))
     for name in ("uniform", "voting", "powerlaw"):
@@ -165,6 +200,16 @@ def test_full_workloads_match_golden(ctx):
         assert g.n_edges == want["n_edges"] and int(np.sum(g.sign < 0)) == want["negative_edges"]
         assert (r.balanced, r.unbalanced, r.wedges) == (want["balanced"], want["unbalanced"],
                                                         want["wedges"]), name
+    # the full power-law graph again with nearly every hashed piece redone
+    g = gen.workload("powerlaw")
+    ctx.set_param(bbc.PARAM_PROBE_LIMIT, 4)
+    try:
+        r = run(ctx, g)
+        assert ctx.stats()[5] > 1000
+    finally:
+        ctx.set_param(bbc.PARAM_PROBE_LIMIT, 256)
+    want = gold["powerlaw"]
+    assert (r.balanced, r.unbalanced, r.wedges) == (want["balanced"], want["unbalanced"], want["wedges"])
 
 
 def test_device_input_and_determinism(ctx):
