@@ -93,6 +93,43 @@ bbc_status bbc_count(bbc_context* ctx, int32_t n_u, int32_t n_v, int64_t n_edges
                      const int32_t* edge_u, const int32_t* edge_v, const int8_t* edge_sign,
                      uint32_t flags, bbc_result* out, int64_t* per_vertex);
 
+/*
+ * Count many independent graphs in one call (the batched workload).
+ *
+ * Graph g has vertex sets {0..n_u[g]-1} and {0..n_v[g]-1} and the edges
+ * i = edge_offset[g] .. edge_offset[g+1]-1 of the concatenated arrays
+ * edge_u / edge_v / edge_sign (ids local to the graph, layout as in
+ * bbc_count).  edge_offset has n_graphs + 1 non-decreasing entries.  The size
+ * arrays and edge_offset are host memory; the edge arrays are host memory, or
+ * device memory with BBC_INPUT_ON_DEVICE.  Only BBC_INPUT_ON_DEVICE is
+ * accepted in flags.
+ *
+ * Every butterfly lies inside one graph, and the method counts it once at its
+ * vertex of highest priority (Theorem 1), so the batch is counted as one
+ * disjoint union: one relabel and CSR build over all graphs, one planner pass
+ * and one persistent wedge-kernel launch whose work items are drawn from all
+ * graphs, with totals kept per graph.  The priority inside each graph is the
+ * same as in bbc_count, so out[g] equals what bbc_count returns for graph g
+ * alone, W included.  Graphs with more than 16384 vertices on a side are
+ * counted one at a time inside the call.
+ *
+ * Outputs (host, n_graphs entries each): status[g] is the bbc_status graph g
+ * would get from bbc_count (VERTEX_RANGE, BAD_SIGN, DUPLICATE_EDGE,
+ * TOO_LARGE, INVALID_ARG for a negative size, OVERFLOW, OUT_OF_MEMORY);
+ * out[g] holds its counts when status[g] == BBC_OK and zeros otherwise.  An
+ * invalid graph does not disturb the others.
+ *
+ * The call returns BBC_OK when every graph got a status, or a call-level error
+ * (INVALID_ARG for NULL arrays / decreasing offsets / unknown flags,
+ * OUT_OF_MEMORY, DEVICE, INTERNAL) with the outputs unspecified.
+ * bbc_last_phase_ms and bbc_last_stats then describe the whole call (sums
+ * over its internal passes).
+ */
+bbc_status bbc_count_batch(bbc_context* ctx, int32_t n_graphs, const int32_t* n_u,
+                           const int32_t* n_v, const int64_t* edge_offset, const int32_t* edge_u,
+                           const int32_t* edge_v, const int8_t* edge_sign, uint32_t flags,
+                           bbc_result* out, int32_t* status);
+
 /* Static description of a status code (never NULL). */
 const char* bbc_status_string(bbc_status status);
 
@@ -138,11 +175,17 @@ bbc_status bbc_last_stats(const bbc_context* ctx, int64_t* stats, int n);
  *   BBC_PARAM_PROBE_LIMIT  hash probes a heavy start's hashed piece tries
  *                          before it gives up; the piece is then redone in
  *                          halves (or densely).  Default 256, range [1, 8192].
+ *   BBC_PARAM_CHUNK_WEDGES least wedges per record chunk when a start with a
+ *                          small end-vertex range is split over several
+ *                          workgroups (partial counts merged exactly by
+ *                          C(a+b,2) = C(a,2) + C(b,2) + ab); the chunk is also
+ *                          at least W / 2048.  Default 65536, range
+ *                          [1024, 2^40].
  * bbc_set_param returns BBC_ERR_INVALID_ARG for a NULL context, an unknown
  * parameter or a value out of range (the setting is then unchanged);
  * bbc_get_param writes the current value to *value.
  */
-enum { BBC_PARAM_HASH_TARGET = 1, BBC_PARAM_PROBE_LIMIT = 2 };
+enum { BBC_PARAM_HASH_TARGET = 1, BBC_PARAM_PROBE_LIMIT = 2, BBC_PARAM_CHUNK_WEDGES = 3 };
 bbc_status bbc_set_param(bbc_context* ctx, int param, int64_t value);
 bbc_status bbc_get_param(const bbc_context* ctx, int param, int64_t* value);
 

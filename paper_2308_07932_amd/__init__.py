@@ -40,6 +40,7 @@ INPUT_ON_DEVICE = 1
 PER_VERTEX = 4
 PARAM_HASH_TARGET = 1
 PARAM_PROBE_LIMIT = 2
+PARAM_CHUNK_WEDGES = 3
 
 PHASE_TOTAL, PHASE_PREP, PHASE_WEDGE, PHASE_PLAN = 0, 1, 2, 3
 
@@ -105,6 +106,8 @@ def load_library():
     lib.bbc_set_param.restype = ctypes.c_int
     lib.bbc_get_param.argtypes = [P, ctypes.c_int, ctypes.POINTER(ctypes.c_int64)]
     lib.bbc_get_param.restype = ctypes.c_int
+    lib.bbc_count_batch.argtypes = [P, I32, P, P, P, P, P, P, U32, P, P]
+    lib.bbc_count_batch.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -244,6 +247,63 @@ class Context:
         r = self.count_raw(n_u, n_v, n, *ptrs, flags=flags, per_vertex_ptr=pv_ptr)
         del keep
         return (r, pv) if per_vertex else r
+
+    def count_batch(self, n_u, n_v, edge_offset, eu, ev, sign) -> "BatchResult":
+        """Count many graphs in one call (bbc_count_batch): n_u, n_v (n_graphs
+        entries), edge_offset (n_graphs + 1) and the concatenated local-id edge
+        arrays (numpy, or torch CUDA tensors).  Returns a BatchResult."""
+        return _count_batch(self, n_u, n_v, edge_offset, eu, ev, sign)
+
+
+class BatchResult(NamedTuple):
+    """Per-graph outputs of count_batch (numpy arrays of length n_graphs)."""
+    balanced: np.ndarray
+    unbalanced: np.ndarray
+    wedges: np.ndarray
+    status: np.ndarray
+
+    def result(self, g: int) -> Result:
+        return Result(int(self.balanced[g]), int(self.unbalanced[g]), int(self.wedges[g]))
+
+
+def concat_graphs(graphs):
+    """Concatenate graphs (objects with n_u, n_v, eu, ev, sign) into the batch
+    layout: (n_u, n_v, edge_offset, eu, ev, sign) as numpy arrays."""
+    nu = np.array([g.n_u for g in graphs], dtype=np.int32)
+    nv = np.array([g.n_v for g in graphs], dtype=np.int32)
+    lens = np.array([len(g.eu) for g in graphs], dtype=np.int64)
+    off = np.zeros(len(graphs) + 1, dtype=np.int64)
+    np.cumsum(lens, out=off[1:])
+    cat = (lambda xs, dt: np.concatenate([np.asarray(x, dtype=dt) for x in xs])
+           if len(xs) else np.zeros(0, dtype=dt))
+    return (nu, nv, off, cat([g.eu for g in graphs], np.int32), cat([g.ev for g in graphs], np.int32),
+            cat([g.sign for g in graphs], np.int8))
+
+
+def _count_batch(ctx, n_u, n_v, edge_offset, eu, ev, sign) -> BatchResult:
+    nu = np.ascontiguousarray(n_u, dtype=np.int32)
+    nv = np.ascontiguousarray(n_v, dtype=np.int32)
+    off = np.ascontiguousarray(edge_offset, dtype=np.int64)
+    G = int(nu.shape[0])
+    if nv.shape[0] != G or off.shape[0] != G + 1:
+        raise ValueError("n_u and n_v need n_graphs entries and edge_offset n_graphs + 1")
+    ptrs, keep, on_dev, n = _prepare(eu, ev, sign)
+    if G and int(off[-1]) > n:
+        raise ValueError("edge_offset points past the edge arrays")
+    if on_dev:
+        import torch
+        cur = torch.cuda.current_stream(keep[0].device)
+        if ctx.stream is None or int(cur.cuda_stream) != int(ctx.stream):
+            cur.synchronize()
+    out = (_CResult * max(G, 1))()
+    st = np.zeros(max(G, 1), dtype=np.int32)
+    rc = ctx._lib.bbc_count_batch(ctx._h, G, nu.ctypes.data, nv.ctypes.data, off.ctypes.data,
+                                  *ptrs, INPUT_ON_DEVICE if on_dev else 0, out, st.ctypes.data)
+    del keep
+    if rc != OK:
+        raise BBCError(rc, ctx.last_error() or status_string(rc))
+    arr = np.frombuffer(out, dtype=np.int64).reshape(-1, 3)[:G]
+    return BatchResult(arr[:, 0].copy(), arr[:, 1].copy(), arr[:, 2].copy(), st[:G].copy())
 
 
 _default: dict[int, Context] = {}

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbbc.so")
-SOURCES = ["scan.hip", "prep.hip", "plan.hip", "wedge.hip", "api.hip"]
+SOURCES = ["scan.hip", "prep.hip", "plan.hip", "wedge.hip", "batch.hip", "api.hip"]
 ARCH = os.environ.get("BBC_OFFLOAD_ARCH", "gfx950")
 
 
@@ -47,7 +47,7 @@ def build(verbose: bool = False, jobs: int = 0) -> str:
     if failed:
         raise RuntimeError(f"hipcc failed for {failed}")
     tmp = LIB + ".tmp"
-    link = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
+    link = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-Wl,--no-undefined", *objs, "-o", tmp]
     if verbose:
         print(" ".join(link), flush=True)
     subprocess.check_call(link)

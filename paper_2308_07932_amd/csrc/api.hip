@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <vector>
 
 #include "bbc.h"
 #include "bbc_internal.h"
@@ -32,19 +33,25 @@ hipError_t launch_tile_table(const uint32_t*, const uint32_t*, Dims, const Contr
                              uint32_t, hipStream_t);
 hipError_t launch_plan_count(const u64*, const u64*, const uint32_t*, const uint32_t*, Dims,
                              uint32_t*, u64*, uint32_t*, uint32_t*, uint32_t*, u64*, u64*, u64*,
-                             hipStream_t);
+                             Control*, hipStream_t);
 hipError_t launch_gather_totals(const uint32_t*, const u64*, const uint32_t*, const uint32_t*,
                                 const uint32_t*, const u64*, uint32_t, Control*, hipStream_t);
 hipError_t launch_plan_write(const u64*, const uint32_t*, const uint32_t*, const uint32_t*,
                              const uint32_t*, const uint32_t*, const u64*, const uint32_t*,
                              const uint32_t*, const uint32_t*, Dims, uint32_t, Piece*, u64*,
-                             uint32_t*, uint32_t*, uint32_t, uint32_t, uint32_t*, hipStream_t);
+                             uint32_t*, uint32_t*, uint32_t, uint32_t, uint32_t*, const Control*,
+                             hipStream_t);
 hipError_t launch_short_wedges(const uint4*, uint32_t, const uint32_t*, const uint32_t*,
                                const uint32_t*, const uint32_t*, const uint32_t*, const uint32_t*,
                                const uint32_t*, uint32_t*, uint32_t*, uint32_t*, bool, hipStream_t);
 hipError_t launch_wedge(const Piece*, const uint32_t*, const uint32_t*, uint32_t, uint32_t,
                         const uint4*, const uint32_t*, const uint32_t*, Dims, const uint32_t[2], u64*,
-                        const uint32_t*, const uint32_t*, Control*, uint32_t, hipStream_t);
+                        const uint32_t*, const uint32_t*, Control*, u64*, uint32_t, hipStream_t);
+hipError_t launch_ingest(const IngestArgs&, hipStream_t);
+hipError_t launch_batch_keys(const uint32_t*, Dims, uint32_t, uint32_t*, hipStream_t);
+hipError_t launch_dup_graphs(const uint32_t*, const uint32_t*, Dims, const Control*, hipStream_t);
+hipError_t launch_row_keys(const uint32_t*, Dims, uint32_t, uint32_t*, hipStream_t);
+hipError_t launch_graph_wedges(const u64*, Dims, u64*, hipStream_t);
 }  // namespace bbc
 
 using namespace bbc;
@@ -65,15 +72,16 @@ struct bbc_context {
     bool own_stream = false;
     uint32_t num_cus = 0;
     size_t budget = 0;  // 0 = unlimited
-    Arena prep, plan;
+    Arena prep, plan, batch;
     Control* host_ctl = nullptr;  // pinned
     hipEvent_t ev[kNumEv] = {};
     bool timing = false;
     bool timing_valid = false;
-    float phase_ms[4] = {0, 0, 0, 0};
+    double phase_ms[4] = {0, 0, 0, 0};
     int64_t stats[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     uint32_t hash_target = bbc::kDefaultHashTarget;
     uint32_t probe_limit = bbc::kDefaultProbeLimit;
+    uint64_t chunk_min = bbc::kRecordChunkWedges;
     char err[512] = {0};
 };
 
@@ -94,7 +102,9 @@ static bbc_status fail(bbc_context* c, bbc_status s, const char* fmt, ...) {
 
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
-static size_t total_reserved(const bbc_context* c) { return c->prep.cap + c->plan.cap; }
+static size_t total_reserved(const bbc_context* c) {
+    return c->prep.cap + c->plan.cap + c->batch.cap;
+}
 
 static bbc_status arena_reserve(bbc_context* c, Arena& a, size_t bytes) {
     if (bytes <= a.cap) return BBC_OK;
@@ -298,6 +308,7 @@ void bbc_destroy(bbc_context* c) {
     if (c->stream) hipStreamSynchronize(c->stream);
     if (c->prep.base) hipFree(c->prep.base);
     if (c->plan.base) hipFree(c->plan.base);
+    if (c->batch.base) hipFree(c->batch.base);
     if (c->host_ctl) hipHostFree(c->host_ctl);
     for (int i = 0; i < kNumEv; ++i)
         if (c->ev[i]) hipEventDestroy(c->ev[i]);
@@ -323,6 +334,10 @@ bbc_status bbc_set_param(bbc_context* c, int param, int64_t value) {
         if (value < 1 || value > (int64_t)bbc::kHashSlots) return BBC_ERR_INVALID_ARG;
         c->probe_limit = (uint32_t)value;
         return BBC_OK;
+    case BBC_PARAM_CHUNK_WEDGES:
+        if (value < 1024 || value > (1ll << 40)) return BBC_ERR_INVALID_ARG;
+        c->chunk_min = (uint64_t)value;
+        return BBC_OK;
     default:
         return BBC_ERR_INVALID_ARG;
     }
@@ -333,6 +348,7 @@ bbc_status bbc_get_param(const bbc_context* c, int param, int64_t* value) {
     switch (param) {
     case BBC_PARAM_HASH_TARGET: *value = c->hash_target; return BBC_OK;
     case BBC_PARAM_PROBE_LIMIT: *value = c->probe_limit; return BBC_OK;
+    case BBC_PARAM_CHUNK_WEDGES: *value = (int64_t)c->chunk_min; return BBC_OK;
     default: return BBC_ERR_INVALID_ARG;
     }
 }
@@ -348,39 +364,47 @@ bbc_status bbc_last_stats(const bbc_context* c, int64_t* stats, int n) {
     for (int i = 0; i < n && i < 8; ++i) stats[i] = c->stats[i];
     return BBC_OK;
 }
+}  // extern "C"
 
-bbc_status bbc_count(bbc_context* c, int32_t n_u, int32_t n_v, int64_t n_edges,
-                     const int32_t* edge_u, const int32_t* edge_v, const int8_t* edge_sign,
-                     uint32_t flags, bbc_result* out, int64_t* per_vertex) {
-    if (!c) return BBC_ERR_INVALID_ARG;
-    c->err[0] = 0;
-    c->timing_valid = false;
-    if (!out) return fail(c, BBC_ERR_INVALID_ARG, "out is NULL");
-    if (n_u < 0 || n_v < 0 || n_edges < 0)
-        return fail(c, BBC_ERR_INVALID_ARG, "negative size (n_u=%d n_v=%d n_edges=%lld)", n_u, n_v,
-                    (long long)n_edges);
-    if (flags & ~(uint32_t)(BBC_INPUT_ON_DEVICE | BBC_PER_VERTEX))
-        return fail(c, BBC_ERR_INVALID_ARG, "unknown flag bits 0x%x", flags);
-    if (n_edges > 0 && (!edge_u || !edge_v || !edge_sign))
-        return fail(c, BBC_ERR_INVALID_ARG, "NULL edge array with n_edges=%lld", (long long)n_edges);
-    if (flags & BBC_PER_VERTEX) {
-        if (!per_vertex) return fail(c, BBC_ERR_INVALID_ARG, "BBC_PER_VERTEX without per_vertex buffer");
-        return fail(c, BBC_ERR_NOT_IMPLEMENTED, "per-vertex counts are not built");
-    }
-    const uint64_t n64 = (uint64_t)n_u + (uint64_t)n_v;
-    if (n64 >= (1ull << 30)) return fail(c, BBC_ERR_TOO_LARGE, "n_u + n_v = %llu >= 2^30", (unsigned long long)n64);
-    if ((uint64_t)n_edges >= (1ull << 31))
-        return fail(c, BBC_ERR_TOO_LARGE, "n_edges = %lld >= 2^31", (long long)n_edges);
-    if (n_edges == 0) {
-        out->balanced = out->unbalanced = out->wedges = 0;
-        memset(c->stats, 0, sizeof(c->stats));
-        return BBC_OK;
-    }
-    HIPCHECK(c, hipSetDevice(c->device));
+// ---------------------------------------------------------------------------
+// One run of the counting pipeline over a graph, or over the union graph of a
+// batch, whose edges are on the device (or on the host with copy_in).
+
+struct BatchDev {
+    uint32_t n_graphs;
+    uint32_t max_side;       // largest |U| or |V| of a graph (bounds the degrees)
+    const uint32_t* blk[2];  // device: sidx block starts per side (n_graphs + 1)
+    u64* gres;               // device: per graph {balanced, unbalanced, wedges, -}
+    u64* gerr;               // device: per graph first bad edge << 4 | code, ~0 if none
+};
+
+struct RunIn {
+    uint32_t nu, nv;
+    uint64_t m;
+    const int32_t* eu;
+    const int32_t* ev;
+    const int8_t* sg;
+    bool copy_in;            // eu/ev/sg are host pointers
+    const BatchDev* bt;      // NULL: one graph
+    const IngestArgs* ingest;  // batches: fills eu/ev/sg first (reports into the control block)
+};
+
+struct RunOut {
+    Control h;               // the control block after the run
+    bool input_error;        // stopped after the input checks (h.edge_err / h.dup)
+    uint32_t n_items, n_heavy;
+    uint32_t n;
+};
+
+static bbc_status run_pipeline(bbc_context* c, const RunIn& in, RunOut& ro) {
     hipStream_t st = c->stream;
-    const uint32_t n = (uint32_t)n64, nu = (uint32_t)n_u, nv = (uint32_t)n_v;
-    const uint64_t m = (uint64_t)n_edges;
-    const bool copy_in = !(flags & BBC_INPUT_ON_DEVICE);
+    const uint32_t nu = in.nu, nv = in.nv, n = nu + nv;
+    const uint64_t m = in.m;
+    const bool copy_in = in.copy_in;
+    const BatchDev* bt = in.bt;
+    ro.input_error = false;
+    ro.n_items = ro.n_heavy = 0;
+    ro.n = n;
 
     Dims d;
     d.n_u = nu;
@@ -392,14 +416,21 @@ bbc_status bbc_count(bbc_context* c, int32_t n_u, int32_t n_v, int64_t n_edges,
     d.size[1] = nv;
     d.ntile[0] = (nu + kTile - 1) / kTile;
     d.ntile[1] = (nv + kTile - 1) / kTile;
+    d.hash_target = c->hash_target;
+    d.probe_limit = c->probe_limit;
+    d.chunk_min = c->chunk_min;
+    d.n_graphs = bt ? bt->n_graphs : 1u;
+    d.blk[0] = bt ? bt->blk[0] : nullptr;
+    d.blk[1] = bt ? bt->blk[1] : nullptr;
+    d.gerr = bt ? bt->gerr : nullptr;
+    d.rlist = nullptr;
     // rows of side Y with more than kLongDeg entries: at most m / (kLongDeg + 1) per side
     uint64_t maxlong0 = std::min<uint64_t>(nu, m / (kLongDeg + 1));
     uint64_t maxlong1 = std::min<uint64_t>(nv, m / (kLongDeg + 1));
-    d.hash_target = c->hash_target;
-    d.probe_limit = c->probe_limit;
     d.tb_off[0] = 0;
     d.tb_off[1] = maxlong0 * (d.ntile[1] + 1);
     uint64_t tb_total = d.tb_off[1] + maxlong1 * (d.ntile[0] + 1);
+    if (bt) tb_total = 0;  // a batch never splits a start into end-vertex tiles
 
     // ---- workspace
     PrepBufs b;
@@ -411,13 +442,13 @@ bbc_status bbc_count(bbc_context* c, int32_t n_u, int32_t n_v, int64_t n_edges,
         Carver cv(c->prep.base);
         carve_prep(cv, b, n, m, copy_in, tb_total);
     }
-    const int32_t* eu = edge_u;
-    const int32_t* ev = edge_v;
-    const int8_t* sg = edge_sign;
+    const int32_t* eu = in.eu;
+    const int32_t* ev = in.ev;
+    const int8_t* sg = in.sg;
     if (copy_in) {
-        HIPCHECK(c, hipMemcpyAsync(b.eu, edge_u, m * 4, hipMemcpyHostToDevice, st));
-        HIPCHECK(c, hipMemcpyAsync(b.ev, edge_v, m * 4, hipMemcpyHostToDevice, st));
-        HIPCHECK(c, hipMemcpyAsync(b.sg, edge_sign, m, hipMemcpyHostToDevice, st));
+        HIPCHECK(c, hipMemcpyAsync(b.eu, in.eu, m * 4, hipMemcpyHostToDevice, st));
+        HIPCHECK(c, hipMemcpyAsync(b.ev, in.ev, m * 4, hipMemcpyHostToDevice, st));
+        HIPCHECK(c, hipMemcpyAsync(b.sg, in.sg, m, hipMemcpyHostToDevice, st));
         eu = b.eu;
         ev = b.ev;
         sg = b.sg;
@@ -433,24 +464,51 @@ bbc_status bbc_count(bbc_context* c, int32_t n_u, int32_t n_v, int64_t n_edges,
         *c->host_ctl = z;
         HIPCHECK(c, hipMemcpyAsync(b.ctl, c->host_ctl, sizeof(Control), hipMemcpyHostToDevice, st));
     }
+    if (in.ingest) {
+        IngestArgs ia = *in.ingest;
+        ia.ctl = b.ctl;
+        HIPCHECK(c, launch_ingest(ia, st));
+    }
 
     // ---- 1. degrees + validation
     HIPCHECK(c, fill_u32(b.deg, 0, n, st));
     HIPCHECK(c, launch_degree(eu, ev, sg, m, nu, nv, b.deg, b.ctl, st));
-    // ---- 2. priority order: stable sort of vertex ids by degree
+    // ---- 2. priority order: stable sort of vertex ids by degree (by graph,
+    // then degree, for a batch)
     uint32_t* inv = nullptr;
-    uint32_t maxdeg_bound = (uint32_t)std::min<uint64_t>(m, std::max(nu, nv));
-    HIPCHECK(c, radix_sort_by_key(b.deg, n, bitlen(maxdeg_bound), b.k0, b.v0, b.k1, b.v1, b.rtmp,
-                                  b.rtmp_bytes, &inv, st));
+    const uint32_t deg_bits = bt ? bitlen(std::min<uint64_t>(m, bt->max_side)) : 0;
+    if (bt) {
+        const uint32_t g_bits = bitlen(bt->n_graphs - 1);
+        if (deg_bits + g_bits > 32)
+            return fail(c, BBC_ERR_INTERNAL, "batch sort key needs %u bits", deg_bits + g_bits);
+        uint32_t* key = b.rowdeg;  // free until the row degrees are assigned
+        HIPCHECK(c, launch_batch_keys(b.deg, d, deg_bits, key, st));
+        HIPCHECK(c, radix_sort_by_key(key, n, deg_bits + g_bits, b.k0, b.v0, b.k1, b.v1, b.rtmp,
+                                      b.rtmp_bytes, &inv, st));
+    } else {
+        uint32_t maxdeg_bound = (uint32_t)std::min<uint64_t>(m, std::max(nu, nv));
+        HIPCHECK(c, radix_sort_by_key(b.deg, n, bitlen(maxdeg_bound), b.k0, b.v0, b.k1, b.v1, b.rtmp,
+                                      b.rtmp_bytes, &inv, st));
+    }
     // ---- 3. per-side index and cross counts
     HIPCHECK(c, launch_sides(inv, n, nu, b.flag, st));
     HIPCHECK(c, scan_excl_u32(b.flag, b.cnt_u, n, b.stmp, b.stmp_bytes, st));
     HIPCHECK(c, launch_assign(inv, b.cnt_u, b.deg, n, nu, b.sidx_of, b.rowdeg, b.rowcross, st));
+    if (bt) {
+        // rows of a batch are in (graph, degree) order; the row sort works on
+        // length classes, so it gets the rows in (side, length) order
+        uint32_t* rlist = nullptr;
+        HIPCHECK(c, launch_row_keys(b.rowdeg, d, deg_bits, b.flag, st));
+        HIPCHECK(c, radix_sort_by_key(b.flag, n, deg_bits + 1, b.k0, b.v0, b.k1, b.v1, b.rtmp,
+                                      b.rtmp_bytes, &rlist, st));
+        d.rlist = rlist;
+    }
     // ---- 4. CSR: offsets, scatter, per-row sort
     HIPCHECK(c, scan_excl_u32(b.rowdeg, b.row_ptr, n, b.stmp, b.stmp_bytes, st));
     HIPCHECK(c, copy_u32(b.row_ptr, b.cursor, n, st));
     HIPCHECK(c, launch_scatter(eu, ev, sg, m, nu, nv, b.sidx_of, b.cursor, b.col_in, st));
     HIPCHECK(c, launch_row_sort(b.rowdeg, b.row_ptr, b.col_in, b.col, d, b.ctl, c->num_cus, st));
+    if (bt) HIPCHECK(c, launch_dup_graphs(b.row_ptr, b.col, d, b.ctl, st));
     // ---- 5. middle counts, 6. records and W_u, 7. tile tables
     HIPCHECK(c, launch_lowcount(b.row_ptr, b.col, b.rowcross, n, b.lowcnt, st));
     HIPCHECK(c, scan_excl_u32(b.lowcnt, b.mptr, n, b.stmp, b.stmp_bytes, st));
@@ -462,12 +520,13 @@ bbc_status bbc_count(bbc_context* c, int32_t n_u, int32_t n_v, int64_t n_edges,
     HIPCHECK(c, fill_u64(b.wsu, 0, n, st));
     HIPCHECK(c, launch_records(b.row_ptr, b.col, b.lowcnt, d, b.ctl, 2 * m, b.cursor, b.back, b.recs,
                                b.wu, b.wsu, st));
-    HIPCHECK(c, launch_tile_table(b.row_ptr, b.col, d, b.ctl, b.tb, c->num_cus, st));
+    if (!bt) HIPCHECK(c, launch_tile_table(b.row_ptr, b.col, d, b.ctl, b.tb, c->num_cus, st));
     if (tm) HIPCHECK(c, hipEventRecord(c->ev[kEvPrepEnd], st));
 
     // ---- planning: piece counts, offsets, totals
     HIPCHECK(c, launch_plan_count(b.wu, b.wsu, b.lowcnt, b.row_ptr, d, b.hp, b.lr, b.lf, b.gs, b.tc,
-                                  b.swc, &b.ctl->wedges, &b.ctl->active_starts, st));
+                                  b.swc, &b.ctl->wedges, &b.ctl->active_starts, b.ctl, st));
+    if (bt) HIPCHECK(c, launch_graph_wedges(b.wu, d, bt->gres, st));
     HIPCHECK(c, scan_excl_u32(b.hp, b.hp_off, n, b.stmp, b.stmp_bytes, st));
     HIPCHECK(c, scan_excl_u64(b.lr, b.lr_off, n, b.stmp, b.stmp_bytes, st));
     HIPCHECK(c, scan_excl_u32(b.lf, b.lf_off, n, b.stmp, b.stmp_bytes, st));
@@ -480,23 +539,22 @@ bbc_status bbc_count(bbc_context* c, int32_t n_u, int32_t n_v, int64_t n_edges,
     HIPCHECK(c, hipMemcpyAsync(c->host_ctl, b.ctl, sizeof(Control), hipMemcpyDeviceToHost, st));
     HIPCHECK(c, hipStreamSynchronize(st));
     Control h = *c->host_ctl;
-    if (h.edge_err != ~0ull) {
-        unsigned long long idx = h.edge_err >> 4;
-        if ((h.edge_err & 15ull) == kErrRange)
-            return fail(c, BBC_ERR_VERTEX_RANGE, "edge %llu: (u=%d, v=%d) outside |U|=%d, |V|=%d", idx,
-                        copy_in ? edge_u[idx] : -1, copy_in ? edge_v[idx] : -1, n_u, n_v);
-        return fail(c, BBC_ERR_BAD_SIGN, "edge %llu: sign %d is not +1/-1", idx,
-                    copy_in ? (int)edge_sign[idx] : 0);
+    ro.h = h;
+    if (h.edge_err != ~0ull || h.dup) {
+        ro.input_error = true;
+        return BBC_OK;
     }
-    if (h.dup) return fail(c, BBC_ERR_DUPLICATE_EDGE, "a (u, v) pair occurs more than once");
+    if (h.internal_err)
+        return fail(c, BBC_ERR_INTERNAL, "a batch graph needs end-vertex tiles");
 
     // ---- planning: write the pieces and the light items
     if (h.tot_heavy + h.tot_light >= (1ull << 31))
         return fail(c, BBC_ERR_INTERNAL, "too many work pieces (%llu)",
                     (unsigned long long)(h.tot_heavy + h.tot_light));
-    if (h.tot_sw >= (1ull << 32) || h.tot_tiles >= (1ull << 32))
-        return fail(c, BBC_ERR_INTERNAL, "too many bucketed short-middle wedges (%llu)",
-                    (unsigned long long)h.tot_sw);
+    if (h.tot_sw >= (1ull << 32) || h.tot_tiles >= (1ull << 32) || h.tot_g >= (1ull << 32))
+        return fail(c, BBC_ERR_INTERNAL, "planner totals exceed 32 bits (%llu %llu %llu)",
+                    (unsigned long long)h.tot_sw, (unsigned long long)h.tot_tiles,
+                    (unsigned long long)h.tot_g);
     const uint32_t n_heavy = (uint32_t)h.tot_heavy, n_light = (uint32_t)h.tot_light;
     const uint64_t n_light_items64 = (h.tot_light_region + kLightWindow - 1) / kLightWindow;
     const uint32_t n_light_items = (uint32_t)n_light_items64;
@@ -539,7 +597,7 @@ bbc_status bbc_count(bbc_context* c, int32_t n_u, int32_t n_v, int64_t n_edges,
     HIPCHECK(c, fill_u64(G, 0, (size_t)h.tot_g, st));
     HIPCHECK(c, launch_plan_write(b.wu, b.lowcnt, b.row_ptr, b.mptr, b.cursor, b.hp_off, b.lr_off,
                                   b.lf_off, b.gs_off, b.tc_off, d, n_heavy, pieces, light_off, hkey,
-                                  tile_piece, n_light, n_light_items, items_first, st));
+                                  tile_piece, n_light, n_light_items, items_first, b.ctl, st));
     // bucket the short-middle wedges of split starts by piece
     HIPCHECK(c, fill_u32(sw_cnt, 0, (size_t)n_heavy + 1, st));
     if (h.tot_sw > 0) {
@@ -561,34 +619,341 @@ bbc_status bbc_count(bbc_context* c, int32_t n_u, int32_t n_v, int64_t n_edges,
     // ---- wedge enumeration and bucket counting
     if (tm) HIPCHECK(c, hipEventRecord(c->ev[kEvWedgeA], st));
     HIPCHECK(c, launch_wedge(pieces, order, items_first, n_heavy, n_items, b.recs, b.col, b.tb, d,
-                             first_long, G, sw_off, sw_list, b.ctl, c->num_cus, st));
+                             first_long, G, sw_off, sw_list, b.ctl, bt ? bt->gres : nullptr,
+                             c->num_cus, st));
     if (tm) HIPCHECK(c, hipEventRecord(c->ev[kEvWedgeB], st));
     if (tm) HIPCHECK(c, hipEventRecord(c->ev[kEvEnd], st));
     HIPCHECK(c, hipMemcpyAsync(c->host_ctl, b.ctl, sizeof(Control), hipMemcpyDeviceToHost, st));
     HIPCHECK(c, hipStreamSynchronize(st));
     h = *c->host_ctl;
+    ro.h = h;
     if (h.internal_err)
         return fail(c, BBC_ERR_INTERNAL, "a hashed work piece could not be split further");
+    if (tm) {
+        c->phase_ms[0] += ev_ms(c, kEvStart, kEvEnd);
+        c->phase_ms[1] += ev_ms(c, kEvStart, kEvPrepEnd);
+        c->phase_ms[2] += ev_ms(c, kEvWedgeA, kEvWedgeB);
+        c->phase_ms[3] += ev_ms(c, kEvPrepEnd, kEvPlanA) + ev_ms(c, kEvPlanB, kEvPlanC);
+    }
+    ro.n_items = n_items;
+    ro.n_heavy = n_heavy;
+    return BBC_OK;
+}
+
+static void add_stats(bbc_context* c, const RunOut& ro, uint64_t m) {
+    c->stats[0] += (int64_t)ro.n;
+    c->stats[1] += (int64_t)m;
+    c->stats[2] += (int64_t)ro.h.wedges;
+    c->stats[3] += (int64_t)m;
+    c->stats[4] += (int64_t)ro.n_items;
+    c->stats[5] += (int64_t)ro.h.resplits;
+    c->stats[6] += (int64_t)ro.h.active_starts;
+    c->stats[7] += (int64_t)ro.n_heavy;
+}
+
+static void begin_call(bbc_context* c) {
+    c->err[0] = 0;
+    c->timing_valid = false;
+    memset(c->stats, 0, sizeof(c->stats));
+    for (double& p : c->phase_ms) p = 0;
+}
+
+extern "C" {
+
+bbc_status bbc_count(bbc_context* c, int32_t n_u, int32_t n_v, int64_t n_edges,
+                     const int32_t* edge_u, const int32_t* edge_v, const int8_t* edge_sign,
+                     uint32_t flags, bbc_result* out, int64_t* per_vertex) {
+    if (!c) return BBC_ERR_INVALID_ARG;
+    begin_call(c);
+    if (!out) return fail(c, BBC_ERR_INVALID_ARG, "out is NULL");
+    if (n_u < 0 || n_v < 0 || n_edges < 0)
+        return fail(c, BBC_ERR_INVALID_ARG, "negative size (n_u=%d n_v=%d n_edges=%lld)", n_u, n_v,
+                    (long long)n_edges);
+    if (flags & ~(uint32_t)(BBC_INPUT_ON_DEVICE | BBC_PER_VERTEX))
+        return fail(c, BBC_ERR_INVALID_ARG, "unknown flag bits 0x%x", flags);
+    if (n_edges > 0 && (!edge_u || !edge_v || !edge_sign))
+        return fail(c, BBC_ERR_INVALID_ARG, "NULL edge array with n_edges=%lld", (long long)n_edges);
+    if (flags & BBC_PER_VERTEX) {
+        if (!per_vertex) return fail(c, BBC_ERR_INVALID_ARG, "BBC_PER_VERTEX without per_vertex buffer");
+        return fail(c, BBC_ERR_NOT_IMPLEMENTED, "per-vertex counts are not built");
+    }
+    const uint64_t n64 = (uint64_t)n_u + (uint64_t)n_v;
+    if (n64 >= (1ull << 30)) return fail(c, BBC_ERR_TOO_LARGE, "n_u + n_v = %llu >= 2^30", (unsigned long long)n64);
+    if ((uint64_t)n_edges >= (1ull << 31))
+        return fail(c, BBC_ERR_TOO_LARGE, "n_edges = %lld >= 2^31", (long long)n_edges);
+    if (n_edges == 0) {
+        out->balanced = out->unbalanced = out->wedges = 0;
+        return BBC_OK;
+    }
+    HIPCHECK(c, hipSetDevice(c->device));
+    const bool copy_in = !(flags & BBC_INPUT_ON_DEVICE);
+    RunIn in{(uint32_t)n_u, (uint32_t)n_v, (uint64_t)n_edges, edge_u, edge_v, edge_sign, copy_in,
+             nullptr, nullptr};
+    RunOut ro;
+    bbc_status s = run_pipeline(c, in, ro);
+    if (s) return s;
+    const Control& h = ro.h;
+    if (ro.input_error) {
+        if (h.edge_err != ~0ull) {
+            unsigned long long idx = h.edge_err >> 4;
+            if ((h.edge_err & 15ull) == kErrRange)
+                return fail(c, BBC_ERR_VERTEX_RANGE, "edge %llu: (u=%d, v=%d) outside |U|=%d, |V|=%d",
+                            idx, copy_in ? edge_u[idx] : -1, copy_in ? edge_v[idx] : -1, n_u, n_v);
+            return fail(c, BBC_ERR_BAD_SIGN, "edge %llu: sign %d is not +1/-1", idx,
+                        copy_in ? (int)edge_sign[idx] : 0);
+        }
+        return fail(c, BBC_ERR_DUPLICATE_EDGE, "a (u, v) pair occurs more than once");
+    }
     if (h.balanced > (u64)INT64_MAX || h.unbalanced > (u64)INT64_MAX || h.wedges > (u64)INT64_MAX)
         return fail(c, BBC_ERR_OVERFLOW, "a count exceeds INT64_MAX");
-    if (tm) {
-        c->phase_ms[0] = ev_ms(c, kEvStart, kEvEnd);
-        c->phase_ms[1] = ev_ms(c, kEvStart, kEvPrepEnd);
-        c->phase_ms[2] = ev_ms(c, kEvWedgeA, kEvWedgeB);
-        c->phase_ms[3] = ev_ms(c, kEvPrepEnd, kEvPlanA) + ev_ms(c, kEvPlanB, kEvPlanC);
-        c->timing_valid = true;
-    }
-    c->stats[0] = (int64_t)n;
-    c->stats[1] = (int64_t)m;
-    c->stats[2] = (int64_t)h.wedges;
-    c->stats[3] = (int64_t)m;
-    c->stats[4] = (int64_t)n_items;
-    c->stats[5] = (int64_t)h.resplits;
-    c->stats[6] = (int64_t)h.active_starts;
-    c->stats[7] = (int64_t)n_heavy;
+    c->timing_valid = c->timing;
+    add_stats(c, ro, (uint64_t)n_edges);
     out->balanced = (int64_t)h.balanced;
     out->unbalanced = (int64_t)h.unbalanced;
     out->wedges = (int64_t)h.wedges;
+    return BBC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batches
+
+static bbc_status status_of_code(u64 e) {
+    switch (e & 15ull) {
+        case kErrRange: return BBC_ERR_VERTEX_RANGE;
+        case kErrSign: return BBC_ERR_BAD_SIGN;
+        default: return BBC_ERR_DUPLICATE_EDGE;
+    }
+}
+
+// Counts the included graphs `gl` (all small) as one union; graphs whose input
+// is invalid get their status and the rest are counted again without them.
+static bbc_status count_union(bbc_context* c, const std::vector<uint32_t>& all, const int32_t* n_u,
+                              const int32_t* n_v, const int64_t* off, const int32_t* edge_u,
+                              const int32_t* edge_v, const int8_t* edge_sign, bool on_device,
+                              bbc_result* out, int32_t* status) {
+    hipStream_t st = c->stream;
+    std::vector<uint32_t> gl = all;
+    while (!gl.empty()) {
+        const uint32_t G = (uint32_t)gl.size();
+        // host-side metadata of the included graphs
+        std::vector<u64> src_off(G);
+        std::vector<uint32_t> dst_off(G + 1), gnu(G), gnv(G), uoff(G + 1), voff(G + 1);
+        const int64_t e0 = off[gl.front()], e1 = off[gl.back() + 1];  // source edge range
+        uint32_t max_side = 1;
+        dst_off[0] = uoff[0] = voff[0] = 0;
+        for (uint32_t j = 0; j < G; ++j) {
+            const uint32_t g = gl[j];
+            src_off[j] = (u64)(off[g] - (on_device ? 0 : e0));
+            gnu[j] = (uint32_t)n_u[g];
+            gnv[j] = (uint32_t)n_v[g];
+            dst_off[j + 1] = dst_off[j] + (uint32_t)(off[g + 1] - off[g]);
+            uoff[j + 1] = uoff[j] + gnu[j];
+            voff[j + 1] = voff[j] + gnv[j];
+            max_side = std::max(max_side, std::max(gnu[j], gnv[j]));
+        }
+        const uint64_t m = dst_off[G];
+        const uint32_t nu = uoff[G], nv = voff[G];
+        const uint64_t src_m = on_device ? 0 : (uint64_t)(e1 - e0);
+        // workspace: metadata, union edges, source copy, per-graph results
+        struct {
+            u64 *src_off, *gres, *gerr;
+            uint32_t *dst_off, *gnu, *gnv, *uoff, *voff;
+            int32_t *eu, *ev, *su, *sv;
+            int8_t *sg, *ss;
+        } w;
+        auto carve = [&](Carver& cv) {
+            w.src_off = cv.take<u64>(G);
+            w.gres = cv.take<u64>(4ull * G);
+            w.gerr = cv.take<u64>(G);
+            w.dst_off = cv.take<uint32_t>(G + 1);
+            w.gnu = cv.take<uint32_t>(G);
+            w.gnv = cv.take<uint32_t>(G);
+            w.uoff = cv.take<uint32_t>(G + 1);
+            w.voff = cv.take<uint32_t>(G + 1);
+            w.eu = cv.take<int32_t>(m);
+            w.ev = cv.take<int32_t>(m);
+            w.sg = cv.take<int8_t>(m);
+            w.su = cv.take<int32_t>(src_m);
+            w.sv = cv.take<int32_t>(src_m);
+            w.ss = cv.take<int8_t>(src_m);
+            return cv.off;
+        };
+        {
+            Carver probe(nullptr);
+            bbc_status s = arena_reserve(c, c->batch, carve(probe));
+            if (s) return s;
+            Carver cv(c->batch.base);
+            carve(cv);
+        }
+        HIPCHECK(c, hipMemcpyAsync(w.src_off, src_off.data(), 8ull * G, hipMemcpyHostToDevice, st));
+        HIPCHECK(c, hipMemcpyAsync(w.dst_off, dst_off.data(), 4ull * (G + 1), hipMemcpyHostToDevice, st));
+        HIPCHECK(c, hipMemcpyAsync(w.gnu, gnu.data(), 4ull * G, hipMemcpyHostToDevice, st));
+        HIPCHECK(c, hipMemcpyAsync(w.gnv, gnv.data(), 4ull * G, hipMemcpyHostToDevice, st));
+        HIPCHECK(c, hipMemcpyAsync(w.uoff, uoff.data(), 4ull * (G + 1), hipMemcpyHostToDevice, st));
+        HIPCHECK(c, hipMemcpyAsync(w.voff, voff.data(), 4ull * (G + 1), hipMemcpyHostToDevice, st));
+        const int32_t* su = edge_u;
+        const int32_t* sv = edge_v;
+        const int8_t* ss = edge_sign;
+        if (!on_device) {
+            HIPCHECK(c, hipMemcpyAsync(w.su, edge_u + e0, 4 * src_m, hipMemcpyHostToDevice, st));
+            HIPCHECK(c, hipMemcpyAsync(w.sv, edge_v + e0, 4 * src_m, hipMemcpyHostToDevice, st));
+            HIPCHECK(c, hipMemcpyAsync(w.ss, edge_sign + e0, src_m, hipMemcpyHostToDevice, st));
+            su = w.su;
+            sv = w.sv;
+            ss = w.ss;
+        }
+        HIPCHECK(c, fill_u64(w.gres, 0, 4ull * G, st));
+        HIPCHECK(c, fill_u64(w.gerr, ~0ull, G, st));
+        RunIn in{nu, nv, m, w.eu, w.ev, w.sg, false, nullptr, nullptr};
+        BatchDev bd;
+        bd.n_graphs = G;
+        bd.max_side = max_side;
+        bd.blk[0] = w.uoff;
+        bd.blk[1] = w.voff;
+        bd.gres = w.gres;
+        bd.gerr = w.gerr;
+        in.bt = &bd;
+        IngestArgs ia;
+        ia.src_u = su;
+        ia.src_v = sv;
+        ia.src_s = ss;
+        ia.src_off = w.src_off;
+        ia.dst_off = w.dst_off;
+        ia.gnu = w.gnu;
+        ia.gnv = w.gnv;
+        ia.uoff = w.uoff;
+        ia.voff = w.voff;
+        ia.n_graphs = G;
+        ia.m = m;
+        ia.eu = w.eu;
+        ia.ev = w.ev;
+        ia.sg = w.sg;
+        ia.gerr = w.gerr;
+        ia.ctl = nullptr;  // set to the run's control block
+        in.ingest = &ia;
+        RunOut ro;
+        bbc_status s = run_pipeline(c, in, ro);
+        if (s) return s;
+        // per-graph errors (from the ingest or the duplicate check)
+        std::vector<u64> gerr(G);
+        HIPCHECK(c, hipMemcpyAsync(gerr.data(), w.gerr, 8ull * G, hipMemcpyDeviceToHost, st));
+        HIPCHECK(c, hipStreamSynchronize(st));
+        std::vector<uint32_t> keep;
+        for (uint32_t j = 0; j < G; ++j) {
+            if (gerr[j] != ~0ull)
+                status[gl[j]] = status_of_code(gerr[j]);
+            else
+                keep.push_back(gl[j]);
+        }
+        if (keep.size() != gl.size()) {  // count the valid graphs again without them
+            gl.swap(keep);
+            continue;
+        }
+        if (ro.input_error)
+            return fail(c, BBC_ERR_INTERNAL, "batch input error without a per-graph cause");
+        std::vector<u64> gres(4ull * G);
+        HIPCHECK(c, hipMemcpyAsync(gres.data(), w.gres, 32ull * G, hipMemcpyDeviceToHost, st));
+        HIPCHECK(c, hipStreamSynchronize(st));
+        for (uint32_t j = 0; j < G; ++j) {
+            const u64 bal = gres[4 * j], unb = gres[4 * j + 1], wed = gres[4 * j + 2];
+            if (bal > (u64)INT64_MAX || unb > (u64)INT64_MAX || wed > (u64)INT64_MAX) {
+                status[gl[j]] = BBC_ERR_OVERFLOW;
+                continue;
+            }
+            out[gl[j]].balanced = (int64_t)bal;
+            out[gl[j]].unbalanced = (int64_t)unb;
+            out[gl[j]].wedges = (int64_t)wed;
+        }
+        add_stats(c, ro, m);
+        break;
+    }
+    return BBC_OK;
+}
+
+bbc_status bbc_count_batch(bbc_context* c, int32_t n_graphs, const int32_t* n_u, const int32_t* n_v,
+                           const int64_t* edge_offset, const int32_t* edge_u, const int32_t* edge_v,
+                           const int8_t* edge_sign, uint32_t flags, bbc_result* out,
+                           int32_t* status) {
+    if (!c) return BBC_ERR_INVALID_ARG;
+    begin_call(c);
+    if (n_graphs < 0) return fail(c, BBC_ERR_INVALID_ARG, "n_graphs = %d", n_graphs);
+    if (n_graphs == 0) return BBC_OK;
+    if (!n_u || !n_v || !edge_offset || !out || !status)
+        return fail(c, BBC_ERR_INVALID_ARG, "NULL size, offset or output array");
+    if (flags & ~(uint32_t)BBC_INPUT_ON_DEVICE)
+        return fail(c, BBC_ERR_INVALID_ARG, "unsupported flag bits 0x%x for a batch", flags);
+    if (edge_offset[0] < 0) return fail(c, BBC_ERR_INVALID_ARG, "edge_offset[0] < 0");
+    for (int32_t g = 0; g < n_graphs; ++g)
+        if (edge_offset[g + 1] < edge_offset[g])
+            return fail(c, BBC_ERR_INVALID_ARG, "edge_offset decreases at graph %d", g);
+    if (edge_offset[n_graphs] > edge_offset[0] && (!edge_u || !edge_v || !edge_sign))
+        return fail(c, BBC_ERR_INVALID_ARG, "NULL edge array");
+    HIPCHECK(c, hipSetDevice(c->device));
+    const bool on_device = (flags & BBC_INPUT_ON_DEVICE) != 0;
+    // classify: empty / invalid sizes are settled here, large graphs run alone,
+    // the rest go into unions of bounded size
+    std::vector<uint32_t> small, big;
+    for (int32_t g = 0; g < n_graphs; ++g) {
+        out[g].balanced = out[g].unbalanced = out[g].wedges = 0;
+        status[g] = BBC_OK;
+        const int64_t mg = edge_offset[g + 1] - edge_offset[g];
+        if (n_u[g] < 0 || n_v[g] < 0)
+            status[g] = BBC_ERR_INVALID_ARG;
+        else if ((uint64_t)n_u[g] + (uint64_t)n_v[g] >= (1ull << 30) || mg >= (1ll << 31))
+            status[g] = BBC_ERR_TOO_LARGE;
+        else if (mg == 0)
+            continue;
+        else if ((uint32_t)n_u[g] > kBatchSide || (uint32_t)n_v[g] > kBatchSide)
+            big.push_back((uint32_t)g);
+        else
+            small.push_back((uint32_t)g);
+    }
+    int64_t stats[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    double ph[4] = {0, 0, 0, 0};
+    auto keep_stats = [&]() {
+        for (int i = 0; i < 8; ++i) stats[i] += c->stats[i];
+        for (int i = 0; i < 4; ++i) ph[i] += c->phase_ms[i];
+    };
+    // unions: consecutive small graphs up to the size limits
+    size_t i = 0;
+    while (i < small.size()) {
+        std::vector<uint32_t> gl;
+        uint64_t me = 0, nn = 0;
+        for (; i < small.size(); ++i) {
+            const uint32_t g = small[i];
+            const uint64_t mg = (uint64_t)(edge_offset[g + 1] - edge_offset[g]);
+            const uint64_t ng = (uint64_t)n_u[g] + (uint64_t)n_v[g];
+            if (!gl.empty() && (me + mg > kBatchMaxEdges || nn + ng > kBatchMaxVertices ||
+                                gl.size() >= kBatchMaxGraphs))
+                break;
+            gl.push_back(g);
+            me += mg;
+            nn += ng;
+        }
+        memset(c->stats, 0, sizeof(c->stats));
+        for (double& p : c->phase_ms) p = 0;
+        bbc_status s = count_union(c, gl, n_u, n_v, edge_offset, edge_u, edge_v, edge_sign, on_device,
+                                   out, status);
+        if (s) return s;
+        keep_stats();
+    }
+    // large graphs, one by one
+    for (uint32_t g : big) {
+        const int64_t e0 = edge_offset[g];
+        bbc_result r;
+        bbc_status s = bbc_count(c, n_u[g], n_v[g], edge_offset[g + 1] - e0, edge_u + e0,
+                                 edge_v + e0, edge_sign + e0, flags, &r, nullptr);
+        if (s == BBC_ERR_DEVICE || s == BBC_ERR_INTERNAL) return s;
+        status[g] = s;
+        if (s == BBC_OK) {
+            out[g] = r;
+            keep_stats();
+        }
+    }
+    memcpy(c->stats, stats, sizeof(stats));
+    for (int k = 0; k < 4; ++k) c->phase_ms[k] = ph[k];
+    c->timing_valid = c->timing;
+    c->err[0] = 0;
     return BBC_OK;
 }
 

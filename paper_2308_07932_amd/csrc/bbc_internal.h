@@ -18,6 +18,12 @@
 //     pos = |{w in Gamma(v) : p(w) < p(u)}|, so the wedges (u, v, .) are the
 //     first pos entries of row v.  A start's records with a long middle row
 //     (more than kLongDeg entries) come first, those with a short one last.
+//   * batches: many graphs are counted as one disjoint union.  The priority
+//     sort key is (graph, degree, id), so each graph's vertices form one
+//     contiguous sidx block per side (blk[side][g] .. blk[side][g+1]) and
+//     priorities are only ever compared inside a graph, exactly as when the
+//     graph is counted alone.  A start's end vertices are then the sidx range
+//     [block start, sidx(u)), and every piece carries its graph's index.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -49,7 +55,12 @@ constexpr uint32_t kLightMax = kHashSlots / 4;     // max wedges of a batched (l
 constexpr uint32_t kMinRegion = 64;
 constexpr uint32_t kMaxItemPieces = (2 * kLightWindow) / kMinRegion + 1;
 constexpr uint32_t kTile = 16384;             // end-vertex tile width (sidx units)
-constexpr u64 kRecordChunkWedges = 65536;     // wedges per record chunk of a small-side start
+constexpr u64 kRecordChunkWedges = 65536;     // min wedges per record chunk of a small-side start
+constexpr uint32_t kChunkDiv = 2048;          // ... and at least W_total / kChunkDiv
+constexpr uint32_t kBatchSide = kDenseW;          // batches: graphs up to this many vertices
+constexpr uint64_t kBatchMaxEdges = 1ull << 30;   //   per side share one union of at most
+constexpr uint64_t kBatchMaxVertices = 1ull << 29;  //   these many edges, vertices, graphs
+constexpr uint32_t kBatchMaxGraphs = 1u << 17;
 constexpr uint32_t kDefaultHashTarget = 4096;   // expected wedges per hashed run of tiles
 constexpr uint32_t kDefaultProbeLimit = 256;    // probes before a split hashed piece gives up
 
@@ -70,11 +81,13 @@ struct Piece {
     uint32_t gbase;       // merge array offset (kPieceMerge)
     uint32_t start_row;   // row of the start vertex
     uint32_t list;        // kPiecePartial: heavy piece owning the bucketed short wedges
+    uint32_t graph;       // graph of the start (batches; 0 for a single graph)
 };
 
 // Error word bits (device -> host); edge errors keep the first offending edge.
 constexpr u64 kErrRange = 1;
 constexpr u64 kErrSign = 2;
+constexpr u64 kErrDup = 3;
 
 // Layout of the small device "control" block.
 struct Control {
@@ -104,7 +117,32 @@ struct Dims {
     uint64_t tb_off[2]; // tile-table offset for rows of side s (entries index the other side)
     uint32_t hash_target;  // planner: expected wedges per hashed tile run
     uint32_t probe_limit;  // wedge kernel: probes before a split hashed piece is halved
+    u64 chunk_min;         // planner: min wedges per record chunk of a small-side start
+    // batches (n_graphs > 1): per-side sidx block starts of the graphs (n_graphs
+    // + 1 entries each) and a per-graph error word (min of index << 4 | code)
+    uint32_t n_graphs;
+    const uint32_t* blk[2];
+    u64* gerr;
+    // rows in ascending (side, length) order, or NULL when the row index order
+    // already is (one graph: rows are sorted by degree within each side)
+    const uint32_t* rlist;
 };
+
+// the row at position p of the (side, length) order
+__device__ inline uint32_t row_at(const Dims& d, uint32_t p) { return d.rlist ? d.rlist[p] : p; }
+
+// index g of the block [blk[g], blk[g+1]) holding x (blk[0] = 0 <= x)
+__host__ __device__ inline uint32_t block_of(const uint32_t* blk, uint32_t nb, uint32_t x) {
+    uint32_t lo = 0, hi = nb;  // last g with blk[g] <= x
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (blk[mid] <= x)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
 
 // ---- small device helpers ---------------------------------------------------
 __device__ inline uint32_t lane_id() { return threadIdx.x & 63u; }
@@ -160,6 +198,26 @@ __device__ inline int agg_slot(uint32_t* keys, uint32_t key) {
     }
     return -1;
 }
+
+// Edge ingestion of a batch into its union graph (batch.hip).
+struct IngestArgs {
+    const int32_t* src_u;   // caller's concatenated edges (local ids)
+    const int32_t* src_v;
+    const int8_t* src_s;
+    const u64* src_off;     // per included graph: index of its first edge in src_*
+    const uint32_t* dst_off;  // per included graph: first union edge (n_graphs + 1 entries)
+    const uint32_t* gnu;    // per included graph: |U|, |V|
+    const uint32_t* gnv;
+    const uint32_t* uoff;   // per included graph: first union U id / V id (sidx block starts)
+    const uint32_t* voff;
+    uint32_t n_graphs;
+    uint64_t m;             // union edges
+    int32_t* eu;            // out: union edges
+    int32_t* ev;
+    int8_t* sg;
+    u64* gerr;              // out: per graph min(local edge index << 4 | code)
+    Control* ctl;           // edge_err gets any code (the batch then needs a redo)
+};
 
 }  // namespace bbc
 

@@ -13,8 +13,10 @@
 // end vertices have sidx in [0, S)):
 //   * light   (W_u <= kLightMax): one hashed piece; many light starts share
 //             one work item, each in its own region of the on-chip table;
-//   * small S (S <= kDenseW): dense counters over [0, S); split into record
-//             chunks of ~kRecordChunkWedges wedges merged through G;
+//   * small S (S - lo <= kDenseW, lo = the start's graph block start, 0 for
+//             a single graph): dense counters over [lo, S); split into record
+//             chunks of at least kRecordChunkWedges and W_total / kChunkDiv
+//             wedges, merged exactly through G;
 //   * else:   the end-vertex space is cut into tiles of kTile.  The wedges of u
 //             are estimated per tile in proportion to the tile's degree mass
 //             (an end vertex is reached through its edges).  A tile expected to
@@ -101,26 +103,39 @@ enum : uint32_t { kClassNone = 0, kClassLight, kClassSmallSide, kClassTiles };
 
 struct StartPlan {
     uint32_t cls, pieces, region, tiles;  // tiles > 0: a split start with T tiles
+    uint32_t graph, lo;                   // the start's graph and its sidx block start
 };
 
+// wedges per record chunk of a small-side start
+__device__ inline u64 chunk_wedges(const Dims& d, const Control* ctl) {
+    const u64 c = ctl->wedges / kChunkDiv;
+    return c > d.chunk_min ? c : d.chunk_min;
+}
+
 __device__ inline StartPlan plan_start(const uint32_t* __restrict__ row_ptr, const Dims& d,
-                                       uint32_t r, u64 W, uint32_t k) {
-    StartPlan sp = {kClassNone, 0, 0, 0};
+                                       uint32_t r, u64 W, uint32_t k, u64 chunk) {
+    StartPlan sp = {kClassNone, 0, 0, 0, 0, 0};
     const uint32_t side = r >= d.n_u ? 1u : 0u;
     const uint32_t S = r - d.base[side];
+    if (d.n_graphs > 1) {
+        sp.graph = block_of(d.blk[side], d.n_graphs, S);
+        sp.lo = d.blk[side][sp.graph];
+    }
     if (W == 0) return sp;
     if (W <= kLightMax) {
         sp.cls = kClassLight;
         sp.region = max(kMinRegion, next_pow2((uint32_t)(2 * W)));
         return sp;
     }
-    if (S <= kDenseW) {
-        u64 np = (W + kRecordChunkWedges - 1) / kRecordChunkWedges;
+    if (S - sp.lo <= kDenseW) {
+        u64 np = (W + chunk - 1) / chunk;
         if (np > k) np = k;
         sp.cls = kClassSmallSide;
         sp.pieces = (uint32_t)np;
         return sp;
     }
+    // (tile pieces index end vertices from sidx 0: a batch never gets here, as
+    // its graphs have at most kDenseW vertices per side)
     const uint32_t T = (S + kTile - 1) / kTile;
     bool whole = false;
     sp.cls = kClassTiles;
@@ -141,15 +156,17 @@ __global__ void k_plan_count(const u64* __restrict__ wu, const u64* __restrict__
                              const uint32_t* __restrict__ row_ptr, Dims d,
                              uint32_t* __restrict__ hp, u64* __restrict__ lr,
                              uint32_t* __restrict__ lf, uint32_t* __restrict__ gs,
-                             uint32_t* __restrict__ tc, u64* __restrict__ swc) {
+                             uint32_t* __restrict__ tc, u64* __restrict__ swc, Control* ctl) {
+    const u64 chunk = chunk_wedges(d, ctl);
     for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < d.n; r += gridDim.x * blockDim.x) {
         const u64 W = wu[r];
-        const StartPlan sp = plan_start(row_ptr, d, r, W, lowcnt[r]);
+        const StartPlan sp = plan_start(row_ptr, d, r, W, lowcnt[r], chunk);
         const uint32_t side = r >= d.n_u ? 1u : 0u;
+        if (sp.cls == kClassTiles && d.n_graphs > 1) atomicOr(&ctl->internal_err, 2u);
         hp[r] = sp.pieces;
         lr[r] = sp.cls == kClassLight ? sp.region : 0u;
         lf[r] = sp.cls == kClassLight ? 1u : 0u;
-        gs[r] = (sp.cls == kClassSmallSide && sp.pieces > 1) ? r - d.base[side] : 0u;
+        gs[r] = (sp.cls == kClassSmallSide && sp.pieces > 1) ? r - d.base[side] - sp.lo : 0u;
         tc[r] = sp.tiles;
         swc[r] = sp.tiles ? wsu[r] : 0ull;
     }
@@ -163,12 +180,14 @@ __global__ void k_plan_write(const u64* __restrict__ wu, const uint32_t* __restr
                              const uint32_t* __restrict__ gs_off,
                              const uint32_t* __restrict__ tc_off, Dims d, uint32_t n_heavy,
                              Piece* __restrict__ pieces, u64* __restrict__ light_off,
-                             uint32_t* __restrict__ hkey, uint32_t* __restrict__ tile_piece) {
+                             uint32_t* __restrict__ hkey, uint32_t* __restrict__ tile_piece,
+                             const Control* ctl) {
+    const u64 chunk = chunk_wedges(d, ctl);
     for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < d.n; r += gridDim.x * blockDim.x) {
         const u64 W = wu[r];
         if (W == 0) continue;
         const uint32_t k = lowcnt[r], m0 = mptr[r];
-        const StartPlan sp = plan_start(row_ptr, d, r, W, k);
+        const StartPlan sp = plan_start(row_ptr, d, r, W, k, chunk);
         const uint32_t side = r >= d.n_u ? 1u : 0u;
         const uint32_t S = r - d.base[side];
         const uint32_t sideflag = side ? kPieceSideV : 0u;
@@ -179,7 +198,7 @@ __global__ void k_plan_write(const u64* __restrict__ wu, const uint32_t* __restr
             Piece p;
             p.rec0 = m0;
             p.nrec = k;
-            p.lo = 0;
+            p.lo = sp.lo;
             p.hi = S;
             p.t0 = kNoTile;
             p.t1 = kNoTile;
@@ -188,6 +207,7 @@ __global__ void k_plan_write(const u64* __restrict__ wu, const uint32_t* __restr
             p.gbase = kEmpty;
             p.start_row = r;
             p.list = kEmpty;
+            p.graph = sp.graph;
             pieces[n_heavy + idx] = p;
             light_off[idx] = off;
             continue;
@@ -200,7 +220,7 @@ __global__ void k_plan_write(const u64* __restrict__ wu, const uint32_t* __restr
                 Piece p;
                 p.rec0 = m0 + c0;
                 p.nrec = c1 - c0;
-                p.lo = 0;
+                p.lo = sp.lo;
                 p.hi = S;
                 p.t0 = kNoTile;
                 p.t1 = kNoTile;
@@ -209,6 +229,7 @@ __global__ void k_plan_write(const u64* __restrict__ wu, const uint32_t* __restr
                 p.gbase = gs_off[r];
                 p.start_row = r;
                 p.list = kEmpty;
+                p.graph = sp.graph;
                 pieces[b + i] = p;
                 hkey[b + i] = cost_key((double)W * (c1 - c0) / k, c1 - c0);
             }
@@ -234,6 +255,7 @@ __global__ void k_plan_write(const u64* __restrict__ wu, const uint32_t* __restr
             p.gbase = kEmpty;
             p.start_row = r;
             p.list = split ? b + i : kEmpty;
+            p.graph = 0;
             pieces[b + i] = p;
             hkey[b + i] = cost_key(est, p.nrec);
             if (split)
@@ -388,10 +410,11 @@ static dim3 grid_n(uint64_t n, uint32_t threads, uint32_t cap = 16384) {
 hipError_t launch_plan_count(const u64* wu, const u64* wsu, const uint32_t* lowcnt,
                              const uint32_t* row_ptr, Dims d, uint32_t* hp, u64* lr, uint32_t* lf,
                              uint32_t* gs, uint32_t* tc, u64* swc, u64* wsum, u64* nonzero,
-                             hipStream_t st) {
-    hipLaunchKernelGGL(k_plan_count, grid_n(d.n, 256), dim3(256), 0, st, wu, wsu, lowcnt, row_ptr, d,
-                       hp, lr, lf, gs, tc, swc);
+                             Control* ctl, hipStream_t st) {
+    // W first: the record-chunk size of small-side starts depends on it
     hipLaunchKernelGGL(k_sum_u64, grid_n(d.n, 256, 512), dim3(256), 0, st, wu, d.n, wsum, nonzero);
+    hipLaunchKernelGGL(k_plan_count, grid_n(d.n, 256), dim3(256), 0, st, wu, wsu, lowcnt, row_ptr, d,
+                       hp, lr, lf, gs, tc, swc, ctl);
     return hipGetLastError();
 }
 
@@ -408,10 +431,11 @@ hipError_t launch_plan_write(const u64* wu, const uint32_t* lowcnt, const uint32
                              const u64* lr_off, const uint32_t* lf_off, const uint32_t* gs_off,
                              const uint32_t* tc_off, Dims d, uint32_t n_heavy, Piece* pieces,
                              u64* light_off, uint32_t* hkey, uint32_t* tile_piece, uint32_t n_light,
-                             uint32_t n_light_items, uint32_t* items_first, hipStream_t st) {
+                             uint32_t n_light_items, uint32_t* items_first, const Control* ctl,
+                             hipStream_t st) {
     hipLaunchKernelGGL(k_plan_write, grid_n(d.n, 256), dim3(256), 0, st, wu, lowcnt, row_ptr, mptr,
                        front, hp_off, lr_off, lf_off, gs_off, tc_off, d, n_heavy, pieces, light_off,
-                       hkey, tile_piece);
+                       hkey, tile_piece, ctl);
     hipLaunchKernelGGL(k_items_first, grid_n((uint64_t)n_light_items + 1, 256), dim3(256), 0, st,
                        (const u64*)light_off, n_light, n_light_items, items_first);
     return hipGetLastError();

@@ -227,8 +227,10 @@ __global__ __launch_bounds__(kAggThreads) void k_scatter(
     }
 }
 
-// Row lengths are non-decreasing inside each side (sidx order is degree
-// order), so each size class is a contiguous row range per side.
+// Row lengths are non-decreasing inside each side in the (side, length)
+// order of rows (the row order itself for one graph, whose sidx order is
+// degree order; the list d.rlist for a batch), so each size class is a
+// contiguous range of positions per side.
 __global__ void k_classes(const uint32_t* __restrict__ rowdeg, Dims d, Control* ctl) {
     uint32_t t = threadIdx.x;
     if (t >= 2 * kNumClassBounds) return;
@@ -237,7 +239,7 @@ __global__ void k_classes(const uint32_t* __restrict__ rowdeg, Dims d, Control* 
     uint32_t th = class_hi((int)c);
     while (lo < hi) {
         uint32_t mid = (lo + hi) >> 1;
-        if (rowdeg[mid] <= th)
+        if (rowdeg[row_at(d, mid)] <= th)
             lo = mid + 1;
         else
             hi = mid;
@@ -269,7 +271,7 @@ __global__ void k_sort_tiny(const uint32_t* __restrict__ row_ptr, const uint32_t
     uint32_t n0 = hi0 - lo0, tot = n0 + (hi1 - lo1);
     bool dup = false;
     for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < tot; q += gridDim.x * blockDim.x) {
-        uint32_t r = q < n0 ? lo0 + q : lo1 + (q - n0);
+        uint32_t r = row_at(d, q < n0 ? lo0 + q : lo1 + (q - n0));
         uint32_t a = row_ptr[r], L = row_ptr[r + 1] - a;
         uint32_t x[8];
 #pragma unroll
@@ -314,7 +316,7 @@ __global__ __launch_bounds__(256) void k_sort_group(const uint32_t* __restrict__
     for (uint32_t it = 0; it < iters; ++it) {
         uint32_t q = gid + it * gstride;
         bool act = q < tot;
-        uint32_t r = act ? (q < n0 ? lo0 + q : lo1 + (q - n0)) : 0;
+        uint32_t r = act ? row_at(d, q < n0 ? lo0 + q : lo1 + (q - n0)) : 0;
         uint32_t a = act ? row_ptr[r] : 0, L = act ? row_ptr[r + 1] - a : 0;
         uint32_t v = gl < L ? in[a + gl] : kEmpty;
 #pragma unroll
@@ -348,7 +350,7 @@ __global__ __launch_bounds__(256) void k_sort_block(const uint32_t* __restrict__
     uint32_t n0 = hi0 - lo0, tot = n0 + (hi1 - lo1);
     bool dup = false;
     for (uint32_t q = blockIdx.x; q < tot; q += gridDim.x) {
-        uint32_t r = q < n0 ? lo0 + q : lo1 + (q - n0);
+        uint32_t r = row_at(d, q < n0 ? lo0 + q : lo1 + (q - n0));
         uint32_t a = row_ptr[r], L = row_ptr[r + 1] - a;
         uint32_t P = 1;
         while (P < L) P <<= 1;
@@ -397,11 +399,11 @@ __device__ inline void big_pair(const Control* ctl, const Dims& d, uint32_t q, u
     uint32_t np0 = (e0 - b0) * ch0, np1 = (e1 - b1) * ch1;
     *ok = 1;
     if (q < np0) {
-        *row = b0 + q / ch0;
+        *row = row_at(d, b0 + q / ch0);
         *chunk = q % ch0;
     } else if (q - np0 < np1) {
         q -= np0;
-        *row = b1 + q / ch1;
+        *row = row_at(d, b1 + q / ch1);
         *chunk = q % ch1;
     } else {
         *ok = 0;
@@ -509,7 +511,6 @@ __global__ __launch_bounds__(kAggThreads) void k_records(
     __shared__ u64 wsum[kRecSlots], wsumS[kRecSlots];
     const uint32_t tid = threadIdx.x;
     const uint64_t nnz = row_ptr[d.n];  // entries actually placed (invalid edges are not)
-    const uint32_t long0 = ctl->cls[0][4], long1 = ctl->cls[1][4];
     for (uint64_t c0 = (uint64_t)blockIdx.x * kRecChunk; c0 < nnz; c0 += (uint64_t)gridDim.x * kRecChunk) {
         for (uint32_t i = tid; i < kRecSlots; i += kAggThreads) {
             keys[i] = kEmpty;
@@ -545,7 +546,7 @@ __global__ __launch_bounds__(kAggThreads) void k_records(
             const uint32_t x = col[e];
             if ((x >> 1) >= d.size[side ^ 1u]) continue;  // hole left by a repeated edge
             const uint32_t urow = d.base[side ^ 1u] + (x >> 1);
-            const bool is_long = r >= (side ? long1 : long0);
+            const bool is_long = row_ptr[r + 1] - rs > kLongDeg;
             rec[k] = make_uint4(rs, (i << 1) | (x & 1u), r - d.base[side], urow);
             const int sl = agg_slot<kRecLog2>(keys, urow);
             if (sl >= 0) {

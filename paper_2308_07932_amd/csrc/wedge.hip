@@ -40,6 +40,29 @@ struct WedgeArgs {
     const uint32_t* sw_off;   // short-middle wedge list of heavy piece p: [sw_off[p], sw_off[p+1])
     const uint32_t* sw_list;  // packed w << 1 | asymmetric
     Control* ctl;
+    u64* gres;  // batches: per graph {balanced, unbalanced, wedges, -}; else NULL (totals in ctl)
+};
+
+// Thread 0's running totals for one graph at a time; flushed to memory when
+// the graph changes and at the end (a single graph flushes once).
+struct GraphAcc {
+    uint32_t g = 0;
+    u64 bal = 0, unb = 0;
+    __device__ void flush(const WedgeArgs& a) {
+        if (bal == 0 && unb == 0) return;
+        u64* dst = a.gres ? a.gres + 4ull * g : &a.ctl->balanced;
+        atomicAdd(dst, bal);
+        atomicAdd(dst + 1, unb);
+        bal = unb = 0;
+    }
+    __device__ void add(const WedgeArgs& a, uint32_t graph, u64 b, u64 u) {
+        if (graph != g) {
+            flush(a);
+            g = graph;
+        }
+        bal += b;
+        unb += u;
+    }
 };
 
 constexpr uint32_t kScanMax = 16;     // short middle prefixes are read whole and filtered
@@ -95,6 +118,7 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
     __shared__ uint32_t s_qadj[kQueue], s_qlen[kQueue], s_qaux[kQueue];  // queued long chunks
     __shared__ uint32_t s_qn, s_qtake;
     __shared__ u64 s_red[2][kWaves];
+    __shared__ u64 s_pb[kMaxItemPieces], s_pu[kMaxItemPieces];  // per-piece totals (batches)
     uint32_t* keys = (uint32_t*)s_tab;
     u64* hvals = s_tab + kHashSlots / 2;
 
@@ -102,7 +126,7 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
     const uint32_t* __restrict__ col = a.col;
     for (uint32_t u = 0; u < kUnroll; ++u) s_head[wave][u * 64 + lane] = 0;
 
-    u64 acc_bal = 0, acc_unb = 0;  // this workgroup's totals (thread 0)
+    GraphAcc acc;                  // this workgroup's totals (thread 0)
     Piece pf;                      // thread 0: the next heavy item's piece, fetched ahead
     uint32_t pf_item = kEmpty;
     if (tid == 0) s_item = atomicAdd(&a.ctl->queue, 1u);
@@ -406,7 +430,29 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
 
             // -- finalize: C(l,2) + C(m,2) and l*m over the buckets
             u64 bal = 0, unb = 0;
-            if (dense) {
+            // a light item of a batch may hold starts of several graphs: one
+            // wave per piece sums the piece's own hash region
+            const bool per_piece = a.gres != nullptr && np > 1;
+            if (per_piece) {
+                for (uint32_t p = wave; p < np; p += kWaves) {
+                    const uint32_t region = s_pc[p].region;
+                    const uint32_t rb = region & 0xFFFFu, sz = 1u << ((region >> 16) & 31u);
+                    u64 pb = 0, pu = 0;
+                    for (uint32_t i = lane; i < sz; i += 64) {
+                        if (keys[rb + i] == kEmpty) continue;
+                        const u64 v = hvals[rb + i];
+                        const u64 l = v & 0xFFFFFFFFull, m = v >> 32;
+                        pb += choose2(l) + choose2(m);
+                        pu += l * m;
+                    }
+                    pb = wave_reduce_sum(pb);
+                    pu = wave_reduce_sum(pu);
+                    if (lane == 0) {
+                        s_pb[p] = pb;
+                        s_pu[p] = pu;
+                    }
+                }
+            } else if (dense) {
                 const bool merge = (s_pc[0].flags & kPieceMerge) != 0;
                 const uint32_t gb = s_pc[0].gbase;
                 for (uint32_t i = tid; i < dwidth; i += kWedgeThreads) {
@@ -416,7 +462,7 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
                     bal += choose2(l) + choose2(m);
                     unb += l * m;
                     if (merge) {
-                        const u64 old = atomicAdd(&a.G[(uint64_t)gb + dlo + i], v);
+                        const u64 old = atomicAdd(&a.G[(uint64_t)gb + i], v);
                         const u64 ol = old & 0xFFFFFFFFull, om = old >> 32;
                         bal += ol * l + om * m;
                         unb += ol * m + om * l;
@@ -431,17 +477,25 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
                     unb += l * m;
                 }
             }
-            bal = wave_reduce_sum(bal);
-            unb = wave_reduce_sum(unb);
-            if (lane == 0) {
-                s_red[0][wave] = bal;
-                s_red[1][wave] = unb;
+            if (!per_piece) {
+                bal = wave_reduce_sum(bal);
+                unb = wave_reduce_sum(unb);
+                if (lane == 0) {
+                    s_red[0][wave] = bal;
+                    s_red[1][wave] = unb;
+                }
             }
             __syncthreads();
             if (tid == 0) {
-                for (uint32_t w = 0; w < kWaves; ++w) {
-                    acc_bal += s_red[0][w];
-                    acc_unb += s_red[1][w];
+                if (per_piece) {
+                    for (uint32_t p = 0; p < np; ++p) acc.add(a, s_pc[p].graph, s_pb[p], s_pu[p]);
+                } else {
+                    u64 sb = 0, su = 0;
+                    for (uint32_t w = 0; w < kWaves; ++w) {
+                        sb += s_red[0][w];
+                        su += s_red[1][w];
+                    }
+                    acc.add(a, s_pc[0].graph, sb, su);
                 }
                 if (s_sp > 0) s_pc[0] = s_stack[--s_sp];
                 else s_sp = kStack + 2;  // done with this item
@@ -451,17 +505,15 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
         }
         if (tid == 0) s_item = next;
     }
-    if (tid == 0) {
-        if (acc_bal) atomicAdd(&a.ctl->balanced, acc_bal);
-        if (acc_unb) atomicAdd(&a.ctl->unbalanced, acc_unb);
-    }
+    if (tid == 0) acc.flush(a);
 }
 
 hipError_t launch_wedge(const Piece* pieces, const uint32_t* order, const uint32_t* items_first,
                         uint32_t n_heavy,
                         uint32_t n_items, const uint4* recs, const uint32_t* col, const uint32_t* tb,
                         Dims d, const uint32_t first_long[2], u64* G, const uint32_t* sw_off,
-                        const uint32_t* sw_list, Control* ctl, uint32_t num_cus, hipStream_t st) {
+                        const uint32_t* sw_list, Control* ctl, u64* gres, uint32_t num_cus,
+                        hipStream_t st) {
     WedgeArgs a;
     a.pieces = pieces;
     a.order = order;
@@ -478,6 +530,7 @@ hipError_t launch_wedge(const Piece* pieces, const uint32_t* order, const uint32
     a.sw_off = sw_off;
     a.sw_list = sw_list;
     a.ctl = ctl;
+    a.gres = gres;
     uint32_t grid = num_cus;
     if (grid > n_items) grid = n_items;
     if (grid == 0) return hipSuccess;

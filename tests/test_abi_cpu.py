@@ -72,3 +72,23 @@ def test_product_never_touches_the_oracle():
             if f.endswith((".py", ".hip", ".h", ".cpp")):
                 text = open(os.path.join(dirpath, f)).read()
                 assert not re.search(r"\bimport oracle\b|from oracle\b|liboracle|bbo_", text), f
+
+
+def test_batch_call_rejects_null_context(lib):
+    import numpy as np
+    nu = np.ones(1, np.int32)
+    off = np.zeros(2, np.int64)
+    assert lib.bbc_count_batch(None, 1, nu.ctypes.data, nu.ctypes.data, off.ctypes.data,
+                               None, None, None, 0, None, None) == bbc.INVALID_ARG
+
+
+def test_concat_graphs_layout():
+    import numpy as np
+    import gen
+    gs = [gen.uniform_graph(seed=i, n_u=10 + i, n_v=8, n_edges=5 * i) for i in range(4)]
+    nu, nv, off, eu, ev, sg = bbc.concat_graphs(gs)
+    assert list(nu) == [10, 11, 12, 13] and list(nv) == [8] * 4
+    assert list(off) == [0, 0, 5, 15, 30]
+    for i, g in enumerate(gs):
+        assert np.array_equal(eu[off[i]:off[i + 1]], g.eu)
+        assert np.array_equal(sg[off[i]:off[i + 1]], g.sign)
