@@ -46,7 +46,9 @@ hipError_t launch_short_wedges(const uint4*, uint32_t, const uint32_t*, const ui
                                const uint32_t*, uint32_t*, uint32_t*, uint32_t*, bool, hipStream_t);
 hipError_t launch_wedge(const Piece*, const uint32_t*, const uint32_t*, uint32_t, uint32_t,
                         const uint4*, const uint32_t*, const uint32_t*, Dims, const uint32_t[2], u64*,
-                        const uint32_t*, const uint32_t*, Control*, u64*, uint32_t, hipStream_t);
+                        const uint32_t*, const uint32_t*, Control*, u64*, u64*, uint32_t,
+                        hipStream_t);
+hipError_t launch_pv_out(const u64*, const uint32_t*, Dims, u64*, hipStream_t);
 hipError_t launch_ingest(const IngestArgs&, hipStream_t);
 hipError_t launch_batch_keys(const uint32_t*, Dims, uint32_t, uint32_t*, hipStream_t);
 hipError_t launch_dup_graphs(const uint32_t*, const uint32_t*, Dims, const Control*, hipStream_t);
@@ -82,6 +84,8 @@ struct bbc_context {
     uint32_t hash_target = bbc::kDefaultHashTarget;
     uint32_t probe_limit = bbc::kDefaultProbeLimit;
     uint64_t chunk_min = bbc::kRecordChunkWedges;
+    int64_t* pv_host = nullptr;  // pinned staging of per-vertex counts
+    size_t pv_host_cap = 0;
     char err[512] = {0};
 };
 
@@ -309,6 +313,7 @@ void bbc_destroy(bbc_context* c) {
     if (c->prep.base) hipFree(c->prep.base);
     if (c->plan.base) hipFree(c->plan.base);
     if (c->batch.base) hipFree(c->batch.base);
+    if (c->pv_host) hipHostFree(c->pv_host);
     if (c->host_ctl) hipHostFree(c->host_ctl);
     for (int i = 0; i < kNumEv; ++i)
         if (c->ev[i]) hipEventDestroy(c->ev[i]);
@@ -387,6 +392,7 @@ struct RunIn {
     bool copy_in;            // eu/ev/sg are host pointers
     const BatchDev* bt;      // NULL: one graph
     const IngestArgs* ingest;  // batches: fills eu/ev/sg first (reports into the control block)
+    int64_t* per_vertex;     // host, n entries: per-vertex counts wanted (one graph only)
 };
 
 struct RunOut {
@@ -424,6 +430,7 @@ static bbc_status run_pipeline(bbc_context* c, const RunIn& in, RunOut& ro) {
     d.blk[1] = bt ? bt->blk[1] : nullptr;
     d.gerr = bt ? bt->gerr : nullptr;
     d.rlist = nullptr;
+    d.per_vertex = in.per_vertex ? 1u : 0u;
     // rows of side Y with more than kLongDeg entries: at most m / (kLongDeg + 1) per side
     uint64_t maxlong0 = std::min<uint64_t>(nu, m / (kLongDeg + 1));
     uint64_t maxlong1 = std::min<uint64_t>(nv, m / (kLongDeg + 1));
@@ -565,6 +572,7 @@ static bbc_status run_pipeline(bbc_context* c, const RunIn& in, RunOut& ro) {
     uint32_t* items_first;
     u64* G;
     uint32_t *hkey, *ok0, *ov0, *ok1, *ov1, *tile_piece, *sw_cnt, *sw_off, *sw_cur, *sw_list;
+    u64 *pv = nullptr, *pv_out = nullptr;
     void* ortmp;
     const size_t ortmp_bytes = radix_tmp_bytes(n_heavy + 1);
     {
@@ -584,6 +592,10 @@ static bbc_status run_pipeline(bbc_context* c, const RunIn& in, RunOut& ro) {
             sw_off = cv.take<uint32_t>((size_t)n_heavy + 1);
             sw_cur = cv.take<uint32_t>((size_t)n_heavy + 1);
             sw_list = cv.take<uint32_t>((size_t)h.tot_sw + 1);
+            if (in.per_vertex) {
+                pv = cv.take<u64>(n);
+                pv_out = cv.take<u64>(n);
+            }
             return cv.off;
         };
         Carver probe(nullptr);
@@ -595,6 +607,7 @@ static bbc_status run_pipeline(bbc_context* c, const RunIn& in, RunOut& ro) {
     }
     if (tm) HIPCHECK(c, hipEventRecord(c->ev[kEvPlanB], st));
     HIPCHECK(c, fill_u64(G, 0, (size_t)h.tot_g, st));
+    if (pv) HIPCHECK(c, fill_u64(pv, 0, n, st));
     HIPCHECK(c, launch_plan_write(b.wu, b.lowcnt, b.row_ptr, b.mptr, b.cursor, b.hp_off, b.lr_off,
                                   b.lf_off, b.gs_off, b.tc_off, d, n_heavy, pieces, light_off, hkey,
                                   tile_piece, n_light, n_light_items, items_first, b.ctl, st));
@@ -619,9 +632,13 @@ static bbc_status run_pipeline(bbc_context* c, const RunIn& in, RunOut& ro) {
     // ---- wedge enumeration and bucket counting
     if (tm) HIPCHECK(c, hipEventRecord(c->ev[kEvWedgeA], st));
     HIPCHECK(c, launch_wedge(pieces, order, items_first, n_heavy, n_items, b.recs, b.col, b.tb, d,
-                             first_long, G, sw_off, sw_list, b.ctl, bt ? bt->gres : nullptr,
+                             first_long, G, sw_off, sw_list, b.ctl, bt ? bt->gres : nullptr, pv,
                              c->num_cus, st));
     if (tm) HIPCHECK(c, hipEventRecord(c->ev[kEvWedgeB], st));
+    if (pv) {
+        HIPCHECK(c, launch_pv_out(pv, b.sidx_of, d, pv_out, st));
+        HIPCHECK(c, hipMemcpyAsync(in.per_vertex, pv_out, 8ull * n, hipMemcpyDeviceToHost, st));
+    }
     if (tm) HIPCHECK(c, hipEventRecord(c->ev[kEvEnd], st));
     HIPCHECK(c, hipMemcpyAsync(c->host_ctl, b.ctl, sizeof(Control), hipMemcpyDeviceToHost, st));
     HIPCHECK(c, hipStreamSynchronize(st));
@@ -673,22 +690,40 @@ bbc_status bbc_count(bbc_context* c, int32_t n_u, int32_t n_v, int64_t n_edges,
         return fail(c, BBC_ERR_INVALID_ARG, "unknown flag bits 0x%x", flags);
     if (n_edges > 0 && (!edge_u || !edge_v || !edge_sign))
         return fail(c, BBC_ERR_INVALID_ARG, "NULL edge array with n_edges=%lld", (long long)n_edges);
-    if (flags & BBC_PER_VERTEX) {
-        if (!per_vertex) return fail(c, BBC_ERR_INVALID_ARG, "BBC_PER_VERTEX without per_vertex buffer");
-        return fail(c, BBC_ERR_NOT_IMPLEMENTED, "per-vertex counts are not built");
-    }
+    if ((flags & BBC_PER_VERTEX) && !per_vertex)
+        return fail(c, BBC_ERR_INVALID_ARG, "BBC_PER_VERTEX without per_vertex buffer");
     const uint64_t n64 = (uint64_t)n_u + (uint64_t)n_v;
     if (n64 >= (1ull << 30)) return fail(c, BBC_ERR_TOO_LARGE, "n_u + n_v = %llu >= 2^30", (unsigned long long)n64);
     if ((uint64_t)n_edges >= (1ull << 31))
         return fail(c, BBC_ERR_TOO_LARGE, "n_edges = %lld >= 2^31", (long long)n_edges);
     if (n_edges == 0) {
         out->balanced = out->unbalanced = out->wedges = 0;
+        if (flags & BBC_PER_VERTEX) memset(per_vertex, 0, 8ull * (size_t)n64);
         return BBC_OK;
     }
     HIPCHECK(c, hipSetDevice(c->device));
     const bool copy_in = !(flags & BBC_INPUT_ON_DEVICE);
+    // per-vertex counts land in a context-owned host buffer first, so that the
+    // caller's buffer is written only on success
+    int64_t* pvh = nullptr;
+    if (flags & BBC_PER_VERTEX) {
+        const size_t bytes = 8ull * (size_t)n64;
+        if (c->pv_host_cap < bytes) {
+            if (c->pv_host) hipHostFree(c->pv_host);
+            c->pv_host = nullptr;
+            c->pv_host_cap = 0;
+            void* hp = nullptr;
+            if (hipHostMalloc(&hp, bytes, hipHostMallocDefault) != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(c, BBC_ERR_OUT_OF_MEMORY, "pinned host buffer of %zu bytes", bytes);
+            }
+            c->pv_host = (int64_t*)hp;
+            c->pv_host_cap = bytes;
+        }
+        pvh = c->pv_host;
+    }
     RunIn in{(uint32_t)n_u, (uint32_t)n_v, (uint64_t)n_edges, edge_u, edge_v, edge_sign, copy_in,
-             nullptr, nullptr};
+             nullptr, nullptr, pvh};
     RunOut ro;
     bbc_status s = run_pipeline(c, in, ro);
     if (s) return s;
@@ -706,6 +741,12 @@ bbc_status bbc_count(bbc_context* c, int32_t n_u, int32_t n_v, int64_t n_edges,
     }
     if (h.balanced > (u64)INT64_MAX || h.unbalanced > (u64)INT64_MAX || h.wedges > (u64)INT64_MAX)
         return fail(c, BBC_ERR_OVERFLOW, "a count exceeds INT64_MAX");
+    if (pvh) {
+        for (uint64_t x = 0; x < n64; ++x)
+            if (pvh[x] < 0) return fail(c, BBC_ERR_OVERFLOW, "vertex %llu: count exceeds INT64_MAX",
+                                        (unsigned long long)x);
+        memcpy(per_vertex, pvh, 8ull * n64);
+    }
     c->timing_valid = c->timing;
     add_stats(c, ro, (uint64_t)n_edges);
     out->balanced = (int64_t)h.balanced;
@@ -804,7 +845,7 @@ static bbc_status count_union(bbc_context* c, const std::vector<uint32_t>& all, 
         }
         HIPCHECK(c, fill_u64(w.gres, 0, 4ull * G, st));
         HIPCHECK(c, fill_u64(w.gerr, ~0ull, G, st));
-        RunIn in{nu, nv, m, w.eu, w.ev, w.sg, false, nullptr, nullptr};
+        RunIn in{nu, nv, m, w.eu, w.ev, w.sg, false, nullptr, nullptr, nullptr};
         BatchDev bd;
         bd.n_graphs = G;
         bd.max_side = max_side;

@@ -123,6 +123,9 @@ struct Dims {
     uint32_t n_graphs;
     const uint32_t* blk[2];
     u64* gerr;
+    // per-vertex mode: starts are not split by record chunks and split starts
+    // keep all their records (no bucketed short-middle wedges)
+    uint32_t per_vertex;
     // rows in ascending (side, length) order, or NULL when the row index order
     // already is (one graph: rows are sorted by degree within each side)
     const uint32_t* rlist;

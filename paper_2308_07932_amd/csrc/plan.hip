@@ -128,7 +128,7 @@ __device__ inline StartPlan plan_start(const uint32_t* __restrict__ row_ptr, con
         return sp;
     }
     if (S - sp.lo <= kDenseW) {
-        u64 np = (W + chunk - 1) / chunk;
+        u64 np = d.per_vertex ? 1 : (W + chunk - 1) / chunk;
         if (np > k) np = k;
         sp.cls = kClassSmallSide;
         sp.pieces = (uint32_t)np;
@@ -168,7 +168,7 @@ __global__ void k_plan_count(const u64* __restrict__ wu, const u64* __restrict__
         lf[r] = sp.cls == kClassLight ? 1u : 0u;
         gs[r] = (sp.cls == kClassSmallSide && sp.pieces > 1) ? r - d.base[side] - sp.lo : 0u;
         tc[r] = sp.tiles;
-        swc[r] = sp.tiles ? wsu[r] : 0ull;
+        swc[r] = (sp.tiles && !d.per_vertex) ? wsu[r] : 0ull;
     }
 }
 
@@ -239,13 +239,14 @@ __global__ void k_plan_write(const u64* __restrict__ wu, const uint32_t* __restr
         // short-middle wedges come from the bucketed list of each piece
         const uint32_t T = (S + kTile - 1) / kTile;
         const bool split = sp.tiles > 0;
+        const bool bucketed = split && !d.per_vertex;  // short-middle wedges come from a list
         const uint32_t nlong = front[r] - m0;
         uint32_t i = 0;
         plan_runs(row_ptr, d.base[side], S, W, d.hash_target, [&](uint32_t t0, uint32_t t1, bool dense, double est) {
             if (i >= h) return;
             Piece p;
             p.rec0 = m0;
-            p.nrec = split ? nlong : k;
+            p.nrec = bucketed ? nlong : k;
             p.lo = t0 * kTile;
             p.hi = min(S, t1 * kTile);
             p.t0 = t0;
@@ -254,7 +255,7 @@ __global__ void k_plan_write(const u64* __restrict__ wu, const uint32_t* __restr
             p.flags = (split ? kPiecePartial : 0u) | (dense ? kPieceDense : 0u) | sideflag;
             p.gbase = kEmpty;
             p.start_row = r;
-            p.list = split ? b + i : kEmpty;
+            p.list = bucketed ? b + i : kEmpty;
             p.graph = 0;
             pieces[b + i] = p;
             hkey[b + i] = cost_key(est, p.nrec);

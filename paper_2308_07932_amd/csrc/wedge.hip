@@ -41,6 +41,7 @@ struct WedgeArgs {
     const uint32_t* sw_list;  // packed w << 1 | asymmetric
     Control* ctl;
     u64* gres;  // batches: per graph {balanced, unbalanced, wedges, -}; else NULL (totals in ctl)
+    u64* pv;    // per-vertex mode: balanced butterflies per row (n entries, zeroed)
 };
 
 // Thread 0's running totals for one graph at a time; flushed to memory when
@@ -101,6 +102,36 @@ __device__ inline bool bucket_add(u64* s_tab, uint32_t* keys, u64* hvals, bool d
     return false;
 }
 
+// Value of a bucket (l symmetric, m asymmetric wedges) in the per-vertex
+// readback: a wedge through middle v lies in l - 1 (symmetric) or m - 1
+// (asymmetric) balanced butterflies with start u and end w (Section 5.1).
+__device__ inline u64 middle_share(u64 v, uint32_t asym) {
+    const u64 l = v & 0xFFFFFFFFull, m = v >> 32;
+    return asym ? m - 1 : l - 1;
+}
+
+// hashed bucket of w in a region (present: the counting pass inserted it)
+__device__ inline u64 bucket_get(const uint32_t* keys, const u64* hvals, uint32_t region,
+                                 uint32_t w) {
+    const uint32_t rb = region & 0xFFFFu, lg = (region >> 16) & 31u;
+    const uint32_t msk = (1u << lg) - 1u;
+    const uint32_t h = hash32(w) >> (32 - lg);
+    for (uint32_t i = 0; i <= msk; ++i) {
+        const uint32_t s = rb + ((h + i) & msk);
+        if (keys[s] == w) return hvals[s];
+        if (keys[s] == kEmpty) break;
+    }
+    return 0;
+}
+
+// PV: per-vertex mode.  After a piece's buckets are complete, a second pass
+// over the same wedges reads back each wedge's bucket and adds its share to
+// the middle vertex; the finalize adds each bucket's C(l,2) + C(m,2) to the
+// end vertex and the piece's total to the start (Section 5.1, Algorithm 3,
+// with the end vertex distinct from the start).  Pieces are then never split
+// by record chunks, long sub-intervals are not queued and short middles are
+// visited through their records, so that every wedge keeps its middle.
+template <bool PV>
 __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
     // on-chip buckets: dense mode uses s_tab[0 .. kDenseW); hash mode uses
     // keys = (uint32_t*)s_tab [0 .. kHashSlots) and vals = s_tab + kHashSlots/2.
@@ -115,7 +146,9 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
     __shared__ uint32_t s_wadj[kWaves][64];   // per wave: compacted sub-intervals' address - start,
     __shared__ uint32_t s_waux[kWaves][64];   // sign(u,v) | filter << 1 | piece << 2,
     __shared__ uint8_t s_head[kWaves][64 * kUnroll];  // head flags of the current windows
-    __shared__ uint32_t s_qadj[kQueue], s_qlen[kQueue], s_qaux[kQueue];  // queued long chunks
+    constexpr uint32_t kQ = PV ? 1 : kQueue;
+    __shared__ uint32_t s_qadj[kQ], s_qlen[kQ], s_qaux[kQ];  // queued long chunks
+    __shared__ uint32_t s_wvrow[PV ? kWaves : 1][64];  // PV: row of each interval's middle
     __shared__ uint32_t s_qn, s_qtake;
     __shared__ u64 s_red[2][kWaves];
     __shared__ u64 s_pb[kMaxItemPieces], s_pu[kMaxItemPieces];  // per-piece totals (batches)
@@ -197,6 +230,9 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
             // records per grab: small items are shared by all waves, large ones in 64s
             const uint32_t bsz = min(64u, max(8u, (total + 63) / 64));
 
+            // pass over the piece's records: count (readback = false) or, in
+            // per-vertex mode, read the complete buckets back (readback = true)
+            auto records_pass = [&](const bool readback) {
             for (;;) {
                 uint32_t base = 0;
                 if (lane == 0) base = atomicAdd(&s_batch, bsz);  // this wave's next records
@@ -217,11 +253,12 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
                     p = lo;
                 }
                 // -- 1. this lane's record and its sub-interval [ia, ib) of row v
-                uint32_t rs = 0, s1 = 0, ia = 0, ib = 0, filt = 0;
+                uint32_t rs = 0, s1 = 0, ia = 0, ib = 0, filt = 0, vrow = 0;
                 if (act) {
                     const Piece& P = s_pc[p];
                     const uint4 rc = a.recs[P.rec0 + (f - s_pre[p])];
                     rs = rc.x;
+                    if (PV) vrow = a.d.base[(P.flags & kPieceSideV) ? 0u : 1u] + rc.z;
                     const uint32_t pos = rc.y >> 1;
                     s1 = rc.y & 1u;
                     ib = pos;
@@ -244,7 +281,7 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
                 }
                 // -- a long sub-interval keeps its first kChunk entries; the rest goes
                 // to the LDS queue in chunks of kChunk (as many as fit)
-                if (ib - ia > kChunk) {
+                if (!PV && ib - ia > kChunk) {
                     const uint32_t want = (ib - ia - 1) / kChunk;  // chunks beyond the first
                     uint32_t old = s_qn, got = 0;
                     for (;;) {
@@ -276,6 +313,7 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
                     const uint32_t ci = (uint32_t)__popcll(nz & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
                     s_wadj[wave][ci] = rs + ia - excl;
                     s_waux[wave][ci] = s1 | (filt << 1) | (p << 2);
+                    if (PV) s_wvrow[wave][ci] = vrow;
                 }
                 // -- 3. all lanes over the concatenated wedges, kUnroll windows of 64 at a
                 // time.  The owner of position q is found from head flags: each interval
@@ -287,7 +325,7 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
                 for (uint32_t j = 0; j < T && ok; j += 64 * kUnroll) {
                     if (len > 0 && excl >= j && excl < j + 64 * kUnroll) s_head[wave][excl - j] = 1;
                     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                    uint32_t x[kUnroll], aux[kUnroll];
+                    uint32_t x[kUnroll], aux[kUnroll], own[PV ? kUnroll : 1];
 #pragma unroll
                     for (uint32_t u = 0; u < kUnroll; ++u) {
                         const uint32_t hd = s_head[wave][u * 64 + lane];
@@ -297,14 +335,43 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
                         const uint32_t q = j + u * 64 + lane;
                         aux[u] = kEmpty;
                         x[u] = 0;
+                        if (PV) own[PV ? u : 0] = kEmpty;
                         if (q < T) {
                             aux[u] = s_waux[wave][idx];
                             x[u] = col[s_wadj[wave][idx] + q];
+                            if (PV) own[PV ? u : 0] = idx;
                         }
                     }
 #pragma unroll
                     for (uint32_t u = 0; u < kUnroll; ++u) s_head[wave][u * 64 + lane] = 0;
-                    if (np == 1 && dense) {
+                    if (PV && readback) {
+                        // each wedge's share, summed per interval over the lanes
+                        // (owners are non-decreasing across lanes), then one
+                        // atomic per interval and window into its middle's count
+#pragma unroll
+                        for (uint32_t u = 0; u < kUnroll; ++u) {
+                            const uint32_t idx = own[PV ? u : 0];
+                            u64 val = 0;
+                            if (aux[u] != kEmpty) {
+                                const uint32_t w = x[u] >> 1;
+                                const bool keep = !((aux[u] & 2u) && (w < plo0 || w >= phi0));
+                                if (keep) {
+                                    const Piece& P = s_pc[aux[u] >> 2];
+                                    const u64 bv = dense ? s_tab[w - dlo]
+                                                         : bucket_get(keys, hvals, P.region, w);
+                                    val = middle_share(bv, (x[u] ^ aux[u]) & 1u);
+                                }
+                            }
+                            for (uint32_t off = 1; off < 64; off <<= 1) {
+                                const u64 o = __shfl_up(val, off, 64);
+                                const uint32_t oi = __shfl_up(idx, off, 64);
+                                if (lane >= off && oi == idx) val += o;
+                            }
+                            const uint32_t ni = __shfl_down(idx, 1, 64);
+                            if ((lane == 63 || ni != idx) && idx != kEmpty && val != 0)
+                                atomicAdd(&a.pv[s_wvrow[wave][idx]], val);
+                        }
+                    } else if (np == 1 && dense) {
                         // one dense piece: counters addressed by w - lo, never full
 #pragma unroll
                         for (uint32_t u = 0; u < kUnroll; ++u) {
@@ -340,9 +407,11 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
                 if (!ok) s_abort = 1;
             }
+            };
+            records_pass(false);
             __syncthreads();
             // -- queued chunks of long sub-intervals: one wave per chunk, coalesced
-            if (np == 1) {
+            if (!PV && np == 1) {
                 bool ok = true;
                 for (;;) {
                     uint32_t c = 0;
@@ -375,7 +444,7 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
                 if (!ok) s_abort = 1;
             }
             // -- bucketed wedges through short middle rows (split starts)
-            if (heavy && (s_pc[0].flags & kPiecePartial) && s_pc[0].list != kEmpty) {
+            if (!PV && heavy && (s_pc[0].flags & kPiecePartial) && s_pc[0].list != kEmpty) {
                 const uint32_t L = s_pc[0].list;
                 const uint32_t b0 = a.sw_off[L], b1 = a.sw_off[L + 1];
                 const uint32_t plo = s_pc[0].lo, phi = s_pc[0].hi, region = s_pc[0].region;
@@ -428,22 +497,34 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
                 continue;
             }
 
+            if (PV) {  // second pass: the middles' shares from the complete buckets
+                if (tid == 0) s_batch = 0;
+                __syncthreads();
+                records_pass(true);
+                __syncthreads();
+            }
+
             // -- finalize: C(l,2) + C(m,2) and l*m over the buckets
             u64 bal = 0, unb = 0;
-            // a light item of a batch may hold starts of several graphs: one
-            // wave per piece sums the piece's own hash region
-            const bool per_piece = a.gres != nullptr && np > 1;
+            // a light item of a batch may hold starts of several graphs, and in
+            // per-vertex mode every start needs its own total: one wave per
+            // piece sums the piece's own hash region
+            const bool per_piece = (a.gres != nullptr || PV) && np > 1;
+            const u64 ubase0 = a.d.base[(s_pc[0].flags & kPieceSideV) ? 1u : 0u];
             if (per_piece) {
                 for (uint32_t p = wave; p < np; p += kWaves) {
                     const uint32_t region = s_pc[p].region;
                     const uint32_t rb = region & 0xFFFFu, sz = 1u << ((region >> 16) & 31u);
+                    const u64 ubase = a.d.base[(s_pc[p].flags & kPieceSideV) ? 1u : 0u];
                     u64 pb = 0, pu = 0;
                     for (uint32_t i = lane; i < sz; i += 64) {
                         if (keys[rb + i] == kEmpty) continue;
                         const u64 v = hvals[rb + i];
                         const u64 l = v & 0xFFFFFFFFull, m = v >> 32;
-                        pb += choose2(l) + choose2(m);
+                        const u64 b = choose2(l) + choose2(m);
+                        pb += b;
                         pu += l * m;
+                        if (PV && b) atomicAdd(&a.pv[ubase + keys[rb + i]], b);
                     }
                     pb = wave_reduce_sum(pb);
                     pu = wave_reduce_sum(pu);
@@ -461,6 +542,8 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
                     const u64 l = v & 0xFFFFFFFFull, m = v >> 32;
                     bal += choose2(l) + choose2(m);
                     unb += l * m;
+                    if (PV && choose2(l) + choose2(m))
+                        atomicAdd(&a.pv[ubase0 + dlo + i], choose2(l) + choose2(m));
                     if (merge) {
                         const u64 old = atomicAdd(&a.G[(uint64_t)gb + i], v);
                         const u64 ol = old & 0xFFFFFFFFull, om = old >> 32;
@@ -475,6 +558,8 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
                     const u64 l = v & 0xFFFFFFFFull, m = v >> 32;
                     bal += choose2(l) + choose2(m);
                     unb += l * m;
+                    if (PV && choose2(l) + choose2(m))
+                        atomicAdd(&a.pv[ubase0 + keys[i]], choose2(l) + choose2(m));
                 }
             }
             if (!per_piece) {
@@ -488,7 +573,10 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
             __syncthreads();
             if (tid == 0) {
                 if (per_piece) {
-                    for (uint32_t p = 0; p < np; ++p) acc.add(a, s_pc[p].graph, s_pb[p], s_pu[p]);
+                    for (uint32_t p = 0; p < np; ++p) {
+                        acc.add(a, s_pc[p].graph, s_pb[p], s_pu[p]);
+                        if (PV && s_pb[p]) atomicAdd(&a.pv[s_pc[p].start_row], s_pb[p]);
+                    }
                 } else {
                     u64 sb = 0, su = 0;
                     for (uint32_t w = 0; w < kWaves; ++w) {
@@ -496,6 +584,7 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
                         su += s_red[1][w];
                     }
                     acc.add(a, s_pc[0].graph, sb, su);
+                    if (PV && sb) atomicAdd(&a.pv[s_pc[0].start_row], sb);
                 }
                 if (s_sp > 0) s_pc[0] = s_stack[--s_sp];
                 else s_sp = kStack + 2;  // done with this item
@@ -508,12 +597,27 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
     if (tid == 0) acc.flush(a);
 }
 
+// per-vertex output by input vertex id: out[x] = count of x's row
+__global__ void k_pv_out(const u64* __restrict__ pv, const uint32_t* __restrict__ sidx_of, Dims d,
+                         u64* __restrict__ out) {
+    for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < d.n; x += gridDim.x * blockDim.x)
+        out[x] = pv[d.base[x >= d.n_u ? 1u : 0u] + sidx_of[x]];
+}
+
+hipError_t launch_pv_out(const u64* pv, const uint32_t* sidx_of, Dims d, u64* out, hipStream_t st) {
+    uint32_t blocks = (d.n + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    if (blocks == 0) blocks = 1;
+    hipLaunchKernelGGL(k_pv_out, dim3(blocks), dim3(256), 0, st, pv, sidx_of, d, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_wedge(const Piece* pieces, const uint32_t* order, const uint32_t* items_first,
                         uint32_t n_heavy,
                         uint32_t n_items, const uint4* recs, const uint32_t* col, const uint32_t* tb,
                         Dims d, const uint32_t first_long[2], u64* G, const uint32_t* sw_off,
-                        const uint32_t* sw_list, Control* ctl, u64* gres, uint32_t num_cus,
-                        hipStream_t st) {
+                        const uint32_t* sw_list, Control* ctl, u64* gres, u64* pv,
+                        uint32_t num_cus, hipStream_t st) {
     WedgeArgs a;
     a.pieces = pieces;
     a.order = order;
@@ -531,10 +635,14 @@ hipError_t launch_wedge(const Piece* pieces, const uint32_t* order, const uint32
     a.sw_list = sw_list;
     a.ctl = ctl;
     a.gres = gres;
+    a.pv = pv;
     uint32_t grid = num_cus;
     if (grid > n_items) grid = n_items;
     if (grid == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_wedge, dim3(grid), dim3(kWedgeThreads), 0, st, a);
+    if (pv)
+        hipLaunchKernelGGL(k_wedge<true>, dim3(grid), dim3(kWedgeThreads), 0, st, a);
+    else
+        hipLaunchKernelGGL(k_wedge<false>, dim3(grid), dim3(kWedgeThreads), 0, st, a);
     return hipGetLastError();
 }
 

@@ -285,3 +285,65 @@ def test_error_paths(ctx):
     assert run(ctx, one) == (0, 0, 0)
     # the context still works after errors
     check(ctx, g)
+
+
+def check_per_vertex(ctx, g, want=None, bu=None):
+    r, pv = ctx.count(g.eu, g.ev, g.sign, g.n_u, g.n_v, per_vertex=True)
+    if want is None:
+        want = oracle.per_vertex(g).astype(np.int64)
+    assert np.array_equal(pv, want), (g.name, np.nonzero(pv != want)[0][:10])
+    b, u = bu if bu is not None else oracle.count(g)
+    assert (r.balanced, r.unbalanced) == (b, u)
+    # every balanced butterfly has two vertices on each side
+    assert int(pv[:g.n_u].sum()) == 2 * b and int(pv[g.n_u:].sum()) == 2 * b
+    return r, pv
+
+
+def test_per_vertex_counts(ctx):
+    fx = json.load(open(os.path.join(GOLDEN, "fig1_butterflies.json")))
+    for pat in fx["patterns"]:
+        g = graph_from_edges(2, 2, pat["edges"], pat["name"])
+        r, pv = check_per_vertex(ctx, g)
+        assert list(pv) == [pat["balanced"]] * 4
+    rng = np.random.default_rng(41)
+    for i in range(40):
+        g = gen.random_graph(rng, int(rng.integers(2, 40)), int(rng.integers(2, 40)),
+                             float(rng.uniform(0.1, 0.8)), p_neg=float(rng.uniform(0, 1)))
+        check_per_vertex(ctx, g)
+    # K_{a,b} all positive: every vertex of U lies in (a-1) C(b,2) butterflies
+    g = gen.complete_graph(30, 50)
+    r, pv = check_per_vertex(ctx, g)
+    assert (pv[:30] == 29 * 50 * 49 // 2).all() and (pv[30:] == 49 * 30 * 29 // 2).all()
+
+
+def test_per_vertex_heavy_shapes(ctx):
+    # heavy starts with small end ranges (dense pieces), hubs, and a side
+    # wider than one end-vertex tile (split starts)
+    check_per_vertex(ctx, gen.voting_graph(seed=6, n_u=80, n_v=3000, p_edge=0.5))
+    check_per_vertex(ctx, gen.chung_lu_graph(seed=11, n_u=60000, n_v=20000, n_edges=250000,
+                                             p_neg=0.25))
+    g = gen.chung_lu_graph(seed=21, n_u=200000, n_v=60000, n_edges=1500000, alpha=2.1, p_neg=0.2)
+    want, bu = oracle.per_vertex(g).astype(np.int64), oracle.count(g)
+    check_per_vertex(ctx, g, want, bu)
+    ctx.set_param(bbc.PARAM_PROBE_LIMIT, 4)  # split pieces redone many times
+    try:
+        check_per_vertex(ctx, g, want, bu)
+        assert ctx.stats()[5] > 100
+    finally:
+        ctx.set_param(bbc.PARAM_PROBE_LIMIT, 256)
+    # the plain count is unchanged by asking for per-vertex counts
+    assert ctx.count(g.eu, g.ev, g.sign, g.n_u, g.n_v)[:2] == bu
+
+
+def test_per_vertex_buffer_untouched_on_error(ctx):
+    g = gen.uniform_graph(seed=3, n_u=100, n_v=80, n_edges=2000)
+    bad = g.sign.copy()
+    bad[5] = 3
+    pv = np.full(180, -7, np.int64)
+    out = bbc._CResult()
+    p = [a.ctypes.data for a in (g.eu, g.ev, bad)]
+    rc = ctx._lib.bbc_count(ctx._h, 100, 80, g.n_edges, *p, bbc.PER_VERTEX, ctypes.byref(out),
+                            pv.ctypes.data)
+    assert rc == bbc.BAD_SIGN and (pv == -7).all()
+    assert ctx._lib.bbc_count(ctx._h, 100, 80, g.n_edges, *p[:2], g.sign.ctypes.data,
+                              bbc.PER_VERTEX, ctypes.byref(out), None) == bbc.INVALID_ARG
