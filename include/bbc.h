@@ -33,6 +33,7 @@ extern "C" {
 #endif
 
 typedef enum bbc_status {
+    BBC_PENDING = 1,              /* bbc_server_poll only: the job has not finished yet */
     BBC_OK = 0,
     BBC_ERR_INVALID_ARG = -1,     /* negative size, NULL pointer with n_edges > 0, bad flag */
     BBC_ERR_VERTEX_RANGE = -2,    /* an edge names u >= n_u, v >= n_v or a negative id */
@@ -129,6 +130,68 @@ bbc_status bbc_count_batch(bbc_context* ctx, int32_t n_graphs, const int32_t* n_
                            const int32_t* n_v, const int64_t* edge_offset, const int32_t* edge_u,
                            const int32_t* edge_v, const int8_t* edge_sign, uint32_t flags,
                            bbc_result* out, int32_t* status);
+
+/*
+ * Device workspace a bbc_count of this size may hold at once (bytes; an
+ * estimate that errs high), or -1 for sizes bbc_count rejects.
+ */
+int64_t bbc_workspace_bytes(int32_t n_u, int32_t n_v, int64_t n_edges);
+
+/*
+ * Counting service with continuous batching.
+ *
+ * A server owns worker threads, each with its own context (workspace and HIP
+ * stream of default priority) on one device.  Jobs (signed bipartite graphs,
+ * host arrays copied at submission) are accepted at any time:
+ *   - jobs with at most small_side vertices on each side wait for the
+ *     batching worker, which, whenever it is free, takes all waiting small
+ *     jobs (up to max_batch_graphs) and counts them with one bbc_count_batch
+ *     call; jobs arriving meanwhile form the next batch;
+ *   - larger jobs go to large_workers workers running bbc_count
+ *     concurrently on their own streams, overlapping on the device with the
+ *     batches.
+ * Admission by device memory: a job reserves its footprint (its input plus
+ * bbc_workspace_bytes) while it runs; a worker starts jobs only while the
+ * reservations stay within memory_budget, and a job larger than the whole
+ * budget finishes with BBC_ERR_OUT_OF_MEMORY.  Results are exact and do not
+ * depend on what else runs.
+ *
+ * bbc_server_create: cfg may be NULL for defaults (device 0, 2 large workers,
+ * budget 90% of the device memory free at creation, small_side 16384,
+ * max_batch_graphs 65536; a zero field takes its default).  INVALID_ARG for
+ * out of range fields, DEVICE if the device cannot be used.
+ * bbc_server_submit: *ticket identifies the job.  INVALID_ARG for bad sizes or
+ * NULL arrays, TOO_LARGE as for bbc_count.  Input errors of the graph itself
+ * (ids, signs, duplicates) are reported as the job's status.
+ * bbc_server_poll: waits up to wait_ms (0: no wait, < 0: until done); returns
+ * BBC_PENDING if the job is still queued or running, or BBC_OK with *out,
+ * *job_status (the bbc_status of the count) and *latency_ms (submission to
+ * completion; may be NULL) filled in, after which the ticket is released.
+ * INVALID_ARG for an unknown ticket.
+ * bbc_server_stats: up to 10 values: [0] jobs submitted, [1] completed,
+ * [2] batches run, [3] jobs counted in batches, [4] largest batch, [5] peak
+ * reserved bytes, [6] peak jobs running at once, [7] memory budget, [8] jobs
+ * waiting now, [9] bytes reserved now.
+ * bbc_server_destroy: finishes every submitted job, then releases the server
+ * (results not polled are dropped).  NULL is a no-op.
+ * One server may be used from several threads at once.
+ */
+typedef struct bbc_server bbc_server;
+typedef struct bbc_server_config {
+    int32_t device;
+    int32_t large_workers;    /* 0..16 */
+    int64_t memory_budget;    /* bytes */
+    int32_t small_side;       /* 0..16384 */
+    int32_t max_batch_graphs;
+} bbc_server_config;
+bbc_status bbc_server_create(const bbc_server_config* cfg, bbc_server** out);
+bbc_status bbc_server_submit(bbc_server* srv, int32_t n_u, int32_t n_v, int64_t n_edges,
+                             const int32_t* edge_u, const int32_t* edge_v,
+                             const int8_t* edge_sign, uint64_t* ticket);
+bbc_status bbc_server_poll(bbc_server* srv, uint64_t ticket, int32_t wait_ms, bbc_result* out,
+                           int32_t* job_status, double* latency_ms);
+bbc_status bbc_server_stats(bbc_server* srv, int64_t* stats, int n);
+void bbc_server_destroy(bbc_server* srv);
 
 /* Static description of a status code (never NULL). */
 const char* bbc_status_string(bbc_status status);

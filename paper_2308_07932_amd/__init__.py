@@ -24,6 +24,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbbc.so")
 HEADER_PATH = os.path.join(_HERE, "..", "include", "bbc.h")
 
+PENDING = 1
 OK = 0
 INVALID_ARG = -1
 VERTEX_RANGE = -2
@@ -108,6 +109,19 @@ def load_library():
     lib.bbc_get_param.restype = ctypes.c_int
     lib.bbc_count_batch.argtypes = [P, I32, P, P, P, P, P, P, U32, P, P]
     lib.bbc_count_batch.restype = ctypes.c_int
+    lib.bbc_workspace_bytes.argtypes = [I32, I32, I64]
+    lib.bbc_workspace_bytes.restype = ctypes.c_int64
+    lib.bbc_server_create.argtypes = [P, ctypes.POINTER(P)]
+    lib.bbc_server_create.restype = ctypes.c_int
+    lib.bbc_server_submit.argtypes = [P, I32, I32, I64, P, P, P, ctypes.POINTER(ctypes.c_uint64)]
+    lib.bbc_server_submit.restype = ctypes.c_int
+    lib.bbc_server_poll.argtypes = [P, ctypes.c_uint64, I32, ctypes.POINTER(_CResult),
+                                    ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]
+    lib.bbc_server_poll.restype = ctypes.c_int
+    lib.bbc_server_stats.argtypes = [P, ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
+    lib.bbc_server_stats.restype = ctypes.c_int
+    lib.bbc_server_destroy.argtypes = [P]
+    lib.bbc_server_destroy.restype = None
     _lib = lib
     return lib
 
@@ -304,6 +318,89 @@ def _count_batch(ctx, n_u, n_v, edge_offset, eu, ev, sign) -> BatchResult:
         raise BBCError(rc, ctx.last_error() or status_string(rc))
     arr = np.frombuffer(out, dtype=np.int64).reshape(-1, 3)[:G]
     return BatchResult(arr[:, 0].copy(), arr[:, 1].copy(), arr[:, 2].copy(), st[:G].copy())
+
+
+class _CServerConfig(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("large_workers", ctypes.c_int32),
+                ("memory_budget", ctypes.c_int64), ("small_side", ctypes.c_int32),
+                ("max_batch_graphs", ctypes.c_int32)]
+
+
+class JobResult(NamedTuple):
+    status: int
+    result: Result
+    latency_ms: float
+
+
+def workspace_bytes(n_u: int, n_v: int, n_edges: int) -> int:
+    return int(load_library().bbc_workspace_bytes(int(n_u), int(n_v), int(n_edges)))
+
+
+class Server:
+    """bbc_server: jobs submitted at any time, small ones counted in continuous
+    batches, large ones on concurrent streams, admitted by device memory."""
+
+    def __init__(self, device: int = 0, large_workers: int = 0, memory_budget: int = 0,
+                 small_side: int = 0, max_batch_graphs: int = 0):
+        lib = load_library()
+        cfg = _CServerConfig(int(device), int(large_workers), int(memory_budget), int(small_side),
+                             int(max_batch_graphs))
+        h = ctypes.c_void_p()
+        rc = lib.bbc_server_create(ctypes.byref(cfg), ctypes.byref(h))
+        if rc != OK:
+            raise BBCError(rc, f"bbc_server_create: {status_string(rc)}")
+        self._lib = lib
+        self._h = h
+
+    def submit(self, eu, ev, sign, n_u: int, n_v: int) -> int:
+        """Queue one graph (host arrays, copied); returns its ticket."""
+        ptrs, keep, on_dev, n = _prepare(eu, ev, sign)
+        if on_dev:
+            raise TypeError("the server takes host arrays")
+        t = ctypes.c_uint64()
+        rc = self._lib.bbc_server_submit(self._h, int(n_u), int(n_v), n, *ptrs, ctypes.byref(t))
+        del keep
+        if rc != OK:
+            raise BBCError(rc, f"bbc_server_submit: {status_string(rc)}")
+        return int(t.value)
+
+    def poll(self, ticket: int, wait_ms: int = -1):
+        """JobResult when the job is done (the ticket is then released), else None."""
+        out = _CResult()
+        st = ctypes.c_int32()
+        lat = ctypes.c_double()
+        rc = self._lib.bbc_server_poll(self._h, int(ticket), int(wait_ms), ctypes.byref(out),
+                                       ctypes.byref(st), ctypes.byref(lat))
+        if rc == PENDING:
+            return None
+        if rc != OK:
+            raise BBCError(rc, f"bbc_server_poll({ticket}): {status_string(rc)}")
+        return JobResult(int(st.value), Result(int(out.balanced), int(out.unbalanced),
+                                               int(out.wedges)), float(lat.value))
+
+    def stats(self) -> dict:
+        a = (ctypes.c_int64 * 10)()
+        self._lib.bbc_server_stats(self._h, a, 10)
+        keys = ("submitted", "completed", "batches", "batched_jobs", "max_batch", "peak_reserved",
+                "peak_running", "budget", "waiting", "reserved")
+        return dict(zip(keys, (int(x) for x in a)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.bbc_server_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 _default: dict[int, Context] = {}

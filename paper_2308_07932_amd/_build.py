@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbbc.so")
-SOURCES = ["scan.hip", "prep.hip", "plan.hip", "wedge.hip", "batch.hip", "api.hip"]
+SOURCES = ["scan.hip", "prep.hip", "plan.hip", "wedge.hip", "batch.hip", "api.hip", "server.hip"]
 ARCH = os.environ.get("BBC_OFFLOAD_ARCH", "gfx950")
 
 

@@ -244,6 +244,7 @@ int bbc_version(void) { return 10000; }
 
 const char* bbc_status_string(bbc_status s) {
     switch (s) {
+        case BBC_PENDING: return "pending";
         case BBC_OK: return "ok";
         case BBC_ERR_INVALID_ARG: return "invalid argument";
         case BBC_ERR_VERTEX_RANGE: return "vertex id out of range";
@@ -368,6 +369,24 @@ bbc_status bbc_last_stats(const bbc_context* c, int64_t* stats, int n) {
     if (!c || !stats || n < 0) return BBC_ERR_INVALID_ARG;
     for (int i = 0; i < n && i < 8; ++i) stats[i] = c->stats[i];
     return BBC_OK;
+}
+
+int64_t bbc_workspace_bytes(int32_t n_u, int32_t n_v, int64_t n_edges) {
+    if (n_u < 0 || n_v < 0 || n_edges < 0) return -1;
+    const uint64_t n64 = (uint64_t)n_u + (uint64_t)n_v;
+    if (n64 >= (1ull << 30) || (uint64_t)n_edges >= (1ull << 31)) return -1;
+    const uint32_t n = (uint32_t)n64;
+    const uint64_t m = (uint64_t)n_edges;
+    const uint32_t nt0 = ((uint32_t)n_u + kTile - 1) / kTile, nt1 = ((uint32_t)n_v + kTile - 1) / kTile;
+    const uint64_t tb = std::min<uint64_t>((uint64_t)n_u, m / (kLongDeg + 1)) * (nt1 + 1) +
+                        std::min<uint64_t>((uint64_t)n_v, m / (kLongDeg + 1)) * (nt0 + 1);
+    PrepBufs b;
+    Carver probe(nullptr);
+    const size_t prep = carve_prep(probe, b, n, m, true, tb);
+    // planning workspace: about one piece per start plus record chunks and
+    // merge rows; taken generously as 96 bytes per vertex and 8 per edge
+    const size_t plan = 96ull * n + 8ull * m + (1u << 20);
+    return (int64_t)(prep + plan);
 }
 }  // extern "C"
 

@@ -92,3 +92,26 @@ def test_concat_graphs_layout():
     for i, g in enumerate(gs):
         assert np.array_equal(eu[off[i]:off[i + 1]], g.eu)
         assert np.array_equal(sg[off[i]:off[i + 1]], g.sign)
+
+
+def test_server_argument_checks(lib):
+    import ctypes
+    cfg = bbc._CServerConfig(0, 99, 0, 0, 0)  # too many workers
+    h = ctypes.c_void_p()
+    assert lib.bbc_server_create(ctypes.byref(cfg), ctypes.byref(h)) == bbc.INVALID_ARG
+    assert lib.bbc_server_create(None, None) == bbc.INVALID_ARG
+    t = ctypes.c_uint64()
+    assert lib.bbc_server_submit(None, 1, 1, 0, None, None, None, ctypes.byref(t)) == bbc.INVALID_ARG
+    out = bbc._CResult()
+    st = ctypes.c_int32()
+    assert lib.bbc_server_poll(None, 1, 0, ctypes.byref(out), ctypes.byref(st), None) == bbc.INVALID_ARG
+    lib.bbc_server_destroy(None)
+
+
+def test_workspace_estimate():
+    assert bbc.workspace_bytes(-1, 5, 5) == -1
+    assert bbc.workspace_bytes(1 << 30, 0, 5) == -1
+    a = bbc.workspace_bytes(1000, 1000, 10000)
+    b = bbc.workspace_bytes(1000, 1000, 100000)
+    c = bbc.workspace_bytes(100000, 1000, 100000)
+    assert 0 < a < b < c
