@@ -161,6 +161,8 @@ def bench_batched(ctx, steps: int, warmup: int, oracle_sample: int):
     log(f"batched: {ms:.2f} ms per batch ({len(graphs) / ms * 1e3:.0f} graphs/s); plain loop "
         f"{plain_s:.2f} s ({len(graphs) / plain_s:.0f} graphs/s), equal={plain_equal}; oracle sample "
         f"{ok}/{len(sample)}")
+    bench_batched.graphs = graphs
+    bench_batched.results = [res.result(i) for i in range(len(graphs))]
     return {
         "workload": "20,000 signed bipartite graphs, |U|,|V| log-uniform in [16, 4096], density "
                     "log-uniform in [1e-3, 0.2], P(sign=-1)=0.3, seeds 4 / 10000+i",
@@ -175,6 +177,93 @@ def bench_batched(ctx, steps: int, warmup: int, oracle_sample: int):
     }
 
 
+def bench_serving(small_graphs, small_results, n_templates: int, n_requests: int,
+                  load: float, seed: int = 99):
+    """Serving: a Poisson stream of jobs, 80% small graphs of the batched
+    workload and 20% large Chung-Lu graphs (sides log-uniform in [1e5, 2e6],
+    edges log-uniform in [1e6, 3e7], P(-1) uniform in [0.1, 0.4]), submitted
+    to a bbc_server at a rate that keeps the device about `load` busy; reports
+    latency percentiles (submission to result) and completed graphs/s, and
+    checks every result against the same graph counted alone."""
+    import threading
+
+    import numpy as np
+
+    import gen
+    import paper_2308_07932_amd as bbc
+    t0 = time.perf_counter()
+    params = gen.serving_large_params(n_templates)
+    large = [gen.chung_lu_graph_fast(sd, nu, nv, m, p_neg=pn) for sd, nu, nv, m, pn in params]
+    log(f"serving: {len(large)} large job graphs ({sum(g.n_edges for g in large)} edges) generated "
+        f"in {time.perf_counter() - t0:.1f}s")
+    # each large graph alone (its reference result and its service time)
+    ctx = bbc.Context(0)
+    alone, t_alone = [], []
+    for g in large:
+        ctx.count(g.eu, g.ev, g.sign, g.n_u, g.n_v)  # warm the workspace
+        t1 = time.perf_counter()
+        alone.append(ctx.count(g.eu, g.ev, g.sign, g.n_u, g.n_v))
+        t_alone.append(time.perf_counter() - t1)
+    ctx.close()
+    mean_large = float(np.mean(t_alone))
+    rate = load / (0.2 * mean_large)  # requests/s; small jobs cost little next to large ones
+    rng = np.random.default_rng(seed)
+    kinds = rng.random(n_requests) < 0.8
+    pick = np.where(kinds, rng.integers(0, len(small_graphs), n_requests),
+                    rng.integers(0, len(large), n_requests))
+    gaps = rng.exponential(1.0 / rate, n_requests)
+    results = [None] * n_requests
+    with bbc.Server(0, large_workers=2) as srv:
+        # warm the workers' workspaces on the largest graph and a small batch
+        big = max(large, key=lambda g: g.n_edges)
+        srv.poll(srv.submit(big.eu, big.ev, big.sign, big.n_u, big.n_v))
+        tickets = [None] * n_requests
+
+        def feed():
+            t_next = time.perf_counter()
+            for i in range(n_requests):
+                t_next += gaps[i]
+                d = t_next - time.perf_counter()
+                if d > 0:
+                    time.sleep(d)
+                g = small_graphs[pick[i]] if kinds[i] else large[pick[i]]
+                tickets[i] = srv.submit(g.eu, g.ev, g.sign, g.n_u, g.n_v)
+
+        t_start = time.perf_counter()
+        th = threading.Thread(target=feed)
+        th.start()
+        th.join()
+        for i in range(n_requests):
+            results[i] = srv.poll(tickets[i], wait_ms=-1)
+        t_end = time.perf_counter()
+        st = srv.stats()
+    lat = np.array([r.latency_ms for r in results])
+    exact = 0
+    for i, r in enumerate(results):
+        want = small_results[pick[i]] if kinds[i] else alone[pick[i]]
+        exact += r.status == bbc.OK and r.result == want
+    ls, ll = lat[kinds], lat[~kinds]
+    out = {
+        "workload": "Poisson arrivals; 80% graphs of the batched workload, 20% Chung-Lu graphs with "
+                    "|U|,|V| log-uniform in [1e5, 2e6], edges log-uniform in [1e6, 3e7], P(-1) "
+                    f"uniform in [0.1, 0.4] ({len(large)} drawn graphs reused)",
+        "requests": n_requests, "rate_per_s": rate, "target_load": load,
+        "graphs_per_s": n_requests / (t_end - t_start),
+        "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+        "small_p50_ms": float(np.percentile(ls, 50)) if ls.size else None,
+        "small_p99_ms": float(np.percentile(ls, 99)) if ls.size else None,
+        "large_p50_ms": float(np.percentile(ll, 50)) if ll.size else None,
+        "large_p99_ms": float(np.percentile(ll, 99)) if ll.size else None,
+        "large_alone_mean_ms": mean_large * 1e3,
+        "batches": st["batches"], "max_batch": st["max_batch"], "peak_running": st["peak_running"],
+        "peak_reserved_bytes": st["peak_reserved"],
+        "exact_vs_alone": f"{exact}/{n_requests}",
+    }
+    log(f"serving: {n_requests} requests at {rate:.0f}/s: {out['graphs_per_s']:.0f} graphs/s, p50 "
+        f"{out['p50_ms']:.2f} ms, p99 {out['p99_ms']:.2f} ms; exact {exact}/{n_requests}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -185,6 +274,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=3)
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=1500)
+    ap.add_argument("--serving-load", type=float, default=0.8)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -235,7 +327,7 @@ def main():
     achieved = alg_bytes / (phase[2] * 1e-3) / 1e9
     traffic = measured_traffic(args.workload)
     out = {
-        "metric": "wedges/sec + total count time (1 GPU)",
+        "metric": "wedges/sec + total count time (1 GPU); batched graphs/sec and p50/p99 latency",
         "value": W / (ms * 1e-3),
         "unit": "wedges/s",
         "n_gpus": 1,
@@ -260,6 +352,9 @@ def main():
     }
     if not args.no_batched:
         out["batched"] = bench_batched(ctx, args.batched_steps, 1, 24)
+        if not args.no_serving:
+            out["serving"] = bench_serving(bench_batched.graphs, bench_batched.results, 4,
+                                           args.serving_requests, args.serving_load)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline(g, W, args.cpu_seconds)

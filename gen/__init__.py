@@ -8,6 +8,8 @@ from .graphs import (  # noqa: F401
     uniform_graph,
     voting_graph,
     chung_lu_graph,
+    chung_lu_graph_fast,
+    serving_large_params,
     random_graph,
     complete_graph,
     batch_graph_params,

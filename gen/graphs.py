@@ -111,6 +111,49 @@ def chung_lu_graph(seed: int = 3, n_u: int = 1_000_000, n_v: int = 300_000,
                  f"chunglu{n_u}x{n_v}e{n_edges}a{alpha}s{seed}")
 
 
+def chung_lu_graph_fast(seed: int, n_u: int, n_v: int, n_edges: int, alpha: float = 2.1,
+                        p_neg: float = 0.2) -> SignedBipartiteGraph:
+    """Chung-Lu graph as chung_lu_graph (Zipf(alpha) weights capped at the
+    other side's size, endpoints drawn independently in proportion to the
+    weights), drawn in bulk for speed: the number of draws landing on each
+    vertex is one multinomial sample per side, the two endpoint lists are
+    shuffled and paired, and repeated pairs are removed by keeping a uniformly
+    random n_edges of the distinct pairs (drawing more while there are too
+    few).  Used for the large jobs of the serving workload (up to 3e7 edges)."""
+    rng = np.random.default_rng(seed)
+    wu = np.minimum(rng.zipf(alpha, n_u), n_v).astype(np.float64)
+    wv = np.minimum(rng.zipf(alpha, n_v), n_u).astype(np.float64)
+    pu = wu / wu.sum()
+    pv = wv / wv.sum()
+    kept = np.empty(0, dtype=np.int64)
+    while kept.shape[0] < n_edges:
+        m = int((n_edges - kept.shape[0]) * 1.3) + 1024
+        u = np.repeat(np.arange(n_u, dtype=np.int64), rng.multinomial(m, pu))
+        v = np.repeat(np.arange(n_v, dtype=np.int64), rng.multinomial(m, pv))
+        rng.shuffle(u)
+        rng.shuffle(v)
+        kept = np.unique(np.concatenate([kept, u * n_v + v]))
+    kept = kept[rng.permutation(kept.shape[0])[:n_edges]]
+    u = kept // n_v
+    v = kept % n_v
+    return _pack(n_u, n_v, u, v, _signs(rng, n_edges, p_neg),
+                 f"chunglufast{n_u}x{n_v}e{n_edges}a{alpha}s{seed}")
+
+
+def serving_large_params(count: int, seed: int = 5):
+    """Large jobs of the serving workload: |U|, |V| log-uniform in [1e5, 2e6],
+    edges log-uniform in [1e6, 3e7] (at most |U||V|/4), P(-1) uniform in
+    [0.1, 0.4]; returns a list of (seed, n_u, n_v, n_edges, p_neg)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        nu = int(round(math.exp(rng.uniform(math.log(1e5), math.log(2e6)))))
+        nv = int(round(math.exp(rng.uniform(math.log(1e5), math.log(2e6)))))
+        m = int(round(math.exp(rng.uniform(math.log(1e6), math.log(3e7)))))
+        out.append((100 + i, nu, nv, min(m, nu * nv // 4), float(rng.uniform(0.1, 0.4))))
+    return out
+
+
 def random_graph(rng: np.random.Generator, n_u: int, n_v: int, density: float,
                  p_neg: float = 0.5) -> SignedBipartiteGraph:
     """Small Erdos-Renyi-style bipartite graph for tests: each pair present with

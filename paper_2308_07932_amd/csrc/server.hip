@@ -261,6 +261,7 @@ bbc_status bbc_server_submit(bbc_server* s, int32_t n_u, int32_t n_v, int64_t n_
     const int64_t fp = bbc_workspace_bytes(n_u, n_v, n_edges);
     if (fp < 0) return BBC_ERR_TOO_LARGE;
     Job* j = new Job();
+    j->t_submit = Clock::now();  // arrival: the input copy below counts toward latency
     j->n_u = n_u;
     j->n_v = n_v;
     j->eu.assign(edge_u, edge_u + n_edges);
@@ -268,7 +269,6 @@ bbc_status bbc_server_submit(bbc_server* s, int32_t n_u, int32_t n_v, int64_t n_
     j->sg.assign(edge_sign, edge_sign + n_edges);
     // input copy on the device, plus the workspace
     j->footprint = (uint64_t)fp + 9ull * (uint64_t)n_edges;
-    j->t_submit = Clock::now();
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->stop) {
         delete j;
