@@ -275,6 +275,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=3)
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--only-batched", action="store_true",
+                    help="run the batched workload alone (for profiling); its line reports graphs/s")
     ap.add_argument("--serving-requests", type=int, default=1500)
     ap.add_argument("--serving-load", type=float, default=0.8)
     args = ap.parse_args()
@@ -289,6 +291,19 @@ def main():
 
     import gen
     import paper_2308_07932_amd as bbc
+
+    if args.only_batched:
+        ctx = bbc.Context(0, stream=torch.cuda.current_stream().cuda_stream)
+        ctx.set_timing(True)
+        b = bench_batched(ctx, args.batched_steps, 1, 24)
+        print(json.dumps({"metric": "batched graphs/sec (1 GPU)", "value": b["graphs_per_s"],
+                          "unit": "graphs/s", "n_gpus": 1, "steps": args.batched_steps, "warmup": 1,
+                          "ms_per_step": b["ms_per_batch"], "higher_is_better": True,
+                          "scaling": "weak", "vs_baseline": None, "dtype": "u64",
+                          "data": "synthetic", "config": {"workload": b["workload"]},
+                          "batched": b}), flush=True)
+        ctx.close()
+        return
 
     t0 = time.perf_counter()
     g = gen.workload(args.workload)
