@@ -244,11 +244,28 @@ bbc_status bbc_last_stats(const bbc_context* ctx, int64_t* stats, int n);
  *                          C(a+b,2) = C(a,2) + C(b,2) + ab); the chunk is also
  *                          at least W / 2048.  Default 65536, range
  *                          [1024, 2^40].
+ *   BBC_PARAM_GRAPHS       1: run the pipeline's two device segments (input
+ *                          checks to work totals; work items to results) as
+ *                          HIP graphs, captured when a segment's sizes,
+ *                          buffers and settings are new and replayed while
+ *                          they repeat (e.g. the same batch shape again).
+ *                          Results are identical either way.  With timing
+ *                          on, phase 1 is then the first segment and phase 2
+ *                          the second.  Default 0.
+ *   BBC_PARAM_GRAPH_CAPTURES, BBC_PARAM_GRAPH_REPLAYS  (bbc_get_param only)
+ *                          segments captured and replayed so far.
  * bbc_set_param returns BBC_ERR_INVALID_ARG for a NULL context, an unknown
  * parameter or a value out of range (the setting is then unchanged);
  * bbc_get_param writes the current value to *value.
  */
-enum { BBC_PARAM_HASH_TARGET = 1, BBC_PARAM_PROBE_LIMIT = 2, BBC_PARAM_CHUNK_WEDGES = 3 };
+enum {
+    BBC_PARAM_HASH_TARGET = 1,
+    BBC_PARAM_PROBE_LIMIT = 2,
+    BBC_PARAM_CHUNK_WEDGES = 3,
+    BBC_PARAM_GRAPHS = 4,         /* 0 / 1 */
+    BBC_PARAM_GRAPH_CAPTURES = 5, /* read only */
+    BBC_PARAM_GRAPH_REPLAYS = 6   /* read only */
+};
 bbc_status bbc_set_param(bbc_context* ctx, int param, int64_t value);
 bbc_status bbc_get_param(const bbc_context* ctx, int param, int64_t* value);
 

@@ -42,6 +42,9 @@ PER_VERTEX = 4
 PARAM_HASH_TARGET = 1
 PARAM_PROBE_LIMIT = 2
 PARAM_CHUNK_WEDGES = 3
+PARAM_GRAPHS = 4
+PARAM_GRAPH_CAPTURES = 5
+PARAM_GRAPH_REPLAYS = 6
 
 PHASE_TOTAL, PHASE_PREP, PHASE_WEDGE, PHASE_PLAN = 0, 1, 2, 3
 

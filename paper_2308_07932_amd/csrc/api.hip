@@ -86,6 +86,12 @@ struct bbc_context {
     uint64_t chunk_min = bbc::kRecordChunkWedges;
     int64_t* pv_host = nullptr;  // pinned staging of per-vertex counts
     size_t pv_host_cap = 0;
+    bool use_graphs = false;     // capture the two device segments and replay them
+    struct GraphSlot {
+        std::vector<uint64_t> key;
+        hipGraphExec_t exec = nullptr;
+    } seg[2];
+    int64_t graph_captures = 0, graph_replays = 0;
     char err[512] = {0};
 };
 
@@ -315,6 +321,8 @@ void bbc_destroy(bbc_context* c) {
     if (c->plan.base) hipFree(c->plan.base);
     if (c->batch.base) hipFree(c->batch.base);
     if (c->pv_host) hipHostFree(c->pv_host);
+    for (auto& g : c->seg)
+        if (g.exec) hipGraphExecDestroy(g.exec);
     if (c->host_ctl) hipHostFree(c->host_ctl);
     for (int i = 0; i < kNumEv; ++i)
         if (c->ev[i]) hipEventDestroy(c->ev[i]);
@@ -344,6 +352,10 @@ bbc_status bbc_set_param(bbc_context* c, int param, int64_t value) {
         if (value < 1024 || value > (1ll << 40)) return BBC_ERR_INVALID_ARG;
         c->chunk_min = (uint64_t)value;
         return BBC_OK;
+    case BBC_PARAM_GRAPHS:
+        if (value != 0 && value != 1) return BBC_ERR_INVALID_ARG;
+        c->use_graphs = value != 0;
+        return BBC_OK;
     default:
         return BBC_ERR_INVALID_ARG;
     }
@@ -355,6 +367,9 @@ bbc_status bbc_get_param(const bbc_context* c, int param, int64_t* value) {
     case BBC_PARAM_HASH_TARGET: *value = c->hash_target; return BBC_OK;
     case BBC_PARAM_PROBE_LIMIT: *value = c->probe_limit; return BBC_OK;
     case BBC_PARAM_CHUNK_WEDGES: *value = (int64_t)c->chunk_min; return BBC_OK;
+    case BBC_PARAM_GRAPHS: *value = c->use_graphs ? 1 : 0; return BBC_OK;
+    case BBC_PARAM_GRAPH_CAPTURES: *value = c->graph_captures; return BBC_OK;
+    case BBC_PARAM_GRAPH_REPLAYS: *value = c->graph_replays; return BBC_OK;
     default: return BBC_ERR_INVALID_ARG;
     }
 }
@@ -421,6 +436,47 @@ struct RunOut {
     uint32_t n;
 };
 
+// Runs one device segment of the pipeline: eagerly, or (graph mode) as a HIP
+// graph captured the first time its key is seen and replayed while the key
+// stays the same.  The key holds every size, address and setting a launch of
+// the segment depends on.  Segments record no memset nodes (all clearing is
+// done by fill kernels) and no events.
+template <class F>
+static bbc_status run_segment(bbc_context* c, int which, const std::vector<uint64_t>& key,
+                              F&& launches) {
+    if (!c->use_graphs) return launches();
+    hipStream_t st = c->stream;
+    auto& slot = c->seg[which];
+    if (!slot.exec || slot.key != key) {
+        if (slot.exec) {
+            HIPCHECK(c, hipGraphExecDestroy(slot.exec));
+            slot.exec = nullptr;
+        }
+        slot.key.clear();
+        HIPCHECK(c, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        const bbc_status s = launches();
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(st, &g);
+        if (s) {
+            if (g) hipGraphDestroy(g);
+            return s;
+        }
+        if (e != hipSuccess) return fail(c, BBC_ERR_DEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+        const hipError_t e2 = hipGraphInstantiate(&slot.exec, g, nullptr, nullptr, 0);
+        hipGraphDestroy(g);
+        if (e2 != hipSuccess) {
+            slot.exec = nullptr;
+            return fail(c, BBC_ERR_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e2));
+        }
+        slot.key = key;
+        c->graph_captures++;
+    } else {
+        c->graph_replays++;
+    }
+    HIPCHECK(c, hipGraphLaunch(slot.exec, st));
+    return BBC_OK;
+}
+
 static bbc_status run_pipeline(bbc_context* c, const RunIn& in, RunOut& ro) {
     hipStream_t st = c->stream;
     const uint32_t nu = in.nu, nv = in.nv, n = nu + nv;
@@ -479,17 +535,41 @@ static bbc_status run_pipeline(bbc_context* c, const RunIn& in, RunOut& ro) {
         ev = b.ev;
         sg = b.sg;
     }
-    const bool tm = c->timing;
-    if (tm) HIPCHECK(c, hipEventRecord(c->ev[kEvStart], st));
-
-    // ---- control block
+    const bool tm_out = c->timing;                   // events around the segments
+    const bool tm = c->timing && !c->use_graphs;     // events between kernels
+    const bool bt_on = bt != nullptr;
+    const uint32_t deg_bits = bt ? bitlen(std::min<uint64_t>(m, bt->max_side)) : 0;
+    const uint32_t g_bits = bt ? bitlen(bt->n_graphs - 1) : 0;
+    if (bt && deg_bits + g_bits > 32)
+        return fail(c, BBC_ERR_INTERNAL, "batch sort key needs %u bits", deg_bits + g_bits);
+    std::vector<uint64_t> keyA = {n, nu, nv, m, (uint64_t)eu, (uint64_t)ev, (uint64_t)sg,
+                                  (uint64_t)c->prep.base, tb_total, d.hash_target, d.probe_limit,
+                                  d.chunk_min, d.per_vertex, bt_on, deg_bits, g_bits};
+    if (bt) {
+        for (uint64_t x : {(uint64_t)bt->n_graphs, (uint64_t)bt->blk[0], (uint64_t)bt->blk[1],
+                           (uint64_t)bt->gres, (uint64_t)bt->gerr})
+            keyA.push_back(x);
+    }
+    if (in.ingest) {
+        const IngestArgs& ia = *in.ingest;
+        for (uint64_t x : {(uint64_t)ia.src_u, (uint64_t)ia.src_v, (uint64_t)ia.src_s,
+                           (uint64_t)ia.src_off, (uint64_t)ia.dst_off, (uint64_t)ia.gnu,
+                           (uint64_t)ia.gnv, (uint64_t)ia.uoff, (uint64_t)ia.voff,
+                           (uint64_t)ia.n_graphs, (uint64_t)ia.m, (uint64_t)ia.eu,
+                           (uint64_t)ia.ev, (uint64_t)ia.sg, (uint64_t)ia.gerr})
+            keyA.push_back(x);
+    }
+    if (tm_out) HIPCHECK(c, hipEventRecord(c->ev[kEvStart], st));
     {
         Control z;
         memset(&z, 0, sizeof(z));
         z.edge_err = ~0ull;
-        *c->host_ctl = z;
-        HIPCHECK(c, hipMemcpyAsync(b.ctl, c->host_ctl, sizeof(Control), hipMemcpyHostToDevice, st));
+        *c->host_ctl = z;  // read by the segment's upload (also when replayed)
     }
+    uint32_t* inv = nullptr;
+    bbc_status sA = run_segment(c, 0, keyA, [&]() -> bbc_status {
+    // ---- control block
+    HIPCHECK(c, hipMemcpyAsync(b.ctl, c->host_ctl, sizeof(Control), hipMemcpyHostToDevice, st));
     if (in.ingest) {
         IngestArgs ia = *in.ingest;
         ia.ctl = b.ctl;
@@ -501,12 +581,7 @@ static bbc_status run_pipeline(bbc_context* c, const RunIn& in, RunOut& ro) {
     HIPCHECK(c, launch_degree(eu, ev, sg, m, nu, nv, b.deg, b.ctl, st));
     // ---- 2. priority order: stable sort of vertex ids by degree (by graph,
     // then degree, for a batch)
-    uint32_t* inv = nullptr;
-    const uint32_t deg_bits = bt ? bitlen(std::min<uint64_t>(m, bt->max_side)) : 0;
     if (bt) {
-        const uint32_t g_bits = bitlen(bt->n_graphs - 1);
-        if (deg_bits + g_bits > 32)
-            return fail(c, BBC_ERR_INTERNAL, "batch sort key needs %u bits", deg_bits + g_bits);
         uint32_t* key = b.rowdeg;  // free until the row degrees are assigned
         HIPCHECK(c, launch_batch_keys(b.deg, d, deg_bits, key, st));
         HIPCHECK(c, radix_sort_by_key(key, n, deg_bits + g_bits, b.k0, b.v0, b.k1, b.v1, b.rtmp,
@@ -563,6 +638,10 @@ static bbc_status run_pipeline(bbc_context* c, const RunIn& in, RunOut& ro) {
                                      b.ctl, st));
     if (tm) HIPCHECK(c, hipEventRecord(c->ev[kEvPlanA], st));
     HIPCHECK(c, hipMemcpyAsync(c->host_ctl, b.ctl, sizeof(Control), hipMemcpyDeviceToHost, st));
+    return BBC_OK;
+    });
+    if (sA) return sA;
+    if (tm_out && c->use_graphs) HIPCHECK(c, hipEventRecord(c->ev[kEvPrepEnd], st));
     HIPCHECK(c, hipStreamSynchronize(st));
     Control h = *c->host_ctl;
     ro.h = h;
@@ -624,7 +703,13 @@ static bbc_status run_pipeline(bbc_context* c, const RunIn& in, RunOut& ro) {
         Carver cv(c->plan.base);
         carve_plan(cv);
     }
-    if (tm) HIPCHECK(c, hipEventRecord(c->ev[kEvPlanB], st));
+    std::vector<uint64_t> keyB = keyA;
+    for (uint64_t x : {(uint64_t)n_heavy, (uint64_t)n_light, (uint64_t)n_light_items, (uint64_t)h.tot_g,
+                       (uint64_t)h.tot_sw, (uint64_t)h.tot_tiles, (uint64_t)c->plan.base, (uint64_t)first_long[0],
+                       (uint64_t)first_long[1], (uint64_t)in.per_vertex})
+        keyB.push_back(x);
+    if (tm_out) HIPCHECK(c, hipEventRecord(c->ev[kEvPlanB], st));
+    bbc_status sB = run_segment(c, 1, keyB, [&]() -> bbc_status {
     HIPCHECK(c, fill_u64(G, 0, (size_t)h.tot_g, st));
     if (pv) HIPCHECK(c, fill_u64(pv, 0, n, st));
     HIPCHECK(c, launch_plan_write(b.wu, b.lowcnt, b.row_ptr, b.mptr, b.cursor, b.hp_off, b.lr_off,
@@ -658,18 +743,25 @@ static bbc_status run_pipeline(bbc_context* c, const RunIn& in, RunOut& ro) {
         HIPCHECK(c, launch_pv_out(pv, b.sidx_of, d, pv_out, st));
         HIPCHECK(c, hipMemcpyAsync(in.per_vertex, pv_out, 8ull * n, hipMemcpyDeviceToHost, st));
     }
-    if (tm) HIPCHECK(c, hipEventRecord(c->ev[kEvEnd], st));
     HIPCHECK(c, hipMemcpyAsync(c->host_ctl, b.ctl, sizeof(Control), hipMemcpyDeviceToHost, st));
+    return BBC_OK;
+    });
+    if (sB) return sB;
+    if (tm_out) HIPCHECK(c, hipEventRecord(c->ev[kEvEnd], st));
     HIPCHECK(c, hipStreamSynchronize(st));
     h = *c->host_ctl;
     ro.h = h;
     if (h.internal_err)
         return fail(c, BBC_ERR_INTERNAL, "a hashed work piece could not be split further");
-    if (tm) {
+    if (tm_out && !c->use_graphs) {
         c->phase_ms[0] += ev_ms(c, kEvStart, kEvEnd);
         c->phase_ms[1] += ev_ms(c, kEvStart, kEvPrepEnd);
         c->phase_ms[2] += ev_ms(c, kEvWedgeA, kEvWedgeB);
         c->phase_ms[3] += ev_ms(c, kEvPrepEnd, kEvPlanA) + ev_ms(c, kEvPlanB, kEvPlanC);
+    } else if (tm_out) {  // graph mode: the two replayed segments
+        c->phase_ms[0] += ev_ms(c, kEvStart, kEvEnd);
+        c->phase_ms[1] += ev_ms(c, kEvStart, kEvPrepEnd);
+        c->phase_ms[2] += ev_ms(c, kEvPlanB, kEvEnd);
     }
     ro.n_items = n_items;
     ro.n_heavy = n_heavy;

@@ -172,3 +172,44 @@ def test_batched_recipe_sample(ctx):
         assert (int(res.balanced[k]), int(res.unbalanced[k])) == (b, u), (idx[k], g.name)
     for k in range(0, len(graphs), 25):
         assert int(res.wedges[k]) == oracle.wedges(graphs[k])
+
+
+def test_graph_replay_matches_eager(ctx):
+    # the pipeline's two segments captured as HIP graphs and replayed for
+    # repeated shapes; eager work and synchronisations run between replays
+    import torch
+    graphs = mixed_graphs(12, 120)
+    nu, nv, off, eu, ev, sg = bbc.concat_graphs(graphs)
+    eager = ctx.count_batch(nu, nv, off, eu, ev, sg)
+    dev = torch.device("cuda:0")
+    t = [torch.from_numpy(x).to(dev) for x in (eu, ev, sg)]
+    torch.cuda.synchronize()
+    gctx = bbc.Context(0)
+    try:
+        gctx.set_param(bbc.PARAM_GRAPHS, 1)
+        other = gen.uniform_graph(seed=77, n_u=500, n_v=400, n_edges=9000)
+        want_other = ctx.count(other.eu, other.ev, other.sign, other.n_u, other.n_v)
+        for rep in range(4):
+            res = gctx.count_batch(nu, nv, off, *t)
+            for a, b in zip(eager, res):
+                assert np.array_equal(a, b), rep
+            # eager work on another context and the torch stream in between
+            assert ctx.count(other.eu, other.ev, other.sign, other.n_u, other.n_v) == want_other
+            x = torch.arange(1 << 20, device=dev, dtype=torch.int64)
+            assert int(x.sum().item()) == (1 << 20) * ((1 << 20) - 1) // 2
+            torch.cuda.synchronize()
+        assert gctx.get_param(bbc.PARAM_GRAPH_CAPTURES) == 2
+        assert gctx.get_param(bbc.PARAM_GRAPH_REPLAYS) == 6
+        # a new shape is captured again and stays exact; single graphs and
+        # per-vertex counts replay as well
+        res = gctx.count_batch(nu[:60], nv[:60], off[:61], *t)
+        for a, b in zip(eager, res):
+            assert np.array_equal(a[:60], b)
+        g = gen.voting_graph(seed=8, n_u=60, n_v=2000, p_edge=0.5)
+        want = ctx.count(g.eu, g.ev, g.sign, g.n_u, g.n_v, per_vertex=True)
+        for rep in range(3):
+            r, pv = gctx.count(g.eu, g.ev, g.sign, g.n_u, g.n_v, per_vertex=True)
+            assert r == want[0] and np.array_equal(pv, want[1]), rep
+            assert gctx.count(g.eu, g.ev, g.sign, g.n_u, g.n_v) == want[0]
+    finally:
+        gctx.close()
