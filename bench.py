@@ -116,6 +116,12 @@ def bench_batched(ctx, steps: int, warmup: int, oracle_sample: int):
     dev = torch.device("cuda:0")
     te = [torch.from_numpy(x).to(dev) for x in cat[3:]]
     torch.cuda.synchronize()
+    # tunables picked by the autotuner on the first 2,000 graphs of the batch
+    k = 2000
+    t0 = time.perf_counter()
+    chosen, _ = ctx.autotune(cat[0][:k], cat[1][:k], cat[2][:k + 1], *te, repeats=2)
+    tune_s = time.perf_counter() - t0
+    log(f"autotune on {k} graphs ({tune_s:.1f}s): {chosen}")
     for _ in range(warmup):
         res = ctx.count_batch(*cat[:3], *te)
     torch.cuda.synchronize()
@@ -131,6 +137,35 @@ def bench_batched(ctx, steps: int, warmup: int, oracle_sample: int):
     st = ctx.stats()
     assert (res.status == bbc.OK).all()
     W = int(res.wedges.sum())
+    # the same batch again with the two pipeline segments replayed as HIP graphs
+    ctx.set_param(bbc.PARAM_GRAPHS, 1)
+    for _ in range(warmup):
+        rg = ctx.count_batch(*cat[:3], *te)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        rg = ctx.count_batch(*cat[:3], *te)
+    torch.cuda.synchronize()
+    ms_graph = (time.perf_counter() - t0) * 1e3 / steps
+    graph_equal = all(np.array_equal(a, b) for a, b in zip(res, rg))
+    ctx.set_param(bbc.PARAM_GRAPHS, 0)
+    # a small batch (the 256 graphs with the fewest edges), where launches
+    # dominate: eager calls vs graph replay
+    small_idx = np.argsort(np.diff(off), kind="stable")[:256]
+    sg_ = [graphs[i] for i in sorted(small_idx)]
+    scat = bbc.concat_graphs(sg_)
+    ste = [torch.from_numpy(x).to(dev) for x in scat[3:]]
+    torch.cuda.synchronize()
+    small_ms = {}
+    for mode in (0, 1):
+        ctx.set_param(bbc.PARAM_GRAPHS, mode)
+        for _ in range(3):
+            ctx.count_batch(*scat[:3], *ste)
+        t0 = time.perf_counter()
+        for _ in range(50):
+            ctx.count_batch(*scat[:3], *ste)
+        small_ms[mode] = (time.perf_counter() - t0) * 1e3 / 50
+    ctx.set_param(bbc.PARAM_GRAPHS, 0)
     # plain loop: one bbc_count per graph, same device-resident edges
     t0 = time.perf_counter()
     plain_equal = True
@@ -170,7 +205,13 @@ def bench_batched(ctx, steps: int, warmup: int, oracle_sample: int):
         "graphs_per_s": len(graphs) / (ms * 1e-3), "ms_per_batch": ms,
         "wedges_per_s": W / (ms * 1e-3),
         "phase_ms": {"prep": phase[1], "plan": phase[3], "wedge_kernel": phase[2]},
-        "work_items": st[4], "plain_loop_graphs_per_s": len(graphs) / plain_s,
+        "work_items": st[4], "autotuned": chosen, "autotune_s": tune_s,
+        "graph_replay_ms_per_batch": ms_graph,
+        "graph_replay_graphs_per_s": len(graphs) / (ms_graph * 1e-3),
+        "graph_replay_results_equal": bool(graph_equal),
+        "small_batch_256": {"edges": int(scat[2][-1]), "eager_ms": small_ms[0],
+                            "graph_replay_ms": small_ms[1]},
+        "plain_loop_graphs_per_s": len(graphs) / plain_s,
         "plain_loop_s": plain_s, "speedup_vs_plain_loop": plain_s / (ms * 1e-3),
         "plain_loop_results_equal": bool(plain_equal),
         "oracle_sample_exact": f"{ok}/{len(sample)}",

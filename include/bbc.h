@@ -193,6 +193,25 @@ bbc_status bbc_server_poll(bbc_server* srv, uint64_t ticket, int32_t wait_ms, bb
 bbc_status bbc_server_stats(bbc_server* srv, int64_t* stats, int n);
 void bbc_server_destroy(bbc_server* srv);
 
+/*
+ * Autotuner: pick the work-split tunables for a workload by measurement.
+ * The input is laid out as for bbc_count_batch (n_graphs = 1 tunes
+ * bbc_count on that graph).  Starting from the context's current settings,
+ * a coordinate search tries record-chunk floors {16K, 64K, 256K, 1M, 4M}
+ * wedges, hash targets {1024, 2048, 4096, 8192} and probe limits
+ * {32, 256, 2048}, timing each setting as the best of `repeats` whole calls
+ * (1..100) and keeping a value only for a gain above 3%.  Every call must
+ * give the same counts and statuses as the first one (else
+ * BBC_ERR_INTERNAL, and the settings are restored).  On success the best
+ * settings stay on the context; chosen[0..2] (may be NULL) receives
+ * {chunk wedges, hash target, probe limit} and *best_ms (may be NULL) the
+ * best call time in milliseconds (host clock).
+ */
+bbc_status bbc_autotune(bbc_context* ctx, int32_t n_graphs, const int32_t* n_u,
+                        const int32_t* n_v, const int64_t* edge_offset, const int32_t* edge_u,
+                        const int32_t* edge_v, const int8_t* edge_sign, uint32_t flags,
+                        int32_t repeats, int64_t* chosen, double* best_ms);
+
 /* Static description of a status code (never NULL). */
 const char* bbc_status_string(bbc_status status);
 

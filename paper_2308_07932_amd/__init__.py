@@ -112,6 +112,9 @@ def load_library():
     lib.bbc_get_param.restype = ctypes.c_int
     lib.bbc_count_batch.argtypes = [P, I32, P, P, P, P, P, P, U32, P, P]
     lib.bbc_count_batch.restype = ctypes.c_int
+    lib.bbc_autotune.argtypes = [P, I32, P, P, P, P, P, P, U32, I32,
+                                 ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]
+    lib.bbc_autotune.restype = ctypes.c_int
     lib.bbc_workspace_bytes.argtypes = [I32, I32, I64]
     lib.bbc_workspace_bytes.restype = ctypes.c_int64
     lib.bbc_server_create.argtypes = [P, ctypes.POINTER(P)]
@@ -264,6 +267,29 @@ class Context:
         r = self.count_raw(n_u, n_v, n, *ptrs, flags=flags, per_vertex_ptr=pv_ptr)
         del keep
         return (r, pv) if per_vertex else r
+
+    def autotune(self, n_u, n_v, edge_offset, eu, ev, sign, repeats: int = 2):
+        """bbc_autotune on a batch (or one graph): returns ({chunk_wedges,
+        hash_target, probe_limit}, best call ms); the settings stay on the context."""
+        nu = np.ascontiguousarray(n_u, dtype=np.int32)
+        nv = np.ascontiguousarray(n_v, dtype=np.int32)
+        off = np.ascontiguousarray(edge_offset, dtype=np.int64)
+        ptrs, keep, on_dev, n = _prepare(eu, ev, sign)
+        if on_dev:
+            import torch
+            cur = torch.cuda.current_stream(keep[0].device)
+            if self.stream is None or int(cur.cuda_stream) != int(self.stream):
+                cur.synchronize()
+        ch = (ctypes.c_int64 * 3)()
+        best = ctypes.c_double()
+        rc = self._lib.bbc_autotune(self._h, int(nu.shape[0]), nu.ctypes.data, nv.ctypes.data,
+                                    off.ctypes.data, *ptrs, INPUT_ON_DEVICE if on_dev else 0,
+                                    int(repeats), ch, ctypes.byref(best))
+        del keep
+        if rc != OK:
+            raise BBCError(rc, self.last_error() or status_string(rc))
+        return {"chunk_wedges": int(ch[0]), "hash_target": int(ch[1]),
+                "probe_limit": int(ch[2])}, float(best.value)
 
     def count_batch(self, n_u, n_v, edge_offset, eu, ev, sign) -> "BatchResult":
         """Count many graphs in one call (bbc_count_batch): n_u, n_v (n_graphs

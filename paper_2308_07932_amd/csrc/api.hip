@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 #include <vector>
 
 #include "bbc.h"
@@ -1110,3 +1111,112 @@ bbc_status bbc_count_batch(bbc_context* c, int32_t n_graphs, const int32_t* n_u,
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Autotuner: coordinate search over the work-split tunables on the caller's
+// own input, timing whole calls.
+
+namespace {
+struct TuneInput {
+    int32_t n_graphs;
+    const int32_t *n_u, *n_v;
+    const int64_t* off;
+    const int32_t *eu, *ev;
+    const int8_t* sg;
+    uint32_t flags;
+};
+
+// One timed call; *sum receives a checksum of every count (balanced,
+// unbalanced, W of every graph) so that all settings can be compared.
+bbc_status tune_call(bbc_context* c, const TuneInput& in, std::vector<bbc_result>& res,
+                     std::vector<int32_t>& st, double* ms) {
+    const auto t0 = std::chrono::steady_clock::now();
+    bbc_status s;
+    if (in.n_graphs == 1) {
+        st[0] = BBC_OK;
+        s = bbc_count(c, in.n_u[0], in.n_v[0], in.off[1] - in.off[0], in.eu + in.off[0],
+                      in.ev + in.off[0], in.sg + in.off[0], in.flags, &res[0], nullptr);
+    } else {
+        s = bbc_count_batch(c, in.n_graphs, in.n_u, in.n_v, in.off, in.eu, in.ev, in.sg, in.flags,
+                            res.data(), st.data());
+    }
+    *ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return s;
+}
+}  // namespace
+
+extern "C" {
+
+bbc_status bbc_autotune(bbc_context* c, int32_t n_graphs, const int32_t* n_u, const int32_t* n_v,
+                        const int64_t* edge_offset, const int32_t* edge_u, const int32_t* edge_v,
+                        const int8_t* edge_sign, uint32_t flags, int32_t repeats,
+                        int64_t* chosen, double* best_ms) {
+    if (!c) return BBC_ERR_INVALID_ARG;
+    if (n_graphs < 1 || !n_u || !n_v || !edge_offset || repeats < 1 || repeats > 100)
+        return fail(c, BBC_ERR_INVALID_ARG, "autotune: bad sizes or repeats");
+    if (flags & ~(uint32_t)BBC_INPUT_ON_DEVICE)
+        return fail(c, BBC_ERR_INVALID_ARG, "autotune: unsupported flags 0x%x", flags);
+    TuneInput in{n_graphs, n_u, n_v, edge_offset, edge_u, edge_v, edge_sign, flags};
+    std::vector<bbc_result> res((size_t)n_graphs), ref((size_t)n_graphs);
+    std::vector<int32_t> st((size_t)n_graphs), ref_st((size_t)n_graphs);
+    const int pids[3] = {BBC_PARAM_CHUNK_WEDGES, BBC_PARAM_HASH_TARGET, BBC_PARAM_PROBE_LIMIT};
+    const std::vector<int64_t> grid[3] = {{16384, 65536, 262144, 1048576, 4194304},
+                                          {1024, 2048, 4096, 8192},
+                                          {32, 256, 2048}};
+    int64_t cur[3];
+    for (int k = 0; k < 3; ++k) bbc_get_param(c, pids[k], &cur[k]);
+    const int64_t saved[3] = {cur[0], cur[1], cur[2]};
+    auto restore = [&]() {
+        for (int k = 0; k < 3; ++k) bbc_set_param(c, pids[k], saved[k]);
+    };
+    // reference counts and a warm workspace at the current settings
+    double ms = 0;
+    bbc_status s = tune_call(c, in, ref, ref_st, &ms);
+    if (s) return s;
+    auto timed = [&](double* best) -> bbc_status {
+        *best = 1e300;
+        for (int r = 0; r < repeats; ++r) {
+            double t = 0;
+            bbc_status e = tune_call(c, in, res, st, &t);
+            if (e) return e;
+            for (int32_t g = 0; g < n_graphs; ++g)
+                if (st[g] != ref_st[g] || res[g].balanced != ref[g].balanced ||
+                    res[g].unbalanced != ref[g].unbalanced || res[g].wedges != ref[g].wedges)
+                    return fail(c, BBC_ERR_INTERNAL, "autotune: graph %d counted differently", g);
+            *best = std::min(*best, t);
+        }
+        return BBC_OK;
+    };
+    double best = 0;
+    s = timed(&best);
+    if (s) {
+        restore();
+        return s;
+    }
+    for (int k = 0; k < 3; ++k) {
+        int64_t keep = cur[k];
+        for (int64_t v : grid[k]) {
+            if (v == keep) continue;
+            if (bbc_set_param(c, pids[k], v) != BBC_OK) continue;
+            double t = 0;
+            s = timed(&t);
+            if (s) {
+                restore();
+                return s;
+            }
+            if (t < best * 0.97) {  // a clear gain only
+                best = t;
+                keep = v;
+            }
+        }
+        cur[k] = keep;
+        bbc_set_param(c, pids[k], keep);
+    }
+    if (chosen)
+        for (int k = 0; k < 3; ++k) chosen[k] = cur[k];
+    if (best_ms) *best_ms = best;
+    return BBC_OK;
+}
+
+}  // extern "C"
+

@@ -213,3 +213,29 @@ def test_graph_replay_matches_eager(ctx):
             assert gctx.count(g.eu, g.ev, g.sign, g.n_u, g.n_v) == want[0]
     finally:
         gctx.close()
+
+
+def test_autotune_keeps_counts(ctx):
+    graphs = mixed_graphs(13, 150)
+    nu, nv, off, eu, ev, sg = bbc.concat_graphs(graphs)
+    before = ctx.count_batch(nu, nv, off, eu, ev, sg)
+    tctx = bbc.Context(0)
+    try:
+        chosen, best = tctx.autotune(nu, nv, off, eu, ev, sg, repeats=1)
+        assert chosen["chunk_wedges"] in (16384, 65536, 262144, 1048576, 4194304)
+        assert chosen["hash_target"] in (1024, 2048, 4096, 8192)
+        assert chosen["probe_limit"] in (32, 256, 2048)
+        assert best > 0
+        assert tctx.get_param(bbc.PARAM_CHUNK_WEDGES) == chosen["chunk_wedges"]
+        assert tctx.get_param(bbc.PARAM_HASH_TARGET) == chosen["hash_target"]
+        after = tctx.count_batch(nu, nv, off, eu, ev, sg)
+        for a, b in zip(before, after):
+            assert np.array_equal(a, b)
+        # one graph with split starts: tuned on bbc_count
+        g = gen.chung_lu_graph(seed=11, n_u=60000, n_v=20000, n_edges=250000, p_neg=0.25)
+        want = ctx.count(g.eu, g.ev, g.sign, g.n_u, g.n_v)
+        chosen, best = tctx.autotune([g.n_u], [g.n_v], [0, g.n_edges], g.eu, g.ev, g.sign,
+                                     repeats=1)
+        assert tctx.count(g.eu, g.ev, g.sign, g.n_u, g.n_v) == want
+    finally:
+        tctx.close()
