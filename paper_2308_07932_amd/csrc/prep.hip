@@ -476,12 +476,16 @@ __global__ __launch_bounds__(kBigThreads) void k_sort_big(const uint32_t* __rest
 }
 
 // --------------------------------------------------- lower neighbour counts --
+// k_r (entries below the row's own priority: its middles) and the rest (its
+// upper entries, each the middle of a record of a higher start)
 __global__ void k_lowcount(const uint32_t* __restrict__ row_ptr, const uint32_t* __restrict__ col,
                            const uint32_t* __restrict__ rowcross, uint32_t n,
-                           uint32_t* __restrict__ lowcnt) {
+                           uint32_t* __restrict__ lowcnt, uint32_t* __restrict__ upcnt) {
     for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
         uint32_t a = row_ptr[r], L = row_ptr[r + 1] - a;
-        lowcnt[r] = lower_bound_u32(col + a, L, rowcross[r] << 1);
+        const uint32_t k = lower_bound_u32(col + a, L, rowcross[r] << 1);
+        lowcnt[r] = k;
+        upcnt[r] = L - k;
     }
 }
 
@@ -489,101 +493,121 @@ __global__ void k_lowcount(const uint32_t* __restrict__ row_ptr, const uint32_t*
 // Records come from the upper part of every row: in the sorted row of v, the
 // entry at index i >= k_v names a neighbour u of higher priority, and exactly
 // i entries precede it, all of lower priority than u -- so pos_v(u) = i with
-// no search.  The record is appended to u's record list: records whose middle
-// row v is long fill u's slots from the front, the others from the back (slots
-// reserved through an LDS table as in the scatter).  i is added to W_u, and to
-// Ws_u (the wedges through short middle rows) for the short ones.  The order of
-// a start's records is otherwise irrelevant to the count.
+// no search.  The records are first written in row-v order (slot uptr[v] +
+// i - k_v) with the key (row u) << 1 | short, short meaning the middle row v
+// has at most kLongDeg entries; a radix sort of the keys and a gather then
+// place each start's records together, long-middle ones first, in the slots
+// [mptr[u], mptr[u+1]).  No slot is reserved by atomics.  W_u (and Ws_u, the
+// wedges through short middle rows) are sums of pos over the sorted records.
 //   .x = first entry of row v, .y = pos << 1 | neg(u, v), .z = sidx(v), .w = row u
-constexpr int kRecPer = 4;  // consecutive CSR entries per thread
-constexpr uint32_t kRecChunk = kAggThreads * kRecPer;
-constexpr uint32_t kRecLog2 = 11;
-constexpr uint32_t kRecSlots = 1u << kRecLog2;
+constexpr int kRecPer = 4;  // consecutive entries per thread
+constexpr int kRecThreads = 256;
 
-__global__ __launch_bounds__(kAggThreads) void k_records(
+__global__ __launch_bounds__(kRecThreads) void k_records_raw(
     const uint32_t* __restrict__ row_ptr, const uint32_t* __restrict__ col,
-    const uint32_t* __restrict__ lowcnt, Dims d, const Control* ctl,
-    uint32_t* __restrict__ front, uint32_t* __restrict__ back, uint4* __restrict__ recs,
-    u64* __restrict__ wu, u64* __restrict__ wsu) {
-    __shared__ uint32_t keys[kRecSlots];
-    __shared__ uint32_t cnt[kRecSlots];  // long count | short count << 16
-    __shared__ uint32_t baseL[kRecSlots], baseS[kRecSlots];
-    __shared__ u64 wsum[kRecSlots], wsumS[kRecSlots];
-    const uint32_t tid = threadIdx.x;
+    const uint32_t* __restrict__ lowcnt, const uint32_t* __restrict__ uptr, Dims d, uint64_t m,
+    uint4* __restrict__ raw, uint32_t* __restrict__ key) {
     const uint64_t nnz = row_ptr[d.n];  // entries actually placed (invalid edges are not)
-    for (uint64_t c0 = (uint64_t)blockIdx.x * kRecChunk; c0 < nnz; c0 += (uint64_t)gridDim.x * kRecChunk) {
-        for (uint32_t i = tid; i < kRecSlots; i += kAggThreads) {
-            keys[i] = kEmpty;
-            cnt[i] = 0;
-            wsum[i] = 0;
-            wsumS[i] = 0;
+    const uint64_t stride = (uint64_t)gridDim.x * kRecThreads * kRecPer;
+    for (uint64_t e0 = ((uint64_t)blockIdx.x * kRecThreads + threadIdx.x) * kRecPer; e0 < nnz;
+         e0 += stride) {
+        uint32_t lo = 0, hi = d.n;  // row holding entry e0: last r with row_ptr[r] <= e0
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (row_ptr[mid] <= e0)
+                lo = mid;
+            else
+                hi = mid;
         }
-        __syncthreads();
-        const uint64_t e0 = c0 + (uint64_t)tid * kRecPer;
-        uint32_t slot[kRecPer], rank[kRecPer];
-        uint4 rec[kRecPer];
-        uint32_t r = 0;
-        if (e0 < nnz) {  // row holding entry e0: last r with row_ptr[r] <= e0
-            uint32_t lo = 0, hi = d.n;
-            while (hi - lo > 1) {
-                uint32_t mid = (lo + hi) >> 1;
-                if (row_ptr[mid] <= e0)
-                    lo = mid;
-                else
-                    hi = mid;
-            }
-            r = lo;
-        }
+        uint32_t r = lo;
         for (int k = 0; k < kRecPer; ++k) {
-            slot[k] = kEmpty - 1;
             const uint64_t e = e0 + k;
-            if (e >= nnz) continue;
+            if (e >= nnz) break;
             while (row_ptr[r + 1] <= e) ++r;
             const uint32_t rs = row_ptr[r];
             const uint32_t i = (uint32_t)(e - rs);
-            if (i < lowcnt[r]) continue;  // lower entry: v's own middle, not a record here
+            const uint32_t kv = lowcnt[r];
+            if (i < kv) continue;  // lower entry: v's own middle, not a record here
+            // descending row-v order: after the (stable) sort a start's records
+            // run from its highest-degree middles down, longest intervals first
+            const uint64_t slot = m - 1 - (uptr[r] + (i - kv));
             const uint32_t side = r >= d.n_u ? 1u : 0u;
             const uint32_t x = col[e];
-            if ((x >> 1) >= d.size[side ^ 1u]) continue;  // hole left by a repeated edge
+            if ((x >> 1) >= d.size[side ^ 1u] || uptr[r] + (i - kv) >= m) continue;  // a hole
             const uint32_t urow = d.base[side ^ 1u] + (x >> 1);
-            const bool is_long = row_ptr[r + 1] - rs > kLongDeg;
-            rec[k] = make_uint4(rs, (i << 1) | (x & 1u), r - d.base[side], urow);
-            const int sl = agg_slot<kRecLog2>(keys, urow);
+            const bool is_short = row_ptr[r + 1] - rs <= kLongDeg;
+            raw[slot] = make_uint4(rs, (i << 1) | (x & 1u), r - d.base[side], urow);
+            key[slot] = (urow << 1) | (is_short ? 1u : 0u);
+        }
+    }
+}
+
+// recs[j] = raw[order[j]]; W_u and Ws_u summed over each start's run of
+// sorted records, aggregated per workgroup in an LDS table (a hub start's
+// records span many threads); front[u] = the first short record of u (preset
+// to mptr[u+1] for a start without any).
+constexpr uint32_t kGatherLog2 = 10;
+constexpr uint32_t kGatherSlots = 1u << kGatherLog2;
+
+__global__ __launch_bounds__(kRecThreads) void k_records_gather(
+    const uint4* __restrict__ raw, const uint32_t* __restrict__ skey,
+    const uint32_t* __restrict__ order, uint64_t m, uint4* __restrict__ recs,
+    u64* __restrict__ wu, u64* __restrict__ wsu, uint32_t* __restrict__ front) {
+    __shared__ uint32_t keys[kGatherSlots];
+    __shared__ u64 sw[kGatherSlots], ss[kGatherSlots];
+    const uint32_t tid = threadIdx.x;
+    constexpr uint64_t kChunk = (uint64_t)kRecThreads * kRecPer;
+    for (uint64_t c0 = (uint64_t)blockIdx.x * kChunk; c0 < m; c0 += (uint64_t)gridDim.x * kChunk) {
+        for (uint32_t i = tid; i < kGatherSlots; i += kRecThreads) {
+            keys[i] = kEmpty;
+            sw[i] = 0;
+            ss[i] = 0;
+        }
+        __syncthreads();
+        uint32_t cur = kEmpty;
+        u64 accW = 0, accS = 0;
+        auto flush = [&]() {
+            if (cur == kEmpty || (accW == 0 && accS == 0)) return;
+            const int sl = agg_slot<kGatherLog2>(keys, cur);
             if (sl >= 0) {
-                slot[k] = (uint32_t)sl | (is_long ? 0u : 0x80000000u);
-                const uint32_t old = atomicAdd(&cnt[sl], is_long ? 1u : 0x10000u);
-                rank[k] = is_long ? (old & 0xFFFFu) : (old >> 16);
-                atomicAdd(&wsum[sl], (u64)i);
-                if (!is_long) atomicAdd(&wsumS[sl], (u64)i);
+                if (accW) atomicAdd(&sw[sl], accW);
+                if (accS) atomicAdd(&ss[sl], accS);
             } else {
-                slot[k] = kEmpty;  // position reserved directly
-                rank[k] = is_long ? atomicAdd(&front[urow], 1u) : atomicSub(&back[urow], 1u) - 1u;
-                atomicAdd(&wu[urow], (u64)i);
-                if (!is_long) atomicAdd(&wsu[urow], (u64)i);
+                if (accW) atomicAdd(&wu[cur], accW);
+                if (accS) atomicAdd(&wsu[cur], accS);
             }
-        }
-        __syncthreads();
-        for (uint32_t i = tid; i < kRecSlots; i += kAggThreads)
-            if (keys[i] != kEmpty) {
-                const uint32_t cl = cnt[i] & 0xFFFFu, cs = cnt[i] >> 16;
-                if (cl) baseL[i] = atomicAdd(&front[keys[i]], cl);
-                if (cs) baseS[i] = atomicSub(&back[keys[i]], cs) - cs;
-                atomicAdd(&wu[keys[i]], wsum[i]);
-                if (wsumS[i]) atomicAdd(&wsu[keys[i]], wsumS[i]);
-            }
-        __syncthreads();
+        };
+        const uint64_t j0 = c0 + (uint64_t)tid * kRecPer;
         for (int k = 0; k < kRecPer; ++k) {
-            const uint32_t sl = slot[k];
-            if (sl == kEmpty - 1) continue;
-            uint32_t at;
-            if (sl == kEmpty)
-                at = rank[k];
-            else if (sl & 0x80000000u)
-                at = baseS[sl & 0x7FFFFFFFu] + rank[k];
-            else
-                at = baseL[sl] + rank[k];
-            recs[at] = rec[k];
+            const uint64_t j = j0 + k;
+            if (j >= m) break;
+            const uint32_t key = skey[j];
+            if (key == kEmpty) {  // never written (invalid input): a harmless record
+                recs[j] = make_uint4(0, 0, 0, 0);
+                continue;
+            }
+            const uint4 rc = raw[order[j]];
+            recs[j] = rc;
+            const uint32_t u = key >> 1;
+            if (u != cur) {
+                flush();
+                cur = u;
+                accW = accS = 0;
+            }
+            const u64 pos = rc.y >> 1;
+            accW += pos;
+            if (key & 1u) {
+                accS += pos;
+                if (j == 0 || skey[j - 1] != key) front[u] = (uint32_t)j;
+            }
         }
+        flush();
+        __syncthreads();
+        for (uint32_t i = tid; i < kGatherSlots; i += kRecThreads)
+            if (keys[i] != kEmpty) {
+                if (sw[i]) atomicAdd(&wu[keys[i]], sw[i]);
+                if (ss[i]) atomicAdd(&wsu[keys[i]], ss[i]);
+            }
         __syncthreads();
     }
 }
@@ -640,7 +664,7 @@ size_t radix_tmp_bytes(uint32_t n) {
 // element indices in sorted order) end in *vals_result.
 hipError_t radix_sort_by_key(const uint32_t* keys_in, uint32_t n, uint32_t bits, uint32_t* k0,
                              uint32_t* v0, uint32_t* k1, uint32_t* v1, void* tmp, size_t tmp_bytes,
-                             uint32_t** vals_result, hipStream_t st) {
+                             uint32_t** vals_result, hipStream_t st, uint32_t** keys_result) {
     uint32_t nb = (n + kRsTile - 1) / kRsTile;
     if (nb == 0) nb = 1;
     uint32_t h = 256 * nb;
@@ -663,6 +687,7 @@ hipError_t radix_sort_by_key(const uint32_t* keys_in, uint32_t n, uint32_t bits,
         kin = ko;
         vin = vo;
         *vals_result = vo;
+        if (keys_result) *keys_result = ko;
         if (ko == k0) {
             ko = k1;
             vo = v1;
@@ -713,17 +738,25 @@ hipError_t launch_row_sort(const uint32_t* rowdeg, const uint32_t* row_ptr, cons
 }
 
 hipError_t launch_lowcount(const uint32_t* row_ptr, const uint32_t* col, const uint32_t* rowcross,
-                           uint32_t n, uint32_t* lowcnt, hipStream_t st) {
+                           uint32_t n, uint32_t* lowcnt, uint32_t* upcnt, hipStream_t st) {
     hipLaunchKernelGGL(k_lowcount, grid_n(n, 256), dim3(256), 0, st, row_ptr, col, rowcross, n,
-                       lowcnt);
+                       lowcnt, upcnt);
     return hipGetLastError();
 }
 
-hipError_t launch_records(const uint32_t* row_ptr, const uint32_t* col, const uint32_t* lowcnt,
-                          Dims d, const Control* ctl, uint64_t nnz_bound, uint32_t* front,
-                          uint32_t* back, uint4* recs, u64* wu, u64* wsu, hipStream_t st) {
-    hipLaunchKernelGGL(k_records, grid_n(nnz_bound, kRecChunk, 4096), dim3(kAggThreads), 0, st,
-                       row_ptr, col, lowcnt, d, ctl, front, back, recs, wu, wsu);
+hipError_t launch_records_raw(const uint32_t* row_ptr, const uint32_t* col, const uint32_t* lowcnt,
+                              const uint32_t* uptr, Dims d, uint64_t m, uint4* raw, uint32_t* key,
+                              hipStream_t st) {
+    hipLaunchKernelGGL(k_records_raw, grid_n(2 * m, kRecThreads * kRecPer, 8192), dim3(kRecThreads),
+                       0, st, row_ptr, col, lowcnt, uptr, d, m, raw, key);
+    return hipGetLastError();
+}
+
+hipError_t launch_records_gather(const uint4* raw, const uint32_t* skey, const uint32_t* order,
+                                 uint64_t m, uint4* recs, u64* wu, u64* wsu, uint32_t* front,
+                                 hipStream_t st) {
+    hipLaunchKernelGGL(k_records_gather, grid_n(m, kRecThreads * kRecPer, 8192), dim3(kRecThreads),
+                       0, st, raw, skey, order, m, recs, wu, wsu, front);
     return hipGetLastError();
 }
 
