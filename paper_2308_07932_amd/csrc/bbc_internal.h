@@ -69,6 +69,7 @@ constexpr uint32_t kPieceDense = 1u;    // counters addressed by w - lo (else ha
 constexpr uint32_t kPieceMerge = 2u;    // partial counts: merge exactly through G
 constexpr uint32_t kPiecePartial = 4u;  // w-range is a tile range: look up sub-intervals
 constexpr uint32_t kPieceSideV = 8u;    // the start vertex lies on side V
+constexpr uint32_t kPieceDense16 = 16u; // dense with 16-bit l | m halves (two tiles wide)
 
 // One unit of counting: records [rec0, rec0 + nrec) of one start vertex,
 // restricted to end vertices with sidx in [lo, hi).

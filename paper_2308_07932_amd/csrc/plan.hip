@@ -57,10 +57,13 @@ __device__ inline uint32_t cost_key(double wedges, uint32_t nrec) {
 // Tile runs of a start with end-vertex space [0, S) on the side whose rows start
 // at `base`; calls emit(t0, t1, dense, expected wedges) per run and returns the
 // number of runs.  A tile of degree mass x is expected to hold W * x / tot
-// wedges; "more than target" is tested exactly as x * W > target * tot.
+// wedges; "more than target" is tested exactly as x * W > target * tot.  With
+// `pair`, two neighbouring dense tiles share one dense piece (t1 = t0 + 2),
+// counted with 16-bit halves (the start has fewer than 2^16 middles, so no
+// bucket can reach 2^16).
 template <typename F>
 __device__ uint32_t plan_runs(const uint32_t* __restrict__ row_ptr, uint32_t base, uint32_t S,
-                              u64 W, uint32_t target, F emit) {
+                              u64 W, uint32_t target, bool pair, F emit) {
     using u128 = unsigned __int128;
     const uint32_t T = (S + kTile - 1) / kTile;
     const u64 tot = row_ptr[base + S] - row_ptr[base];
@@ -76,6 +79,16 @@ __device__ uint32_t plan_runs(const uint32_t* __restrict__ row_ptr, uint32_t bas
                 emit(rs, t, false, est(rx));
                 ++n;
                 rs = kNoTile;
+            }
+            if (pair && t + 1 < T) {
+                const uint32_t hi2 = min(S, hi + kTile);
+                const u64 x2 = row_ptr[base + hi2] - row_ptr[base + hi];
+                if ((u128)x2 * W > lim) {
+                    emit(t, t + 2, true, est(x + x2));
+                    ++n;
+                    ++t;
+                    continue;
+                }
             }
             emit(t, t + 1, true, est(x));
             ++n;
@@ -140,7 +153,7 @@ __device__ inline StartPlan plan_start(const uint32_t* __restrict__ row_ptr, con
     bool whole = false;
     sp.cls = kClassTiles;
     sp.pieces = plan_runs(row_ptr, d.base[side], S, W, d.hash_target,
-                          [&](uint32_t t0, uint32_t t1, bool dense, double) {
+                          !d.per_vertex && k < (1u << 16), [&](uint32_t t0, uint32_t t1, bool dense, double) {
                               whole = whole || (t0 == 0 && t1 == T && !dense);
                           });
     // One hashed run over everything is left unsplit only when its W wedges
@@ -242,7 +255,8 @@ __global__ void k_plan_write(const u64* __restrict__ wu, const uint32_t* __restr
         const bool bucketed = split && !d.per_vertex;  // short-middle wedges come from a list
         const uint32_t nlong = front[r] - m0;
         uint32_t i = 0;
-        plan_runs(row_ptr, d.base[side], S, W, d.hash_target, [&](uint32_t t0, uint32_t t1, bool dense, double est) {
+        plan_runs(row_ptr, d.base[side], S, W, d.hash_target, !d.per_vertex && k < (1u << 16),
+                  [&](uint32_t t0, uint32_t t1, bool dense, double est) {
             if (i >= h) return;
             Piece p;
             p.rec0 = m0;
@@ -252,7 +266,8 @@ __global__ void k_plan_write(const u64* __restrict__ wu, const uint32_t* __restr
             p.t0 = t0;
             p.t1 = t1;
             p.region = log2_pow2(kHashSlots) << 16;
-            p.flags = (split ? kPiecePartial : 0u) | (dense ? kPieceDense : 0u) | sideflag;
+            p.flags = (split ? kPiecePartial : 0u) | (dense ? kPieceDense : 0u) |
+                      ((dense && t1 - t0 == 2) ? kPieceDense16 : 0u) | sideflag;
             p.gbase = kEmpty;
             p.start_row = r;
             p.list = bucketed ? b + i : kEmpty;

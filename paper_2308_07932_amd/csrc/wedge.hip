@@ -154,6 +154,7 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
     __shared__ u64 s_pb[kMaxItemPieces], s_pu[kMaxItemPieces];  // per-piece totals (batches)
     uint32_t* keys = (uint32_t*)s_tab;
     u64* hvals = s_tab + kHashSlots / 2;
+    uint32_t* s32 = (uint32_t*)s_tab;  // 16-bit-half dense counters
 
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
     const uint32_t* __restrict__ col = a.col;
@@ -206,6 +207,7 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
                 s_qtake = 0;
             }
             const bool dense = (s_pc[0].flags & kPieceDense) != 0;
+            const bool d16 = (s_pc[0].flags & kPieceDense16) != 0;  // u32 counters l | m << 16
             const uint32_t dlo = s_pc[0].lo;
             const uint32_t dwidth = s_pc[0].hi - s_pc[0].lo;
             // a split piece may give up early (it is halved and redone); an
@@ -214,7 +216,8 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
                 (heavy && (s_pc[0].flags & kPiecePartial)) ? a.d.probe_limit : kHashSlots;
             const uint32_t plo0 = s_pc[0].lo, phi0 = s_pc[0].hi, region0 = s_pc[0].region;
             if (dense) {
-                for (uint32_t i = tid; i < dwidth; i += kWedgeThreads) s_tab[i] = 0;
+                const uint32_t words = d16 ? (dwidth + 1) / 2 : dwidth;
+                for (uint32_t i = tid; i < words; i += kWedgeThreads) s_tab[i] = 0;
             } else {
                 for (uint32_t i = tid; i < kHashSlots; i += kWedgeThreads) {
                     keys[i] = kEmpty;
@@ -357,8 +360,14 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
                                 const bool keep = !((aux[u] & 2u) && (w < plo0 || w >= phi0));
                                 if (keep) {
                                     const Piece& P = s_pc[aux[u] >> 2];
-                                    const u64 bv = dense ? s_tab[w - dlo]
-                                                         : bucket_get(keys, hvals, P.region, w);
+                                    u64 bv;
+                                    if (dense && d16) {
+                                        const uint32_t c = s32[w - dlo];
+                                        bv = (c & 0xFFFFu) | ((u64)(c >> 16) << 32);
+                                    } else {
+                                        bv = dense ? s_tab[w - dlo]
+                                                   : bucket_get(keys, hvals, P.region, w);
+                                    }
                                     val = middle_share(bv, (x[u] ^ aux[u]) & 1u);
                                 }
                             }
@@ -371,7 +380,7 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
                             if ((lane == 63 || ni != idx) && idx != kEmpty && val != 0)
                                 atomicAdd(&a.pv[s_wvrow[wave][idx]], val);
                         }
-                    } else if (np == 1 && dense) {
+                    } else if (np == 1 && dense && !d16) {
                         // one dense piece: counters addressed by w - lo, never full
 #pragma unroll
                         for (uint32_t u = 0; u < kUnroll; ++u) {
@@ -379,6 +388,14 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
                             const uint32_t w = x[u] >> 1;
                             if ((aux[u] & 2u) && (w < plo0 || w >= phi0)) continue;
                             atomicAdd(&s_tab[w - dlo], ((x[u] ^ aux[u]) & 1u) ? (1ull << 32) : 1ull);
+                        }
+                    } else if (np == 1 && dense) {  // two tiles, 16-bit halves
+#pragma unroll
+                        for (uint32_t u = 0; u < kUnroll; ++u) {
+                            if (aux[u] == kEmpty) continue;
+                            const uint32_t w = x[u] >> 1;
+                            if ((aux[u] & 2u) && (w < plo0 || w >= phi0)) continue;
+                            atomicAdd(&s32[w - dlo], ((x[u] ^ aux[u]) & 1u) ? 0x10000u : 1u);
                         }
                     } else if (np == 1) {
                         bool lok = true;
@@ -433,7 +450,9 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
                             const uint32_t w = x[u] >> 1;
                             if ((aux & 2u) && (w < plo0 || w >= phi0)) continue;
                             const u64 inc = ((x[u] ^ aux) & 1u) ? (1ull << 32) : 1ull;
-                            if (dense)
+                            if (dense && d16)
+                                atomicAdd(&s32[w - dlo], ((x[u] ^ aux) & 1u) ? 0x10000u : 1u);
+                            else if (dense)
                                 atomicAdd(&s_tab[w - dlo], inc);
                             else
                                 lok = bucket_add(s_tab, keys, hvals, false, 0, region0, lim0, w, inc);
@@ -461,8 +480,11 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
                         if (x[u] == kEmpty || !ok) continue;
                         const uint32_t w = x[u] >> 1;
                         if (w < plo || w >= phi) continue;  // a re-split half keeps its share
-                        ok = bucket_add(s_tab, keys, hvals, dense, dlo, region, lim0, w,
-                                        (x[u] & 1u) ? (1ull << 32) : 1ull);
+                        if (dense && d16)
+                            atomicAdd(&s32[w - dlo], (x[u] & 1u) ? 0x10000u : 1u);
+                        else
+                            ok = bucket_add(s_tab, keys, hvals, dense, dlo, region, lim0, w,
+                                            (x[u] & 1u) ? (1ull << 32) : 1ull);
                     }
                 }
                 if (!ok) s_abort = 1;
@@ -537,7 +559,13 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
                 const bool merge = (s_pc[0].flags & kPieceMerge) != 0;
                 const uint32_t gb = s_pc[0].gbase;
                 for (uint32_t i = tid; i < dwidth; i += kWedgeThreads) {
-                    const u64 v = s_tab[i];
+                    u64 v;
+                    if (d16) {
+                        const uint32_t c = s32[i];
+                        v = (c & 0xFFFFu) | ((u64)(c >> 16) << 32);
+                    } else {
+                        v = s_tab[i];
+                    }
                     if (v == 0) continue;
                     const u64 l = v & 0xFFFFFFFFull, m = v >> 32;
                     bal += choose2(l) + choose2(m);
