@@ -84,7 +84,7 @@ struct bbc_context {
     bool timing = false;
     bool timing_valid = false;
     double phase_ms[4] = {0, 0, 0, 0};
-    int64_t stats[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int64_t stats[11] = {0};
     uint32_t hash_target = bbc::kDefaultHashTarget;
     uint32_t probe_limit = bbc::kDefaultProbeLimit;
     uint64_t chunk_min = bbc::kRecordChunkWedges;
@@ -392,7 +392,7 @@ bbc_status bbc_last_phase_ms(const bbc_context* c, int phase, double* ms) {
 
 bbc_status bbc_last_stats(const bbc_context* c, int64_t* stats, int n) {
     if (!c || !stats || n < 0) return BBC_ERR_INVALID_ARG;
-    for (int i = 0; i < n && i < 8; ++i) stats[i] = c->stats[i];
+    for (int i = 0; i < n && i < 11; ++i) stats[i] = c->stats[i];
     return BBC_OK;
 }
 
@@ -795,6 +795,9 @@ static void add_stats(bbc_context* c, const RunOut& ro, uint64_t m) {
     c->stats[5] += (int64_t)ro.h.resplits;
     c->stats[6] += (int64_t)ro.h.active_starts;
     c->stats[7] += (int64_t)ro.n_heavy;
+    c->stats[8] += (int64_t)ro.h.n_dense;
+    c->stats[9] += (int64_t)ro.h.n_dense16;
+    c->stats[10] += (int64_t)ro.h.n_hashed;
 }
 
 static void begin_call(bbc_context* c) {
@@ -1078,10 +1081,10 @@ bbc_status bbc_count_batch(bbc_context* c, int32_t n_graphs, const int32_t* n_u,
         else
             small.push_back((uint32_t)g);
     }
-    int64_t stats[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int64_t stats[11] = {0};
     double ph[4] = {0, 0, 0, 0};
     auto keep_stats = [&]() {
-        for (int i = 0; i < 8; ++i) stats[i] += c->stats[i];
+        for (int i = 0; i < 11; ++i) stats[i] += c->stats[i];
         for (int i = 0; i < 4; ++i) ph[i] += c->phase_ms[i];
     };
     // unions: consecutive small graphs up to the size limits

@@ -70,6 +70,7 @@ constexpr uint32_t kPieceMerge = 2u;    // partial counts: merge exactly through
 constexpr uint32_t kPiecePartial = 4u;  // w-range is a tile range: look up sub-intervals
 constexpr uint32_t kPieceSideV = 8u;    // the start vertex lies on side V
 constexpr uint32_t kPieceDense16 = 16u; // dense with 16-bit l | m halves (two tiles wide)
+constexpr uint32_t kPieceHash16 = 32u;  // hashed with 16-bit l | m halves (2 x kHashSlots slots)
 
 // One unit of counting: records [rec0, rec0 + nrec) of one start vertex,
 // restricted to end vertices with sidx in [lo, hi).
@@ -108,6 +109,7 @@ struct Control {
     u64 active_starts;   // vertices with W_u > 0
     u64 tot_tiles;       // tile-to-piece map entries of split starts
     u64 tot_sw;          // bucketed short-middle wedges of split starts
+    u64 n_dense, n_dense16, n_hashed;  // tile pieces by kind
 };
 
 struct Dims {

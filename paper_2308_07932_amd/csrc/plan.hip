@@ -58,9 +58,10 @@ __device__ inline uint32_t cost_key(double wedges, uint32_t nrec) {
 // at `base`; calls emit(t0, t1, dense, expected wedges) per run and returns the
 // number of runs.  A tile of degree mass x is expected to hold W * x / tot
 // wedges; "more than target" is tested exactly as x * W > target * tot.  With
-// `pair`, two neighbouring dense tiles share one dense piece (t1 = t0 + 2),
-// counted with 16-bit halves (the start has fewer than 2^16 middles, so no
-// bucket can reach 2^16).
+// `pair` (the start has fewer than 2^16 middles, so no bucket can reach 2^16
+// and 16-bit counter halves suffice), two neighbouring dense tiles share one
+// dense piece (t1 = t0 + 2), and hashed runs, whose table then has twice the
+// slots, may hold twice the target.
 template <typename F>
 __device__ uint32_t plan_runs(const uint32_t* __restrict__ row_ptr, uint32_t base, uint32_t S,
                               u64 W, uint32_t target, bool pair, F emit) {
@@ -68,6 +69,7 @@ __device__ uint32_t plan_runs(const uint32_t* __restrict__ row_ptr, uint32_t bas
     const uint32_t T = (S + kTile - 1) / kTile;
     const u64 tot = row_ptr[base + S] - row_ptr[base];
     const u128 lim = (u128)target * tot;
+    const u128 lim_run = pair ? 2 * lim : lim;
     auto est = [&](u64 x) { return tot > 0 ? (double)x * (double)W / (double)tot : 0.0; };
     uint32_t n = 0, rs = kNoTile;
     u64 rx = 0;  // degree mass of the open run
@@ -92,7 +94,7 @@ __device__ uint32_t plan_runs(const uint32_t* __restrict__ row_ptr, uint32_t bas
             }
             emit(t, t + 1, true, est(x));
             ++n;
-        } else if (rs != kNoTile && (u128)(rx + x) * W > lim) {
+        } else if (rs != kNoTile && (u128)(rx + x) * W > lim_run) {
             emit(rs, t, false, est(rx));
             ++n;
             rs = t;
@@ -176,6 +178,19 @@ __global__ void k_plan_count(const u64* __restrict__ wu, const u64* __restrict__
         const StartPlan sp = plan_start(row_ptr, d, r, W, lowcnt[r], chunk);
         const uint32_t side = r >= d.n_u ? 1u : 0u;
         if (sp.cls == kClassTiles && d.n_graphs > 1) atomicOr(&ctl->internal_err, 2u);
+        if (sp.cls == kClassTiles) {  // tile pieces by kind (statistics)
+            u64 nd = 0, nd16 = 0, nh = 0;
+            plan_runs(row_ptr, d.base[side], r - d.base[side], W, d.hash_target,
+                      !d.per_vertex && lowcnt[r] < (1u << 16),
+                      [&](uint32_t t0, uint32_t t1, bool dense, double) {
+                          if (!dense) ++nh;
+                          else if (t1 - t0 == 2) ++nd16;
+                          else ++nd;
+                      });
+            if (nd) atomicAdd(&ctl->n_dense, nd);
+            if (nd16) atomicAdd(&ctl->n_dense16, nd16);
+            if (nh) atomicAdd(&ctl->n_hashed, nh);
+        }
         hp[r] = sp.pieces;
         lr[r] = sp.cls == kClassLight ? sp.region : 0u;
         lf[r] = sp.cls == kClassLight ? 1u : 0u;
@@ -266,8 +281,10 @@ __global__ void k_plan_write(const u64* __restrict__ wu, const uint32_t* __restr
             p.t0 = t0;
             p.t1 = t1;
             p.region = log2_pow2(kHashSlots) << 16;
+            const bool pair = !d.per_vertex && k < (1u << 16);
             p.flags = (split ? kPiecePartial : 0u) | (dense ? kPieceDense : 0u) |
-                      ((dense && t1 - t0 == 2) ? kPieceDense16 : 0u) | sideflag;
+                      ((dense && t1 - t0 == 2) ? kPieceDense16 : 0u) |
+                      ((!dense && split && pair) ? kPieceHash16 : 0u) | sideflag;
             p.gbase = kEmpty;
             p.start_row = r;
             p.list = bucketed ? b + i : kEmpty;

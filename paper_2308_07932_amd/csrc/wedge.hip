@@ -75,6 +75,27 @@ constexpr uint32_t kQueue = 256;      // queued in LDS and shared by all waves a
 
 __device__ inline uint32_t hash32(uint32_t w) { return w * 0x9E3779B1u; }
 
+// The 16-bit-half hash table: 2 x kHashSlots keys, then as many u32 counters
+// (l | m << 16).  Returns false if w finds no slot within `lim` probes.
+constexpr uint32_t kHash16Slots = 2 * kHashSlots;
+__device__ inline bool bucket_add16(uint32_t* s32, uint32_t lim, uint32_t w, uint32_t inc) {
+    constexpr uint32_t lg = 31u - __builtin_clz(kHash16Slots);
+    const uint32_t h = hash32(w) >> (32 - lg);
+    for (uint32_t i = 0; i < lim; ++i) {
+        const uint32_t s = (h + i) & (kHash16Slots - 1u);
+        uint32_t k = s32[s];
+        if (k == kEmpty) {
+            k = atomicCAS(&s32[s], kEmpty, w);
+            if (k == kEmpty) k = w;
+        }
+        if (k == w) {
+            atomicAdd(&s32[kHash16Slots + s], inc);
+            return true;
+        }
+    }
+    return false;
+}
+
 // Add one wedge to the bucket of end vertex w.  Returns false if the hashed
 // region has no room for w within `lim` probes.
 __device__ inline bool bucket_add(u64* s_tab, uint32_t* keys, u64* hvals, bool dense,
@@ -208,6 +229,7 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
             }
             const bool dense = (s_pc[0].flags & kPieceDense) != 0;
             const bool d16 = (s_pc[0].flags & kPieceDense16) != 0;  // u32 counters l | m << 16
+            const bool h16 = !dense && (s_pc[0].flags & kPieceHash16) != 0;
             const uint32_t dlo = s_pc[0].lo;
             const uint32_t dwidth = s_pc[0].hi - s_pc[0].lo;
             // a split piece may give up early (it is halved and redone); an
@@ -218,6 +240,11 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
             if (dense) {
                 const uint32_t words = d16 ? (dwidth + 1) / 2 : dwidth;
                 for (uint32_t i = tid; i < words; i += kWedgeThreads) s_tab[i] = 0;
+            } else if (h16) {
+                for (uint32_t i = tid; i < kHash16Slots; i += kWedgeThreads) {
+                    s32[i] = kEmpty;
+                    s32[kHash16Slots + i] = 0;
+                }
             } else {
                 for (uint32_t i = tid; i < kHashSlots; i += kWedgeThreads) {
                     keys[i] = kEmpty;
@@ -397,6 +424,16 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
                             if ((aux[u] & 2u) && (w < plo0 || w >= phi0)) continue;
                             atomicAdd(&s32[w - dlo], ((x[u] ^ aux[u]) & 1u) ? 0x10000u : 1u);
                         }
+                    } else if (np == 1 && h16) {
+                        bool lok = true;
+#pragma unroll 1
+                        for (uint32_t u = 0; u < kUnroll; ++u) {
+                            if (aux[u] == kEmpty || !lok) continue;
+                            const uint32_t w = x[u] >> 1;
+                            if ((aux[u] & 2u) && (w < plo0 || w >= phi0)) continue;
+                            lok = bucket_add16(s32, lim0, w, ((x[u] ^ aux[u]) & 1u) ? 0x10000u : 1u);
+                        }
+                        ok = __ballot(!lok) == 0;
                     } else if (np == 1) {
                         bool lok = true;
 #pragma unroll 1
@@ -454,6 +491,8 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
                                 atomicAdd(&s32[w - dlo], ((x[u] ^ aux) & 1u) ? 0x10000u : 1u);
                             else if (dense)
                                 atomicAdd(&s_tab[w - dlo], inc);
+                            else if (h16)
+                                lok = bucket_add16(s32, lim0, w, ((x[u] ^ aux) & 1u) ? 0x10000u : 1u);
                             else
                                 lok = bucket_add(s_tab, keys, hvals, false, 0, region0, lim0, w, inc);
                         }
@@ -482,6 +521,8 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
                         if (w < plo || w >= phi) continue;  // a re-split half keeps its share
                         if (dense && d16)
                             atomicAdd(&s32[w - dlo], (x[u] & 1u) ? 0x10000u : 1u);
+                        else if (h16)
+                            ok = bucket_add16(s32, lim0, w, (x[u] & 1u) ? 0x10000u : 1u);
                         else
                             ok = bucket_add(s_tab, keys, hvals, dense, dlo, region, lim0, w,
                                             (x[u] & 1u) ? (1ull << 32) : 1ull);
@@ -578,6 +619,14 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
                         bal += ol * l + om * m;
                         unb += ol * m + om * l;
                     }
+                }
+            } else if (h16) {
+                for (uint32_t i = tid; i < kHash16Slots; i += kWedgeThreads) {
+                    if (s32[i] == kEmpty) continue;
+                    const uint32_t c = s32[kHash16Slots + i];
+                    const u64 l = c & 0xFFFFu, m = c >> 16;
+                    bal += choose2(l) + choose2(m);
+                    unb += l * m;
                 }
             } else {
                 for (uint32_t i = tid; i < kHashSlots; i += kWedgeThreads) {

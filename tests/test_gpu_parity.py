@@ -151,7 +151,15 @@ def test_resplit_path(ctx):
                              rng.choice([1, -1], size=len(eu)).astype(np.int8), "resplit")
     r = check(ctx, g)
     assert r.balanced > 0
-    assert ctx.stats()[5] > 0, "expected a hashed piece to be redone"
+    # A hashed run of one tile can no longer overflow by capacity when its
+    # start has fewer than 2^16 middles (16-bit halves give as many slots as
+    # the tile has vertices), so the redo is forced by a short probe limit.
+    ctx.set_param(bbc.PARAM_PROBE_LIMIT, 8)
+    try:
+        assert run(ctx, g) == r
+        assert ctx.stats()[5] > 0, "expected a hashed piece to be redone"
+    finally:
+        ctx.set_param(bbc.PARAM_PROBE_LIMIT, 256)
 
 
 def test_forced_resplits_stay_exact(ctx):
