@@ -15,7 +15,7 @@
 namespace bbc {
 // launchers defined in prep.hip / plan.hip / wedge.hip
 hipError_t launch_degree(const int32_t*, const int32_t*, const int8_t*, uint64_t, uint32_t, uint32_t,
-                         uint32_t*, Control*, hipStream_t);
+                         uint32_t*, uint2*, Control*, hipStream_t);
 size_t radix_tmp_bytes(uint32_t n);
 hipError_t radix_sort_by_key(const uint32_t*, uint32_t, uint32_t, uint32_t*, uint32_t*, uint32_t*,
                              uint32_t*, void*, size_t, uint32_t**, hipStream_t,
@@ -24,7 +24,8 @@ hipError_t launch_sides(const uint32_t*, uint32_t, uint32_t, uint32_t*, hipStrea
 hipError_t launch_assign(const uint32_t*, const uint32_t*, const uint32_t*, uint32_t, uint32_t,
                          uint32_t*, uint32_t*, uint32_t*, hipStream_t);
 hipError_t launch_scatter(const int32_t*, const int32_t*, const int8_t*, uint64_t, uint32_t,
-                          uint32_t, const uint32_t*, uint32_t*, uint32_t*, hipStream_t);
+                          uint32_t, const uint32_t*, const uint32_t*, const uint2*, uint32_t*,
+                          hipStream_t);
 hipError_t launch_row_sort(const uint32_t*, const uint32_t*, const uint32_t*, uint32_t*, Dims,
                            Control*, uint32_t, hipStream_t);
 hipError_t launch_lowcount(const uint32_t*, const uint32_t*, const uint32_t*, uint32_t, uint32_t*,
@@ -588,7 +589,9 @@ static bbc_status run_pipeline(bbc_context* c, const RunIn& in, RunOut& ro) {
 
     // ---- 1. degrees + validation
     HIPCHECK(c, fill_u32(b.deg, 0, n, st));
-    HIPCHECK(c, launch_degree(eu, ev, sg, m, nu, nv, b.deg, b.ctl, st));
+    // every edge's slots in its two rows go to b.raw (free until the records)
+    uint2* slots = reinterpret_cast<uint2*>(b.raw);
+    HIPCHECK(c, launch_degree(eu, ev, sg, m, nu, nv, b.deg, slots, b.ctl, st));
     // ---- 2. priority order: stable sort of vertex ids by degree (by graph,
     // then degree, for a batch)
     if (bt) {
@@ -616,8 +619,7 @@ static bbc_status run_pipeline(bbc_context* c, const RunIn& in, RunOut& ro) {
     }
     // ---- 4. CSR: offsets, scatter, per-row sort
     HIPCHECK(c, scan_excl_u32(b.rowdeg, b.row_ptr, n, b.stmp, b.stmp_bytes, st));
-    HIPCHECK(c, copy_u32(b.row_ptr, b.cursor, n, st));
-    HIPCHECK(c, launch_scatter(eu, ev, sg, m, nu, nv, b.sidx_of, b.cursor, b.col_in, st));
+    HIPCHECK(c, launch_scatter(eu, ev, sg, m, nu, nv, b.sidx_of, b.row_ptr, slots, b.col_in, st));
     HIPCHECK(c, launch_row_sort(b.rowdeg, b.row_ptr, b.col_in, b.col, d, b.ctl, c->num_cus, st));
     if (bt) HIPCHECK(c, launch_dup_graphs(b.row_ptr, b.col, d, b.ctl, st));
     // ---- 5. middle counts, 6. records and W_u, 7. tile tables

@@ -1,13 +1,13 @@
-// Preprocessing of the bucket method (paper: Section 4.1, Algorithm 2, lines
-// "compute p(u)" and "rearrange Gamma(u) in ascending order"; Section 4.2 notes
-// the O(n) binning sort of the vertices):
-//   1. validate edges and count degrees;
+// Preprocessing of the bucket method (Section 4.1, Algorithm 2: the vertex
+// priorities and the neighbour lists in priority order; Section 4.2 notes the
+// O(n) binning sort of the vertices):
+//   1. validate edges, count degrees and reserve each edge's slot in its rows;
 //   2. order all vertices by priority (degree, id) with a stable LSD radix sort
 //      on the degree (ids enter in ascending order, so ties keep id order);
 //   3. per-side index (sidx) and cross counts from a scan of side flags;
-//   4. signed CSR: row offsets by scan, scatter, then a segmented sort of every
-//      row by neighbour priority (size classes: registers, lane groups, LDS
-//      bitonic, LDS bitmaps);
+//   4. signed CSR: row offsets by scan, entries placed at the reserved slots,
+//      then a segmented sort of every row by neighbour priority (size classes:
+//      registers, lane groups, LDS bitonic, LDS bitmaps);
 //   5. per row the number k of lower-priority neighbours (middle vertices);
 //   6. one record per edge, oriented from its higher-priority end, holding the
 //      middle row and the prefix length pos; W_u = sum of pos over u's records;
@@ -17,11 +17,15 @@
 namespace bbc {
 
 // ---------------------------------------------------------------- degrees ----
-// Each workgroup takes chunks of kAggChunk edges and counts endpoint degrees in
-// an LDS table first, so a hub endpoint costs one global atomic per chunk
-// instead of one per edge.
+// One pass over the edges counts the degrees and gives every edge its slot in
+// both of its rows: the value a row's counter had when the endpoint was added
+// (any order of the slots is fine, the rows are sorted afterwards).  Each
+// workgroup takes chunks of kAggChunk edges; the endpoints of one vertex inside
+// a chunk are ranked in an LDS table and reserve their slots with one global
+// returning atomic, so a hub costs one global atomic per chunk instead of one
+// per edge.  Endpoints that find no table slot reserve theirs directly.
 constexpr int kAggThreads = 256;
-constexpr int kAggPer = 8;  // edges per thread per chunk
+constexpr int kAggPer = 16;  // edges per thread per chunk
 constexpr uint32_t kAggChunk = kAggThreads * kAggPer;
 constexpr uint32_t kAggLog2 = 12;
 constexpr uint32_t kAggSlots = 1u << kAggLog2;
@@ -34,9 +38,11 @@ __global__ __launch_bounds__(kAggThreads) void k_degree(const int32_t* __restric
                                                         const int32_t* __restrict__ ev,
                                                         const int8_t* __restrict__ sg, uint64_t m,
                                                         uint32_t n_u, uint32_t n_v,
-                                                        uint32_t* __restrict__ deg, Control* ctl) {
+                                                        uint32_t* __restrict__ deg,
+                                                        uint2* __restrict__ rank, Control* ctl) {
+    constexpr uint32_t kSkip = kEmpty - 1;  // slot mark: invalid edge or past the end
     __shared__ uint32_t keys[kAggSlots];
-    __shared__ uint32_t cnt[kAggSlots];
+    __shared__ uint32_t cnt[kAggSlots];  // ranks handed out; after the flush, the reserved base
     const uint32_t tid = threadIdx.x;
     for (uint64_t c0 = (uint64_t)blockIdx.x * kAggChunk; c0 < m; c0 += (uint64_t)gridDim.x * kAggChunk) {
         for (uint32_t i = tid; i < kAggSlots; i += kAggThreads) {
@@ -44,9 +50,11 @@ __global__ __launch_bounds__(kAggThreads) void k_degree(const int32_t* __restric
             cnt[i] = 0;
         }
         __syncthreads();
+        uint32_t slot[kAggPer][2], rk[kAggPer][2];
         for (int k = 0; k < kAggPer; ++k) {
+            slot[k][0] = slot[k][1] = kSkip;
             const uint64_t e = c0 + (uint64_t)k * kAggThreads + tid;
-            if (e >= m) break;
+            if (e >= m) continue;
             const int32_t u = eu[e], v = ev[e];
             const int8_t s = sg[e];
             if (!edge_ok(u, v, s, n_u, n_v)) {
@@ -57,15 +65,26 @@ __global__ __launch_bounds__(kAggThreads) void k_degree(const int32_t* __restric
             const uint32_t x[2] = {(uint32_t)u, n_u + (uint32_t)v};
             for (int t = 0; t < 2; ++t) {
                 const int sl = agg_slot<kAggLog2>(keys, x[t]);
-                if (sl >= 0)
-                    atomicAdd(&cnt[sl], 1u);
-                else
-                    atomicAdd(&deg[x[t]], 1u);
+                if (sl >= 0) {
+                    slot[k][t] = (uint32_t)sl;
+                    rk[k][t] = atomicAdd(&cnt[sl], 1u);
+                } else {
+                    slot[k][t] = kEmpty;  // slot reserved directly
+                    rk[k][t] = atomicAdd(&deg[x[t]], 1u);
+                }
             }
         }
         __syncthreads();
         for (uint32_t i = tid; i < kAggSlots; i += kAggThreads)
-            if (keys[i] != kEmpty) atomicAdd(&deg[keys[i]], cnt[i]);
+            if (keys[i] != kEmpty) cnt[i] = atomicAdd(&deg[keys[i]], cnt[i]);
+        __syncthreads();
+        for (int k = 0; k < kAggPer; ++k) {
+            if (slot[k][0] == kSkip) continue;
+            uint32_t r[2];
+            for (int t = 0; t < 2; ++t)
+                r[t] = slot[k][t] == kEmpty ? rk[k][t] : cnt[slot[k][t]] + rk[k][t];
+            rank[c0 + (uint64_t)k * kAggThreads + tid] = make_uint2(r[0], r[1]);
+        }
         __syncthreads();
     }
 }
@@ -171,59 +190,26 @@ __global__ void k_assign(const uint32_t* __restrict__ inv, const uint32_t* __res
     }
 }
 
-// Each edge lands in row u (entry sidx(v)) and row v (entry sidx(u)).  Slots
-// inside a row are reserved with one global atomic per (workgroup chunk, row)
-// through an LDS table; the order inside a row is fixed later by the sort.
-__global__ __launch_bounds__(kAggThreads) void k_scatter(
-    const int32_t* __restrict__ eu, const int32_t* __restrict__ ev, const int8_t* __restrict__ sg,
-    uint64_t m, uint32_t n_u, uint32_t n_v, const uint32_t* __restrict__ sidx_of,
-    uint32_t* __restrict__ cursor, uint32_t* __restrict__ col) {
-    __shared__ uint32_t keys[kAggSlots];
-    __shared__ uint32_t cnt[kAggSlots];
-    __shared__ uint32_t base[kAggSlots];
-    const uint32_t tid = threadIdx.x;
-    for (uint64_t c0 = (uint64_t)blockIdx.x * kAggChunk; c0 < m; c0 += (uint64_t)gridDim.x * kAggChunk) {
-        for (uint32_t i = tid; i < kAggSlots; i += kAggThreads) {
-            keys[i] = kEmpty;
-            cnt[i] = 0;
-        }
-        __syncthreads();
-        uint32_t slot[kAggPer][2], rank[kAggPer][2], val[kAggPer][2];
-        for (int k = 0; k < kAggPer; ++k) {
-            slot[k][0] = slot[k][1] = kEmpty - 1;  // marks an edge to skip
-            const uint64_t e = c0 + (uint64_t)k * kAggThreads + tid;
-            if (e >= m) continue;
-            const int32_t u = eu[e], v = ev[e];
-            const int8_t s = sg[e];
-            if (!edge_ok(u, v, s, n_u, n_v)) continue;
-            const uint32_t su = sidx_of[u], sv = sidx_of[n_u + (uint32_t)v];
-            const uint32_t neg = s < 0 ? 1u : 0u;
-            const uint32_t row[2] = {su, n_u + sv};
-            val[k][0] = (sv << 1) | neg;
-            val[k][1] = (su << 1) | neg;
-            for (int t = 0; t < 2; ++t) {
-                const int sl = agg_slot<kAggLog2>(keys, row[t]);
-                if (sl >= 0) {
-                    slot[k][t] = (uint32_t)sl;
-                    rank[k][t] = atomicAdd(&cnt[sl], 1u);
-                } else {
-                    slot[k][t] = kEmpty;  // position reserved directly
-                    rank[k][t] = atomicAdd(&cursor[row[t]], 1u);
-                }
-            }
-        }
-        __syncthreads();
-        for (uint32_t i = tid; i < kAggSlots; i += kAggThreads)
-            if (keys[i] != kEmpty) base[i] = atomicAdd(&cursor[keys[i]], cnt[i]);
-        __syncthreads();
-        for (int k = 0; k < kAggPer; ++k)
-            for (int t = 0; t < 2; ++t) {
-                const uint32_t sl = slot[k][t];
-                if (sl == kEmpty - 1) continue;
-                const uint32_t p = sl == kEmpty ? rank[k][t] : base[sl] + rank[k][t];
-                col[p] = val[k][t];
-            }
-        __syncthreads();
+// Each edge lands in row u (entry sidx(v)) and row v (entry sidx(u)), at the
+// slots the degree pass reserved for it.
+__global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ eu,
+                                                 const int32_t* __restrict__ ev,
+                                                 const int8_t* __restrict__ sg, uint64_t m,
+                                                 uint32_t n_u, uint32_t n_v,
+                                                 const uint32_t* __restrict__ sidx_of,
+                                                 const uint32_t* __restrict__ row_ptr,
+                                                 const uint2* __restrict__ rank,
+                                                 uint32_t* __restrict__ col) {
+    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
+         e += (uint64_t)gridDim.x * blockDim.x) {
+        const int32_t u = eu[e], v = ev[e];
+        const int8_t s = sg[e];
+        if (!edge_ok(u, v, s, n_u, n_v)) continue;
+        const uint32_t su = sidx_of[u], sv = sidx_of[n_u + (uint32_t)v];
+        const uint2 r = rank[e];
+        const uint32_t neg = s < 0 ? 1u : 0u;
+        col[row_ptr[su] + r.x] = (sv << 1) | neg;
+        col[row_ptr[n_u + sv] + r.y] = (su << 1) | neg;
     }
 }
 
@@ -647,9 +633,10 @@ static dim3 grid_n(uint64_t n, uint32_t threads, uint32_t cap = 16384) {
 }
 
 hipError_t launch_degree(const int32_t* eu, const int32_t* ev, const int8_t* sg, uint64_t m,
-                         uint32_t n_u, uint32_t n_v, uint32_t* deg, Control* ctl, hipStream_t st) {
+                         uint32_t n_u, uint32_t n_v, uint32_t* deg, uint2* rank, Control* ctl,
+                         hipStream_t st) {
     hipLaunchKernelGGL(k_degree, grid_n(m, kAggChunk, 2048), dim3(kAggThreads), 0, st, eu, ev, sg, m,
-                       n_u, n_v, deg, ctl);
+                       n_u, n_v, deg, rank, ctl);
     return hipGetLastError();
 }
 
@@ -714,10 +701,11 @@ hipError_t launch_assign(const uint32_t* inv, const uint32_t* cnt_u, const uint3
 }
 
 hipError_t launch_scatter(const int32_t* eu, const int32_t* ev, const int8_t* sg, uint64_t m,
-                          uint32_t n_u, uint32_t n_v, const uint32_t* sidx_of, uint32_t* cursor,
-                          uint32_t* col, hipStream_t st) {
-    hipLaunchKernelGGL(k_scatter, grid_n(m, kAggChunk, 2048), dim3(kAggThreads), 0, st, eu, ev, sg,
-                       m, n_u, n_v, sidx_of, cursor, col);
+                          uint32_t n_u, uint32_t n_v, const uint32_t* sidx_of,
+                          const uint32_t* row_ptr, const uint2* rank, uint32_t* col,
+                          hipStream_t st) {
+    hipLaunchKernelGGL(k_scatter, grid_n(m, 256), dim3(256), 0, st, eu, ev, sg, m, n_u, n_v,
+                       sidx_of, row_ptr, rank, col);
     return hipGetLastError();
 }
 
