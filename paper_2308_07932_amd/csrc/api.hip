@@ -48,7 +48,7 @@ hipError_t launch_plan_write(const u64*, const uint32_t*, const uint32_t*, const
                              hipStream_t);
 hipError_t launch_short_wedges(const uint4*, uint32_t, const uint32_t*, const uint32_t*,
                                const uint32_t*, const uint32_t*, const uint32_t*, const uint32_t*,
-                               const uint32_t*, uint32_t*, uint32_t*, uint32_t*, bool, hipStream_t);
+                               uint32_t*, uint32_t*, uint32_t*, bool, hipStream_t);
 hipError_t launch_wedge(const Piece*, const uint32_t*, const uint32_t*, uint32_t, uint32_t,
                         const uint4*, const uint32_t*, const uint32_t*, Dims, const uint32_t[2], u64*,
                         const uint32_t*, const uint32_t*, Control*, u64*, u64*, uint32_t,
@@ -738,13 +738,13 @@ static bbc_status run_pipeline(bbc_context* c, const RunIn& in, RunOut& ro) {
     // bucket the short-middle wedges of split starts by piece
     HIPCHECK(c, fill_u32(sw_cnt, 0, (size_t)n_heavy + 1, st));
     if (h.tot_sw > 0) {
-        HIPCHECK(c, launch_short_wedges(b.recs, (uint32_t)m, b.col, b.mptr, b.cursor, b.tc, b.tc_off,
+        HIPCHECK(c, launch_short_wedges(b.recs, (uint32_t)m, b.col, b.cursor, b.tc, b.tc_off,
                                         b.hp_off, tile_piece, sw_cnt, sw_cur, sw_list, false, st));
     }
     HIPCHECK(c, scan_excl_u32(sw_cnt, sw_off, n_heavy, ortmp, ortmp_bytes, st));
     if (h.tot_sw > 0) {
         HIPCHECK(c, copy_u32(sw_off, sw_cur, n_heavy, st));
-        HIPCHECK(c, launch_short_wedges(b.recs, (uint32_t)m, b.col, b.mptr, b.cursor, b.tc, b.tc_off,
+        HIPCHECK(c, launch_short_wedges(b.recs, (uint32_t)m, b.col, b.cursor, b.tc, b.tc_off,
                                         b.hp_off, tile_piece, sw_cnt, sw_cur, sw_list, true, st));
     }
     uint32_t* order = nullptr;

@@ -299,29 +299,44 @@ __global__ void k_plan_write(const u64* __restrict__ wu, const uint32_t* __restr
 }
 
 // -- bucketing of the short-middle wedges of split starts, two passes over
-// their short records: count per piece, then place.  Counts and reservations
-// go through an LDS table keyed by piece, one global atomic per (chunk, piece).
+// their short records: count per piece, then place.  A workgroup takes 256
+// records, 64 per wave; a wave reads the concatenation of the prefixes of its
+// short records of split starts 64 entries at a time (coalesced), finding each
+// entry's owner from head flags that mark where each prefix begins.  A prefix
+// is sorted by end vertex, so its tiles, and the pieces they belong to, do not
+// decrease: a window splits into runs of one piece.  Runs are counted in an LDS
+// table keyed by piece and reach global memory once per (workgroup, piece).
+// The fill pass reserves each piece's slots then and walks the prefixes again,
+// each run taking consecutive slots.  A piece that finds no table slot goes to
+// global memory directly, run by run.
 constexpr int kSwThreads = 256;
+constexpr uint32_t kSwWaves = kSwThreads / 64;
 constexpr uint32_t kSwLog2 = 11;
 constexpr uint32_t kSwSlots = 1u << kSwLog2;
 
 template <bool kFill>
 __global__ __launch_bounds__(kSwThreads) void k_short_wedges(
     const uint4* __restrict__ recs, uint32_t m, const uint32_t* __restrict__ col,
-    const uint32_t* __restrict__ mptr, const uint32_t* __restrict__ front,
-    const uint32_t* __restrict__ tc, const uint32_t* __restrict__ tc_off,
-    const uint32_t* __restrict__ hp_off, const uint32_t* __restrict__ tile_piece,
-    uint32_t* __restrict__ counts, uint32_t* __restrict__ cursor, uint32_t* __restrict__ list) {
+    const uint32_t* __restrict__ front, const uint32_t* __restrict__ tc,
+    const uint32_t* __restrict__ tc_off, const uint32_t* __restrict__ hp_off,
+    const uint32_t* __restrict__ tile_piece, uint32_t* __restrict__ counts,
+    uint32_t* __restrict__ cursor, uint32_t* __restrict__ list) {
     __shared__ uint32_t keys[kSwSlots];
     __shared__ uint32_t cnt[kSwSlots];
     __shared__ uint32_t base[kSwSlots];
-    const uint32_t tid = threadIdx.x;
+    __shared__ uint32_t s_adj[kSwWaves][64];  // per non-empty prefix: address - its first position
+    __shared__ uint32_t s_tb[kSwWaves][64];   // its start's tile-to-piece table
+    __shared__ uint32_t s_pb[kSwWaves][64];   // its start's first heavy piece
+    __shared__ uint32_t s_s1[kSwWaves][64];   // sign(u, v) of its record
+    __shared__ uint8_t s_head[kSwWaves][64];
+    const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
+    const u64 le_mask = ~0ull >> (63 - lane);  // lanes 0..lane
+    s_head[wave][lane] = 0;
     for (uint32_t c0 = blockIdx.x * kSwThreads; c0 < m; c0 += gridDim.x * kSwThreads) {
         for (uint32_t i = tid; i < kSwSlots; i += kSwThreads) {
             keys[i] = kEmpty;
             cnt[i] = 0;
         }
-        __syncthreads();
         const uint32_t j = c0 + tid;
         uint4 rc = make_uint4(0, 0, 0, 0);
         bool mine = false;
@@ -330,27 +345,69 @@ __global__ __launch_bounds__(kSwThreads) void k_short_wedges(
             const uint32_t u = rc.w;
             mine = tc[u] > 0 && j >= front[u];  // short record of a split start
         }
-        const uint32_t pos = mine ? rc.y >> 1 : 0u;
-        const uint32_t s1 = rc.y & 1u;
-        uint32_t tb0 = 0, pb = 0;
-        if (mine) {
-            tb0 = tc_off[rc.w];
-            pb = hp_off[rc.w];
+        const uint32_t len = mine ? rc.y >> 1 : 0u;
+        const u64 nz = __ballot(len > 0);
+        const uint32_t excl = wave_incl_scan(len) - len;
+        const uint32_t T = __shfl(excl + len, 63, 64);
+        if (len > 0) {
+            const uint32_t ci = (uint32_t)__popcll(nz & (le_mask >> 1));
+            s_adj[wave][ci] = rc.x - excl;
+            s_tb[wave][ci] = tc_off[rc.w];
+            s_pb[wave][ci] = hp_off[rc.w];
+            s_s1[wave][ci] = rc.y & 1u;
         }
-        // pass over the prefix: per entry, the piece of its tile
-        for (uint32_t e = 0; e < pos; ++e) {
-            const uint32_t x = col[rc.x + e];
-            const uint32_t gp = pb + tile_piece[tb0 + (x >> 1) / kTile];
-            const int sl = agg_slot<kSwLog2>(keys, gp);
-            if (!kFill) {
-                if (sl >= 0)
-                    atomicAdd(&cnt[sl], 1u);
-                else
-                    atomicAdd(&counts[gp], 1u);
-            } else if (sl >= 0) {
-                atomicAdd(&cnt[sl], 1u);
+        __syncthreads();
+        // place = false: count runs per piece; place = true (fill pass): each
+        // run takes consecutive slots from its piece's reserved range
+        auto walk = [&](const bool place) {
+            uint32_t before = 0;
+            for (uint32_t w0 = 0; w0 < T; w0 += 64) {
+                if (len > 0 && excl >= w0 && excl < w0 + 64) s_head[wave][excl - w0] = 1;
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                const u64 M = __ballot(s_head[wave][lane] != 0);
+                const uint32_t idx = before + (uint32_t)__popcll(M & le_mask) - 1u;
+                before += (uint32_t)__popcll(M);
+                const uint32_t q = w0 + lane;
+                const bool valid = q < T;
+                uint32_t gp = kEmpty, val = 0;
+                if (valid) {
+                    const uint32_t x = col[s_adj[wave][idx] + q];
+                    gp = s_pb[wave][idx] + tile_piece[s_tb[wave][idx] + (x >> 1) / kTile];
+                    val = (x & ~1u) | ((x ^ s_s1[wave][idx]) & 1u);
+                }
+                s_head[wave][lane] = 0;
+                // runs of equal piece among the valid lanes (a prefix of the window)
+                const uint32_t prev = __shfl_up(gp, 1, 64);
+                const u64 H = __ballot(valid && (lane == 0 || prev != gp));
+                const uint32_t nvalid = min(64u, T - w0);
+                const uint32_t head = 63u - (uint32_t)__clzll(H & le_mask);  // this lane's run
+                uint32_t rlen = 0;
+                if ((H >> lane) & 1ull) {
+                    const u64 later = lane < 63 ? H >> (lane + 1) : 0ull;
+                    rlen = later ? (uint32_t)__builtin_ctzll(later) + 1u : nvalid - lane;
+                }
+                uint32_t at = kEmpty;  // the run's first slot, if this pass writes it
+                if (rlen) {
+                    const int sl = agg_slot<kSwLog2>(keys, gp);
+                    if (!place) {
+                        if (sl >= 0)
+                            atomicAdd(&cnt[sl], rlen);
+                        else if (!kFill)
+                            atomicAdd(&counts[gp], rlen);
+                        else
+                            at = atomicAdd(&cursor[gp], rlen);  // no slot: placed now
+                    } else if (sl >= 0) {
+                        at = base[sl] + atomicAdd(&cnt[sl], rlen);
+                    }
+                }
+                if (kFill) {
+                    at = __shfl(at, (int)head, 64);
+                    if (valid && at != kEmpty) list[at + (lane - head)] = val;
+                }
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             }
-        }
+        };
+        walk(false);
         __syncthreads();
         for (uint32_t i = tid; i < kSwSlots; i += kSwThreads)
             if (keys[i] != kEmpty) {
@@ -361,16 +418,7 @@ __global__ __launch_bounds__(kSwThreads) void k_short_wedges(
                 cnt[i] = 0;
             }
         __syncthreads();
-        if (kFill) {
-            for (uint32_t e = 0; e < pos; ++e) {
-                const uint32_t x = col[rc.x + e];
-                const uint32_t gp = pb + tile_piece[tb0 + (x >> 1) / kTile];
-                const int sl = agg_slot<kSwLog2>(keys, gp);  // finds the slot taken above
-                const uint32_t at = sl >= 0 ? base[sl] + atomicAdd(&cnt[sl], 1u)
-                                            : atomicAdd(&cursor[gp], 1u);
-                list[at] = (x & ~1u) | ((x ^ s1) & 1u);
-            }
-        }
+        if (kFill) walk(true);
         __syncthreads();
     }
 }
@@ -475,18 +523,17 @@ hipError_t launch_plan_write(const u64* wu, const uint32_t* lowcnt, const uint32
 }
 
 hipError_t launch_short_wedges(const uint4* recs, uint32_t m, const uint32_t* col,
-                               const uint32_t* mptr, const uint32_t* front, const uint32_t* tc,
-                               const uint32_t* tc_off, const uint32_t* hp_off,
-                               const uint32_t* tile_piece, uint32_t* counts, uint32_t* cursor,
-                               uint32_t* list, bool fill, hipStream_t st) {
+                               const uint32_t* front, const uint32_t* tc, const uint32_t* tc_off,
+                               const uint32_t* hp_off, const uint32_t* tile_piece,
+                               uint32_t* counts, uint32_t* cursor, uint32_t* list, bool fill,
+                               hipStream_t st) {
     if (fill)
         hipLaunchKernelGGL(k_short_wedges<true>, grid_n(m, kSwThreads, 8192), dim3(kSwThreads), 0, st,
-                           recs, m, col, mptr, front, tc, tc_off, hp_off, tile_piece, counts, cursor,
-                           list);
+                           recs, m, col, front, tc, tc_off, hp_off, tile_piece, counts, cursor, list);
     else
         hipLaunchKernelGGL(k_short_wedges<false>, grid_n(m, kSwThreads, 8192), dim3(kSwThreads), 0,
-                           st, recs, m, col, mptr, front, tc, tc_off, hp_off, tile_piece, counts,
-                           cursor, list);
+                           st, recs, m, col, front, tc, tc_off, hp_off, tile_piece, counts, cursor,
+                           list);
     return hipGetLastError();
 }
 
