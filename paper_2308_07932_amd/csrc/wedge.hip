@@ -47,8 +47,12 @@ struct WedgeArgs {
 // Thread 0's running totals for one graph at a time; flushed to memory when
 // the graph changes and at the end (a single graph flushes once).
 struct GraphAcc {
-    uint32_t g = 0;
-    u64 bal = 0, unb = 0;
+    uint32_t g;
+    u64 bal, unb;
+    __device__ void reset() {
+        g = 0;
+        bal = unb = 0;
+    }
     __device__ void flush(const WedgeArgs& a) {
         if (bal == 0 && unb == 0) return;
         u64* dst = a.gres ? a.gres + 4ull * g : &a.ctl->balanced;
@@ -70,7 +74,7 @@ constexpr uint32_t kScanMax = 16;     // short middle prefixes are read whole an
 constexpr uint32_t kUnroll = 4;       // independent CSR loads in flight per lane
 constexpr uint32_t kWaves = kWedgeThreads / 64;
 constexpr uint32_t kStack = 16;       // pending halves of an abandoned piece
-constexpr uint32_t kChunk = 2048;     // longer sub-intervals are cut; the tail chunks are
+constexpr uint32_t kChunk = 1024;     // longer sub-intervals are cut; the tail chunks are
 constexpr uint32_t kQueue = 256;      // queued in LDS and shared by all waves afterwards
 
 __device__ inline uint32_t hash32(uint32_t w) { return w * 0x9E3779B1u; }
@@ -181,10 +185,14 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
     const uint32_t* __restrict__ col = a.col;
     for (uint32_t u = 0; u < kUnroll; ++u) s_head[wave][u * 64 + lane] = 0;
 
-    GraphAcc acc;                  // this workgroup's totals (thread 0)
-    Piece pf;                      // thread 0: the next heavy item's piece, fetched ahead
-    uint32_t pf_item = kEmpty;
-    if (tid == 0) s_item = atomicAdd(&a.ctl->queue, 1u);
+    __shared__ GraphAcc s_acc;     // this workgroup's totals (thread 0)
+    __shared__ Piece s_pf;         // the next heavy item's piece, fetched ahead
+    __shared__ uint32_t s_pf_item;
+    if (tid == 0) {
+        s_acc.reset();
+        s_pf_item = kEmpty;
+        s_item = atomicAdd(&a.ctl->queue, 1u);
+    }
     for (;;) {
         __syncthreads();  // every thread is done with the previous item; s_item is set
         const uint32_t item = s_item;
@@ -193,7 +201,7 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
         if (tid == 0) next = atomicAdd(&a.ctl->queue, 1u);  // in flight while this item runs
         uint32_t np = 1;
         if (item < a.n_heavy) {
-            if (tid == 0) s_pc[0] = (pf_item == item) ? pf : a.pieces[a.order[item]];
+            if (tid == 0) s_pc[0] = (s_pf_item == item) ? s_pf : a.pieces[a.order[item]];
         } else {
             const uint32_t li = item - a.n_heavy;
             const uint32_t p0 = a.n_heavy + a.items_first[li];
@@ -238,7 +246,8 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
                 (heavy && (s_pc[0].flags & kPiecePartial)) ? a.d.probe_limit : kHashSlots;
             const uint32_t plo0 = s_pc[0].lo, phi0 = s_pc[0].hi, region0 = s_pc[0].region;
             if (dense) {
-                const uint32_t words = d16 ? (dwidth + 1) / 2 : dwidth;
+                // up to a whole 16-byte unit past the width, which the finalize reads
+                const uint32_t words = d16 ? (dwidth + 3) / 4 * 2 : (dwidth + 1) / 2 * 2;
                 for (uint32_t i = tid; i < words; i += kWedgeThreads) s_tab[i] = 0;
             } else if (h16) {
                 for (uint32_t i = tid; i < kHash16Slots; i += kWedgeThreads) {
@@ -251,14 +260,14 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
                     hvals[i] = 0;
                 }
             }
-            if (tid == 0 && next < a.n_heavy && pf_item != next) {
-                pf = a.pieces[a.order[next]];
-                pf_item = next;
+            if (tid == 0 && next < a.n_heavy && s_pf_item != next) {
+                s_pf = a.pieces[a.order[next]];
+                s_pf_item = next;
             }
             __syncthreads();
             const uint32_t total = s_pre[np];
             // records per grab: small items are shared by all waves, large ones in 64s
-            const uint32_t bsz = min(64u, max(8u, (total + 63) / 64));
+            const uint32_t bsz = min(32u, max(8u, (total + 63) / 64));
 
             // pass over the piece's records: count (readback = false) or, in
             // per-vertex mode, read the complete buckets back (readback = true)
@@ -596,6 +605,32 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
                         s_pu[p] = pu;
                     }
                 }
+            } else if (!PV && dense && d16 && !(s_pc[0].flags & kPieceMerge)) {
+                // 16-bit halves: C(l,2) + C(m,2) and l*m fit 32 bits; entries past
+                // the width are zero, and so are buckets no wedge reached
+                const uint4* t4 = reinterpret_cast<const uint4*>(s32);
+                for (uint32_t g = tid; g < (dwidth + 3) / 4; g += kWedgeThreads) {
+                    const uint4 c = t4[g];
+                    const uint32_t cc[4] = {c.x, c.y, c.z, c.w};
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const uint32_t l = cc[k] & 0xFFFFu, mm = cc[k] >> 16;
+                        bal += ((l * (l - 1u)) >> 1) + ((mm * (mm - 1u)) >> 1);
+                        unb += l * mm;
+                    }
+                }
+            } else if (!PV && dense && !(s_pc[0].flags & kPieceMerge)) {
+                const ulonglong2* t2 = reinterpret_cast<const ulonglong2*>(s_tab);
+                for (uint32_t g = tid; g < (dwidth + 1) / 2; g += kWedgeThreads) {
+                    const ulonglong2 c = t2[g];
+                    const u64 cc[2] = {c.x, c.y};
+#pragma unroll
+                    for (int k = 0; k < 2; ++k) {
+                        const u64 l = cc[k] & 0xFFFFFFFFull, mm = cc[k] >> 32;
+                        bal += choose2(l) + choose2(mm);
+                        unb += l * mm;
+                    }
+                }
             } else if (dense) {
                 const bool merge = (s_pc[0].flags & kPieceMerge) != 0;
                 const uint32_t gb = s_pc[0].gbase;
@@ -621,12 +656,29 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
                     }
                 }
             } else if (h16) {
-                for (uint32_t i = tid; i < kHash16Slots; i += kWedgeThreads) {
-                    if (s32[i] == kEmpty) continue;
-                    const uint32_t c = s32[kHash16Slots + i];
-                    const u64 l = c & 0xFFFFu, m = c >> 16;
-                    bal += choose2(l) + choose2(m);
-                    unb += l * m;
+                // counters of empty slots are zero
+                const uint4* c4 = reinterpret_cast<const uint4*>(s32 + kHash16Slots);
+                for (uint32_t g = tid; g < kHash16Slots / 4; g += kWedgeThreads) {
+                    const uint4 c = c4[g];
+                    const uint32_t cc[4] = {c.x, c.y, c.z, c.w};
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const uint32_t l = cc[k] & 0xFFFFu, mm = cc[k] >> 16;
+                        bal += ((l * (l - 1u)) >> 1) + ((mm * (mm - 1u)) >> 1);
+                        unb += l * mm;
+                    }
+                }
+            } else if (!PV) {
+                const ulonglong2* v2 = reinterpret_cast<const ulonglong2*>(hvals);
+                for (uint32_t g = tid; g < kHashSlots / 2; g += kWedgeThreads) {
+                    const ulonglong2 c = v2[g];
+                    const u64 cc[2] = {c.x, c.y};
+#pragma unroll
+                    for (int k = 0; k < 2; ++k) {
+                        const u64 l = cc[k] & 0xFFFFFFFFull, mm = cc[k] >> 32;
+                        bal += choose2(l) + choose2(mm);
+                        unb += l * mm;
+                    }
                 }
             } else {
                 for (uint32_t i = tid; i < kHashSlots; i += kWedgeThreads) {
@@ -651,7 +703,7 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
             if (tid == 0) {
                 if (per_piece) {
                     for (uint32_t p = 0; p < np; ++p) {
-                        acc.add(a, s_pc[p].graph, s_pb[p], s_pu[p]);
+                        s_acc.add(a, s_pc[p].graph, s_pb[p], s_pu[p]);
                         if (PV && s_pb[p]) atomicAdd(&a.pv[s_pc[p].start_row], s_pb[p]);
                     }
                 } else {
@@ -660,7 +712,7 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
                         sb += s_red[0][w];
                         su += s_red[1][w];
                     }
-                    acc.add(a, s_pc[0].graph, sb, su);
+                    s_acc.add(a, s_pc[0].graph, sb, su);
                     if (PV && sb) atomicAdd(&a.pv[s_pc[0].start_row], sb);
                 }
                 if (s_sp > 0) s_pc[0] = s_stack[--s_sp];
@@ -671,7 +723,7 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
         }
         if (tid == 0) s_item = next;
     }
-    if (tid == 0) acc.flush(a);
+    if (tid == 0) s_acc.flush(a);
 }
 
 // per-vertex output by input vertex id: out[x] = count of x's row
