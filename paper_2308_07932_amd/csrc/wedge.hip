@@ -174,7 +174,7 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
     constexpr uint32_t kQ = PV ? 1 : kQueue;
     __shared__ uint32_t s_qadj[kQ], s_qlen[kQ], s_qaux[kQ];  // queued long chunks
     __shared__ uint32_t s_wvrow[PV ? kWaves : 1][64];  // PV: row of each interval's middle
-    __shared__ uint32_t s_qn, s_qtake;
+    __shared__ uint32_t s_qn, s_qtake, s_swtake;
     __shared__ u64 s_red[2][kWaves];
     __shared__ u64 s_pb[kMaxItemPieces], s_pu[kMaxItemPieces];  // per-piece totals (batches)
     uint32_t* keys = (uint32_t*)s_tab;
@@ -234,6 +234,7 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
                 s_batch = 0;
                 s_qn = 0;
                 s_qtake = 0;
+                s_swtake = 0;
             }
             const bool dense = (s_pc[0].flags & kPieceDense) != 0;
             const bool d16 = (s_pc[0].flags & kPieceDense16) != 0;  // u32 counters l | m << 16
@@ -472,6 +473,41 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
             }
             };
             records_pass(false);
+            // -- the bucketed wedges through short middle rows (split starts) fill
+            // the tail of the record sweep: waves take 64 * kUnroll at a time
+            if (!PV && heavy && (s_pc[0].flags & kPiecePartial) && s_pc[0].list != kEmpty) {
+                const uint32_t b0 = a.sw_off[s_pc[0].list];
+                const uint32_t n_sw = a.sw_off[s_pc[0].list + 1] - b0;
+                bool ok = true;
+                for (;;) {
+                    uint32_t c = 0;
+                    if (lane == 0) c = atomicAdd(&s_swtake, 64 * kUnroll);
+                    c = __shfl(c, 0, 64);
+                    if (c >= n_sw || s_abort || !ok) break;
+                    uint32_t x[kUnroll];
+#pragma unroll
+                    for (uint32_t u = 0; u < kUnroll; ++u) {
+                        const uint32_t q = c + u * 64 + lane;
+                        x[u] = q < n_sw ? a.sw_list[b0 + q] : kEmpty;
+                    }
+                    bool lok = true;
+#pragma unroll
+                    for (uint32_t u = 0; u < kUnroll; ++u) {
+                        if (x[u] == kEmpty || !lok) continue;
+                        const uint32_t w = x[u] >> 1;
+                        if (w < plo0 || w >= phi0) continue;  // a re-split half keeps its share
+                        if (dense && d16)
+                            atomicAdd(&s32[w - dlo], (x[u] & 1u) ? 0x10000u : 1u);
+                        else if (h16)
+                            lok = bucket_add16(s32, lim0, w, (x[u] & 1u) ? 0x10000u : 1u);
+                        else
+                            lok = bucket_add(s_tab, keys, hvals, dense, dlo, region0, lim0, w,
+                                             (x[u] & 1u) ? (1ull << 32) : 1ull);
+                    }
+                    ok = __ballot(!lok) == 0;  // wave-uniform: lane 0 keeps taking entries
+                }
+                if (!ok) s_abort = 1;
+            }
             __syncthreads();
             // -- queued chunks of long sub-intervals: one wave per chunk, coalesced
             if (!PV && np == 1) {
@@ -506,35 +542,6 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
                                 lok = bucket_add(s_tab, keys, hvals, false, 0, region0, lim0, w, inc);
                         }
                         ok = __ballot(!lok) == 0;  // wave-uniform: lane 0 keeps taking chunks
-                    }
-                }
-                if (!ok) s_abort = 1;
-            }
-            // -- bucketed wedges through short middle rows (split starts)
-            if (!PV && heavy && (s_pc[0].flags & kPiecePartial) && s_pc[0].list != kEmpty) {
-                const uint32_t L = s_pc[0].list;
-                const uint32_t b0 = a.sw_off[L], b1 = a.sw_off[L + 1];
-                const uint32_t plo = s_pc[0].lo, phi = s_pc[0].hi, region = s_pc[0].region;
-                bool ok = true;
-                for (uint32_t q0 = b0 + tid; q0 < b1 && ok && !s_abort; q0 += kWedgeThreads * kUnroll) {
-                    uint32_t x[kUnroll];
-#pragma unroll
-                    for (uint32_t u = 0; u < kUnroll; ++u) {
-                        const uint32_t q = q0 + u * kWedgeThreads;
-                        x[u] = q < b1 ? a.sw_list[q] : kEmpty;
-                    }
-#pragma unroll
-                    for (uint32_t u = 0; u < kUnroll; ++u) {
-                        if (x[u] == kEmpty || !ok) continue;
-                        const uint32_t w = x[u] >> 1;
-                        if (w < plo || w >= phi) continue;  // a re-split half keeps its share
-                        if (dense && d16)
-                            atomicAdd(&s32[w - dlo], (x[u] & 1u) ? 0x10000u : 1u);
-                        else if (h16)
-                            ok = bucket_add16(s32, lim0, w, (x[u] & 1u) ? 0x10000u : 1u);
-                        else
-                            ok = bucket_add(s_tab, keys, hvals, dense, dlo, region, lim0, w,
-                                            (x[u] & 1u) ? (1ull << 32) : 1ull);
                     }
                 }
                 if (!ok) s_abort = 1;
