@@ -324,12 +324,79 @@ __global__ __launch_bounds__(256) void k_sort_group(const uint32_t* __restrict__
     if (dup) atomicOr(&ctl->dup, 1u);
 }
 
-// rows with 64 < len <= 4096: one workgroup per row, bitonic sort in LDS
+// Entries of a row are per-side indices of the other side; in a batch they lie
+// in the row's graph's block of that side.
+__device__ inline void entry_range(const Dims& d, uint32_t r, uint32_t* lo, uint32_t* hi) {
+    const uint32_t side = r >= d.n_u ? 1u : 0u;
+    if (d.blk[0]) {
+        const uint32_t g = block_of(d.blk[side], d.n_graphs, r - d.base[side]);
+        *lo = d.blk[side ^ 1u][g];
+        *hi = d.blk[side ^ 1u][g + 1];
+    } else {
+        *lo = 0;
+        *hi = d.size[side ^ 1u];
+    }
+}
+
+// Emits the set bits of an LDS bitmap (bit y: entry (lo + y) << 1 | sign) in
+// order to out[base ..), each thread owning `per` consecutive words, and fills
+// [base + set bits, base + want) with copies of the last entry: fewer bits than
+// entries means a repeated neighbour, and the copies keep every entry in range
+// and the repetition visible to the per-graph duplicate check.  Returns after a
+// barrier; s_scan needs blockDim / 64 words.
+__device__ inline void bitmap_emit(const uint32_t* bm, const uint32_t* sg, uint32_t words,
+                                   uint32_t per, uint32_t lo, uint32_t* __restrict__ out,
+                                   uint64_t base, uint32_t want, uint32_t* s_scan,
+                                   uint32_t* s_last) {
+    const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
+    const uint32_t nw = blockDim.x >> 6;
+    const uint32_t w0 = tid * per, w1 = min(words, w0 + per);
+    uint32_t cnt = 0, last = 0;  // last: 1 + highest set bit of this thread's words
+    for (uint32_t i = w0; i < w1; ++i) {
+        cnt += __popc(bm[i]);
+        if (bm[i]) last = i * 32 + (32 - __clz(bm[i]));
+    }
+    const uint32_t incl = wave_incl_scan(cnt);
+    for (uint32_t off = 32; off > 0; off >>= 1) last = max(last, __shfl_xor(last, off, 64));
+    if (lane == 63) s_scan[wave] = incl;
+    if (lane == 0) atomicMax(s_last, last);
+    __syncthreads();
+    uint32_t off = 0, total = 0;
+    for (uint32_t w = 0; w < nw; ++w) {
+        if (w < wave) off += s_scan[w];
+        total += s_scan[w];
+    }
+    uint64_t pos = base + off + incl - cnt;
+    for (uint32_t i = w0; i < w1; ++i) {
+        uint32_t bits = bm[i];
+        while (bits) {
+            const uint32_t bt = __ffs(bits) - 1;
+            if (pos < base + want) out[pos] = ((lo + i * 32 + bt) << 1) | ((sg[i] >> bt) & 1u);
+            ++pos;
+            bits &= bits - 1;
+        }
+    }
+    if (total < want && *s_last > 0) {
+        const uint32_t y = *s_last - 1;
+        const uint32_t v = ((lo + y) << 1) | ((sg[y >> 5] >> (y & 31)) & 1u);
+        for (uint32_t i = total + tid; i < want; i += blockDim.x) out[base + i] = v;
+    }
+    __syncthreads();
+}
+
+// rows with 64 < len <= 4096: one workgroup per row.  If the row's entries
+// span at most kMidBits indices (every row of a batch), an LDS bitmap (plus a
+// sign bitmap) sorts them; otherwise a bitonic sort in LDS.
+constexpr uint32_t kMidBits = 16384;
+
 __global__ __launch_bounds__(256) void k_sort_block(const uint32_t* __restrict__ row_ptr,
                                                    const uint32_t* __restrict__ in,
                                                    uint32_t* __restrict__ out, Dims d,
                                                    Control* ctl) {
     __shared__ uint32_t s[4096];
+    __shared__ uint32_t s_scan[4];
+    __shared__ uint32_t s_last;
+    static_assert(2 * kMidBits / 32 <= 4096, "bitmaps fit the sort buffer");
     uint32_t lo0, hi0, lo1, hi1;
     class_range(ctl, d, 0, 5, 5, &lo0, &hi0);
     class_range(ctl, d, 1, 5, 5, &lo1, &hi1);
@@ -338,6 +405,31 @@ __global__ __launch_bounds__(256) void k_sort_block(const uint32_t* __restrict__
     for (uint32_t q = blockIdx.x; q < tot; q += gridDim.x) {
         uint32_t r = row_at(d, q < n0 ? lo0 + q : lo1 + (q - n0));
         uint32_t a = row_ptr[r], L = row_ptr[r + 1] - a;
+        uint32_t elo, ehi;
+        entry_range(d, r, &elo, &ehi);
+        if (ehi - elo <= kMidBits) {
+            const uint32_t words = (ehi - elo + 31) / 32;
+            uint32_t* bm = s;
+            uint32_t* sg = s + kMidBits / 32;
+            for (uint32_t i = threadIdx.x; i < words; i += blockDim.x) {
+                bm[i] = 0;
+                sg[i] = 0;
+            }
+            if (threadIdx.x == 0) s_last = 0;
+            __syncthreads();
+            for (uint32_t i = threadIdx.x; i < L; i += blockDim.x) {
+                const uint32_t x = in[a + i];
+                const uint32_t y = (x >> 1) - elo;
+                if (y >= ehi - elo) continue;  // cannot happen: entries lie in the block
+                const uint32_t msk = 1u << (y & 31);
+                if (atomicOr(&bm[y >> 5], msk) & msk) dup = true;
+                if (x & 1u) atomicOr(&sg[y >> 5], msk);
+            }
+            __syncthreads();
+            bitmap_emit(bm, sg, words, (words + blockDim.x - 1) / blockDim.x, elo, out, a, L,
+                        s_scan, &s_last);
+            continue;
+        }
         uint32_t P = 1;
         while (P < L) P <<= 1;
         for (uint32_t i = threadIdx.x; i < P; i += blockDim.x) s[i] = i < L ? in[a + i] : kEmpty;
@@ -403,8 +495,8 @@ __global__ __launch_bounds__(kBigThreads) void k_sort_big(const uint32_t* __rest
     __shared__ uint32_t bm[kBigWords];
     __shared__ uint32_t sgn[kBigWords];
     __shared__ uint32_t s_wave[kBigThreads / 64];
-    __shared__ uint32_t s_before;
-    const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
+    __shared__ uint32_t s_before, s_inside, s_last;
+    const uint32_t tid = threadIdx.x, lane = lane_id();
     bool dup = false;
     for (uint32_t q = blockIdx.x;; q += gridDim.x) {
         uint32_t r, c, ok;
@@ -414,17 +506,22 @@ __global__ __launch_bounds__(kBigThreads) void k_sort_big(const uint32_t* __rest
             bm[i] = 0;
             sgn[i] = 0;
         }
-        if (tid == 0) s_before = 0;
+        if (tid == 0) {
+            s_before = 0;
+            s_inside = 0;
+            s_last = 0;
+        }
         __syncthreads();
         const uint32_t a = row_ptr[r], L = row_ptr[r + 1] - a;
         const uint32_t c0 = c * kBitmapChunk;
-        uint32_t before = 0;
+        uint32_t before = 0, inside = 0;  // entries below this chunk / in it (with repeats)
         for (uint32_t e = tid; e < L; e += kBigThreads) {
             uint32_t x = in[a + e];
             uint32_t y = x >> 1;
             if (y < c0) {
                 before++;
             } else if (y - c0 < kBitmapChunk) {
+                inside++;
                 uint32_t bit = y - c0;
                 uint32_t m = 1u << (bit & 31);
                 uint32_t old = atomicOr(&bm[bit >> 5], m);
@@ -433,30 +530,15 @@ __global__ __launch_bounds__(kBigThreads) void k_sort_big(const uint32_t* __rest
             }
         }
         before = wave_reduce_sum(before);
-        if (lane == 0) atomicAdd(&s_before, before);
-        __syncthreads();
-        // compaction: each thread owns kBigWords / kBigThreads consecutive words
-        constexpr uint32_t kPer = kBigWords / kBigThreads;
-        uint32_t cnt = 0;
-        for (uint32_t i = 0; i < kPer; ++i) cnt += __popc(bm[tid * kPer + i]);
-        uint32_t incl = wave_incl_scan(cnt);
-        if (lane == 63) s_wave[wave] = incl;
-        __syncthreads();
-        uint32_t off = 0;
-        for (uint32_t w = 0; w < wave; ++w) off += s_wave[w];
-        uint32_t pos = a + s_before + off + incl - cnt;
-        for (uint32_t i = 0; i < kPer; ++i) {
-            uint32_t wi = tid * kPer + i;
-            uint32_t bits = bm[wi], sb = sgn[wi];
-            while (bits) {
-                uint32_t b = __ffs(bits) - 1;
-                uint32_t y = c0 + wi * 32 + b;
-                if (pos < a + L) out[pos] = (y << 1) | ((sb >> b) & 1u);
-                pos++;
-                bits &= bits - 1;
-            }
+        inside = wave_reduce_sum(inside);
+        if (lane == 0) {
+            atomicAdd(&s_before, before);
+            atomicAdd(&s_inside, inside);
         }
         __syncthreads();
+        // this chunk's entries take [a + s_before, a + s_before + s_inside)
+        bitmap_emit(bm, sgn, kBigWords, kBigWords / kBigThreads, c0, out, (uint64_t)a + s_before,
+                    min(s_inside, L - min(L, s_before)), s_wave, &s_last);
     }
     if (dup) atomicOr(&ctl->dup, 1u);
 }

@@ -146,6 +146,30 @@ def test_batch_with_a_large_graph(ctx):
         assert res.result(i) == expect(g), (i, g.name)
 
 
+def test_batch_long_rows_and_repeats(ctx):
+    # rows sorted through LDS bitmaps: medium rows (65..4096 entries, every row
+    # of a batch spans one small graph block) and rows above 4096 entries; a
+    # repeated edge in such a row is reported for its graph only
+    rng = np.random.default_rng(21)
+    graphs = mixed_graphs(14, 12)
+    graphs.insert(2, gen.complete_graph(3, 3000, rng.choice([1, -1], 3), rng.choice([1, -1], 3000)))
+    graphs.insert(5, gen.complete_graph(2, 6000, rng.choice([1, -1], 2), rng.choice([1, -1], 6000)))
+    big = gen.complete_graph(2, 5000)
+    graphs.insert(7, big._replace(eu=np.append(big.eu, np.int32(1)), ev=np.append(big.ev, np.int32(4321)),
+                                  sign=np.append(big.sign, np.int8(-1))))
+    mid = gen.complete_graph(3, 2000)
+    graphs.insert(9, mid._replace(eu=np.append(mid.eu, np.int32(2)), ev=np.append(mid.ev, np.int32(1234)),
+                                  sign=np.append(mid.sign, np.int8(1))))
+    res = run_batch(ctx, graphs)
+    for i, g in enumerate(graphs):
+        if i in (7, 9):
+            assert res.status[i] == bbc.DUPLICATE_EDGE, (i, res.status[i])
+            assert res.result(i) == bbc.Result(0, 0, 0)
+        else:
+            assert res.status[i] == bbc.OK, (i, res.status[i])
+            assert res.result(i) == expect(g), (i, g.name)
+
+
 def test_batch_device_input_matches_host(ctx):
     import torch
     graphs = mixed_graphs(11, 90)

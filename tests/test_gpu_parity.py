@@ -280,6 +280,11 @@ def test_error_paths(ctx):
     dup = k._replace(eu=np.append(k.eu, np.int32(1)), ev=np.append(k.ev, np.int32(4321)),
                      sign=np.append(k.sign, np.int8(-1)))
     assert _raw(ctx, dup)[0] == bbc.DUPLICATE_EDGE
+    # duplicate inside a medium row whose neighbours span few ids (bitmap-sorted)
+    k = gen.complete_graph(3, 2000)
+    dup = k._replace(eu=np.append(k.eu, np.int32(2)), ev=np.append(k.ev, np.int32(1234)),
+                     sign=np.append(k.sign, np.int8(1)))
+    assert _raw(ctx, dup)[0] == bbc.DUPLICATE_EDGE
     # sizes and pointers
     out = bbc._CResult()
     assert ctx._lib.bbc_count(ctx._h, -1, 5, 0, None, None, None, 0, ctypes.byref(out), None) == bbc.INVALID_ARG
