@@ -175,6 +175,7 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
     __shared__ uint32_t s_qadj[kQ], s_qlen[kQ], s_qaux[kQ];  // queued long chunks
     __shared__ uint32_t s_wvrow[PV ? kWaves : 1][64];  // PV: row of each interval's middle
     __shared__ uint32_t s_qn, s_qtake, s_swtake;
+    __shared__ bool s_multi;
     __shared__ u64 s_red[2][kWaves];
     __shared__ u64 s_pb[kMaxItemPieces], s_pu[kMaxItemPieces];  // per-piece totals (batches)
     uint32_t* keys = (uint32_t*)s_tab;
@@ -220,14 +221,19 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
             // prefix of record counts over the pieces (wave 0)
             if (wave == 0) {
                 uint32_t carry = 0;
+                u64 multi = 0;  // pieces of more than one graph (batches)
                 for (uint32_t c = 0; c < np; c += 64) {
                     uint32_t i = c + lane;
                     uint32_t v = i < np ? s_pc[i].nrec : 0u;
                     uint32_t incl = wave_incl_scan(v);
                     if (i < np) s_pre[i] = carry + incl - v;
                     carry += __shfl(incl, 63, 64);
+                    multi |= __ballot(i < np && s_pc[i].graph != s_pc[0].graph);
                 }
-                if (lane == 0) s_pre[np] = carry;
+                if (lane == 0) {
+                    s_pre[np] = carry;
+                    s_multi = multi != 0;
+                }
             }
             if (tid == 0) {
                 s_abort = 0;
@@ -586,9 +592,9 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
             // -- finalize: C(l,2) + C(m,2) and l*m over the buckets
             u64 bal = 0, unb = 0;
             // a light item of a batch may hold starts of several graphs, and in
-            // per-vertex mode every start needs its own total: one wave per
-            // piece sums the piece's own hash region
-            const bool per_piece = (a.gres != nullptr || PV) && np > 1;
+            // per-vertex mode every start needs its own total: then one wave
+            // per piece sums the piece's own hash region
+            const bool per_piece = np > 1 && (PV || (a.gres != nullptr && s_multi));
             const u64 ubase0 = a.d.base[(s_pc[0].flags & kPieceSideV) ? 1u : 0u];
             if (per_piece) {
                 for (uint32_t p = wave; p < np; p += kWaves) {
