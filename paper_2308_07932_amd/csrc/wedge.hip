@@ -176,6 +176,7 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
     __shared__ uint32_t s_wvrow[PV ? kWaves : 1][64];  // PV: row of each interval's middle
     __shared__ uint32_t s_qn, s_qtake, s_swtake;
     __shared__ bool s_multi;
+    __shared__ uint32_t s_next, s_nextok, s_done;
     __shared__ u64 s_red[2][kWaves];
     __shared__ u64 s_pb[kMaxItemPieces], s_pu[kMaxItemPieces];  // per-piece totals (batches)
     uint32_t* keys = (uint32_t*)s_tab;
@@ -198,8 +199,7 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
         __syncthreads();  // every thread is done with the previous item; s_item is set
         const uint32_t item = s_item;
         if (item >= a.n_items) break;
-        uint32_t next = 0;
-        if (tid == 0) next = atomicAdd(&a.ctl->queue, 1u);  // in flight while this item runs
+        if (tid == 0) s_nextok = 0;  // the next item is taken during this one
         uint32_t np = 1;
         if (item < a.n_heavy) {
             if (tid == 0) s_pc[0] = (s_pf_item == item) ? s_pf : a.pieces[a.order[item]];
@@ -208,7 +208,7 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
             const uint32_t p0 = a.n_heavy + a.items_first[li];
             np = a.n_heavy + a.items_first[li + 1] - p0;
             if (np == 0 || np > kMaxItemPieces) {  // never planned; uniform across the block
-                if (tid == 0) s_item = next;
+                if (tid == 0) s_item = atomicAdd(&a.ctl->queue, 1u);
                 continue;
             }
             if (tid < np) s_pc[tid] = a.pieces[p0 + tid];
@@ -241,6 +241,7 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
                 s_qn = 0;
                 s_qtake = 0;
                 s_swtake = 0;
+                s_done = 0;
             }
             const bool dense = (s_pc[0].flags & kPieceDense) != 0;
             const bool d16 = (s_pc[0].flags & kPieceDense16) != 0;  // u32 counters l | m << 16
@@ -266,10 +267,6 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
                     keys[i] = kEmpty;
                     hvals[i] = 0;
                 }
-            }
-            if (tid == 0 && next < a.n_heavy && s_pf_item != next) {
-                s_pf = a.pieces[a.order[next]];
-                s_pf_item = next;
             }
             __syncthreads();
             const uint32_t total = s_pre[np];
@@ -514,6 +511,21 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
                 }
                 if (!ok) s_abort = 1;
             }
+            // the first wave done with the sweep takes the next item from the queue
+            // and fetches its piece while the other waves finish
+            {
+                uint32_t f = 1;
+                if (lane == 0) f = atomicAdd(&s_done, 1u);
+                if (lane == 0 && f == 0 && !s_nextok) {
+                    const uint32_t nx = atomicAdd(&a.ctl->queue, 1u);
+                    if (nx < a.n_heavy && s_pf_item != nx) {
+                        s_pf = a.pieces[a.order[nx]];
+                        s_pf_item = nx;
+                    }
+                    s_next = nx;
+                    s_nextok = 1;
+                }
+            }
             __syncthreads();
             // -- queued chunks of long sub-intervals: one wave per chunk, coalesced
             if (!PV && np == 1) {
@@ -734,7 +746,7 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
             __syncthreads();
             if (s_sp > kStack) break;
         }
-        if (tid == 0) s_item = next;
+        if (tid == 0) s_item = s_nextok ? s_next : atomicAdd(&a.ctl->queue, 1u);
     }
     if (tid == 0) s_acc.flush(a);
 }
