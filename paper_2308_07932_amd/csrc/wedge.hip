@@ -322,9 +322,11 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
                         }
                     }
                 }
-                // -- a long sub-interval keeps its first kChunk entries; the rest goes
-                // to the LDS queue in chunks of kChunk (as many as fit)
-                if (!PV && ib - ia > kChunk) {
+                // -- a long sub-interval of a one-piece item keeps its first kChunk
+                // entries; the rest goes to the LDS queue in chunks of kChunk (as many
+                // as fit).  The queue is drained with the first piece's buckets, so an
+                // item of several pieces keeps its intervals whole.
+                if (!PV && np == 1 && ib - ia > kChunk) {
                     const uint32_t want = (ib - ia - 1) / kChunk;  // chunks beyond the first
                     uint32_t old = s_qn, got = 0;
                     for (;;) {

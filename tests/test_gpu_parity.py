@@ -255,6 +255,35 @@ def _raw(ctx, g, flags=0, pv=None):
     return rc, (out.balanced, out.unbalanced, out.wedges)
 
 
+def long_interval_light_graph(seed: int) -> SignedBipartiteGraph:
+    """A light start u (2000 wedges) whose middle v1 holds 1100 of u's ends in one
+    interval, packed into one work item with two other light starts that come
+    before it in priority order (U vertices of a K(3,3) raised above their
+    middles by two leaves each): the interval exceeds the kernel's queued-chunk
+    length inside an item of several pieces.  v2 shares 900 of the ends, so
+    every end's bucket matters.  U: 0 = u, 1..1100 = the ends, 1101..1103 = the
+    K(3,3) side a; V: 0 = v1, 1 = v2, 2..1101 = leaves of u (raising its
+    priority), 1102..1104 = the K(3,3) side b, 1105..1110 = leaves of side a."""
+    rng = np.random.default_rng(seed)
+    e = [(0, 0), (0, 1)] + [(0, 2 + i) for i in range(1100)]
+    e += [(1 + i, 0) for i in range(1100)] + [(1 + i, 1) for i in range(200, 1100)]
+    e += [(1101 + i, 1102 + j) for i in range(3) for j in range(3)]
+    e += [(1101 + i, 1105 + 2 * i + k) for i in range(3) for k in range(2)]
+    e = np.array(e)
+    s = rng.choice([1, -1], len(e), p=[0.7, 0.3]).astype(np.int8)
+    return SignedBipartiteGraph(1104, 1111, e[:, 0].astype(np.int32), e[:, 1].astype(np.int32), s,
+                                f"long_interval_light_{seed}")
+
+
+def test_long_interval_in_light_item(ctx):
+    for seed in range(3):
+        g = long_interval_light_graph(seed)
+        check(ctx, g)
+        r = ctx.count_batch(*bbc.concat_graphs([g, gen.complete_graph(4, 5), g]))
+        want = bbc.Result(*oracle.count(g), oracle.wedges(g))
+        assert r.result(0) == want and r.result(2) == want
+
+
 def test_error_paths(ctx):
     g = gen.uniform_graph(seed=3, n_u=100, n_v=80, n_edges=2000)
     bad = g.ev.copy()
