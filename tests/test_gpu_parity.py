@@ -284,6 +284,52 @@ def test_long_interval_in_light_item(ctx):
         assert r.result(0) == want and r.result(2) == want
 
 
+def threshold_graph(seed: int) -> SignedBipartiteGraph:
+    """Hubs on both sides whose degrees sit at the wedge kernel's size limits
+    (short-prefix scan 16, long middle 64, queued chunk 1024, light start
+    2048) over a random background, plus on each side two "leafy" starts: a
+    vertex raised above every hub by fresh leaf neighbours and joined to a hub
+    of degree 1300 or 1400 and one of degree 400 or 500, so that it is a light
+    start (about 1700 wedges) whose interval through the first hub is longer
+    than a queued chunk and shares ends with the second."""
+    rng = np.random.default_rng(seed)
+    n = [int(rng.integers(2500, 4000)), int(rng.integers(2500, 4000))]
+    degs = [15, 16, 17, 63, 64, 65, 1023, 1024, 1025, 2047, 2049]
+    pairs = set()
+    hubs = [[], []]
+    for side in (0, 1):
+        cand = rng.choice(n[side], len(degs) + 4, replace=False)
+        for h, dg in zip(cand, degs + [1300, 1400, 400, 500]):
+            hubs[side].append(int(h))
+            for o in rng.choice(n[1 - side], min(dg, n[1 - side]), replace=False):
+                pairs.add((int(h), int(o)) if side == 0 else (int(o), int(h)))
+    m_bg = int(rng.integers(5000, 20000))
+    for u, v in zip(rng.integers(0, n[0], m_bg), rng.integers(0, n[1], m_bg)):
+        pairs.add((int(u), int(v)))
+    for side in (0, 1):
+        for k in range(2):
+            x = int(rng.integers(0, n[side]))
+            mids = [hubs[1 - side][11 + k], hubs[1 - side][13 + k]]  # degrees 1300/1400, 400/500
+            leaves = int(rng.integers(2100, 2600))
+            first = n[1 - side]
+            n[1 - side] += leaves
+            for o in mids + list(range(first, first + leaves)):
+                pairs.add((x, o) if side == 0 else (o, x))
+    e = np.array(sorted(pairs))[rng.permutation(len(pairs))]
+    sg = rng.choice([1, -1], len(e), p=[0.6, 0.4]).astype(np.int8)
+    return SignedBipartiteGraph(n[0], n[1], e[:, 0].astype(np.int32), e[:, 1].astype(np.int32), sg,
+                                f"thresholds{seed}")
+
+
+def test_size_limit_structures(ctx):
+    graphs = [threshold_graph(seed) for seed in range(6)]
+    for g in graphs:
+        check(ctx, g)
+    r = ctx.count_batch(*bbc.concat_graphs(graphs))
+    for i, g in enumerate(graphs):
+        assert r.result(i) == expect(g), (i, g.name)
+
+
 def test_error_paths(ctx):
     g = gen.uniform_graph(seed=3, n_u=100, n_v=80, n_edges=2000)
     bad = g.ev.copy()
