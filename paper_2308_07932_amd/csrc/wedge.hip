@@ -177,6 +177,7 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
     __shared__ uint32_t s_qn, s_qtake, s_swtake;
     __shared__ bool s_multi;
     __shared__ uint32_t s_next, s_nextok, s_done;
+    __shared__ bool s_more;
     __shared__ u64 s_red[2][kWaves];
     __shared__ u64 s_pb[kMaxItemPieces], s_pu[kMaxItemPieces];  // per-piece totals (batches)
     uint32_t* keys = (uint32_t*)s_tab;
@@ -530,7 +531,8 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
             }
             __syncthreads();
             // -- queued chunks of long sub-intervals: one wave per chunk, coalesced
-            if (!PV && np == 1) {
+            // (s_qn is final after the barrier above, so the branch is uniform)
+            if (!PV && np == 1 && s_qn > 0) {
                 bool ok = true;
                 for (;;) {
                     uint32_t c = 0;
@@ -565,8 +567,8 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
                     }
                 }
                 if (!ok) s_abort = 1;
+                __syncthreads();
             }
-            __syncthreads();
 
             if (s_abort) {
                 // Abandon this piece's counts; redo it as two halves of its tile
@@ -726,7 +728,12 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
                     s_red[1][wave] = unb;
                 }
             }
+            // whether re-split halves remain, decided before the barrier; thread 0
+            // pops the next half after it, and the barrier at the top of the piece
+            // loop (or of the item loop) orders that pop before any use
+            if (tid == 0) s_more = s_sp > 0 && s_sp <= kStack;
             __syncthreads();
+            const bool more = s_more;
             if (tid == 0) {
                 if (per_piece) {
                     for (uint32_t p = 0; p < np; ++p) {
@@ -742,11 +749,9 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
                     s_acc.add(a, s_pc[0].graph, sb, su);
                     if (PV && sb) atomicAdd(&a.pv[s_pc[0].start_row], sb);
                 }
-                if (s_sp > 0) s_pc[0] = s_stack[--s_sp];
-                else s_sp = kStack + 2;  // done with this item
+                if (more) s_pc[0] = s_stack[--s_sp];
             }
-            __syncthreads();
-            if (s_sp > kStack) break;
+            if (!more) break;
         }
         if (tid == 0) s_item = s_nextok ? s_next : atomicAdd(&a.ctl->queue, 1u);
     }
