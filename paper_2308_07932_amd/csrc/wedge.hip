@@ -271,8 +271,14 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
             }
             __syncthreads();
             const uint32_t total = s_pre[np];
-            // records per grab: small items are shared by all waves, large ones in 64s
-            const uint32_t bsz = min(32u, max(8u, (total + 63) / 64));
+            // records per grab.  Each grab is one chain of dependent loads (records,
+            // tile offsets, entries), so fewer, larger grabs per wave are faster,
+            // unless the sub-intervals vary widely: split starts and hashed whole
+            // starts take up to 32 in grabs of total/32 (at least 4); dense whole
+            // starts and light items up to 64 in grabs of total/16 (at least 8).
+            const bool varied = (s_pc[0].flags & kPiecePartial) || (heavy && !dense);
+            const uint32_t bsz = varied ? min(32u, max(4u, (total + 31) / 32))
+                                        : min(64u, max(8u, (total + 15) / 16));
 
             // pass over the piece's records: count (readback = false) or, in
             // per-vertex mode, read the complete buckets back (readback = true)
