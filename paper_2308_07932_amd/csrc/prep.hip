@@ -112,19 +112,28 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_hist(const uint32_t* __restri
     hist[(uint64_t)threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
 }
 
-// vals == nullptr means value = element index
+// vals == nullptr means value = element index.  The tile is ranked by digit
+// (stable: by round, wave and lane, i.e. by index), placed in digit order in
+// LDS, and then written out so that consecutive threads write consecutive
+// elements of one digit's run (coalesced).
 __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(
     const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals, uint32_t n,
     uint32_t shift, const uint32_t* __restrict__ offs, uint32_t* __restrict__ keys_out,
     uint32_t* __restrict__ vals_out) {
-    __shared__ uint32_t cnt[256];
+    __shared__ uint32_t sk[kRsTile], sv[kRsTile];
+    __shared__ uint32_t gofs[256];  // where this tile's run of each digit starts in the output
+    __shared__ uint32_t tofs[256];  // where it starts in the tile
+    __shared__ uint32_t loc[256];   // elements of each digit ranked so far
     __shared__ uint32_t wh[kRsThreads / 64][256];
+    __shared__ uint32_t wsum[kRsThreads / 64];
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
-    cnt[tid] = offs[(uint64_t)tid * gridDim.x + blockIdx.x];
+    gofs[tid] = offs[(uint64_t)tid * gridDim.x + blockIdx.x];
+    loc[tid] = 0;
     for (int w = 0; w < kRsThreads / 64; ++w) wh[w][tid] = 0;
     __syncthreads();
     const uint64_t base = (uint64_t)blockIdx.x * kRsTile;
     const u64 lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    uint32_t kk[kRsItems], vv[kRsItems], dd[kRsItems], rk[kRsItems];
     for (int r = 0; r < kRsItems; ++r) {
         uint64_t idx = base + (uint64_t)r * kRsThreads + tid;
         bool valid = idx < n;
@@ -140,23 +149,48 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(
         if (valid && lrank == 0) wh[wave][d] = (uint32_t)__popcll(peers);
         __syncthreads();
         {
-            uint32_t run = cnt[tid];
+            uint32_t run = loc[tid];
             for (int w = 0; w < kRsThreads / 64; ++w) {
                 uint32_t c = wh[w][tid];
                 wh[w][tid] = run;
                 run += c;
             }
-            cnt[tid] = run;
+            loc[tid] = run;
         }
         __syncthreads();
-        if (valid) {
-            uint32_t dst = wh[wave][d] + lrank;
-            keys_out[dst] = key;
-            vals_out[dst] = val;
-        }
+        kk[r] = key;
+        vv[r] = val;
+        dd[r] = valid ? d : 256u;
+        rk[r] = valid ? wh[wave][d] + lrank : 0u;
         __syncthreads();
         for (int w = 0; w < kRsThreads / 64; ++w) wh[w][tid] = 0;
         __syncthreads();
+    }
+    // tile-local start of each digit: exclusive scan of the counts
+    {
+        const uint32_t c = loc[tid];
+        const uint32_t inc = wave_incl_scan(c);
+        if (lane == 63) wsum[wave] = inc;
+        __syncthreads();
+        uint32_t add = 0;
+        for (uint32_t w = 0; w < wave; ++w) add += wsum[w];
+        tofs[tid] = add + inc - c;
+    }
+    __syncthreads();
+    for (int r = 0; r < kRsItems; ++r)
+        if (dd[r] < 256u) {
+            const uint32_t pos = tofs[dd[r]] + rk[r];
+            sk[pos] = kk[r];
+            sv[pos] = vv[r];
+        }
+    __syncthreads();
+    const uint32_t in_tile = (uint32_t)min<uint64_t>(kRsTile, n > base ? n - base : 0);
+    for (uint32_t i = tid; i < in_tile; i += kRsThreads) {
+        const uint32_t key = sk[i];
+        const uint32_t d = (key >> shift) & 255u;
+        const uint32_t dst = gofs[d] + (i - tofs[d]);
+        keys_out[dst] = key;
+        vals_out[dst] = sv[i];
     }
 }
 
