@@ -517,6 +517,7 @@ static bbc_status run_pipeline(bbc_context* c, const RunIn& in, RunOut& ro) {
     d.gerr = bt ? bt->gerr : nullptr;
     d.rlist = nullptr;
     d.per_vertex = in.per_vertex ? 1u : 0u;
+    d.light_window = in.per_vertex ? kLightWindow : kLightWindow16;
     // rows of side Y with more than kLongDeg entries: at most m / (kLongDeg + 1) per side
     uint64_t maxlong0 = std::min<uint64_t>(nu, m / (kLongDeg + 1));
     uint64_t maxlong1 = std::min<uint64_t>(nv, m / (kLongDeg + 1));
@@ -681,7 +682,7 @@ static bbc_status run_pipeline(bbc_context* c, const RunIn& in, RunOut& ro) {
                     (unsigned long long)h.tot_sw, (unsigned long long)h.tot_tiles,
                     (unsigned long long)h.tot_g);
     const uint32_t n_heavy = (uint32_t)h.tot_heavy, n_light = (uint32_t)h.tot_light;
-    const uint64_t n_light_items64 = (h.tot_light_region + kLightWindow - 1) / kLightWindow;
+    const uint64_t n_light_items64 = (h.tot_light_region + d.light_window - 1) / d.light_window;
     const uint32_t n_light_items = (uint32_t)n_light_items64;
     const uint32_t n_items = n_heavy + n_light_items;
     uint32_t first_long[2] = {h.cls[0][4] - d.base[0], h.cls[1][4] - d.base[1]};

@@ -50,10 +50,18 @@ constexpr uint32_t kBitmapChunk = 1u << 18;  // sidx span handled per block by t
 constexpr int kWedgeThreads = 1024;
 constexpr uint32_t kDenseW = 16384;           // dense counters per item (u64 each, 128 KiB)
 constexpr uint32_t kHashSlots = 8192;         // hash slots (u32 key + u64 counters)
-constexpr uint32_t kLightWindow = kHashSlots / 2;  // H: light regions start inside [iH, iH+H)
 constexpr uint32_t kLightMax = kHashSlots / 4;     // max wedges of a batched (light) start
 constexpr uint32_t kMinRegion = 64;
-constexpr uint32_t kMaxItemPieces = (2 * kLightWindow) / kMinRegion + 1;
+// Light item i holds the light starts whose region offset lies in [iH, iH+H);
+// a region is at most 2 * kLightMax slots, so the item's regions end below
+// H + 2 * kLightMax: H = kLightWindow for the table of u32 keys and u64
+// counters (per-vertex mode), kLightWindow16 for the table of 2 * kHashSlots
+// u32 keys and u32 counters (l | m << 16; a light start has at most
+// kLightMax < 2^16 wedges, so no count can reach 2^16).
+constexpr uint32_t kLightWindow = kHashSlots - 2 * kLightMax;
+constexpr uint32_t kLightWindow16 = 2 * kHashSlots - 2 * kLightMax;
+// offsets of one window lie at least kMinRegion apart
+constexpr uint32_t kMaxItemPieces = kLightWindow16 / kMinRegion + 1;
 constexpr uint32_t kTile = 16384;             // end-vertex tile width (sidx units)
 constexpr u64 kRecordChunkWedges = 65536;     // min wedges per record chunk of a small-side start
 constexpr uint32_t kChunkDiv = 2048;          // ... and at least W_total / kChunkDiv
@@ -129,6 +137,7 @@ struct Dims {
     // per-vertex mode: starts are not split by record chunks and split starts
     // keep all their records (no bucketed short-middle wedges)
     uint32_t per_vertex;
+    uint32_t light_window;  // H of the light items: kLightWindow or kLightWindow16
     // rows in ascending (side, length) order, or NULL when the row index order
     // already is (one graph: rows are sorted by degree within each side)
     const uint32_t* rlist;

@@ -222,7 +222,7 @@ __global__ void k_plan_write(const u64* __restrict__ wu, const uint32_t* __restr
         if (sp.cls == kClassLight) {
             const uint32_t idx = lf_off[r];
             const u64 off = lr_off[r];
-            const u64 item = off / kLightWindow;
+            const u64 item = off / d.light_window;
             Piece p;
             p.rec0 = m0;
             p.nrec = k;
@@ -230,8 +230,9 @@ __global__ void k_plan_write(const u64* __restrict__ wu, const uint32_t* __restr
             p.hi = S;
             p.t0 = kNoTile;
             p.t1 = kNoTile;
-            p.region = (uint32_t)(off - item * kLightWindow) | (log2_pow2(sp.region) << 16);
-            p.flags = sideflag;
+            p.region = (uint32_t)(off - item * d.light_window) | (log2_pow2(sp.region) << 16);
+            // the 16-bit-half table unless every wedge must keep its middle
+            p.flags = sideflag | (d.per_vertex ? 0u : kPieceHash16);
             p.gbase = kEmpty;
             p.start_row = r;
             p.list = kEmpty;
@@ -465,10 +466,10 @@ __global__ void k_gather_totals(const uint32_t* __restrict__ hp_off, const u64* 
 // first light piece of each light item: item i holds the pieces whose region
 // offset lies in [i H, (i+1) H)
 __global__ void k_items_first(const u64* __restrict__ light_off, uint32_t n_light,
-                              uint32_t n_items, uint32_t* __restrict__ first) {
+                              uint32_t n_items, u64 H, uint32_t* __restrict__ first) {
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i <= n_items;
          i += gridDim.x * blockDim.x) {
-        u64 key = (u64)i * kLightWindow;
+        u64 key = (u64)i * H;
         uint32_t lo = 0, hi = n_light;
         while (lo < hi) {
             uint32_t mid = (lo + hi) >> 1;
@@ -518,7 +519,8 @@ hipError_t launch_plan_write(const u64* wu, const uint32_t* lowcnt, const uint32
                        front, hp_off, lr_off, lf_off, gs_off, tc_off, d, n_heavy, pieces, light_off,
                        hkey, tile_piece, ctl);
     hipLaunchKernelGGL(k_items_first, grid_n((uint64_t)n_light_items + 1, 256), dim3(256), 0, st,
-                       (const u64*)light_off, n_light, n_light_items, items_first);
+                       (const u64*)light_off, n_light, n_light_items, (u64)d.light_window,
+                       items_first);
     return hipGetLastError();
 }
 

@@ -82,11 +82,36 @@ __device__ inline uint32_t hash32(uint32_t w) { return w * 0x9E3779B1u; }
 // The 16-bit-half hash table: 2 x kHashSlots keys, then as many u32 counters
 // (l | m << 16).  Returns false if w finds no slot within `lim` probes.
 constexpr uint32_t kHash16Slots = 2 * kHashSlots;
+static_assert(kLightWindow + 2 * kLightMax <= kHashSlots &&
+                  kLightWindow16 + 2 * kLightMax <= kHash16Slots,
+              "a light item's regions fit its table");
 __device__ inline bool bucket_add16(uint32_t* s32, uint32_t lim, uint32_t w, uint32_t inc) {
     constexpr uint32_t lg = 31u - __builtin_clz(kHash16Slots);
     const uint32_t h = hash32(w) >> (32 - lg);
     for (uint32_t i = 0; i < lim; ++i) {
         const uint32_t s = (h + i) & (kHash16Slots - 1u);
+        uint32_t k = s32[s];
+        if (k == kEmpty) {
+            k = atomicCAS(&s32[s], kEmpty, w);
+            if (k == kEmpty) k = w;
+        }
+        if (k == w) {
+            atomicAdd(&s32[kHash16Slots + s], inc);
+            return true;
+        }
+    }
+    return false;
+}
+
+// The same table for the light starts of an item: w is hashed into its
+// start's region, probed whole (a region holds more slots than the start has
+// distinct ends, so it never fills).
+__device__ inline bool bucket_add16r(uint32_t* s32, uint32_t region, uint32_t w, uint32_t inc) {
+    const uint32_t rb = region & 0xFFFFu, lg = (region >> 16) & 31u;
+    const uint32_t msk = (1u << lg) - 1u;
+    const uint32_t h = hash32(w) >> (32 - lg);
+    for (uint32_t i = 0; i <= msk; ++i) {
+        const uint32_t s = rb + ((h + i) & msk);
         uint32_t k = s32[s];
         if (k == kEmpty) {
             k = atomicCAS(&s32[s], kEmpty, w);
@@ -467,6 +492,15 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
                                              ((x[u] ^ aux[u]) & 1u) ? (1ull << 32) : 1ull);
                         }
                         ok = __ballot(!lok) == 0;  // the whole wave leaves together
+                    } else if (h16) {  // light starts, 16-bit halves
+                        bool lok = true;
+#pragma unroll 1
+                        for (uint32_t u = 0; u < kUnroll; ++u) {
+                            if (aux[u] == kEmpty || !lok) continue;
+                            lok = bucket_add16r(s32, s_pc[aux[u] >> 2].region, x[u] >> 1,
+                                                ((x[u] ^ aux[u]) & 1u) ? 0x10000u : 1u);
+                        }
+                        ok = __ballot(!lok) == 0;
                     } else {
                         bool lok = true;
 #pragma unroll 1
@@ -624,7 +658,15 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
                     const uint32_t rb = region & 0xFFFFu, sz = 1u << ((region >> 16) & 31u);
                     const u64 ubase = a.d.base[(s_pc[p].flags & kPieceSideV) ? 1u : 0u];
                     u64 pb = 0, pu = 0;
-                    for (uint32_t i = lane; i < sz; i += 64) {
+                    if (h16) {  // light starts with 16-bit halves (not in per-vertex mode)
+                        for (uint32_t i = lane; i < sz; i += 64) {
+                            const uint32_t c = s32[kHash16Slots + rb + i];
+                            const uint32_t l = c & 0xFFFFu, mm = c >> 16;
+                            pb += ((l * (l - 1u)) >> 1) + ((mm * (mm - 1u)) >> 1);
+                            pu += l * mm;
+                        }
+                    }
+                    for (uint32_t i = lane; i < sz && !h16; i += 64) {
                         if (keys[rb + i] == kEmpty) continue;
                         const u64 v = hvals[rb + i];
                         const u64 l = v & 0xFFFFFFFFull, m = v >> 32;
