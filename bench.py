@@ -96,6 +96,31 @@ def cpu_baseline(g, W: int, budget_s: float):
     }
 
 
+def bench_per_vertex(ctx, g, eu, ev, sg, r, steps: int):
+    """Per-vertex balanced counts (BBC_PER_VERTEX) of the same device-resident
+    graph: whole calls, whose per-vertex array is returned to the host.  The
+    output is checked by what holds at any size: each balanced butterfly has
+    four vertices, so the counts sum to 4 x the balanced total, and the totals
+    equal those of the plain count."""
+    rr, pv = ctx.count(eu, ev, sg, g.n_u, g.n_v, per_vertex=True)  # warm-up
+    torch.cuda.synchronize()
+    dev_ms = wedge_ms = 0.0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        rr, pv = ctx.count(eu, ev, sg, g.n_u, g.n_v, per_vertex=True)
+        dev_ms += ctx.phase_ms(0)
+        wedge_ms += ctx.phase_ms(2)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    ok_sum = int(pv.sum()) == 4 * r.balanced
+    log(f"per-vertex: {ms:.3f} ms per call (device {dev_ms / steps:.3f} ms, wedge kernel "
+        f"{wedge_ms / steps:.3f} ms); sum = 4 x balanced: {ok_sum}; totals equal: {rr == r}")
+    return {"ms_per_call": ms, "device_ms": dev_ms / steps, "wedge_kernel_ms": wedge_ms / steps,
+            "wedges_per_s": r.wedges / (ms * 1e-3), "steps": steps,
+            "output": f"{g.n_u + g.n_v} int64 counts copied to host memory inside each call",
+            "sum_is_4x_balanced": ok_sum, "totals_equal_plain_count": rr == r}
+
+
 def bench_batched(ctx, steps: int, warmup: int, oracle_sample: int, plain_loop: bool = True):
     """The batched workload: 20,000 graphs (sides log-uniform in [16, 4096],
     density log-uniform in [1e-3, 0.2], P(-1)=0.3) counted by one
@@ -315,6 +340,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-per-vertex", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=3)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--only-batched", action="store_true",
@@ -409,6 +435,8 @@ def main():
                      "traffic": traffic, "kernel": "bbc::k_wedge",
                      "algorithmic_bytes_per_launch": alg_bytes},
     }
+    if not args.no_per_vertex:
+        out["per_vertex"] = bench_per_vertex(ctx, g, eu, ev, sg, r, 5)
     if not args.no_batched:
         out["batched"] = bench_batched(ctx, args.batched_steps, 1, 24)
         if not args.no_serving:
