@@ -102,6 +102,7 @@ def bench_per_vertex(ctx, g, eu, ev, sg, r, steps: int):
     output is checked by what holds at any size: each balanced butterfly has
     four vertices, so the counts sum to 4 x the balanced total, and the totals
     equal those of the plain count."""
+    import torch
     rr, pv = ctx.count(eu, ev, sg, g.n_u, g.n_v, per_vertex=True)  # warm-up
     torch.cuda.synchronize()
     dev_ms = wedge_ms = 0.0
