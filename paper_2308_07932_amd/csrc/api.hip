@@ -48,11 +48,12 @@ hipError_t launch_plan_write(const u64*, const uint32_t*, const uint32_t*, const
                              hipStream_t);
 hipError_t launch_short_wedges(const uint4*, uint32_t, const uint32_t*, const uint32_t*,
                                const uint32_t*, const uint32_t*, const uint32_t*, const uint32_t*,
-                               uint32_t*, uint32_t*, uint32_t*, bool, hipStream_t);
+                               uint32_t, uint32_t*, uint32_t*, uint32_t*, uint32_t*, bool,
+                               hipStream_t);
 hipError_t launch_wedge(const Piece*, const uint32_t*, const uint32_t*, uint32_t, uint32_t,
                         const uint4*, const uint32_t*, const uint32_t*, Dims, const uint32_t[2], u64*,
-                        const uint32_t*, const uint32_t*, Control*, u64*, u64*, uint32_t,
-                        hipStream_t);
+                        const uint32_t*, const uint32_t*, const uint32_t*, Control*, u64*, u64*,
+                        uint32_t, hipStream_t);
 hipError_t launch_pv_out(const u64*, const uint32_t*, Dims, u64*, hipStream_t);
 hipError_t launch_ingest(const IngestArgs&, hipStream_t);
 hipError_t launch_batch_keys(const uint32_t*, Dims, uint32_t, uint32_t*, hipStream_t);
@@ -691,6 +692,7 @@ static bbc_status run_pipeline(bbc_context* c, const RunIn& in, RunOut& ro) {
     uint32_t* items_first;
     u64* G;
     uint32_t *hkey, *ok0, *ov0, *ok1, *ov1, *tile_piece, *sw_cnt, *sw_off, *sw_cur, *sw_list;
+    uint32_t* sw_mid = nullptr;  // per-vertex mode: the middle row of each listed wedge
     u64 *pv = nullptr, *pv_out = nullptr;
     void* ortmp;
     const size_t ortmp_bytes = radix_tmp_bytes(n_heavy + 1);
@@ -714,6 +716,7 @@ static bbc_status run_pipeline(bbc_context* c, const RunIn& in, RunOut& ro) {
             if (in.per_vertex) {
                 pv = cv.take<u64>(n);
                 pv_out = cv.take<u64>(n);
+                sw_mid = cv.take<uint32_t>((size_t)h.tot_sw + 1);
             }
             return cv.off;
         };
@@ -740,13 +743,15 @@ static bbc_status run_pipeline(bbc_context* c, const RunIn& in, RunOut& ro) {
     HIPCHECK(c, fill_u32(sw_cnt, 0, (size_t)n_heavy + 1, st));
     if (h.tot_sw > 0) {
         HIPCHECK(c, launch_short_wedges(b.recs, (uint32_t)m, b.col, b.cursor, b.tc, b.tc_off,
-                                        b.hp_off, tile_piece, sw_cnt, sw_cur, sw_list, false, st));
+                                        b.hp_off, tile_piece, nu, sw_cnt, sw_cur, sw_list, sw_mid,
+                                        false, st));
     }
     HIPCHECK(c, scan_excl_u32(sw_cnt, sw_off, n_heavy, ortmp, ortmp_bytes, st));
     if (h.tot_sw > 0) {
         HIPCHECK(c, copy_u32(sw_off, sw_cur, n_heavy, st));
         HIPCHECK(c, launch_short_wedges(b.recs, (uint32_t)m, b.col, b.cursor, b.tc, b.tc_off,
-                                        b.hp_off, tile_piece, sw_cnt, sw_cur, sw_list, true, st));
+                                        b.hp_off, tile_piece, nu, sw_cnt, sw_cur, sw_list, sw_mid,
+                                        true, st));
     }
     uint32_t* order = nullptr;
     if (n_heavy > 0)  // heavy pieces, most expensive first
@@ -757,7 +762,8 @@ static bbc_status run_pipeline(bbc_context* c, const RunIn& in, RunOut& ro) {
     // ---- wedge enumeration and bucket counting
     if (tm) HIPCHECK(c, hipEventRecord(c->ev[kEvWedgeA], st));
     HIPCHECK(c, launch_wedge(pieces, order, items_first, n_heavy, n_items, b.recs, b.col, b.tb, d,
-                             first_long, G, sw_off, sw_list, b.ctl, bt ? bt->gres : nullptr, pv,
+                             first_long, G, sw_off, sw_list, sw_mid, b.ctl,
+                             bt ? bt->gres : nullptr, pv,
                              c->num_cus, st));
     if (tm) HIPCHECK(c, hipEventRecord(c->ev[kEvWedgeB], st));
     if (pv) {

@@ -196,7 +196,7 @@ __global__ void k_plan_count(const u64* __restrict__ wu, const u64* __restrict__
         lf[r] = sp.cls == kClassLight ? 1u : 0u;
         gs[r] = (sp.cls == kClassSmallSide && sp.pieces > 1) ? r - d.base[side] - sp.lo : 0u;
         tc[r] = sp.tiles;
-        swc[r] = (sp.tiles && !d.per_vertex) ? wsu[r] : 0ull;
+        swc[r] = sp.tiles ? wsu[r] : 0ull;
     }
 }
 
@@ -265,10 +265,11 @@ __global__ void k_plan_write(const u64* __restrict__ wu, const uint32_t* __restr
             continue;
         }
         // tile runs; a split start keeps only its long-middle records, the
-        // short-middle wedges come from the bucketed list of each piece
+        // short-middle wedges come from the bucketed list of each piece (with
+        // their middles in per-vertex mode)
         const uint32_t T = (S + kTile - 1) / kTile;
         const bool split = sp.tiles > 0;
-        const bool bucketed = split && !d.per_vertex;  // short-middle wedges come from a list
+        const bool bucketed = split;
         const uint32_t nlong = front[r] - m0;
         uint32_t i = 0;
         plan_runs(row_ptr, d.base[side], S, W, d.hash_target, !d.per_vertex && k < (1u << 16),
@@ -309,7 +310,8 @@ __global__ void k_plan_write(const u64* __restrict__ wu, const uint32_t* __restr
 // table keyed by piece and reach global memory once per (workgroup, piece).
 // The fill pass reserves each piece's slots then and walks the prefixes again,
 // each run taking consecutive slots.  A piece that finds no table slot goes to
-// global memory directly, run by run.
+// global memory directly, run by run.  In per-vertex mode `mids` receives, for
+// every list entry, the row of the wedge's middle vertex.
 constexpr int kSwThreads = 256;
 constexpr uint32_t kSwWaves = kSwThreads / 64;
 constexpr uint32_t kSwLog2 = 11;
@@ -320,8 +322,8 @@ __global__ __launch_bounds__(kSwThreads) void k_short_wedges(
     const uint4* __restrict__ recs, uint32_t m, const uint32_t* __restrict__ col,
     const uint32_t* __restrict__ front, const uint32_t* __restrict__ tc,
     const uint32_t* __restrict__ tc_off, const uint32_t* __restrict__ hp_off,
-    const uint32_t* __restrict__ tile_piece, uint32_t* __restrict__ counts,
-    uint32_t* __restrict__ cursor, uint32_t* __restrict__ list) {
+    const uint32_t* __restrict__ tile_piece, uint32_t n_u, uint32_t* __restrict__ counts,
+    uint32_t* __restrict__ cursor, uint32_t* __restrict__ list, uint32_t* __restrict__ mids) {
     __shared__ uint32_t keys[kSwSlots];
     __shared__ uint32_t cnt[kSwSlots];
     __shared__ uint32_t base[kSwSlots];
@@ -329,6 +331,7 @@ __global__ __launch_bounds__(kSwThreads) void k_short_wedges(
     __shared__ uint32_t s_tb[kSwWaves][64];   // its start's tile-to-piece table
     __shared__ uint32_t s_pb[kSwWaves][64];   // its start's first heavy piece
     __shared__ uint32_t s_s1[kSwWaves][64];   // sign(u, v) of its record
+    __shared__ uint32_t s_mid[kSwWaves][64];  // the row of its middle v (per-vertex mode)
     __shared__ uint8_t s_head[kSwWaves][64];
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
     const u64 le_mask = ~0ull >> (63 - lane);  // lanes 0..lane
@@ -356,6 +359,7 @@ __global__ __launch_bounds__(kSwThreads) void k_short_wedges(
             s_tb[wave][ci] = tc_off[rc.w];
             s_pb[wave][ci] = hp_off[rc.w];
             s_s1[wave][ci] = rc.y & 1u;
+            s_mid[wave][ci] = (rc.w < n_u ? n_u : 0u) + rc.z;  // v lies on the other side
         }
         __syncthreads();
         // place = false: count runs per piece; place = true (fill pass): each
@@ -370,11 +374,12 @@ __global__ __launch_bounds__(kSwThreads) void k_short_wedges(
                 before += (uint32_t)__popcll(M);
                 const uint32_t q = w0 + lane;
                 const bool valid = q < T;
-                uint32_t gp = kEmpty, val = 0;
+                uint32_t gp = kEmpty, val = 0, mid = 0;
                 if (valid) {
                     const uint32_t x = col[s_adj[wave][idx] + q];
                     gp = s_pb[wave][idx] + tile_piece[s_tb[wave][idx] + (x >> 1) / kTile];
                     val = (x & ~1u) | ((x ^ s_s1[wave][idx]) & 1u);
+                    mid = s_mid[wave][idx];
                 }
                 s_head[wave][lane] = 0;
                 // runs of equal piece among the valid lanes (a prefix of the window)
@@ -403,7 +408,10 @@ __global__ __launch_bounds__(kSwThreads) void k_short_wedges(
                 }
                 if (kFill) {
                     at = __shfl(at, (int)head, 64);
-                    if (valid && at != kEmpty) list[at + (lane - head)] = val;
+                    if (valid && at != kEmpty) {
+                        list[at + (lane - head)] = val;
+                        if (mids) mids[at + (lane - head)] = mid;
+                    }
                 }
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             }
@@ -526,16 +534,17 @@ hipError_t launch_plan_write(const u64* wu, const uint32_t* lowcnt, const uint32
 
 hipError_t launch_short_wedges(const uint4* recs, uint32_t m, const uint32_t* col,
                                const uint32_t* front, const uint32_t* tc, const uint32_t* tc_off,
-                               const uint32_t* hp_off, const uint32_t* tile_piece,
-                               uint32_t* counts, uint32_t* cursor, uint32_t* list, bool fill,
-                               hipStream_t st) {
+                               const uint32_t* hp_off, const uint32_t* tile_piece, uint32_t n_u,
+                               uint32_t* counts, uint32_t* cursor, uint32_t* list, uint32_t* mids,
+                               bool fill, hipStream_t st) {
     if (fill)
         hipLaunchKernelGGL(k_short_wedges<true>, grid_n(m, kSwThreads, 8192), dim3(kSwThreads), 0, st,
-                           recs, m, col, front, tc, tc_off, hp_off, tile_piece, counts, cursor, list);
+                           recs, m, col, front, tc, tc_off, hp_off, tile_piece, n_u, counts, cursor,
+                           list, mids);
     else
         hipLaunchKernelGGL(k_short_wedges<false>, grid_n(m, kSwThreads, 8192), dim3(kSwThreads), 0,
-                           st, recs, m, col, front, tc, tc_off, hp_off, tile_piece, counts, cursor,
-                           list);
+                           st, recs, m, col, front, tc, tc_off, hp_off, tile_piece, n_u, counts,
+                           cursor, list, mids);
     return hipGetLastError();
 }
 

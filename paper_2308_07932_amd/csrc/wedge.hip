@@ -39,6 +39,7 @@ struct WedgeArgs {
     u64* G;
     const uint32_t* sw_off;   // short-middle wedge list of heavy piece p: [sw_off[p], sw_off[p+1])
     const uint32_t* sw_list;  // packed w << 1 | asymmetric
+    const uint32_t* sw_mid;   // per-vertex mode: the row of each listed wedge's middle
     Control* ctl;
     u64* gres;  // batches: per graph {balanced, unbalanced, wedges, -}; else NULL (totals in ctl)
     u64* pv;    // per-vertex mode: balanced butterflies per row (n entries, zeroed)
@@ -521,7 +522,7 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
             records_pass(false);
             // -- the bucketed wedges through short middle rows (split starts) fill
             // the tail of the record sweep: waves take 64 * kUnroll at a time
-            if (!PV && heavy && (s_pc[0].flags & kPiecePartial) && s_pc[0].list != kEmpty) {
+            if (heavy && (s_pc[0].flags & kPiecePartial) && s_pc[0].list != kEmpty) {
                 const uint32_t b0 = a.sw_off[s_pc[0].list];
                 const uint32_t n_sw = a.sw_off[s_pc[0].list + 1] - b0;
                 bool ok = true;
@@ -639,9 +640,49 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
             }
 
             if (PV) {  // second pass: the middles' shares from the complete buckets
-                if (tid == 0) s_batch = 0;
+                if (tid == 0) {
+                    s_batch = 0;
+                    s_swtake = 0;
+                }
                 __syncthreads();
                 records_pass(true);
+                // the listed short-middle wedges: each share goes to the wedge's
+                // middle, summed over runs of one middle (consecutive lanes)
+                if (heavy && (s_pc[0].flags & kPiecePartial) && s_pc[0].list != kEmpty) {
+                    const uint32_t b0 = a.sw_off[s_pc[0].list];
+                    const uint32_t n_sw = a.sw_off[s_pc[0].list + 1] - b0;
+                    const u64 le = ~0ull >> (63 - lane);
+                    for (;;) {
+                        uint32_t c = 0;
+                        if (lane == 0) c = atomicAdd(&s_swtake, 64u);
+                        c = __shfl(c, 0, 64);
+                        if (c >= n_sw) break;
+                        const uint32_t q = c + lane;
+                        uint32_t x = kEmpty, mid = kEmpty;
+                        if (q < n_sw) {
+                            x = a.sw_list[b0 + q];
+                            mid = a.sw_mid[b0 + q];
+                        }
+                        u64 val = 0;
+                        if (x != kEmpty) {
+                            const uint32_t w = x >> 1;
+                            if (w >= plo0 && w < phi0) {
+                                const u64 bv = dense ? s_tab[w - dlo] : bucket_get(keys, hvals, region0, w);
+                                val = middle_share(bv, x & 1u);
+                            }
+                        }
+                        const u64 heads = __ballot(lane == 0 || __shfl_up(mid, 1, 64) != mid);
+                        const uint32_t seg = (uint32_t)__popcll(heads & le);
+                        for (uint32_t off = 1; off < 64; off <<= 1) {
+                            const u64 o = __shfl_up(val, off, 64);
+                            const uint32_t os = __shfl_up(seg, off, 64);
+                            if (lane >= off && os == seg) val += o;
+                        }
+                        const uint32_t ns = __shfl_down(seg, 1, 64);
+                        if ((lane == 63 || ns != seg) && mid != kEmpty && val != 0)
+                            atomicAdd(&a.pv[mid], val);
+                    }
+                }
                 __syncthreads();
             }
 
@@ -825,7 +866,8 @@ hipError_t launch_wedge(const Piece* pieces, const uint32_t* order, const uint32
                         uint32_t n_heavy,
                         uint32_t n_items, const uint4* recs, const uint32_t* col, const uint32_t* tb,
                         Dims d, const uint32_t first_long[2], u64* G, const uint32_t* sw_off,
-                        const uint32_t* sw_list, Control* ctl, u64* gres, u64* pv,
+                        const uint32_t* sw_list, const uint32_t* sw_mid, Control* ctl, u64* gres,
+                        u64* pv,
                         uint32_t num_cus, hipStream_t st) {
     WedgeArgs a;
     a.pieces = pieces;
@@ -842,6 +884,7 @@ hipError_t launch_wedge(const Piece* pieces, const uint32_t* order, const uint32
     a.G = G;
     a.sw_off = sw_off;
     a.sw_list = sw_list;
+    a.sw_mid = sw_mid;
     a.ctl = ctl;
     a.gres = gres;
     a.pv = pv;
