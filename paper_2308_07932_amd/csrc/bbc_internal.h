@@ -134,8 +134,8 @@ struct Dims {
     uint32_t n_graphs;
     const uint32_t* blk[2];
     u64* gerr;
-    // per-vertex mode: starts are not split by record chunks and split starts
-    // keep all their records (no bucketed short-middle wedges)
+    // per-vertex mode: starts are not split by record chunks, the listed
+    // short-middle wedges carry their middles, light items keep 64-bit counters
     uint32_t per_vertex;
     uint32_t light_window;  // H of the light items: kLightWindow or kLightWindow16
     // rows in ascending (side, length) order, or NULL when the row index order

@@ -155,7 +155,7 @@ __device__ inline StartPlan plan_start(const uint32_t* __restrict__ row_ptr, con
     bool whole = false;
     sp.cls = kClassTiles;
     sp.pieces = plan_runs(row_ptr, d.base[side], S, W, d.hash_target,
-                          !d.per_vertex && k < (1u << 16), [&](uint32_t t0, uint32_t t1, bool dense, double) {
+                          k < (1u << 16), [&](uint32_t t0, uint32_t t1, bool dense, double) {
                               whole = whole || (t0 == 0 && t1 == T && !dense);
                           });
     // One hashed run over everything is left unsplit only when its W wedges
@@ -181,7 +181,7 @@ __global__ void k_plan_count(const u64* __restrict__ wu, const u64* __restrict__
         if (sp.cls == kClassTiles) {  // tile pieces by kind (statistics)
             u64 nd = 0, nd16 = 0, nh = 0;
             plan_runs(row_ptr, d.base[side], r - d.base[side], W, d.hash_target,
-                      !d.per_vertex && lowcnt[r] < (1u << 16),
+                      lowcnt[r] < (1u << 16),
                       [&](uint32_t t0, uint32_t t1, bool dense, double) {
                           if (!dense) ++nh;
                           else if (t1 - t0 == 2) ++nd16;
@@ -231,7 +231,8 @@ __global__ void k_plan_write(const u64* __restrict__ wu, const uint32_t* __restr
             p.t0 = kNoTile;
             p.t1 = kNoTile;
             p.region = (uint32_t)(off - item * d.light_window) | (log2_pow2(sp.region) << 16);
-            // the 16-bit-half table unless every wedge must keep its middle
+            // the 16-bit-half table, except in per-vertex mode, whose light items
+            // finalize and read back per start from the 64-bit layout
             p.flags = sideflag | (d.per_vertex ? 0u : kPieceHash16);
             p.gbase = kEmpty;
             p.start_row = r;
@@ -272,7 +273,7 @@ __global__ void k_plan_write(const u64* __restrict__ wu, const uint32_t* __restr
         const bool bucketed = split;
         const uint32_t nlong = front[r] - m0;
         uint32_t i = 0;
-        plan_runs(row_ptr, d.base[side], S, W, d.hash_target, !d.per_vertex && k < (1u << 16),
+        plan_runs(row_ptr, d.base[side], S, W, d.hash_target, k < (1u << 16),
                   [&](uint32_t t0, uint32_t t1, bool dense, double est) {
             if (i >= h) return;
             Piece p;
@@ -283,7 +284,7 @@ __global__ void k_plan_write(const u64* __restrict__ wu, const uint32_t* __restr
             p.t0 = t0;
             p.t1 = t1;
             p.region = log2_pow2(kHashSlots) << 16;
-            const bool pair = !d.per_vertex && k < (1u << 16);
+            const bool pair = k < (1u << 16);
             p.flags = (split ? kPiecePartial : 0u) | (dense ? kPieceDense : 0u) |
                       ((dense && t1 - t0 == 2) ? kPieceDense16 : 0u) |
                       ((!dense && split && pair) ? kPieceHash16 : 0u) | sideflag;

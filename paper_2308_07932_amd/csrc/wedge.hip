@@ -126,6 +126,22 @@ __device__ inline bool bucket_add16r(uint32_t* s32, uint32_t region, uint32_t w,
     return false;
 }
 
+// counters (l | m << 16) of w in the 16-bit-half table, present after the
+// counting pass, as a 64-bit bucket value (l + (m << 32))
+__device__ inline u64 bucket_get16(const uint32_t* s32, uint32_t w) {
+    constexpr uint32_t lg = 31u - __builtin_clz(kHash16Slots);
+    const uint32_t h = hash32(w) >> (32 - lg);
+    for (uint32_t i = 0; i < kHash16Slots; ++i) {
+        const uint32_t s = (h + i) & (kHash16Slots - 1u);
+        if (s32[s] == w) {
+            const uint32_t c = s32[kHash16Slots + s];
+            return (c & 0xFFFFu) | ((u64)(c >> 16) << 32);
+        }
+        if (s32[s] == kEmpty) break;
+    }
+    return 0;
+}
+
 // Add one wedge to the bucket of end vertex w.  Returns false if the hashed
 // region has no room for w within `lim` probes.
 __device__ inline bool bucket_add(u64* s_tab, uint32_t* keys, u64* hvals, bool dense,
@@ -179,9 +195,11 @@ __device__ inline u64 bucket_get(const uint32_t* keys, const u64* hvals, uint32_
 // over the same wedges reads back each wedge's bucket and adds its share to
 // the middle vertex; the finalize adds each bucket's C(l,2) + C(m,2) to the
 // end vertex and the piece's total to the start (Section 5.1, Algorithm 3,
-// with the end vertex distinct from the start).  Pieces are then never split
-// by record chunks, long sub-intervals are not queued and short middles are
-// visited through their records, so that every wedge keeps its middle.
+// with the end vertex distinct from the start).  Every wedge must keep its
+// middle: pieces are then never split by record chunks, long sub-intervals are
+// not queued, the listed short-middle wedges carry their middle's row, and
+// light items keep 64-bit counters (their per-start finalize and readback read
+// that layout).
 template <bool PV>
 __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
     // on-chip buckets: dense mode uses s_tab[0 .. kDenseW); hash mode uses
@@ -439,6 +457,8 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
                                     if (dense && d16) {
                                         const uint32_t c = s32[w - dlo];
                                         bv = (c & 0xFFFFu) | ((u64)(c >> 16) << 32);
+                                    } else if (h16) {
+                                        bv = bucket_get16(s32, w);
                                     } else {
                                         bv = dense ? s_tab[w - dlo]
                                                    : bucket_get(keys, hvals, P.region, w);
@@ -667,7 +687,15 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
                         if (x != kEmpty) {
                             const uint32_t w = x >> 1;
                             if (w >= plo0 && w < phi0) {
-                                const u64 bv = dense ? s_tab[w - dlo] : bucket_get(keys, hvals, region0, w);
+                                u64 bv;
+                                if (dense && d16) {
+                                    const uint32_t c = s32[w - dlo];
+                                    bv = (c & 0xFFFFu) | ((u64)(c >> 16) << 32);
+                                } else if (h16) {
+                                    bv = bucket_get16(s32, w);
+                                } else {
+                                    bv = dense ? s_tab[w - dlo] : bucket_get(keys, hvals, region0, w);
+                                }
                                 val = middle_share(bv, x & 1u);
                             }
                         }
@@ -772,6 +800,16 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
                         bal += ol * l + om * m;
                         unb += ol * m + om * l;
                     }
+                }
+            } else if (PV && h16) {  // end vertices get their buckets' counts
+                for (uint32_t i = tid; i < kHash16Slots; i += kWedgeThreads) {
+                    if (s32[i] == kEmpty) continue;
+                    const uint32_t c = s32[kHash16Slots + i];
+                    const uint32_t l = c & 0xFFFFu, mm = c >> 16;
+                    const u64 b = ((l * (l - 1u)) >> 1) + ((mm * (mm - 1u)) >> 1);
+                    bal += b;
+                    unb += l * mm;
+                    if (b) atomicAdd(&a.pv[ubase0 + s32[i]], b);
                 }
             } else if (h16) {
                 // counters of empty slots are zero
