@@ -97,28 +97,29 @@ def cpu_baseline(g, W: int, budget_s: float):
 
 
 def bench_per_vertex(ctx, g, eu, ev, sg, r, steps: int):
-    """Per-vertex balanced counts (BBC_PER_VERTEX) of the same device-resident
-    graph: whole calls, whose per-vertex array is returned to the host.  The
-    output is checked by what holds at any size: each balanced butterfly has
-    four vertices, so the counts sum to 4 x the balanced total, and the totals
-    equal those of the plain count."""
+    """Per-vertex balanced counts (BBC_PER_VERTEX | BBC_OUTPUT_ON_DEVICE) of
+    the same device-resident graph: whole calls whose per-vertex array stays in
+    device memory.  The output is checked by what holds at any size: each
+    balanced butterfly has four vertices, so the counts sum to 4 x the balanced
+    total, and the totals equal those of the plain count."""
     import torch
-    rr, pv = ctx.count(eu, ev, sg, g.n_u, g.n_v, per_vertex=True)  # warm-up
+    rr, pv = ctx.count(eu, ev, sg, g.n_u, g.n_v, per_vertex=True,
+                       per_vertex_on_device=True)  # warm-up
     torch.cuda.synchronize()
     dev_ms = wedge_ms = 0.0
     t0 = time.perf_counter()
     for _ in range(steps):
-        rr, pv = ctx.count(eu, ev, sg, g.n_u, g.n_v, per_vertex=True)
+        rr, pv = ctx.count(eu, ev, sg, g.n_u, g.n_v, per_vertex=True, per_vertex_on_device=True)
         dev_ms += ctx.phase_ms(0)
         wedge_ms += ctx.phase_ms(2)
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / steps
-    ok_sum = int(pv.sum()) == 4 * r.balanced
+    ok_sum = int(pv.sum().item()) == 4 * r.balanced
     log(f"per-vertex: {ms:.3f} ms per call (device {dev_ms / steps:.3f} ms, wedge kernel "
         f"{wedge_ms / steps:.3f} ms); sum = 4 x balanced: {ok_sum}; totals equal: {rr == r}")
     return {"ms_per_call": ms, "device_ms": dev_ms / steps, "wedge_kernel_ms": wedge_ms / steps,
             "wedges_per_s": r.wedges / (ms * 1e-3), "steps": steps,
-            "output": f"{g.n_u + g.n_v} int64 counts copied to host memory inside each call",
+            "output": f"{g.n_u + g.n_v} int64 counts left in device memory",
             "sum_is_4x_balanced": ok_sum, "totals_equal_plain_count": rr == r}
 
 

@@ -58,9 +58,11 @@ typedef struct bbc_result {
 
 /* flags for bbc_count */
 enum {
-    BBC_INPUT_ON_DEVICE = 1u, /* edge_u/edge_v/edge_sign are device pointers on the
-                                 context's device, ordered on its stream */
-    BBC_PER_VERTEX = 4u       /* also fill per_vertex (see bbc_count) */
+    BBC_INPUT_ON_DEVICE = 1u,  /* edge_u/edge_v/edge_sign are device pointers on the
+                                  context's device, ordered on its stream */
+    BBC_OUTPUT_ON_DEVICE = 2u, /* with BBC_PER_VERTEX: per_vertex is a device pointer
+                                  on the context's device */
+    BBC_PER_VERTEX = 4u        /* also fill per_vertex (see bbc_count) */
 };
 
 /*
@@ -86,6 +88,10 @@ void bbc_destroy(bbc_context* ctx);
  * `out` (host) receives the counts.  With BBC_PER_VERTEX, `per_vertex` (host,
  * n_u + n_v entries, U first then V) receives for every vertex the number of
  * balanced butterflies that contain it (Section 5.1); otherwise it may be NULL.
+ * With BBC_OUTPUT_ON_DEVICE as well, `per_vertex` is a device buffer of that
+ * size on the context's device (written on the device, never copied to the
+ * host); the flag without BBC_PER_VERTEX is INVALID_ARG.  Either buffer is
+ * written only when the call returns BBC_OK.
  *
  * The call is synchronous: it returns when the counts are on the host.
  * An empty graph, or one with fewer than two vertices on a side, gives zeros.

@@ -38,6 +38,7 @@ NOT_IMPLEMENTED = -9
 INTERNAL = -10
 
 INPUT_ON_DEVICE = 1
+OUTPUT_ON_DEVICE = 2
 PER_VERTEX = 4
 PARAM_HASH_TARGET = 1
 PARAM_PROBE_LIMIT = 2
@@ -247,21 +248,32 @@ class Context:
             raise BBCError(rc, self.last_error() or status_string(rc))
         return Result(int(out.balanced), int(out.unbalanced), int(out.wedges))
 
-    def count(self, eu, ev, sign, n_u: int, n_v: int, per_vertex: bool = False):
+    def count(self, eu, ev, sign, n_u: int, n_v: int, per_vertex: bool = False,
+              per_vertex_on_device: bool = False):
         """Count the balanced butterflies of the signed bipartite graph given by
         edges (eu[i], ev[i]) with sign[i] in {+1, -1}.  Returns a Result, or
-        (Result, per-vertex int64 array) when per_vertex is set."""
+        (Result, per-vertex int64 array) when per_vertex is set: a numpy array,
+        or with per_vertex_on_device a torch tensor on the context's device."""
         ptrs, keep, on_dev, n = _prepare(eu, ev, sign)
         flags = INPUT_ON_DEVICE if on_dev else 0
         pv = None
         pv_ptr = None
-        if per_vertex:
+        if per_vertex and per_vertex_on_device:
+            import torch
+            flags |= PER_VERTEX | OUTPUT_ON_DEVICE
+            pv = torch.empty(int(n_u) + int(n_v), dtype=torch.int64,
+                             device=torch.device("cuda", self.device))
+            pv_ptr = pv.data_ptr()
+        elif per_vertex:
             flags |= PER_VERTEX
             pv = np.zeros(int(n_u) + int(n_v), dtype=np.int64)
             pv_ptr = pv.ctypes.data
-        if on_dev:
+        if on_dev or (per_vertex and per_vertex_on_device):
+            # torch's pending work on these buffers is done before the library's
+            # stream reads or writes them (the call itself ends synchronized)
             import torch
-            cur = torch.cuda.current_stream(keep[0].device)
+            dev = keep[0].device if on_dev else torch.device("cuda", self.device)
+            cur = torch.cuda.current_stream(dev)
             if self.stream is None or int(cur.cuda_stream) != int(self.stream):
                 cur.synchronize()
         r = self.count_raw(n_u, n_v, n, *ptrs, flags=flags, per_vertex_ptr=pv_ptr)

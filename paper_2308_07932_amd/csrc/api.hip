@@ -438,7 +438,8 @@ struct RunIn {
     bool copy_in;            // eu/ev/sg are host pointers
     const BatchDev* bt;      // NULL: one graph
     const IngestArgs* ingest;  // batches: fills eu/ev/sg first (reports into the control block)
-    int64_t* per_vertex;     // host, n entries: per-vertex counts wanted (one graph only)
+    bool per_vertex;         // per-vertex counts wanted (one graph only)
+    int64_t* pv_host;        // host, n entries: where they are copied (NULL: left on the device)
 };
 
 struct RunOut {
@@ -446,6 +447,7 @@ struct RunOut {
     bool input_error;        // stopped after the input checks (h.edge_err / h.dup)
     uint32_t n_items, n_heavy;
     uint32_t n;
+    const u64* pv_dev;       // per-vertex counts by input id on the device (per-vertex mode)
 };
 
 // Runs one device segment of the pipeline: eagerly, or (graph mode) as a HIP
@@ -498,6 +500,7 @@ static bbc_status run_pipeline(bbc_context* c, const RunIn& in, RunOut& ro) {
     ro.input_error = false;
     ro.n_items = ro.n_heavy = 0;
     ro.n = n;
+    ro.pv_dev = nullptr;
 
     Dims d;
     d.n_u = nu;
@@ -718,6 +721,7 @@ static bbc_status run_pipeline(bbc_context* c, const RunIn& in, RunOut& ro) {
                 pv_out = cv.take<u64>(n);
                 sw_mid = cv.take<uint32_t>((size_t)h.tot_sw + 1);
             }
+            ro.pv_dev = pv_out;
             return cv.off;
         };
         Carver probe(nullptr);
@@ -730,7 +734,7 @@ static bbc_status run_pipeline(bbc_context* c, const RunIn& in, RunOut& ro) {
     std::vector<uint64_t> keyB = keyA;
     for (uint64_t x : {(uint64_t)n_heavy, (uint64_t)n_light, (uint64_t)n_light_items, (uint64_t)h.tot_g,
                        (uint64_t)h.tot_sw, (uint64_t)h.tot_tiles, (uint64_t)c->plan.base, (uint64_t)first_long[0],
-                       (uint64_t)first_long[1], (uint64_t)in.per_vertex})
+                       (uint64_t)first_long[1], (uint64_t)in.per_vertex, (uint64_t)in.pv_host})
         keyB.push_back(x);
     if (tm_out) HIPCHECK(c, hipEventRecord(c->ev[kEvPlanB], st));
     bbc_status sB = run_segment(c, 1, keyB, [&]() -> bbc_status {
@@ -768,7 +772,8 @@ static bbc_status run_pipeline(bbc_context* c, const RunIn& in, RunOut& ro) {
     if (tm) HIPCHECK(c, hipEventRecord(c->ev[kEvWedgeB], st));
     if (pv) {
         HIPCHECK(c, launch_pv_out(pv, b.sidx_of, d, pv_out, st));
-        HIPCHECK(c, hipMemcpyAsync(in.per_vertex, pv_out, 8ull * n, hipMemcpyDeviceToHost, st));
+        if (in.pv_host)
+            HIPCHECK(c, hipMemcpyAsync(in.pv_host, pv_out, 8ull * n, hipMemcpyDeviceToHost, st));
     }
     HIPCHECK(c, hipMemcpyAsync(c->host_ctl, b.ctl, sizeof(Control), hipMemcpyDeviceToHost, st));
     return BBC_OK;
@@ -827,8 +832,11 @@ bbc_status bbc_count(bbc_context* c, int32_t n_u, int32_t n_v, int64_t n_edges,
     if (n_u < 0 || n_v < 0 || n_edges < 0)
         return fail(c, BBC_ERR_INVALID_ARG, "negative size (n_u=%d n_v=%d n_edges=%lld)", n_u, n_v,
                     (long long)n_edges);
-    if (flags & ~(uint32_t)(BBC_INPUT_ON_DEVICE | BBC_PER_VERTEX))
+    if (flags & ~(uint32_t)(BBC_INPUT_ON_DEVICE | BBC_OUTPUT_ON_DEVICE | BBC_PER_VERTEX))
         return fail(c, BBC_ERR_INVALID_ARG, "unknown flag bits 0x%x", flags);
+    if ((flags & BBC_OUTPUT_ON_DEVICE) && !(flags & BBC_PER_VERTEX))
+        return fail(c, BBC_ERR_INVALID_ARG, "BBC_OUTPUT_ON_DEVICE without BBC_PER_VERTEX");
+    const bool pv_on_device = (flags & BBC_OUTPUT_ON_DEVICE) != 0;
     if (n_edges > 0 && (!edge_u || !edge_v || !edge_sign))
         return fail(c, BBC_ERR_INVALID_ARG, "NULL edge array with n_edges=%lld", (long long)n_edges);
     if ((flags & BBC_PER_VERTEX) && !per_vertex)
@@ -838,8 +846,14 @@ bbc_status bbc_count(bbc_context* c, int32_t n_u, int32_t n_v, int64_t n_edges,
     if ((uint64_t)n_edges >= (1ull << 31))
         return fail(c, BBC_ERR_TOO_LARGE, "n_edges = %lld >= 2^31", (long long)n_edges);
     if (n_edges == 0) {
+        if ((flags & BBC_PER_VERTEX) && pv_on_device && n64 > 0) {
+            HIPCHECK(c, hipSetDevice(c->device));
+            HIPCHECK(c, fill_u64((u64*)per_vertex, 0, n64, c->stream));
+            HIPCHECK(c, hipStreamSynchronize(c->stream));
+        } else if (flags & BBC_PER_VERTEX) {
+            memset(per_vertex, 0, 8ull * (size_t)n64);
+        }
         out->balanced = out->unbalanced = out->wedges = 0;
-        if (flags & BBC_PER_VERTEX) memset(per_vertex, 0, 8ull * (size_t)n64);
         return BBC_OK;
     }
     HIPCHECK(c, hipSetDevice(c->device));
@@ -847,7 +861,7 @@ bbc_status bbc_count(bbc_context* c, int32_t n_u, int32_t n_v, int64_t n_edges,
     // per-vertex counts land in a context-owned host buffer first, so that the
     // caller's buffer is written only on success
     int64_t* pvh = nullptr;
-    if (flags & BBC_PER_VERTEX) {
+    if ((flags & BBC_PER_VERTEX) && !pv_on_device) {
         const size_t bytes = 8ull * (size_t)n64;
         if (c->pv_host_cap < bytes) {
             if (c->pv_host) hipHostFree(c->pv_host);
@@ -864,7 +878,7 @@ bbc_status bbc_count(bbc_context* c, int32_t n_u, int32_t n_v, int64_t n_edges,
         pvh = c->pv_host;
     }
     RunIn in{(uint32_t)n_u, (uint32_t)n_v, (uint64_t)n_edges, edge_u, edge_v, edge_sign, copy_in,
-             nullptr, nullptr, pvh};
+             nullptr, nullptr, (flags & BBC_PER_VERTEX) != 0, pvh};
     RunOut ro;
     bbc_status s = run_pipeline(c, in, ro);
     if (s) return s;
@@ -887,6 +901,13 @@ bbc_status bbc_count(bbc_context* c, int32_t n_u, int32_t n_v, int64_t n_edges,
             if (pvh[x] < 0) return fail(c, BBC_ERR_OVERFLOW, "vertex %llu: count exceeds INT64_MAX",
                                         (unsigned long long)x);
         memcpy(per_vertex, pvh, 8ull * n64);
+    }
+    if (pv_on_device) {
+        // every vertex count is at most the balanced total, checked above; the
+        // caller's buffer is written only now, on success
+        HIPCHECK(c, hipMemcpyAsync(per_vertex, ro.pv_dev, 8ull * n64, hipMemcpyDeviceToDevice,
+                                   c->stream));
+        HIPCHECK(c, hipStreamSynchronize(c->stream));
     }
     c->timing_valid = c->timing;
     add_stats(c, ro, (uint64_t)n_edges);
@@ -986,7 +1007,7 @@ static bbc_status count_union(bbc_context* c, const std::vector<uint32_t>& all, 
         }
         HIPCHECK(c, fill_u64(w.gres, 0, 4ull * G, st));
         HIPCHECK(c, fill_u64(w.gerr, ~0ull, G, st));
-        RunIn in{nu, nv, m, w.eu, w.ev, w.sg, false, nullptr, nullptr, nullptr};
+        RunIn in{nu, nv, m, w.eu, w.ev, w.sg, false, nullptr, nullptr, false, nullptr};
         BatchDev bd;
         bd.n_graphs = G;
         bd.max_side = max_side;

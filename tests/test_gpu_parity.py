@@ -423,6 +423,31 @@ def test_per_vertex_heavy_shapes(ctx):
     assert ctx.count(g.eu, g.ev, g.sign, g.n_u, g.n_v)[:2] == bu
 
 
+def test_per_vertex_on_device(ctx):
+    # the per-vertex counts written straight into a device buffer equal the
+    # host copy; on error the device buffer is left as it was
+    import torch
+    for g in (gen.voting_graph(seed=6, n_u=80, n_v=3000, p_edge=0.5),
+              gen.chung_lu_graph(seed=11, n_u=60000, n_v=20000, n_edges=250000, p_neg=0.25)):
+        r_h, pv_h = ctx.count(g.eu, g.ev, g.sign, g.n_u, g.n_v, per_vertex=True)
+        r_d, pv_d = ctx.count(g.eu, g.ev, g.sign, g.n_u, g.n_v, per_vertex=True,
+                              per_vertex_on_device=True)
+        assert pv_d.is_cuda and r_d == r_h
+        assert np.array_equal(pv_d.cpu().numpy(), pv_h)
+    empty = ctx.count(np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0, np.int8), 7, 5,
+                      per_vertex=True, per_vertex_on_device=True)
+    assert empty[0] == (0, 0, 0) and int(empty[1].abs().sum()) == 0 and empty[1].numel() == 12
+    g = gen.uniform_graph(seed=3, n_u=100, n_v=80, n_edges=2000)
+    bad = g.ev.copy()
+    bad[5] = 80
+    buf = torch.full((180,), -7, dtype=torch.int64, device="cuda:0")
+    torch.cuda.synchronize()
+    rc, _ = _raw(ctx, g._replace(ev=bad), bbc.PER_VERTEX | bbc.OUTPUT_ON_DEVICE, buf.data_ptr())
+    assert rc == bbc.VERTEX_RANGE and bool((buf == -7).all())
+    # the flag without per-vertex counts is rejected
+    assert _raw(ctx, g, bbc.OUTPUT_ON_DEVICE)[0] == bbc.INVALID_ARG
+
+
 def test_per_vertex_buffer_untouched_on_error(ctx):
     g = gen.uniform_graph(seed=3, n_u=100, n_v=80, n_edges=2000)
     bad = g.sign.copy()
