@@ -318,6 +318,27 @@ constexpr uint32_t kSwWaves = kSwThreads / 64;
 constexpr uint32_t kSwLog2 = 11;
 constexpr uint32_t kSwSlots = 1u << kSwLog2;
 
+// Slot of `key` in the chunk's LDS table (inserting it), or -1 after 8 probes;
+// a newly taken slot is appended to `used`, so that the flush and the reset
+// touch only the slots in use.
+__device__ inline int sw_slot(uint32_t* keys, uint32_t key, uint32_t* used, uint32_t* n_used) {
+    constexpr uint32_t kMask = kSwSlots - 1u;
+    const uint32_t h = (key * 0x9E3779B1u) >> (32 - kSwLog2);
+    for (uint32_t i = 0; i < 8; ++i) {
+        const uint32_t s = (h + i) & kMask;
+        uint32_t k = keys[s];
+        if (k == kEmpty) {
+            k = atomicCAS(&keys[s], kEmpty, key);
+            if (k == kEmpty) {
+                used[atomicAdd(n_used, 1u)] = s;
+                return (int)s;
+            }
+        }
+        if (k == key) return (int)s;
+    }
+    return -1;
+}
+
 template <bool kFill>
 __global__ __launch_bounds__(kSwThreads) void k_short_wedges(
     const uint4* __restrict__ recs, uint32_t m, const uint32_t* __restrict__ col,
@@ -334,14 +355,18 @@ __global__ __launch_bounds__(kSwThreads) void k_short_wedges(
     __shared__ uint32_t s_s1[kSwWaves][64];   // sign(u, v) of its record
     __shared__ uint32_t s_mid[kSwWaves][64];  // the row of its middle v (per-vertex mode)
     __shared__ uint8_t s_head[kSwWaves][64];
+    __shared__ uint32_t s_used[kSwSlots];  // table slots taken in this chunk
+    __shared__ uint32_t s_nused;
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
     const u64 le_mask = ~0ull >> (63 - lane);  // lanes 0..lane
     s_head[wave][lane] = 0;
+    for (uint32_t i = tid; i < kSwSlots; i += kSwThreads) {
+        keys[i] = kEmpty;
+        cnt[i] = 0;
+    }
+    if (tid == 0) s_nused = 0;
+    __syncthreads();
     for (uint32_t c0 = blockIdx.x * kSwThreads; c0 < m; c0 += gridDim.x * kSwThreads) {
-        for (uint32_t i = tid; i < kSwSlots; i += kSwThreads) {
-            keys[i] = kEmpty;
-            cnt[i] = 0;
-        }
         const uint32_t j = c0 + tid;
         uint4 rc = make_uint4(0, 0, 0, 0);
         bool mine = false;
@@ -351,6 +376,9 @@ __global__ __launch_bounds__(kSwThreads) void k_short_wedges(
             mine = tc[u] > 0 && j >= front[u];  // short record of a split start
         }
         const uint32_t len = mine ? rc.y >> 1 : 0u;
+        // chunks without a short record of a split start are skipped whole (the
+        // table is clean: every chunk resets the slots it used)
+        if (!__syncthreads_or(len > 0)) continue;
         const u64 nz = __ballot(len > 0);
         const uint32_t excl = wave_incl_scan(len) - len;
         const uint32_t T = __shfl(excl + len, 63, 64);
@@ -395,7 +423,7 @@ __global__ __launch_bounds__(kSwThreads) void k_short_wedges(
                 }
                 uint32_t at = kEmpty;  // the run's first slot, if this pass writes it
                 if (rlen) {
-                    const int sl = agg_slot<kSwLog2>(keys, gp);
+                    const int sl = sw_slot(keys, gp, s_used, &s_nused);
                     if (!place) {
                         if (sl >= 0)
                             atomicAdd(&cnt[sl], rlen);
@@ -419,17 +447,25 @@ __global__ __launch_bounds__(kSwThreads) void k_short_wedges(
         };
         walk(false);
         __syncthreads();
-        for (uint32_t i = tid; i < kSwSlots; i += kSwThreads)
-            if (keys[i] != kEmpty) {
-                if (!kFill)
-                    atomicAdd(&counts[keys[i]], cnt[i]);
-                else
-                    base[i] = atomicAdd(&cursor[keys[i]], cnt[i]);
-                cnt[i] = 0;
-            }
+        const uint32_t nused = s_nused;
+        for (uint32_t k = tid; k < nused; k += kSwThreads) {
+            const uint32_t i = s_used[k];
+            if (!kFill)
+                atomicAdd(&counts[keys[i]], cnt[i]);
+            else
+                base[i] = atomicAdd(&cursor[keys[i]], cnt[i]);
+            cnt[i] = 0;
+        }
         __syncthreads();
         if (kFill) walk(true);
         __syncthreads();
+        for (uint32_t k = tid; k < nused; k += kSwThreads) {
+            const uint32_t i = s_used[k];
+            keys[i] = kEmpty;
+            cnt[i] = 0;
+        }
+        __syncthreads();
+        if (tid == 0) s_nused = 0;  // ordered before the next chunk's inserts by its barrier
     }
 }
 
