@@ -521,7 +521,7 @@ static bbc_status run_pipeline(bbc_context* c, const RunIn& in, RunOut& ro) {
     d.gerr = bt ? bt->gerr : nullptr;
     d.rlist = nullptr;
     d.per_vertex = in.per_vertex ? 1u : 0u;
-    d.light_window = in.per_vertex ? kLightWindow : kLightWindow16;
+    d.light_window = kLightWindow16;
     // rows of side Y with more than kLongDeg entries: at most m / (kLongDeg + 1) per side
     uint64_t maxlong0 = std::min<uint64_t>(nu, m / (kLongDeg + 1));
     uint64_t maxlong1 = std::min<uint64_t>(nv, m / (kLongDeg + 1));

@@ -52,13 +52,11 @@ constexpr uint32_t kDenseW = 16384;           // dense counters per item (u64 ea
 constexpr uint32_t kHashSlots = 8192;         // hash slots (u32 key + u64 counters)
 constexpr uint32_t kLightMax = kHashSlots / 4;     // max wedges of a batched (light) start
 constexpr uint32_t kMinRegion = 64;
-// Light item i holds the light starts whose region offset lies in [iH, iH+H);
-// a region is at most 2 * kLightMax slots, so the item's regions end below
-// H + 2 * kLightMax: H = kLightWindow for the table of u32 keys and u64
-// counters (per-vertex mode), kLightWindow16 for the table of 2 * kHashSlots
-// u32 keys and u32 counters (l | m << 16; a light start has at most
+// Light item i holds the light starts whose region offset lies in [iH, iH+H)
+// with H = kLightWindow16; a region is at most 2 * kLightMax slots, so the
+// item's regions end below H + 2 * kLightMax = 2 * kHashSlots, the size of the
+// table of u32 keys and u32 counters (l | m << 16; a light start has at most
 // kLightMax < 2^16 wedges, so no count can reach 2^16).
-constexpr uint32_t kLightWindow = kHashSlots - 2 * kLightMax;
 constexpr uint32_t kLightWindow16 = 2 * kHashSlots - 2 * kLightMax;
 // offsets of one window lie at least kMinRegion apart
 constexpr uint32_t kMaxItemPieces = kLightWindow16 / kMinRegion + 1;
@@ -134,10 +132,10 @@ struct Dims {
     uint32_t n_graphs;
     const uint32_t* blk[2];
     u64* gerr;
-    // per-vertex mode: starts are not split by record chunks, the listed
-    // short-middle wedges carry their middles, light items keep 64-bit counters
+    // per-vertex mode: starts are not split by record chunks, and the listed
+    // short-middle wedges carry their middles
     uint32_t per_vertex;
-    uint32_t light_window;  // H of the light items: kLightWindow or kLightWindow16
+    uint32_t light_window;  // H of the light items (kLightWindow16)
     // rows in ascending (side, length) order, or NULL when the row index order
     // already is (one graph: rows are sorted by degree within each side)
     const uint32_t* rlist;

@@ -231,9 +231,8 @@ __global__ void k_plan_write(const u64* __restrict__ wu, const uint32_t* __restr
             p.t0 = kNoTile;
             p.t1 = kNoTile;
             p.region = (uint32_t)(off - item * d.light_window) | (log2_pow2(sp.region) << 16);
-            // the 16-bit-half table, except in per-vertex mode, whose light items
-            // finalize and read back per start from the 64-bit layout
-            p.flags = sideflag | (d.per_vertex ? 0u : kPieceHash16);
+            // the 16-bit-half table (a light start has at most kLightMax < 2^16 wedges)
+            p.flags = sideflag | kPieceHash16;
             p.gbase = kEmpty;
             p.start_row = r;
             p.list = kEmpty;

@@ -83,9 +83,7 @@ __device__ inline uint32_t hash32(uint32_t w) { return w * 0x9E3779B1u; }
 // The 16-bit-half hash table: 2 x kHashSlots keys, then as many u32 counters
 // (l | m << 16).  Returns false if w finds no slot within `lim` probes.
 constexpr uint32_t kHash16Slots = 2 * kHashSlots;
-static_assert(kLightWindow + 2 * kLightMax <= kHashSlots &&
-                  kLightWindow16 + 2 * kLightMax <= kHash16Slots,
-              "a light item's regions fit its table");
+static_assert(kLightWindow16 + 2 * kLightMax <= kHash16Slots, "a light item's regions fit its table");
 __device__ inline bool bucket_add16(uint32_t* s32, uint32_t lim, uint32_t w, uint32_t inc) {
     constexpr uint32_t lg = 31u - __builtin_clz(kHash16Slots);
     const uint32_t h = hash32(w) >> (32 - lg);
@@ -124,6 +122,23 @@ __device__ inline bool bucket_add16r(uint32_t* s32, uint32_t region, uint32_t w,
         }
     }
     return false;
+}
+
+// counters (l | m << 16) of w in a region of the 16-bit-half table (light
+// starts of an item), as a 64-bit bucket value (l + (m << 32))
+__device__ inline u64 bucket_get16r(const uint32_t* s32, uint32_t region, uint32_t w) {
+    const uint32_t rb = region & 0xFFFFu, lg = (region >> 16) & 31u;
+    const uint32_t msk = (1u << lg) - 1u;
+    const uint32_t h = hash32(w) >> (32 - lg);
+    for (uint32_t i = 0; i <= msk; ++i) {
+        const uint32_t s = rb + ((h + i) & msk);
+        if (s32[s] == w) {
+            const uint32_t c = s32[kHash16Slots + s];
+            return (c & 0xFFFFu) | ((u64)(c >> 16) << 32);
+        }
+        if (s32[s] == kEmpty) break;
+    }
+    return 0;
 }
 
 // counters (l | m << 16) of w in the 16-bit-half table, present after the
@@ -197,9 +212,7 @@ __device__ inline u64 bucket_get(const uint32_t* keys, const u64* hvals, uint32_
 // end vertex and the piece's total to the start (Section 5.1, Algorithm 3,
 // with the end vertex distinct from the start).  Every wedge must keep its
 // middle: pieces are then never split by record chunks, long sub-intervals are
-// not queued, the listed short-middle wedges carry their middle's row, and
-// light items keep 64-bit counters (their per-start finalize and readback read
-// that layout).
+// not queued, and the listed short-middle wedges carry their middle's row.
 template <bool PV>
 __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
     // on-chip buckets: dense mode uses s_tab[0 .. kDenseW); hash mode uses
@@ -457,8 +470,9 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
                                     if (dense && d16) {
                                         const uint32_t c = s32[w - dlo];
                                         bv = (c & 0xFFFFu) | ((u64)(c >> 16) << 32);
-                                    } else if (h16) {
-                                        bv = bucket_get16(s32, w);
+                                    } else if (h16) {  // light items of several pieces: regions
+                                        bv = np > 1 ? bucket_get16r(s32, P.region, w)
+                                                    : bucket_get16(s32, w);
                                     } else {
                                         bv = dense ? s_tab[w - dlo]
                                                    : bucket_get(keys, hvals, P.region, w);
@@ -727,12 +741,14 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
                     const uint32_t rb = region & 0xFFFFu, sz = 1u << ((region >> 16) & 31u);
                     const u64 ubase = a.d.base[(s_pc[p].flags & kPieceSideV) ? 1u : 0u];
                     u64 pb = 0, pu = 0;
-                    if (h16) {  // light starts with 16-bit halves (not in per-vertex mode)
+                    if (h16) {  // light starts with 16-bit halves
                         for (uint32_t i = lane; i < sz; i += 64) {
                             const uint32_t c = s32[kHash16Slots + rb + i];
                             const uint32_t l = c & 0xFFFFu, mm = c >> 16;
-                            pb += ((l * (l - 1u)) >> 1) + ((mm * (mm - 1u)) >> 1);
+                            const u64 b = ((l * (l - 1u)) >> 1) + ((mm * (mm - 1u)) >> 1);
+                            pb += b;
                             pu += l * mm;
+                            if (PV && b) atomicAdd(&a.pv[ubase + s32[rb + i]], b);
                         }
                     }
                     for (uint32_t i = lane; i < sz && !h16; i += 64) {
