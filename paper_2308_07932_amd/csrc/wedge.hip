@@ -527,24 +527,13 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
                                              ((x[u] ^ aux[u]) & 1u) ? (1ull << 32) : 1ull);
                         }
                         ok = __ballot(!lok) == 0;  // the whole wave leaves together
-                    } else if (h16) {  // light starts, 16-bit halves
+                    } else {  // light starts of an item: regions of the 16-bit-half table
                         bool lok = true;
 #pragma unroll 1
                         for (uint32_t u = 0; u < kUnroll; ++u) {
                             if (aux[u] == kEmpty || !lok) continue;
                             lok = bucket_add16r(s32, s_pc[aux[u] >> 2].region, x[u] >> 1,
                                                 ((x[u] ^ aux[u]) & 1u) ? 0x10000u : 1u);
-                        }
-                        ok = __ballot(!lok) == 0;
-                    } else {
-                        bool lok = true;
-#pragma unroll 1
-                        for (uint32_t u = 0; u < kUnroll; ++u) {
-                            if (aux[u] == kEmpty || !lok) continue;
-                            const uint32_t region = s_pc[aux[u] >> 2].region;
-                            const uint32_t lim = 1u << ((region >> 16) & 31u);
-                            lok = bucket_add(s_tab, keys, hvals, false, 0, region, lim, x[u] >> 1,
-                                             ((x[u] ^ aux[u]) & 1u) ? (1ull << 32) : 1ull);
                         }
                         ok = __ballot(!lok) == 0;
                     }
@@ -741,24 +730,13 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
                     const uint32_t rb = region & 0xFFFFu, sz = 1u << ((region >> 16) & 31u);
                     const u64 ubase = a.d.base[(s_pc[p].flags & kPieceSideV) ? 1u : 0u];
                     u64 pb = 0, pu = 0;
-                    if (h16) {  // light starts with 16-bit halves
-                        for (uint32_t i = lane; i < sz; i += 64) {
-                            const uint32_t c = s32[kHash16Slots + rb + i];
-                            const uint32_t l = c & 0xFFFFu, mm = c >> 16;
-                            const u64 b = ((l * (l - 1u)) >> 1) + ((mm * (mm - 1u)) >> 1);
-                            pb += b;
-                            pu += l * mm;
-                            if (PV && b) atomicAdd(&a.pv[ubase + s32[rb + i]], b);
-                        }
-                    }
-                    for (uint32_t i = lane; i < sz && !h16; i += 64) {
-                        if (keys[rb + i] == kEmpty) continue;
-                        const u64 v = hvals[rb + i];
-                        const u64 l = v & 0xFFFFFFFFull, m = v >> 32;
-                        const u64 b = choose2(l) + choose2(m);
+                    for (uint32_t i = lane; i < sz; i += 64) {  // light starts: 16-bit halves
+                        const uint32_t c = s32[kHash16Slots + rb + i];
+                        const uint32_t l = c & 0xFFFFu, mm = c >> 16;
+                        const u64 b = ((l * (l - 1u)) >> 1) + ((mm * (mm - 1u)) >> 1);
                         pb += b;
-                        pu += l * m;
-                        if (PV && b) atomicAdd(&a.pv[ubase + keys[rb + i]], b);
+                        pu += l * mm;
+                        if (PV && b) atomicAdd(&a.pv[ubase + s32[rb + i]], b);
                     }
                     pb = wave_reduce_sum(pb);
                     pu = wave_reduce_sum(pu);
