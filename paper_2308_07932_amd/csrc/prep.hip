@@ -418,19 +418,89 @@ __device__ inline void bitmap_emit(const uint32_t* bm, const uint32_t* sg, uint3
     __syncthreads();
 }
 
-// rows with 64 < len <= 4096: one workgroup per row.  If the row's entries
-// span at most kMidBits indices (every row of a batch), an LDS bitmap (plus a
-// sign bitmap) sorts them; otherwise a bitonic sort in LDS.
+// rows with 64 < len <= 4096 whose entries span at most kMidBits indices
+// (every row of a batch): one wave per row, an LDS bitmap (plus a sign bitmap)
+// per wave, no workgroup barriers.  A repeated neighbour leaves fewer bits than
+// entries; the row's remaining slots get copies of its last entry, as in
+// bitmap_emit.
 constexpr uint32_t kMidBits = 16384;
+constexpr uint32_t kMidWords = kMidBits / 32;
+
+__global__ __launch_bounds__(256) void k_sort_mid_bitmap(const uint32_t* __restrict__ row_ptr,
+                                                        const uint32_t* __restrict__ in,
+                                                        uint32_t* __restrict__ out, Dims d,
+                                                        Control* ctl) {
+    __shared__ uint32_t s_bm[4][kMidWords];
+    __shared__ uint32_t s_sg[4][kMidWords];
+    const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
+    uint32_t* bm = s_bm[wave];
+    uint32_t* sg = s_sg[wave];
+    uint32_t lo0, hi0, lo1, hi1;
+    class_range(ctl, d, 0, 5, 5, &lo0, &hi0);
+    class_range(ctl, d, 1, 5, 5, &lo1, &hi1);
+    const uint32_t n0 = hi0 - lo0, tot = n0 + (hi1 - lo1);
+    bool dup = false;
+    for (uint32_t q = blockIdx.x * 4 + wave; q < tot; q += gridDim.x * 4) {
+        const uint32_t r = row_at(d, q < n0 ? lo0 + q : lo1 + (q - n0));
+        uint32_t elo, ehi;
+        entry_range(d, r, &elo, &ehi);
+        const uint32_t R = ehi - elo;
+        if (R > kMidBits) continue;  // k_sort_block sorts this row
+        const uint32_t a = row_ptr[r], L = row_ptr[r + 1] - a;
+        const uint32_t words = (R + 31) / 32;
+        for (uint32_t i = lane; i < words; i += 64) {
+            bm[i] = 0;
+            sg[i] = 0;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        for (uint32_t i = lane; i < L; i += 64) {
+            const uint32_t x = in[a + i];
+            const uint32_t y = (x >> 1) - elo;
+            if (y >= R) continue;  // cannot happen: entries lie in the block
+            const uint32_t msk = 1u << (y & 31);
+            if (atomicOr(&bm[y >> 5], msk) & msk) dup = true;
+            if (x & 1u) atomicOr(&sg[y >> 5], msk);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        // lane owns words [w0, w1); emit in order after a wave scan of counts
+        const uint32_t per = (words + 63) / 64;
+        const uint32_t w0 = lane * per, w1 = min(words, w0 + per);
+        uint32_t cnt = 0, last = 0;  // last: 1 + highest set bit
+        for (uint32_t i = w0; i < w1; ++i) {
+            cnt += __popc(bm[i]);
+            if (bm[i]) last = i * 32 + (32 - __clz(bm[i]));
+        }
+        const uint32_t incl = wave_incl_scan(cnt);
+        const uint32_t total = __shfl(incl, 63, 64);
+        for (uint32_t off = 32; off > 0; off >>= 1) last = max(last, __shfl_xor(last, off, 64));
+        uint32_t pos = incl - cnt;
+        for (uint32_t i = w0; i < w1; ++i) {
+            uint32_t bits = bm[i];
+            while (bits) {
+                const uint32_t bt = __ffs(bits) - 1;
+                if (pos < L) out[a + pos] = ((elo + i * 32 + bt) << 1) | ((sg[i] >> bt) & 1u);
+                ++pos;
+                bits &= bits - 1;
+            }
+        }
+        if (total < L && last > 0) {
+            const uint32_t y = last - 1;
+            const uint32_t v = ((elo + y) << 1) | ((sg[y >> 5] >> (y & 31)) & 1u);
+            for (uint32_t i = total + lane; i < L; i += 64) out[a + i] = v;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    }
+    if (dup) atomicOr(&ctl->dup, 1u);
+}
+
+// rows with 64 < len <= 4096 whose entries span more than kMidBits indices: one
+// workgroup per row, bitonic sort in LDS.
 
 __global__ __launch_bounds__(256) void k_sort_block(const uint32_t* __restrict__ row_ptr,
                                                    const uint32_t* __restrict__ in,
                                                    uint32_t* __restrict__ out, Dims d,
                                                    Control* ctl) {
     __shared__ uint32_t s[4096];
-    __shared__ uint32_t s_scan[4];
-    __shared__ uint32_t s_last;
-    static_assert(2 * kMidBits / 32 <= 4096, "bitmaps fit the sort buffer");
     uint32_t lo0, hi0, lo1, hi1;
     class_range(ctl, d, 0, 5, 5, &lo0, &hi0);
     class_range(ctl, d, 1, 5, 5, &lo1, &hi1);
@@ -441,29 +511,7 @@ __global__ __launch_bounds__(256) void k_sort_block(const uint32_t* __restrict__
         uint32_t a = row_ptr[r], L = row_ptr[r + 1] - a;
         uint32_t elo, ehi;
         entry_range(d, r, &elo, &ehi);
-        if (ehi - elo <= kMidBits) {
-            const uint32_t words = (ehi - elo + 31) / 32;
-            uint32_t* bm = s;
-            uint32_t* sg = s + kMidBits / 32;
-            for (uint32_t i = threadIdx.x; i < words; i += blockDim.x) {
-                bm[i] = 0;
-                sg[i] = 0;
-            }
-            if (threadIdx.x == 0) s_last = 0;
-            __syncthreads();
-            for (uint32_t i = threadIdx.x; i < L; i += blockDim.x) {
-                const uint32_t x = in[a + i];
-                const uint32_t y = (x >> 1) - elo;
-                if (y >= ehi - elo) continue;  // cannot happen: entries lie in the block
-                const uint32_t msk = 1u << (y & 31);
-                if (atomicOr(&bm[y >> 5], msk) & msk) dup = true;
-                if (x & 1u) atomicOr(&sg[y >> 5], msk);
-            }
-            __syncthreads();
-            bitmap_emit(bm, sg, words, (words + blockDim.x - 1) / blockDim.x, elo, out, a, L,
-                        s_scan, &s_last);
-            continue;
-        }
+        if (ehi - elo <= kMidBits) continue;  // k_sort_mid_bitmap sorts this row
         uint32_t P = 1;
         while (P < L) P <<= 1;
         for (uint32_t i = threadIdx.x; i < P; i += blockDim.x) s[i] = i < L ? in[a + i] : kEmpty;
@@ -835,6 +883,8 @@ hipError_t launch_row_sort(const uint32_t* rowdeg, const uint32_t* row_ptr, cons
                        row_ptr, in, out, d, ctl);
     hipLaunchKernelGGL(k_sort_group<64>, grid_n((uint64_t)d.n * 64, 256, 8192), dim3(256), 0, st,
                        row_ptr, in, out, d, ctl);
+    hipLaunchKernelGGL(k_sort_mid_bitmap, dim3(num_cus * 8), dim3(256), 0, st, row_ptr, in, out, d,
+                       ctl);
     hipLaunchKernelGGL(k_sort_block, dim3(num_cus * 8), dim3(256), 0, st, row_ptr, in, out, d, ctl);
     hipLaunchKernelGGL(k_sort_big, dim3(num_cus * 2), dim3(kBigThreads), 0, st, row_ptr, in, out, d,
                        ctl);
