@@ -24,8 +24,8 @@ hipError_t launch_sides(const uint32_t*, uint32_t, uint32_t, uint32_t*, hipStrea
 hipError_t launch_assign(const uint32_t*, const uint32_t*, const uint32_t*, uint32_t, uint32_t,
                          uint32_t*, uint32_t*, uint32_t*, hipStream_t);
 hipError_t launch_scatter(const int32_t*, const int32_t*, const int8_t*, uint64_t, uint32_t,
-                          uint32_t, const uint32_t*, const uint32_t*, const uint2*, uint32_t*,
-                          hipStream_t);
+                          uint32_t, const uint32_t*, const uint32_t*, const uint2*, uint2*,
+                          uint32_t*, hipStream_t);
 hipError_t launch_row_sort(const uint32_t*, const uint32_t*, const uint32_t*, uint32_t*, Dims,
                            Control*, uint32_t, hipStream_t);
 hipError_t launch_lowcount(const uint32_t*, const uint32_t*, const uint32_t*, uint32_t, uint32_t*,
@@ -176,6 +176,7 @@ struct PrepBufs {
         *cursor, *col_in, *col, *lowcnt, *mptr, *tb, *hp, *hp_off, *lf, *lf_off, *gs, *gs_off,
         *tc, *tc_off, *upcnt, *uptr, *rkey, *rk1, *rv1;
     uint4* raw;
+    uint2* vx;  // per input vertex: {sidx, row start} (the scatter's lookups)
     u64 *lr, *lr_off, *wu, *wsu, *swc, *swc_off;
     uint4* recs;
     void* rtmp;
@@ -204,6 +205,7 @@ static size_t carve_prep(Carver& cv, PrepBufs& b, uint32_t n, uint64_t m, bool c
     b.rowcross = cv.take<uint32_t>(n);
     b.row_ptr = cv.take<uint32_t>(n + 1);
     b.cursor = cv.take<uint32_t>(n);
+    b.vx = cv.take<uint2>(n);
     b.col_in = cv.take<uint32_t>(2 * m);
     b.col = cv.take<uint32_t>(2 * m);
     b.lowcnt = cv.take<uint32_t>(n);
@@ -624,7 +626,8 @@ static bbc_status run_pipeline(bbc_context* c, const RunIn& in, RunOut& ro) {
     }
     // ---- 4. CSR: offsets, scatter, per-row sort
     HIPCHECK(c, scan_excl_u32(b.rowdeg, b.row_ptr, n, b.stmp, b.stmp_bytes, st));
-    HIPCHECK(c, launch_scatter(eu, ev, sg, m, nu, nv, b.sidx_of, b.row_ptr, slots, b.col_in, st));
+    HIPCHECK(c, launch_scatter(eu, ev, sg, m, nu, nv, b.sidx_of, b.row_ptr, slots, b.vx, b.col_in,
+                               st));
     HIPCHECK(c, launch_row_sort(b.rowdeg, b.row_ptr, b.col_in, b.col, d, b.ctl, c->num_cus, st));
     if (bt) HIPCHECK(c, launch_dup_graphs(b.row_ptr, b.col, d, b.ctl, st));
     // ---- 5. middle counts, 6. records and W_u, 7. tile tables

@@ -224,14 +224,24 @@ __global__ void k_assign(const uint32_t* __restrict__ inv, const uint32_t* __res
     }
 }
 
+// Per input vertex x: {sidx(x), start of its row}, so that the scatter reads
+// one 8-byte entry per endpoint (a random read costs a whole memory sector).
+__global__ void k_vertex_pack(const uint32_t* __restrict__ sidx_of,
+                              const uint32_t* __restrict__ row_ptr, uint32_t n, uint32_t n_u,
+                              uint2* __restrict__ vx) {
+    for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < n; x += gridDim.x * blockDim.x) {
+        const uint32_t s = sidx_of[x];
+        vx[x] = make_uint2(s, row_ptr[(x < n_u ? 0u : n_u) + s]);
+    }
+}
+
 // Each edge lands in row u (entry sidx(v)) and row v (entry sidx(u)), at the
 // slots the degree pass reserved for it.
 __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ eu,
                                                  const int32_t* __restrict__ ev,
                                                  const int8_t* __restrict__ sg, uint64_t m,
                                                  uint32_t n_u, uint32_t n_v,
-                                                 const uint32_t* __restrict__ sidx_of,
-                                                 const uint32_t* __restrict__ row_ptr,
+                                                 const uint2* __restrict__ vx,
                                                  const uint2* __restrict__ rank,
                                                  uint32_t* __restrict__ col) {
     for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
@@ -239,11 +249,11 @@ __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ eu,
         const int32_t u = eu[e], v = ev[e];
         const int8_t s = sg[e];
         if (!edge_ok(u, v, s, n_u, n_v)) continue;
-        const uint32_t su = sidx_of[u], sv = sidx_of[n_u + (uint32_t)v];
+        const uint2 pu = vx[u], pv = vx[n_u + (uint32_t)v];  // {sidx, row start}
         const uint2 r = rank[e];
         const uint32_t neg = s < 0 ? 1u : 0u;
-        col[row_ptr[su] + r.x] = (sv << 1) | neg;
-        col[row_ptr[n_u + sv] + r.y] = (su << 1) | neg;
+        col[pu.y + r.x] = (pv.x << 1) | neg;
+        col[pv.y + r.y] = (pu.x << 1) | neg;
     }
 }
 
@@ -866,10 +876,13 @@ hipError_t launch_assign(const uint32_t* inv, const uint32_t* cnt_u, const uint3
 
 hipError_t launch_scatter(const int32_t* eu, const int32_t* ev, const int8_t* sg, uint64_t m,
                           uint32_t n_u, uint32_t n_v, const uint32_t* sidx_of,
-                          const uint32_t* row_ptr, const uint2* rank, uint32_t* col,
+                          const uint32_t* row_ptr, const uint2* rank, uint2* vx, uint32_t* col,
                           hipStream_t st) {
+    const uint32_t n = n_u + n_v;
+    hipLaunchKernelGGL(k_vertex_pack, grid_n(n, 256), dim3(256), 0, st, sidx_of, row_ptr, n, n_u,
+                       vx);
     hipLaunchKernelGGL(k_scatter, grid_n(m, 256), dim3(256), 0, st, eu, ev, sg, m, n_u, n_v,
-                       sidx_of, row_ptr, rank, col);
+                       (const uint2*)vx, rank, col);
     return hipGetLastError();
 }
 
