@@ -304,7 +304,9 @@ __global__ void k_plan_write(const u64* __restrict__ wu, const uint32_t* __restr
 // their short records: count per piece, then place.  A workgroup takes 256
 // records, 64 per wave; a wave reads the concatenation of the prefixes of its
 // short records of split starts 64 entries at a time (coalesced), finding each
-// entry's owner from head flags that mark where each prefix begins.  A prefix
+// entry's owner from head flags that mark where each prefix begins; four such
+// windows are loaded together, so the two dependent reads of an entry (the
+// entry, then its tile's piece) are waited for once per four windows.  A prefix
 // is sorted by end vertex, so its tiles, and the pieces they belong to, do not
 // decrease: a window splits into runs of one piece.  Runs are counted in an LDS
 // table keyed by piece and reach global memory once per (workgroup, piece).
@@ -314,8 +316,9 @@ __global__ void k_plan_write(const u64* __restrict__ wu, const uint32_t* __restr
 // every list entry, the row of the wedge's middle vertex.
 constexpr int kSwThreads = 256;
 constexpr uint32_t kSwWaves = kSwThreads / 64;
-constexpr uint32_t kSwLog2 = 11;
+constexpr uint32_t kSwLog2 = 9;
 constexpr uint32_t kSwSlots = 1u << kSwLog2;
+constexpr uint32_t kSwUnroll = 4;  // windows of 64 entries loaded together
 
 // Slot of `key` in the chunk's LDS table (inserting it), or -1 after 8 probes;
 // a newly taken slot is appended to `used`, so that the flush and the reset
@@ -353,12 +356,12 @@ __global__ __launch_bounds__(kSwThreads) void k_short_wedges(
     __shared__ uint32_t s_pb[kSwWaves][64];   // its start's first heavy piece
     __shared__ uint32_t s_s1[kSwWaves][64];   // sign(u, v) of its record
     __shared__ uint32_t s_mid[kSwWaves][64];  // the row of its middle v (per-vertex mode)
-    __shared__ uint8_t s_head[kSwWaves][64];
+    __shared__ uint8_t s_head[kSwWaves][64 * kSwUnroll];
     __shared__ uint32_t s_used[kSwSlots];  // table slots taken in this chunk
     __shared__ uint32_t s_nused;
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
     const u64 le_mask = ~0ull >> (63 - lane);  // lanes 0..lane
-    s_head[wave][lane] = 0;
+    for (uint32_t u = 0; u < kSwUnroll; ++u) s_head[wave][u * 64 + lane] = 0;
     for (uint32_t i = tid; i < kSwSlots; i += kSwThreads) {
         keys[i] = kEmpty;
         cnt[i] = 0;
@@ -394,51 +397,63 @@ __global__ __launch_bounds__(kSwThreads) void k_short_wedges(
         // run takes consecutive slots from its piece's reserved range
         auto walk = [&](const bool place) {
             uint32_t before = 0;
-            for (uint32_t w0 = 0; w0 < T; w0 += 64) {
-                if (len > 0 && excl >= w0 && excl < w0 + 64) s_head[wave][excl - w0] = 1;
+            for (uint32_t w0 = 0; w0 < T; w0 += 64 * kSwUnroll) {
+                if (len > 0 && excl >= w0 && excl < w0 + 64 * kSwUnroll) s_head[wave][excl - w0] = 1;
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                const u64 M = __ballot(s_head[wave][lane] != 0);
-                const uint32_t idx = before + (uint32_t)__popcll(M & le_mask) - 1u;
-                before += (uint32_t)__popcll(M);
-                const uint32_t q = w0 + lane;
-                const bool valid = q < T;
-                uint32_t gp = kEmpty, val = 0, mid = 0;
-                if (valid) {
-                    const uint32_t x = col[s_adj[wave][idx] + q];
-                    gp = s_pb[wave][idx] + tile_piece[s_tb[wave][idx] + (x >> 1) / kTile];
-                    val = (x & ~1u) | ((x ^ s_s1[wave][idx]) & 1u);
-                    mid = s_mid[wave][idx];
+                uint32_t idx[kSwUnroll], x[kSwUnroll], gp[kSwUnroll];
+#pragma unroll
+                for (uint32_t u = 0; u < kSwUnroll; ++u) {
+                    const u64 M = __ballot(s_head[wave][u * 64 + lane] != 0);
+                    idx[u] = before + (uint32_t)__popcll(M & le_mask) - 1u;
+                    before += (uint32_t)__popcll(M);
+                    const uint32_t q = w0 + u * 64 + lane;
+                    x[u] = q < T ? col[s_adj[wave][idx[u]] + q] : 0u;
                 }
-                s_head[wave][lane] = 0;
-                // runs of equal piece among the valid lanes (a prefix of the window)
-                const uint32_t prev = __shfl_up(gp, 1, 64);
-                const u64 H = __ballot(valid && (lane == 0 || prev != gp));
-                const uint32_t nvalid = min(64u, T - w0);
-                const uint32_t head = 63u - (uint32_t)__clzll(H & le_mask);  // this lane's run
-                uint32_t rlen = 0;
-                if ((H >> lane) & 1ull) {
-                    const u64 later = lane < 63 ? H >> (lane + 1) : 0ull;
-                    rlen = later ? (uint32_t)__builtin_ctzll(later) + 1u : nvalid - lane;
+#pragma unroll
+                for (uint32_t u = 0; u < kSwUnroll; ++u) {
+                    const uint32_t q = w0 + u * 64 + lane;
+                    gp[u] = q < T ? s_pb[wave][idx[u]] +
+                                        tile_piece[s_tb[wave][idx[u]] + (x[u] >> 1) / kTile]
+                                  : kEmpty;
+                    s_head[wave][u * 64 + lane] = 0;
                 }
-                uint32_t at = kEmpty;  // the run's first slot, if this pass writes it
-                if (rlen) {
-                    const int sl = sw_slot(keys, gp, s_used, &s_nused);
-                    if (!place) {
-                        if (sl >= 0)
-                            atomicAdd(&cnt[sl], rlen);
-                        else if (!kFill)
-                            atomicAdd(&counts[gp], rlen);
-                        else
-                            at = atomicAdd(&cursor[gp], rlen);  // no slot: placed now
-                    } else if (sl >= 0) {
-                        at = base[sl] + atomicAdd(&cnt[sl], rlen);
+#pragma unroll
+                for (uint32_t u = 0; u < kSwUnroll; ++u) {
+                    const uint32_t wu = w0 + u * 64;
+                    if (wu >= T) continue;  // uniform over the wave
+                    const bool valid = wu + lane < T;
+                    const uint32_t val =
+                        valid ? (x[u] & ~1u) | ((x[u] ^ s_s1[wave][idx[u]]) & 1u) : 0u;
+                    // runs of equal piece among the valid lanes (a prefix of the window)
+                    const uint32_t prev = __shfl_up(gp[u], 1, 64);
+                    const u64 H = __ballot(valid && (lane == 0 || prev != gp[u]));
+                    const uint32_t nvalid = min(64u, T - wu);
+                    const uint32_t head = 63u - (uint32_t)__clzll(H & le_mask);  // this lane's run
+                    uint32_t rlen = 0;
+                    if ((H >> lane) & 1ull) {
+                        const u64 later = lane < 63 ? H >> (lane + 1) : 0ull;
+                        rlen = later ? (uint32_t)__builtin_ctzll(later) + 1u : nvalid - lane;
                     }
-                }
-                if (kFill) {
-                    at = __shfl(at, (int)head, 64);
-                    if (valid && at != kEmpty) {
-                        list[at + (lane - head)] = val;
-                        if (mids) mids[at + (lane - head)] = mid;
+                    uint32_t at = kEmpty;  // the run's first slot, if this pass writes it
+                    if (rlen) {
+                        const int sl = sw_slot(keys, gp[u], s_used, &s_nused);
+                        if (!place) {
+                            if (sl >= 0)
+                                atomicAdd(&cnt[sl], rlen);
+                            else if (!kFill)
+                                atomicAdd(&counts[gp[u]], rlen);
+                            else
+                                at = atomicAdd(&cursor[gp[u]], rlen);  // no slot: placed now
+                        } else if (sl >= 0) {
+                            at = base[sl] + atomicAdd(&cnt[sl], rlen);
+                        }
+                    }
+                    if (kFill) {
+                        at = __shfl(at, (int)head, 64);
+                        if (valid && at != kEmpty) {
+                            list[at + (lane - head)] = val;
+                            if (mids) mids[at + (lane - head)] = s_mid[wave][idx[u]];
+                        }
                     }
                 }
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
