@@ -455,7 +455,7 @@ __global__ __launch_bounds__(256) void k_sort_mid_bitmap(const uint32_t* __restr
         uint32_t elo, ehi;
         entry_range(d, r, &elo, &ehi);
         const uint32_t R = ehi - elo;
-        if (R > kMidBits) continue;  // k_sort_block sorts this row
+        if (R > kMidBits) continue;  // k_sort_wave or k_sort_block sorts this row
         const uint32_t a = row_ptr[r], L = row_ptr[r + 1] - a;
         const uint32_t words = (R + 31) / 32;
         for (uint32_t i = lane; i < words; i += 64) {
@@ -503,8 +503,94 @@ __global__ __launch_bounds__(256) void k_sort_mid_bitmap(const uint32_t* __restr
     if (dup) atomicOr(&ctl->dup, 1u);
 }
 
-// rows with 64 < len <= 4096 whose entries span more than kMidBits indices: one
-// workgroup per row, bitonic sort in LDS.
+// rows with 64 < len <= kWaveRowMax whose entries span more than kMidBits
+// indices: one wave per row, a bitonic sort in registers.  Lane l holds the
+// row's entries l, 64 + l, ... (padded with kEmpty, above every entry); a
+// compare-exchange at distance j >= 64 stays in the lane, one at j < 64 takes a
+// shuffle.  No LDS and no barriers.
+constexpr uint32_t kWaveRowMax = 256;
+
+template <int E>
+__device__ inline void wave_bitonic(uint32_t (&x)[E], uint32_t lane) {
+#pragma unroll
+    for (uint32_t k = 2; k <= 64u * E; k <<= 1) {
+#pragma unroll
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            if (j >= 64) {
+#pragma unroll
+                for (int r = 0; r < E; ++r) {
+                    const int r2 = r ^ (int)(j >> 6);
+                    if (r2 > r) {
+                        const bool asc = ((r * 64u + lane) & k) == 0;
+                        const uint32_t lo = min(x[r], x[r2]), hi = max(x[r], x[r2]);
+                        x[r] = asc ? lo : hi;
+                        x[r2] = asc ? hi : lo;
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < E; ++r) {
+                    const uint32_t o = __shfl_xor(x[r], (int)j, 64);
+                    const bool asc = ((r * 64u + lane) & k) == 0;
+                    const bool low = (lane & j) == 0;
+                    x[r] = (low == asc) ? min(x[r], o) : max(x[r], o);
+                }
+            }
+        }
+    }
+}
+
+template <int E>
+__device__ inline bool wave_sort_row(const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
+                                     uint32_t a, uint32_t L, uint32_t lane) {
+    uint32_t x[E];
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+        const uint32_t i = r * 64u + lane;
+        x[r] = i < L ? in[a + i] : kEmpty;
+    }
+    wave_bitonic<E>(x, lane);
+    bool dup = false;
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+        const uint32_t i = r * 64u + lane;
+        uint32_t prev = __shfl_up(x[r], 1, 64);
+        if (r > 0) {
+            const uint32_t last = __shfl(x[r > 0 ? r - 1 : 0], 63, 64);
+            if (lane == 0) prev = last;
+        }
+        if (i < L) {
+            out[a + i] = x[r];
+            if (i > 0 && (prev >> 1) == (x[r] >> 1)) dup = true;
+        }
+    }
+    return dup;
+}
+
+__global__ __launch_bounds__(256) void k_sort_wave(const uint32_t* __restrict__ row_ptr,
+                                                  const uint32_t* __restrict__ in,
+                                                  uint32_t* __restrict__ out, Dims d,
+                                                  Control* ctl) {
+    const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
+    uint32_t lo0, hi0, lo1, hi1;
+    class_range(ctl, d, 0, 5, 5, &lo0, &hi0);
+    class_range(ctl, d, 1, 5, 5, &lo1, &hi1);
+    const uint32_t n0 = hi0 - lo0, tot = n0 + (hi1 - lo1);
+    bool dup = false;
+    for (uint32_t q = blockIdx.x * 4 + wave; q < tot; q += gridDim.x * 4) {
+        const uint32_t r = row_at(d, q < n0 ? lo0 + q : lo1 + (q - n0));
+        const uint32_t a = row_ptr[r], L = row_ptr[r + 1] - a;
+        if (L > kWaveRowMax) continue;  // k_sort_block sorts this row
+        uint32_t elo, ehi;
+        entry_range(d, r, &elo, &ehi);
+        if (ehi - elo <= kMidBits) continue;  // k_sort_mid_bitmap sorts this row
+        dup |= L <= 128 ? wave_sort_row<2>(in, out, a, L, lane) : wave_sort_row<4>(in, out, a, L, lane);
+    }
+    if (dup) atomicOr(&ctl->dup, 1u);
+}
+
+// rows with kWaveRowMax < len <= 4096 whose entries span more than kMidBits
+// indices: one workgroup per row, bitonic sort in LDS.
 
 __global__ __launch_bounds__(256) void k_sort_block(const uint32_t* __restrict__ row_ptr,
                                                    const uint32_t* __restrict__ in,
@@ -519,6 +605,7 @@ __global__ __launch_bounds__(256) void k_sort_block(const uint32_t* __restrict__
     for (uint32_t q = blockIdx.x; q < tot; q += gridDim.x) {
         uint32_t r = row_at(d, q < n0 ? lo0 + q : lo1 + (q - n0));
         uint32_t a = row_ptr[r], L = row_ptr[r + 1] - a;
+        if (L <= kWaveRowMax) continue;  // k_sort_wave or k_sort_mid_bitmap sorts this row
         uint32_t elo, ehi;
         entry_range(d, r, &elo, &ehi);
         if (ehi - elo <= kMidBits) continue;  // k_sort_mid_bitmap sorts this row
@@ -607,18 +694,28 @@ __global__ __launch_bounds__(kBigThreads) void k_sort_big(const uint32_t* __rest
         const uint32_t a = row_ptr[r], L = row_ptr[r + 1] - a;
         const uint32_t c0 = c * kBitmapChunk;
         uint32_t before = 0, inside = 0;  // entries below this chunk / in it (with repeats)
-        for (uint32_t e = tid; e < L; e += kBigThreads) {
-            uint32_t x = in[a + e];
-            uint32_t y = x >> 1;
-            if (y < c0) {
-                before++;
-            } else if (y - c0 < kBitmapChunk) {
-                inside++;
-                uint32_t bit = y - c0;
-                uint32_t m = 1u << (bit & 31);
-                uint32_t old = atomicOr(&bm[bit >> 5], m);
-                if (old & m) dup = true;
-                if (x & 1u) atomicOr(&sgn[bit >> 5], m);
+        constexpr int kLoads = 8;  // entries loaded together per thread
+        for (uint32_t e0 = 0; e0 < L; e0 += kLoads * kBigThreads) {
+            uint32_t xs[kLoads];
+#pragma unroll
+            for (int k = 0; k < kLoads; ++k) {
+                const uint32_t e = e0 + k * kBigThreads + tid;
+                xs[k] = e < L ? in[a + e] : 0u;
+            }
+#pragma unroll
+            for (int k = 0; k < kLoads; ++k) {
+                if (e0 + k * kBigThreads + tid >= L) continue;
+                const uint32_t x = xs[k], y = x >> 1;
+                if (y < c0) {
+                    before++;
+                } else if (y - c0 < kBitmapChunk) {
+                    inside++;
+                    const uint32_t bit = y - c0;
+                    const uint32_t m = 1u << (bit & 31);
+                    const uint32_t old = atomicOr(&bm[bit >> 5], m);
+                    if (old & m) dup = true;
+                    if (x & 1u) atomicOr(&sgn[bit >> 5], m);
+                }
             }
         }
         before = wave_reduce_sum(before);
@@ -898,6 +995,7 @@ hipError_t launch_row_sort(const uint32_t* rowdeg, const uint32_t* row_ptr, cons
                        row_ptr, in, out, d, ctl);
     hipLaunchKernelGGL(k_sort_mid_bitmap, dim3(num_cus * 8), dim3(256), 0, st, row_ptr, in, out, d,
                        ctl);
+    hipLaunchKernelGGL(k_sort_wave, dim3(num_cus * 8), dim3(256), 0, st, row_ptr, in, out, d, ctl);
     hipLaunchKernelGGL(k_sort_block, dim3(num_cus * 8), dim3(256), 0, st, row_ptr, in, out, d, ctl);
     hipLaunchKernelGGL(k_sort_big, dim3(num_cus * 2), dim3(kBigThreads), 0, st, row_ptr, in, out, d,
                        ctl);
