@@ -463,13 +463,23 @@ __global__ __launch_bounds__(256) void k_sort_mid_bitmap(const uint32_t* __restr
             sg[i] = 0;
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        for (uint32_t i = lane; i < L; i += 64) {
-            const uint32_t x = in[a + i];
-            const uint32_t y = (x >> 1) - elo;
-            if (y >= R) continue;  // cannot happen: entries lie in the block
-            const uint32_t msk = 1u << (y & 31);
-            if (atomicOr(&bm[y >> 5], msk) & msk) dup = true;
-            if (x & 1u) atomicOr(&sg[y >> 5], msk);
+        for (uint32_t i0 = 0; i0 < L; i0 += 4 * 64) {
+            uint32_t xs[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint32_t i = i0 + k * 64 + lane;
+                xs[k] = i < L ? in[a + i] : 0u;
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (i0 + k * 64 + lane >= L) continue;
+                const uint32_t x = xs[k];
+                const uint32_t y = (x >> 1) - elo;
+                if (y >= R) continue;  // cannot happen: entries lie in the block
+                const uint32_t msk = 1u << (y & 31);
+                if (atomicOr(&bm[y >> 5], msk) & msk) dup = true;
+                if (x & 1u) atomicOr(&sg[y >> 5], msk);
+            }
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         // lane owns words [w0, w1); emit in order after a wave scan of counts
@@ -508,7 +518,7 @@ __global__ __launch_bounds__(256) void k_sort_mid_bitmap(const uint32_t* __restr
 // row's entries l, 64 + l, ... (padded with kEmpty, above every entry); a
 // compare-exchange at distance j >= 64 stays in the lane, one at j < 64 takes a
 // shuffle.  No LDS and no barriers.
-constexpr uint32_t kWaveRowMax = 256;
+constexpr uint32_t kWaveRowMax = 1024;
 
 template <int E>
 __device__ inline void wave_bitonic(uint32_t (&x)[E], uint32_t lane) {
@@ -584,7 +594,14 @@ __global__ __launch_bounds__(256) void k_sort_wave(const uint32_t* __restrict__ 
         uint32_t elo, ehi;
         entry_range(d, r, &elo, &ehi);
         if (ehi - elo <= kMidBits) continue;  // k_sort_mid_bitmap sorts this row
-        dup |= L <= 128 ? wave_sort_row<2>(in, out, a, L, lane) : wave_sort_row<4>(in, out, a, L, lane);
+        if (L <= 128)
+            dup |= wave_sort_row<2>(in, out, a, L, lane);
+        else if (L <= 256)
+            dup |= wave_sort_row<4>(in, out, a, L, lane);
+        else if (L <= 512)
+            dup |= wave_sort_row<8>(in, out, a, L, lane);
+        else
+            dup |= wave_sort_row<16>(in, out, a, L, lane);
     }
     if (dup) atomicOr(&ctl->dup, 1u);
 }

@@ -360,13 +360,15 @@ def test_error_paths(ctx):
     dup = k._replace(eu=np.append(k.eu, np.int32(2)), ev=np.append(k.ev, np.int32(1234)),
                      sign=np.append(k.sign, np.int8(1)))
     assert _raw(ctx, dup)[0] == bbc.DUPLICATE_EDGE
-    # rows of 100, 200 and 1000 entries whose neighbours span more than 16384 ids
-    # (one-wave register sorts for up to 256 entries, the workgroup sort above):
-    # counted exactly, and a repeated pair in each is reported
-    wide = graph_from_edges(3, 40000, [[u, (i * 397 + u * 13) % 40000, 1 if (i + u) % 3 else -1]
-                                       for u, L in enumerate((100, 200, 1000)) for i in range(L)])
+    # rows of 100 to 2000 entries whose neighbours span more than 16384 ids
+    # (one-wave register sorts of 2, 4, 8 or 16 entries per lane up to 1024
+    # entries, the workgroup sort above): counted exactly, and a repeated pair in
+    # each is reported
+    wide = graph_from_edges(5, 40000, [[u, (i * 397 + u * 13) % 40000, 1 if (i + u) % 3 else -1]
+                                       for u, L in enumerate((100, 200, 400, 1000, 2000))
+                                       for i in range(L)])
     check(ctx, wide)
-    for row, i in ((0, 57), (1, 150), (2, 700)):
+    for row, i in ((0, 57), (1, 150), (2, 399), (3, 700), (4, 1999)):
         e = int(np.nonzero(wide.eu == row)[0][i])
         dup = wide._replace(eu=np.append(wide.eu, wide.eu[e]), ev=np.append(wide.ev, wide.ev[e]),
                             sign=np.append(wide.sign, np.int8(-wide.sign[e])))
