@@ -608,8 +608,9 @@ __global__ __launch_bounds__(256) void k_sort_wave(const uint32_t* __restrict__ 
 
 // rows with kWaveRowMax < len <= 4096 whose entries span more than kMidBits
 // indices: one workgroup per row, bitonic sort in LDS.
+constexpr int kBlockSortThreads = 1024;
 
-__global__ __launch_bounds__(256) void k_sort_block(const uint32_t* __restrict__ row_ptr,
+__global__ __launch_bounds__(kBlockSortThreads) void k_sort_block(const uint32_t* __restrict__ row_ptr,
                                                    const uint32_t* __restrict__ in,
                                                    uint32_t* __restrict__ out, Dims d,
                                                    Control* ctl) {
@@ -660,7 +661,7 @@ __global__ __launch_bounds__(256) void k_sort_block(const uint32_t* __restrict__
 // row's entries of the chunk in an LDS bitmap (plus a sign bitmap), then emit
 // the set bits in order.  Entries are distinct unless an edge is repeated,
 // which the bitmap detects.
-constexpr int kBigThreads = 512;
+constexpr int kBigThreads = 1024;
 constexpr uint32_t kBigWords = kBitmapChunk / 32;
 
 __device__ inline void big_pair(const Control* ctl, const Dims& d, uint32_t q, uint32_t* row,
@@ -1013,7 +1014,8 @@ hipError_t launch_row_sort(const uint32_t* rowdeg, const uint32_t* row_ptr, cons
     hipLaunchKernelGGL(k_sort_mid_bitmap, dim3(num_cus * 8), dim3(256), 0, st, row_ptr, in, out, d,
                        ctl);
     hipLaunchKernelGGL(k_sort_wave, dim3(num_cus * 8), dim3(256), 0, st, row_ptr, in, out, d, ctl);
-    hipLaunchKernelGGL(k_sort_block, dim3(num_cus * 8), dim3(256), 0, st, row_ptr, in, out, d, ctl);
+    hipLaunchKernelGGL(k_sort_block, dim3(num_cus * 2), dim3(kBlockSortThreads), 0, st, row_ptr, in,
+                       out, d, ctl);
     hipLaunchKernelGGL(k_sort_big, dim3(num_cus * 2), dim3(kBigThreads), 0, st, row_ptr, in, out, d,
                        ctl);
     return hipGetLastError();

@@ -1,7 +1,9 @@
 // Device-wide exclusive prefix sums (u32, u64) and fill/copy kernels.
 //
-// Three launches per scan: per-tile sums, one workgroup scanning the tile sums,
-// then the per-tile scan with its offset added.  out has n + 1 entries;
+// Per-tile sums, then the per-tile scan with its offset added.  With few tiles
+// (at most kScanFewTiles) each tile adds up the sums of the tiles before it
+// itself; with more, one workgroup scans the tile sums in between (three
+// launches).  out has n + 1 entries;
 // out[n] is the total.  Fills are plain kernels (no hipMemset) so that the
 // whole pipeline stays capturable in a HIP graph.
 #include "bbc_internal.h"
@@ -94,6 +96,34 @@ __global__ __launch_bounds__(kScanThreads) void k_tile_scan(const T* in, T* out,
     if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = *total;
 }
 
+// the per-tile scan, taking its offset as the sum of the earlier tiles' sums;
+// the last tile writes the total
+constexpr uint32_t kScanFewTiles = 1024;
+
+template <typename T>
+__global__ __launch_bounds__(kScanThreads) void k_tile_scan_few(const T* in, T* out, uint32_t n,
+                                                                const T* sums) {
+    __shared__ T s_wave[kScanThreads / 64];
+    const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
+    T pre = 0;
+    for (uint32_t i = threadIdx.x; i < blockIdx.x; i += kScanThreads) pre += sums[i];
+    T v[kScanItems];
+    T acc = 0;
+    const uint64_t my = base + (uint64_t)threadIdx.x * kScanItems;
+    for (int i = 0; i < kScanItems; ++i) {
+        v[i] = (my + i < n) ? in[my + i] : 0;
+        acc += v[i];
+    }
+    T off, tot;
+    block_excl_scan(pre, s_wave, &off);  // off: the sum of all earlier tiles
+    T run = block_excl_scan(acc, s_wave, &tot) + off;
+    for (int i = 0; i < kScanItems; ++i) {
+        if (my + i < n) out[my + i] = run;
+        run += v[i];
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = off + tot;
+}
+
 size_t scan_tmp_bytes(uint32_t n) {
     size_t nb = (size_t)(n + kScanTile - 1) / kScanTile + 1;
     return (nb + 2) * sizeof(u64) + 256;
@@ -108,6 +138,11 @@ static hipError_t scan_impl(const T* in, T* out, uint32_t n, void* tmp, size_t t
     T* sums = (T*)tmp;
     T* total = sums + nb;
     hipLaunchKernelGGL(k_tile_sums<T>, dim3(nb), dim3(kScanThreads), 0, st, in, n, sums);
+    if (nb <= kScanFewTiles) {
+        hipLaunchKernelGGL(k_tile_scan_few<T>, dim3(nb), dim3(kScanThreads), 0, st, in, out, n,
+                           (const T*)sums);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_scan_sums<T>, dim3(1), dim3(1024), 0, st, sums, nb, total);
     hipLaunchKernelGGL(k_tile_scan<T>, dim3(nb), dim3(kScanThreads), 0, st, in, out, n,
                        (const T*)sums, (const T*)total);
