@@ -227,9 +227,11 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
     __shared__ uint32_t s_batch;
     __shared__ uint32_t s_wadj[kWaves][64];   // per wave: compacted sub-intervals' address - start,
     __shared__ uint32_t s_waux[kWaves][64];   // sign(u,v) | filter << 1 | piece << 2,
-    // head flags of the current kUnroll windows, interleaved: the flag of window
-    // position p is byte (p % 64) * kUnroll + p / 64, so a lane reads its flags
-    // for all windows in one 32-bit word
+    // head flags of the current kUnroll windows (one byte per position).  The
+    // plain count interleaves them: the flag of window position p is byte
+    // (p % 64) * kUnroll + p / 64, so a lane reads its flags for all windows in
+    // one 32-bit word.  Per-vertex mode, whose readback keeps more registers
+    // live, reads them window by window (byte p), which measured faster there.
     __shared__ uint32_t s_head[kWaves][64];
     static_assert(kUnroll == 4, "one 32-bit word of head flags per lane");
     constexpr uint32_t kQ = PV ? 1 : kQueue;
@@ -436,31 +438,51 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
                 uint32_t before = 0;
                 const u64 le_mask = ~0ull >> (63 - lane);  // lanes 0..lane
                 for (uint32_t j = 0; j < T && ok; j += 64 * kUnroll) {
+                    uint8_t* hb = (uint8_t*)s_head[wave];
                     if (len > 0 && excl >= j && excl < j + 64 * kUnroll) {
                         const uint32_t hp = excl - j;
-                        ((uint8_t*)s_head[wave])[(hp & 63u) * kUnroll + (hp >> 6)] = 1;
+                        hb[PV ? hp : (hp & 63u) * kUnroll + (hp >> 6)] = 1;
                     }
                     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                    const uint32_t hd4 = s_head[wave][lane];
-                    uint32_t x[kUnroll], aux[kUnroll], adj[kUnroll], own[PV ? kUnroll : 1];
-                    // owners and their interval entries for all windows first (the
-                    // LDS reads are waited for together), then the CSR loads
+                    uint32_t x[kUnroll], aux[kUnroll], own[PV ? kUnroll : 1];
+                    if constexpr (PV) {
 #pragma unroll
-                    for (uint32_t u = 0; u < kUnroll; ++u) {
-                        const u64 M = __ballot(((hd4 >> (8 * u)) & 0xFFu) != 0);
-                        const uint32_t idx = before + (uint32_t)__popcll(M & le_mask) - 1u;
-                        before += (uint32_t)__popcll(M);
-                        const bool in = j + u * 64 + lane < T;
-                        const uint32_t ii = in ? idx : 0u;  // a filled entry either way
-                        aux[u] = in ? s_waux[wave][ii] : kEmpty;
-                        adj[u] = s_wadj[wave][ii];
-                        if (PV) own[PV ? u : 0] = in ? idx : kEmpty;
-                    }
+                        for (uint32_t u = 0; u < kUnroll; ++u) {
+                            const u64 M = __ballot(hb[u * 64 + lane] != 0);
+                            const uint32_t idx = before + (uint32_t)__popcll(M & le_mask) - 1u;
+                            before += (uint32_t)__popcll(M);
+                            const uint32_t q = j + u * 64 + lane;
+                            aux[u] = kEmpty;
+                            x[u] = 0;
+                            own[PV ? u : 0] = kEmpty;
+                            if (q < T) {
+                                aux[u] = s_waux[wave][idx];
+                                x[u] = col[s_wadj[wave][idx] + q];
+                                own[PV ? u : 0] = idx;
+                            }
+                        }
+                    } else {
+                        // owners and their interval entries for all windows first (the
+                        // LDS reads are waited for together), then the CSR loads
+                        const uint32_t hd4 = s_head[wave][lane];
+                        uint32_t adj[kUnroll];
 #pragma unroll
-                    for (uint32_t u = 0; u < kUnroll; ++u) {
-                        const uint32_t q = j + u * 64 + lane;
-                        x[u] = q < T ? col[adj[u] + q] : 0u;
+                        for (uint32_t u = 0; u < kUnroll; ++u) {
+                            const u64 M = __ballot(((hd4 >> (8 * u)) & 0xFFu) != 0);
+                            const uint32_t idx = before + (uint32_t)__popcll(M & le_mask) - 1u;
+                            before += (uint32_t)__popcll(M);
+                            const bool in = j + u * 64 + lane < T;
+                            const uint32_t ii = in ? idx : 0u;  // a filled entry either way
+                            aux[u] = in ? s_waux[wave][ii] : kEmpty;
+                            adj[u] = s_wadj[wave][ii];
+                        }
+#pragma unroll
+                        for (uint32_t u = 0; u < kUnroll; ++u) {
+                            const uint32_t q = j + u * 64 + lane;
+                            x[u] = q < T ? col[adj[u] + q] : 0u;
+                        }
                     }
+                    // the wave's flags are cleared (all 4 * 64 bytes, either layout)
                     s_head[wave][lane] = 0;
                     if (PV && readback) {
                         // each wedge's share, summed per interval over the lanes
