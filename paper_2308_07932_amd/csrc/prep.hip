@@ -520,34 +520,51 @@ __global__ __launch_bounds__(256) void k_sort_mid_bitmap(const uint32_t* __restr
 // shuffle.  No LDS and no barriers.
 constexpr uint32_t kWaveRowMax = 1024;
 
+// One compare-exchange step of a bitonic network (block size k, distance j)
+// over the wave's 64 * E entries, which are entries gbase + r * 64 + lane of
+// the whole sequence (so the direction follows the global index).
 template <int E>
-__device__ inline void wave_bitonic(uint32_t (&x)[E], uint32_t lane) {
+__device__ inline void wave_bitonic_step(uint32_t (&x)[E], uint32_t lane, uint32_t gbase,
+                                         uint32_t k, uint32_t j) {
+    if (j >= 64) {
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+            const int r2 = r ^ (int)(j >> 6);
+            if (r2 > r) {
+                const bool asc = ((gbase + r * 64u + lane) & k) == 0;
+                const uint32_t lo = min(x[r], x[r2]), hi = max(x[r], x[r2]);
+                x[r] = asc ? lo : hi;
+                x[r2] = asc ? hi : lo;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+            const uint32_t o = __shfl_xor(x[r], (int)j, 64);
+            const bool asc = ((gbase + r * 64u + lane) & k) == 0;
+            const bool low = (lane & j) == 0;
+            x[r] = (low == asc) ? min(x[r], o) : max(x[r], o);
+        }
+    }
+}
+
+// all blocks k <= 64 * E: sorts the wave's entries, ascending when gbase is
+// an even multiple of 64 * E, descending when an odd one
+template <int E>
+__device__ inline void wave_bitonic(uint32_t (&x)[E], uint32_t lane, uint32_t gbase = 0) {
 #pragma unroll
     for (uint32_t k = 2; k <= 64u * E; k <<= 1) {
 #pragma unroll
-        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-            if (j >= 64) {
-#pragma unroll
-                for (int r = 0; r < E; ++r) {
-                    const int r2 = r ^ (int)(j >> 6);
-                    if (r2 > r) {
-                        const bool asc = ((r * 64u + lane) & k) == 0;
-                        const uint32_t lo = min(x[r], x[r2]), hi = max(x[r], x[r2]);
-                        x[r] = asc ? lo : hi;
-                        x[r2] = asc ? hi : lo;
-                    }
-                }
-            } else {
-#pragma unroll
-                for (int r = 0; r < E; ++r) {
-                    const uint32_t o = __shfl_xor(x[r], (int)j, 64);
-                    const bool asc = ((r * 64u + lane) & k) == 0;
-                    const bool low = (lane & j) == 0;
-                    x[r] = (low == asc) ? min(x[r], o) : max(x[r], o);
-                }
-            }
-        }
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) wave_bitonic_step<E>(x, lane, gbase, k, j);
     }
+}
+
+// the steps of block size k (> 64 * E) with distance below 64 * E
+template <int E>
+__device__ inline void wave_bitonic_merge(uint32_t (&x)[E], uint32_t lane, uint32_t gbase,
+                                          uint32_t k) {
+#pragma unroll
+    for (uint32_t j = 32u * E; j > 0; j >>= 1) wave_bitonic_step<E>(x, lane, gbase, k, j);
 }
 
 template <int E>
@@ -607,14 +624,21 @@ __global__ __launch_bounds__(256) void k_sort_wave(const uint32_t* __restrict__ 
 }
 
 // rows with kWaveRowMax < len <= 4096 whose entries span more than kMidBits
-// indices: one workgroup per row, bitonic sort in LDS.
+// indices: one workgroup per row, a bitonic sort of P = 2^ceil(log2 len)
+// entries (padded with kEmpty).  Each wave holds a chunk of 256 entries in
+// registers for the steps of distance below 256 (first the whole chunk sort,
+// then after each block size's larger-distance steps, which run in LDS with a
+// barrier each): about 10 barriers per row instead of 78.
 constexpr int kBlockSortThreads = 1024;
+constexpr uint32_t kSortChunk = 256;  // 4 entries per lane
 
 __global__ __launch_bounds__(kBlockSortThreads) void k_sort_block(const uint32_t* __restrict__ row_ptr,
-                                                   const uint32_t* __restrict__ in,
-                                                   uint32_t* __restrict__ out, Dims d,
-                                                   Control* ctl) {
+                                                                  const uint32_t* __restrict__ in,
+                                                                  uint32_t* __restrict__ out, Dims d,
+                                                                  Control* ctl) {
+    static_assert(kBlockSortThreads / 64 * kSortChunk >= 4096, "a chunk per wave covers a row");
     __shared__ uint32_t s[4096];
+    const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
     uint32_t lo0, hi0, lo1, hi1;
     class_range(ctl, d, 0, 5, 5, &lo0, &hi0);
     class_range(ctl, d, 1, 5, 5, &lo1, &hi1);
@@ -627,30 +651,50 @@ __global__ __launch_bounds__(kBlockSortThreads) void k_sort_block(const uint32_t
         uint32_t elo, ehi;
         entry_range(d, r, &elo, &ehi);
         if (ehi - elo <= kMidBits) continue;  // k_sort_mid_bitmap sorts this row
-        uint32_t P = 1;
+        uint32_t P = kSortChunk;
         while (P < L) P <<= 1;
-        for (uint32_t i = threadIdx.x; i < P; i += blockDim.x) s[i] = i < L ? in[a + i] : kEmpty;
+        const bool mine = wave * kSortChunk < P;  // this wave holds a chunk
+        const uint32_t gbase = wave * kSortChunk;
+        uint32_t x[kSortChunk / 64];
+        if (mine) {
+#pragma unroll
+            for (int k = 0; k < (int)(kSortChunk / 64); ++k) {
+                const uint32_t i = gbase + k * 64u + lane;
+                x[k] = i < L ? in[a + i] : kEmpty;
+            }
+            wave_bitonic<kSortChunk / 64>(x, lane, gbase);
+#pragma unroll
+            for (int k = 0; k < (int)(kSortChunk / 64); ++k) s[gbase + k * 64u + lane] = x[k];
+        }
         __syncthreads();
-        for (uint32_t k = 2; k <= P; k <<= 1) {
-            for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-                for (uint32_t i = threadIdx.x; i < P; i += blockDim.x) {
-                    uint32_t ij = i ^ j;
+        for (uint32_t k = 2 * kSortChunk; k <= P; k <<= 1) {
+            for (uint32_t j = k >> 1; j >= kSortChunk; j >>= 1) {
+                for (uint32_t i = tid; i < P; i += kBlockSortThreads) {
+                    const uint32_t ij = i ^ j;
                     if (ij > i) {
-                        uint32_t x = s[i], y = s[ij];
-                        bool asc = (i & k) == 0;
-                        if ((x > y) == asc) {
-                            s[i] = y;
-                            s[ij] = x;
+                        const uint32_t xa = s[i], ya = s[ij];
+                        const bool asc = (i & k) == 0;
+                        if ((xa > ya) == asc) {
+                            s[i] = ya;
+                            s[ij] = xa;
                         }
                     }
                 }
                 __syncthreads();
             }
+            if (mine) {
+#pragma unroll
+                for (int kk = 0; kk < (int)(kSortChunk / 64); ++kk) x[kk] = s[gbase + kk * 64u + lane];
+                wave_bitonic_merge<kSortChunk / 64>(x, lane, gbase, k);
+#pragma unroll
+                for (int kk = 0; kk < (int)(kSortChunk / 64); ++kk) s[gbase + kk * 64u + lane] = x[kk];
+            }
+            __syncthreads();
         }
-        for (uint32_t i = threadIdx.x; i < L; i += blockDim.x) {
-            uint32_t x = s[i];
-            out[a + i] = x;
-            if (i > 0 && (s[i - 1] >> 1) == (x >> 1)) dup = true;
+        for (uint32_t i = tid; i < L; i += kBlockSortThreads) {
+            uint32_t v = s[i];
+            out[a + i] = v;
+            if (i > 0 && (s[i - 1] >> 1) == (v >> 1)) dup = true;
         }
         __syncthreads();
     }
