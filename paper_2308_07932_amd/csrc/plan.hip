@@ -316,6 +316,8 @@ __global__ void k_plan_write(const u64* __restrict__ wu, const uint32_t* __restr
 // every list entry, the row of the wedge's middle vertex.
 constexpr int kSwThreads = 256;
 constexpr uint32_t kSwWaves = kSwThreads / 64;
+// 512 table slots: a chunk of 256 records meets a few hundred pieces at most,
+// and the small table (14.6 KiB of LDS per workgroup) keeps 7-8 waves per SIMD
 constexpr uint32_t kSwLog2 = 9;
 constexpr uint32_t kSwSlots = 1u << kSwLog2;
 constexpr uint32_t kSwUnroll = 4;  // windows of 64 entries loaded together
