@@ -1057,9 +1057,15 @@ hipError_t launch_row_sort(const uint32_t* rowdeg, const uint32_t* row_ptr, cons
                        row_ptr, in, out, d, ctl);
     hipLaunchKernelGGL(k_sort_mid_bitmap, dim3(num_cus * 8), dim3(256), 0, st, row_ptr, in, out, d,
                        ctl);
-    hipLaunchKernelGGL(k_sort_wave, dim3(num_cus * 8), dim3(256), 0, st, row_ptr, in, out, d, ctl);
-    hipLaunchKernelGGL(k_sort_block, dim3(num_cus * 2), dim3(kBlockSortThreads), 0, st, row_ptr, in,
-                       out, d, ctl);
+    // a batch's graphs have at most kBatchSide <= kMidBits vertices per side, so
+    // the bitmap sort takes every medium row of a batch
+    static_assert(kBatchSide <= kMidBits, "batch rows are bitmap-sorted");
+    if (!d.blk[0]) {
+        hipLaunchKernelGGL(k_sort_wave, dim3(num_cus * 8), dim3(256), 0, st, row_ptr, in, out, d,
+                           ctl);
+        hipLaunchKernelGGL(k_sort_block, dim3(num_cus * 2), dim3(kBlockSortThreads), 0, st, row_ptr,
+                           in, out, d, ctl);
+    }
     hipLaunchKernelGGL(k_sort_big, dim3(num_cus * 2), dim3(kBigThreads), 0, st, row_ptr, in, out, d,
                        ctl);
     return hipGetLastError();
