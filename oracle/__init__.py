@@ -57,11 +57,12 @@ def _load():
         I32, I64, I = ctypes.c_int32, ctypes.c_int64, ctypes.c_int
         lib.bbo_brute_force.argtypes = [I32, I32, I64, P, P, P, P, P]
         lib.bbo_pairs.argtypes = [I32, I32, I64, P, P, P, I, I, P]
-        lib.bbo_pairs_rows.argtypes = [I32, I32, I64, P, P, P, I, I32, I32, P]
+        lib.bbo_pairs_rows.argtypes = [I32, I32, I64, P, P, P, I, I32, I32, I, P]
+        lib.bbo_bucket.argtypes = [I32, I32, I64, P, P, P, I, P]
         lib.bbo_per_vertex.argtypes = [I32, I32, I64, P, P, P, I, P]
         lib.bbo_wedges.argtypes = [I32, I32, I64, P, P, P, I, P]
         for f in (lib.bbo_brute_force, lib.bbo_pairs, lib.bbo_pairs_rows, lib.bbo_per_vertex,
-                  lib.bbo_wedges):
+                  lib.bbo_wedges, lib.bbo_bucket):
             f.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -105,12 +106,13 @@ def pair_count(g, side: int = 0, threads: int | None = None):
     return int(out[0]), int(out[1])
 
 
-def pair_count_rows(g, side: int, x0: int, x1: int):
-    """O1 restricted to rows [x0, x1) of one side, single thread (for timing a
-    bounded sample): (balanced, unbalanced) over pairs {x, z}, x0 <= x < x1, z > x."""
+def pair_count_rows(g, side: int, x0: int, x1: int, threads: int = 1):
+    """O1 restricted to rows [x0, x1) of one side (for timing a bounded sample):
+    (balanced, unbalanced) over pairs {x, z}, x0 <= x < x1, z > x.  The rows are
+    split over `threads` threads."""
     keep, a = _args(g)
     out = np.zeros(2, np.uint64)
-    _check(_load().bbo_pairs_rows(*a, int(side), int(x0), int(x1), out.ctypes.data))
+    _check(_load().bbo_pairs_rows(*a, int(side), int(x0), int(x1), int(threads), out.ctypes.data))
     del keep
     return int(out[0]), int(out[1])
 
@@ -132,6 +134,16 @@ def per_vertex(g, threads: int | None = None) -> np.ndarray:
     _check(_load().bbo_per_vertex(*a, int(threads or default_threads()), out.ctypes.data))
     del keep
     return out
+
+
+def bucket(g, threads: int | None = None):
+    """The bucket method on the CPU (Algorithm 2; starts in parallel as in
+    Algorithm 4): (balanced, unbalanced, W)."""
+    keep, a = _args(g)
+    out = np.zeros(3, np.uint64)
+    _check(_load().bbo_bucket(*a, int(threads or default_threads()), out.ctypes.data))
+    del keep
+    return int(out[0]), int(out[1]), int(out[2])
 
 
 def wedges(g, threads: int | None = None) -> int:

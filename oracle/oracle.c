@@ -31,6 +31,9 @@
  *                    (degree, then id; ids are global: U first, then V) -- the
  *                    number of innermost iterations of the bucket algorithm
  *                    (Algorithm 2, Section 4.1).
+ *   bbo_bucket       the bucket method itself (Algorithm 2 in the paper's
+ *                    order, starts in parallel as in Algorithm 4): balanced,
+ *                    unbalanced and W; a third route to the same totals.
  *
  * Every function validates its input like the library must: ids in range, sign
  * in {+1,-1}, no (u,v) pair twice (E is a set of pairs, Section 2).
@@ -262,10 +265,12 @@ int bbo_pairs(int32_t n_u, int32_t n_v, int64_t m, const int32_t* eu, const int3
 }
 
 /* Same as bbo_pairs but for a subset of the rows of side X only: rows
- * [x0, x1) each summed over their partners z > x.  Used to time a bounded
- * sample of the full computation. */
+ * [x0, x1) each summed over their partners z > x, split over nthreads threads.
+ * Summing the results of consecutive row blocks that cover the whole side
+ * gives bbo_pairs.  Used to time a bounded sample of the full computation. */
 int bbo_pairs_rows(int32_t n_u, int32_t n_v, int64_t m, const int32_t* eu, const int32_t* ev,
-                   const int8_t* sg, int side, int32_t x0, int32_t x1, uint64_t* out) {
+                   const int8_t* sg, int side, int32_t x0, int32_t x1, int nthreads,
+                   uint64_t* out) {
     int rc = check_input(n_u, n_v, m, eu, ev, sg);
     if (rc) return rc;
     adj_t au, av;
@@ -277,15 +282,31 @@ int bbo_pairs_rows(int32_t n_u, int32_t n_v, int64_t m, const int32_t* eu, const
     int32_t nx = side == 0 ? n_u : n_v;
     if (x0 < 0) x0 = 0;
     if (x1 > nx) x1 = nx;
-    pair_job j = {side == 0 ? &au : &av, side == 0 ? &av : &au, nx, x0, x1 < x0 ? x0 : x1, 0, 0, 0,
-                  NULL, 0};
-    pair_worker(&j);
+    if (x1 < x0) x1 = x0;
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > 256) nthreads = 256;
+    pair_job jobs[256];
+    pthread_t th[256];
+    int32_t per = (x1 - x0) / nthreads + 1;
+    for (int t = 0; t < nthreads; ++t) {
+        int64_t a = (int64_t)x0 + (int64_t)t * per, b = a + per;
+        jobs[t] = (pair_job){side == 0 ? &au : &av, side == 0 ? &av : &au, nx,
+                             (int32_t)(a > x1 ? x1 : a), (int32_t)(b > x1 ? x1 : b), 0, 0, 0, NULL, 0};
+        pthread_create(&th[t], NULL, pair_worker, &jobs[t]);
+    }
+    u128 bal = 0, unb = 0;
+    for (int t = 0; t < nthreads; ++t) {
+        pthread_join(th[t], NULL);
+        if (jobs[t].err) rc = jobs[t].err;
+        bal += jobs[t].bal;
+        unb += jobs[t].unb;
+    }
     adj_free(&au);
     adj_free(&av);
-    if (j.err) return j.err;
-    if ((j.bal >> 64) || (j.unb >> 64)) return BBO_ERR_OVERFLOW;
-    out[0] = (uint64_t)j.bal;
-    out[1] = (uint64_t)j.unb;
+    if (rc) return rc;
+    if ((bal >> 64) || (unb >> 64)) return BBO_ERR_OVERFLOW;
+    out[0] = (uint64_t)bal;
+    out[1] = (uint64_t)unb;
     return BBO_OK;
 }
 
@@ -386,4 +407,185 @@ int bbo_wedges(int32_t n_u, int32_t n_v, int64_t m, const int32_t* eu, const int
     free(nbr);
     *out_w = w;
     return BBO_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* The bucket method itself on the CPU (Section 4.1, Algorithm 2; run with
+ * the parallel loop over start vertices of Section 5.2, Algorithm 4).
+ *
+ * A third, independent way to the same totals, and the paper's own method
+ * timed on host cores.  Steps, in the paper's order:
+ *   1. the priority p(x) of every vertex: degree, then global id
+ *      (Definition 4; ids are U = 0..n_u-1, V = n_u..n-1);
+ *   2. every neighbour list sorted by ascending priority;
+ *   3. for every start u: for every neighbour v with p(v) < p(u) (a prefix of
+ *      the sorted list), for every neighbour w of v with p(w) < p(u) (a prefix
+ *      too), the wedge u-v-w goes to bucket B1[w] when sign(u,v) == sign(v,w)
+ *      (symmetric, Definition 5) and to B2[w] otherwise (asymmetric,
+ *      Definition 6);
+ *   4. then every touched w adds C(B1[w],2) + C(B2[w],2) balanced butterflies
+ *      (Lemma 2) and B1[w] * B2[w] unbalanced ones; the buckets are emptied
+ *      before the next start (they belong to one start; Algorithm 2 declares
+ *      them once, but a bucket shared by two starts would pair wedges with
+ *      different ends).
+ * out[0] = balanced, out[1] = unbalanced, out[2] = wedges enumerated (W).
+ * Threads take starts from a shared counter, a few at a time. */
+
+typedef struct {
+    const int64_t* off;  /* neighbour list of x: nbr[off[x] .. off[x+1]), by priority */
+    const int32_t* nbr;  /* neighbour ids (global) */
+    const int8_t* sgn;
+    const int32_t* prio; /* p(x) as a rank: 0 = lowest priority */
+    int32_t n;
+    int64_t* next;       /* shared: next start to take */
+    u128 bal, unb;
+    uint64_t w;
+    int err;
+} bucket_job;
+
+static const int32_t* g_sort_prio; /* comparator context (only set while sorting) */
+
+static int cmp_by_prio(const void* a, const void* b) {
+    int32_t x = g_sort_prio[((const int64_t*)a)[0]], y = g_sort_prio[((const int64_t*)b)[0]];
+    return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+static const int64_t* g_sort_deg;
+
+static int cmp_vertex_prio(const void* a, const void* b) {
+    int32_t x = *(const int32_t*)a, y = *(const int32_t*)b;
+    if (g_sort_deg[x] != g_sort_deg[y]) return g_sort_deg[x] < g_sort_deg[y] ? -1 : 1;
+    return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+static void* bucket_worker(void* arg) {
+    bucket_job* j = (bucket_job*)arg;
+    uint32_t* b1 = (uint32_t*)calloc((size_t)j->n + 1, sizeof(uint32_t));
+    uint32_t* b2 = (uint32_t*)calloc((size_t)j->n + 1, sizeof(uint32_t));
+    int32_t* touched = (int32_t*)malloc(((size_t)j->n + 1) * sizeof(int32_t));
+    if (!b1 || !b2 || !touched) {
+        j->err = BBO_ERR_OUT_OF_MEMORY;
+        free(b1);
+        free(b2);
+        free(touched);
+        return NULL;
+    }
+    for (;;) {
+        int64_t u0 = __atomic_fetch_add(j->next, 16, __ATOMIC_RELAXED);
+        if (u0 >= j->n) break;
+        int64_t u1 = u0 + 16 > j->n ? j->n : u0 + 16;
+        for (int32_t u = (int32_t)u0; u < (int32_t)u1; ++u) {
+            const int32_t pu = j->prio[u];
+            int32_t nt = 0;
+            for (int64_t e = j->off[u]; e < j->off[u + 1]; ++e) {
+                const int32_t v = j->nbr[e];
+                if (j->prio[v] >= pu) break; /* sorted: the rest rank higher */
+                for (int64_t f = j->off[v]; f < j->off[v + 1]; ++f) {
+                    const int32_t w = j->nbr[f];
+                    if (j->prio[w] >= pu) break;
+                    j->w++;
+                    if (b1[w] == 0 && b2[w] == 0) touched[nt++] = w;
+                    if (j->sgn[e] == j->sgn[f])
+                        b1[w]++;
+                    else
+                        b2[w]++;
+                }
+            }
+            for (int32_t i = 0; i < nt; ++i) {
+                const int32_t w = touched[i];
+                j->bal += (u128)choose2(b1[w]) + (u128)choose2(b2[w]);
+                j->unb += (u128)b1[w] * (u128)b2[w];
+                b1[w] = 0;
+                b2[w] = 0;
+            }
+        }
+    }
+    free(b1);
+    free(b2);
+    free(touched);
+    return NULL;
+}
+
+int bbo_bucket(int32_t n_u, int32_t n_v, int64_t m, const int32_t* eu, const int32_t* ev,
+               const int8_t* sg, int nthreads, uint64_t* out) {
+    int rc = check_input(n_u, n_v, m, eu, ev, sg);
+    if (rc) return rc;
+    const int32_t n = n_u + n_v;
+    int64_t* off = (int64_t*)calloc((size_t)n + 1, sizeof(int64_t));
+    int64_t* deg = (int64_t*)calloc((size_t)n + 1, sizeof(int64_t));
+    int64_t* fill = (int64_t*)calloc((size_t)n + 1, sizeof(int64_t));
+    int32_t* byprio = (int32_t*)malloc(((size_t)n + 1) * sizeof(int32_t));
+    int32_t* prio = (int32_t*)malloc(((size_t)n + 1) * sizeof(int32_t));
+    int64_t* tmp = (int64_t*)malloc((size_t)(2 * m + 1) * 2 * sizeof(int64_t));
+    int32_t* nbr = (int32_t*)malloc((size_t)(2 * m + 1) * sizeof(int32_t));
+    int8_t* sgn = (int8_t*)malloc((size_t)(2 * m + 1));
+    if (!off || !deg || !fill || !byprio || !prio || !tmp || !nbr || !sgn) {
+        rc = BBO_ERR_OUT_OF_MEMORY;
+        goto done;
+    }
+    /* 1. priorities: vertices in ascending (degree, id) order */
+    for (int64_t i = 0; i < m; ++i) {
+        deg[eu[i]]++;
+        deg[n_u + ev[i]]++;
+    }
+    for (int32_t x = 0; x < n; ++x) byprio[x] = x;
+    g_sort_deg = deg;
+    qsort(byprio, (size_t)n, sizeof(int32_t), cmp_vertex_prio);
+    for (int32_t r = 0; r < n; ++r) prio[byprio[r]] = r;
+    /* 2. neighbour lists (global ids), each sorted by ascending priority;
+     *    tmp holds (neighbour, edge index) pairs while sorting */
+    for (int32_t x = 0; x < n; ++x) off[x + 1] = off[x] + deg[x];
+    for (int64_t i = 0; i < m; ++i) {
+        const int32_t a = eu[i], b = n_u + ev[i];
+        int64_t at = off[a] + fill[a]++;
+        tmp[2 * at] = b;
+        tmp[2 * at + 1] = i;
+        at = off[b] + fill[b]++;
+        tmp[2 * at] = a;
+        tmp[2 * at + 1] = i;
+    }
+    g_sort_prio = prio;
+    for (int32_t x = 0; x < n; ++x)
+        qsort(tmp + 2 * off[x], (size_t)(off[x + 1] - off[x]), 2 * sizeof(int64_t), cmp_by_prio);
+    for (int64_t k = 0; k < 2 * m; ++k) {
+        nbr[k] = (int32_t)tmp[2 * k];
+        sgn[k] = sg[tmp[2 * k + 1]];
+    }
+    /* 3-4. the starts, in parallel */
+    {
+        if (nthreads < 1) nthreads = 1;
+        if (nthreads > 256) nthreads = 256;
+        bucket_job jobs[256];
+        pthread_t th[256];
+        int64_t next = 0;
+        for (int t = 0; t < nthreads; ++t) {
+            jobs[t] = (bucket_job){off, nbr, sgn, prio, n, &next, 0, 0, 0, 0};
+            pthread_create(&th[t], NULL, bucket_worker, &jobs[t]);
+        }
+        u128 bal = 0, unb = 0;
+        uint64_t w = 0;
+        for (int t = 0; t < nthreads; ++t) {
+            pthread_join(th[t], NULL);
+            if (jobs[t].err) rc = jobs[t].err;
+            bal += jobs[t].bal;
+            unb += jobs[t].unb;
+            w += jobs[t].w;
+        }
+        if (!rc && ((bal >> 64) || (unb >> 64))) rc = BBO_ERR_OVERFLOW;
+        if (!rc) {
+            out[0] = (uint64_t)bal;
+            out[1] = (uint64_t)unb;
+            out[2] = w;
+        }
+    }
+done:
+    free(off);
+    free(deg);
+    free(fill);
+    free(byprio);
+    free(prio);
+    free(tmp);
+    free(nbr);
+    free(sgn);
+    return rc;
 }

@@ -9,7 +9,10 @@ Each check is independent of the oracle's own formulas:
   * invariances of the definition (switching, negation, transpose, relabelling,
     disjoint union);
   * the priority-filtered wedge count W against a per-vertex degree formula;
-  * per-vertex counts against a pure-Python brute force and their sum rule.
+  * per-vertex counts against a pure-Python brute force and their sum rule;
+  * the row-range pair count against a pure-Python count of the butterflies
+    whose lower same-side vertex lies in the range, and its additivity;
+  * the CPU bucket method (Algorithm 2) against all of the above.
 """
 import itertools
 import json
@@ -42,7 +45,10 @@ def all_counts_agree(g):
     bu, uu = oracle.pair_count(g, 0, threads=2)
     bv, uv = oracle.pair_count(g, 1, threads=3)
     bg, ug = gram_count(g)
-    assert (bu, uu) == (bv, uv) == (bg, ug), (g.name, (bu, uu), (bv, uv), (bg, ug))
+    bb, ub, wb = oracle.bucket(g, threads=2)
+    assert (bu, uu) == (bv, uv) == (bg, ug) == (bb, ub), (g.name, (bu, uu), (bv, uv), (bg, ug),
+                                                          (bb, ub))
+    assert wb == oracle.wedges(g, threads=1), g.name
     assert bu == b0 and bu + uu == t0, (g.name, b0, t0, bu, uu)
     return b0, t0
 
@@ -268,3 +274,61 @@ def test_workload_sizes_and_closed_form():
     b, u = oracle.count(g)
     assert abs(b / (b + u) - 0.5128) < 0.03
     assert math.isfinite(b)
+
+
+def butterflies_by_low_vertex(g, side, x0, x1):
+    """Pure Python, from Definitions 1-2: (balanced, unbalanced) butterflies
+    whose lower-id vertex on `side` lies in [x0, x1)."""
+    sgn = {}
+    for u, v, s in zip(g.eu.tolist(), g.ev.tolist(), g.sign.tolist()):
+        sgn[(u, v) if side == 0 else (v, u)] = s
+    nx, ny = (g.n_u, g.n_v) if side == 0 else (g.n_v, g.n_u)
+    bal = unb = 0
+    for x in range(max(0, x0), min(nx, x1)):
+        for z in range(x + 1, nx):
+            for y1 in range(ny):
+                for y2 in range(y1 + 1, ny):
+                    e = [sgn.get((x, y1)), sgn.get((x, y2)), sgn.get((z, y1)), sgn.get((z, y2))]
+                    if None in e:
+                        continue
+                    if e[0] * e[1] * e[2] * e[3] > 0:
+                        bal += 1
+                    else:
+                        unb += 1
+    return bal, unb
+
+
+def test_pair_count_rows_pins():
+    rng = np.random.default_rng(2024)
+    for _ in range(60):
+        nu, nv = int(rng.integers(1, 9)), int(rng.integers(1, 9))
+        g = gen.random_graph(rng, nu, nv, float(rng.uniform(0.3, 1.0)), float(rng.uniform(0, 1)))
+        for side in (0, 1):
+            nx = nu if side == 0 else nv
+            x0 = int(rng.integers(0, nx + 1))
+            x1 = int(rng.integers(x0, nx + 2))
+            got = oracle.pair_count_rows(g, side, x0, x1, threads=int(rng.integers(1, 4)))
+            assert got == butterflies_by_low_vertex(g, side, x0, x1), (g.name, side, x0, x1)
+
+
+def test_pair_count_rows_blocks_add_up():
+    rng = np.random.default_rng(77)
+    for nu, nv, m in [(300, 200, 6000), (40, 900, 9000), (1000, 50, 8000)]:
+        g = gen.uniform_graph(seed=int(rng.integers(1 << 30)), n_u=nu, n_v=nv, n_edges=m, p_neg=0.4)
+        for side in (0, 1):
+            nx = nu if side == 0 else nv
+            cuts = sorted(int(c) for c in rng.integers(0, nx + 1, size=3))
+            parts = [oracle.pair_count_rows(g, side, a, b, threads=3)
+                     for a, b in zip([0] + cuts, cuts + [nx])]
+            assert tuple(map(sum, zip(*parts))) == oracle.pair_count(g, side), (g.name, side, cuts)
+            assert oracle.pair_count_rows(g, side, 0, nx, threads=1) == oracle.pair_count(g, side)
+
+
+def test_bucket_method_on_larger_graphs():
+    # the paper's method on the CPU against the pair enumeration and W
+    for g in [gen.uniform_graph(seed=5, n_u=700, n_v=400, n_edges=12000, p_neg=0.3),
+              gen.uniform_graph(seed=6, n_u=30, n_v=3000, n_edges=40000, p_neg=0.45)]:
+        b, u, w = oracle.bucket(g, threads=4)
+        assert (b, u) == oracle.count(g)
+        assert w == oracle.wedges(g) == wedge_count_by_degrees(g)
+        assert oracle.bucket(g, threads=1) == (b, u, w)
