@@ -944,12 +944,13 @@ static bbc_status count_union(bbc_context* c, const std::vector<uint32_t>& all, 
         // host-side metadata of the included graphs
         std::vector<u64> src_off(G);
         std::vector<uint32_t> dst_off(G + 1), gnu(G), gnv(G), uoff(G + 1), voff(G + 1);
-        const int64_t e0 = off[gl.front()], e1 = off[gl.back() + 1];  // source edge range
         uint32_t max_side = 1;
         dst_off[0] = uoff[0] = voff[0] = 0;
         for (uint32_t j = 0; j < G; ++j) {
             const uint32_t g = gl[j];
-            src_off[j] = (u64)(off[g] - (on_device ? 0 : e0));
+            // host input is copied packed (graph j's edges at dst_off[j]), so
+            // graphs counted elsewhere are never copied
+            src_off[j] = on_device ? (u64)off[g] : (u64)dst_off[j];
             gnu[j] = (uint32_t)n_u[g];
             gnv[j] = (uint32_t)n_v[g];
             dst_off[j + 1] = dst_off[j] + (uint32_t)(off[g + 1] - off[g]);
@@ -959,7 +960,7 @@ static bbc_status count_union(bbc_context* c, const std::vector<uint32_t>& all, 
         }
         const uint64_t m = dst_off[G];
         const uint32_t nu = uoff[G], nv = voff[G];
-        const uint64_t src_m = on_device ? 0 : (uint64_t)(e1 - e0);
+        const uint64_t src_m = on_device ? 0 : m;
         // workspace: metadata, union edges, source copy, per-graph results
         struct {
             u64 *src_off, *gres, *gerr;
@@ -1001,9 +1002,19 @@ static bbc_status count_union(bbc_context* c, const std::vector<uint32_t>& all, 
         const int32_t* sv = edge_v;
         const int8_t* ss = edge_sign;
         if (!on_device) {
-            HIPCHECK(c, hipMemcpyAsync(w.su, edge_u + e0, 4 * src_m, hipMemcpyHostToDevice, st));
-            HIPCHECK(c, hipMemcpyAsync(w.sv, edge_v + e0, 4 * src_m, hipMemcpyHostToDevice, st));
-            HIPCHECK(c, hipMemcpyAsync(w.ss, edge_sign + e0, src_m, hipMemcpyHostToDevice, st));
+            // one copy per run of graphs whose edges follow each other in the input
+            for (uint32_t j = 0; j < G;) {
+                uint32_t k = j + 1;
+                while (k < G && off[gl[k]] == off[gl[k - 1] + 1]) ++k;
+                const int64_t e0 = off[gl[j]];
+                const uint64_t d0 = dst_off[j], len = dst_off[k] - dst_off[j];
+                if (len > 0) {
+                    HIPCHECK(c, hipMemcpyAsync(w.su + d0, edge_u + e0, 4 * len, hipMemcpyHostToDevice, st));
+                    HIPCHECK(c, hipMemcpyAsync(w.sv + d0, edge_v + e0, 4 * len, hipMemcpyHostToDevice, st));
+                    HIPCHECK(c, hipMemcpyAsync(w.ss + d0, edge_sign + e0, len, hipMemcpyHostToDevice, st));
+                }
+                j = k;
+            }
             su = w.su;
             sv = w.sv;
             ss = w.ss;

@@ -19,9 +19,12 @@
 namespace bbc {
 
 
-// An edge that fails the checks is still written in range (id 0 of its graph,
-// sign +1) so that the rest of the pipeline stays within its buffers; its
-// graph is reported and left out of the redo.
+// An edge whose ids are out of range is written with u = -1, so that the
+// degree and scatter passes drop it (their own range check fails) instead of
+// placing it in another graph's id block (a graph with no vertex on a side
+// shares its block start with the next graph); an edge with a bad sign keeps
+// its in-range ids with sign +1.  Either way its graph is reported and left
+// out of the redo, and the other graphs' rows never see the edge.
 __global__ void k_ingest(IngestArgs a) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.m;
          i += (uint64_t)gridDim.x * blockDim.x) {
@@ -31,10 +34,10 @@ __global__ void k_ingest(IngestArgs a) {
         int32_t u = a.src_u[src], v = a.src_v[src];
         int8_t s = a.src_s[src];
         u64 code = 0;
+        bool drop = false;
         if (u < 0 || v < 0 || (uint32_t)u >= a.gnu[j] || (uint32_t)v >= a.gnv[j]) {
             code = kErrRange;
-            u = 0;
-            v = 0;
+            drop = true;
         } else if (s != 1 && s != -1) {
             code = kErrSign;
             s = 1;
@@ -43,8 +46,8 @@ __global__ void k_ingest(IngestArgs a) {
             atomicMin(&a.gerr[j], (e << 4) | code);
             atomicMin(&a.ctl->edge_err, code);
         }
-        a.eu[i] = (int32_t)(a.uoff[j] + (uint32_t)u);
-        a.ev[i] = (int32_t)(a.voff[j] + (uint32_t)v);
+        a.eu[i] = drop ? -1 : (int32_t)(a.uoff[j] + (uint32_t)u);
+        a.ev[i] = drop ? 0 : (int32_t)(a.voff[j] + (uint32_t)v);
         a.sg[i] = s;
     }
 }
@@ -55,8 +58,8 @@ __global__ void k_batch_keys(const uint32_t* __restrict__ deg, Dims d, uint32_t 
     for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < d.n; x += gridDim.x * blockDim.x) {
         const uint32_t side = x >= d.n_u ? 1u : 0u;
         const uint32_t g = block_of(d.blk[side], d.n_graphs, x - d.base[side]);
-        // a graph with bad edges (written as placeholders) may exceed the bound;
-        // its counts are discarded, so clamping only keeps its key in range
+        // a graph with repeated pairs may exceed the bound; its counts are
+        // discarded, so clamping only keeps its key in range
         key[x] = (g << deg_bits) | min(deg[x], (1u << deg_bits) - 1u);
     }
 }

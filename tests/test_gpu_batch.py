@@ -135,6 +135,27 @@ def test_batch_isolates_invalid_graphs(ctx):
     assert res.status[3] == bbc.INVALID_ARG and res.status[0] == bbc.OK
 
 
+def test_batch_empty_side_with_edges(ctx):
+    # A graph with no vertex on one side shares its id block start with the
+    # next graph, so its (necessarily out-of-range) edges must be dropped, not
+    # placed: its neighbours (rows longer than 64 entries) stay exact.
+    rng = np.random.default_rng(77)
+    dense = [gen.random_graph(rng, 90, 120, 0.7, p_neg=0.4) for _ in range(3)]
+    no_v = SignedBipartiteGraph(5, 0, np.array([0, 1, 2], np.int32), np.array([0, 0, 1], np.int32),
+                                np.array([1, -1, 1], np.int8), "no_v")
+    no_u = SignedBipartiteGraph(0, 80, np.zeros(70, np.int32), np.arange(70, dtype=np.int32),
+                                rng.choice([1, -1], 70).astype(np.int8), "no_u")
+    graphs = [no_v, dense[0], no_u, dense[1], no_v, no_u, dense[2]]
+    res = run_batch(ctx, graphs)
+    for i, g in enumerate(graphs):
+        if g.name in ("no_v", "no_u"):
+            assert res.status[i] == bbc.VERTEX_RANGE, (i, res.status[i])
+            assert res.result(i) == bbc.Result(0, 0, 0)
+        else:
+            assert res.status[i] == bbc.OK, (i, res.status[i])
+            assert res.result(i) == expect(g), (i, g.name)
+
+
 def test_batch_with_a_large_graph(ctx):
     # more than 16384 vertices on a side: counted on its own inside the call
     big = gen.chung_lu_graph(seed=31, n_u=40000, n_v=9000, n_edges=150000, alpha=2.1, p_neg=0.3)
