@@ -101,6 +101,32 @@ bbc_status bbc_count(bbc_context* ctx, int32_t n_u, int32_t n_v, int64_t n_edges
                      uint32_t flags, bbc_result* out, int64_t* per_vertex);
 
 /*
+ * bbc_count without any allocation, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments, results and errors as bbc_count, with
+ * these limits:
+ *  - flags must hold BBC_INPUT_ON_DEVICE (device edge arrays), and
+ *    BBC_PER_VERTEX needs BBC_OUTPUT_ON_DEVICE (a caller's device buffer);
+ *    anything else is BBC_ERR_INVALID_ARG;
+ *  - the whole workspace comes from one static device array of
+ *    BBC_NOALLOC_SCRATCH_BYTES per device, which the library holds from its
+ *    first use on that device until the process ends; a graph whose workspace
+ *    does not fit gets BBC_ERR_TOO_LARGE (bbc_workspace_bytes estimates it;
+ *    about 2 million edges fit), with the outputs untouched;
+ *  - the call makes no hipMalloc / hipFree / hipHostMalloc and no host heap
+ *    allocation; HIP-graph replay (BBC_PARAM_GRAPHS) is not used for it.
+ * Every allocation-free call on one device uses the same array, whatever the
+ * context: calls that overlap in time on one device race and give wrong
+ * results, so they must be serialised by the caller.  The array keeps the
+ * last call's contents; the call clears whatever it needs.
+ */
+#define BBC_NOALLOC_SCRATCH_BYTES (256ull << 20)
+bbc_status bbc_count_noalloc(bbc_context* ctx, int32_t n_u, int32_t n_v, int64_t n_edges,
+                             const int32_t* edge_u, const int32_t* edge_v,
+                             const int8_t* edge_sign, uint32_t flags, bbc_result* out,
+                             int64_t* per_vertex);
+
+/*
  * Count many independent graphs in one call (the batched workload).
  *
  * Graph g has vertex sets {0..n_u[g]-1} and {0..n_v[g]-1} and the edges

@@ -49,6 +49,9 @@ PARAM_GRAPH_REPLAYS = 6
 
 PHASE_TOTAL, PHASE_PREP, PHASE_WEDGE, PHASE_PLAN = 0, 1, 2, 3
 
+# size of the static device scratch that bbc_count_noalloc works in (bbc.h)
+NOALLOC_SCRATCH_BYTES = 256 << 20
+
 
 class LibraryNotBuilt(ImportError):
     pass
@@ -111,6 +114,8 @@ def load_library():
     lib.bbc_set_param.restype = ctypes.c_int
     lib.bbc_get_param.argtypes = [P, ctypes.c_int, ctypes.POINTER(ctypes.c_int64)]
     lib.bbc_get_param.restype = ctypes.c_int
+    lib.bbc_count_noalloc.argtypes = [P, I32, I32, I64, P, P, P, U32, ctypes.POINTER(_CResult), P]
+    lib.bbc_count_noalloc.restype = ctypes.c_int
     lib.bbc_count_batch.argtypes = [P, I32, P, P, P, P, P, P, U32, P, P]
     lib.bbc_count_batch.restype = ctypes.c_int
     lib.bbc_autotune.argtypes = [P, I32, P, P, P, P, P, P, U32, I32,
@@ -279,6 +284,34 @@ class Context:
         r = self.count_raw(n_u, n_v, n, *ptrs, flags=flags, per_vertex_ptr=pv_ptr)
         del keep
         return (r, pv) if per_vertex else r
+
+    def count_noalloc(self, eu, ev, sign, n_u: int, n_v: int, per_vertex_out=None) -> Result:
+        """bbc_count_noalloc: the count without any allocation in the library.
+        eu, ev, sign are torch tensors on the context's device; per_vertex_out,
+        if given, is a caller-allocated int64 device tensor of n_u + n_v
+        entries that receives the per-vertex counts."""
+        ptrs, keep, on_dev, n = _prepare(eu, ev, sign)
+        if not on_dev:
+            raise ValueError("count_noalloc takes device tensors")
+        flags = INPUT_ON_DEVICE
+        pv_ptr = None
+        if per_vertex_out is not None:
+            if str(per_vertex_out.dtype) != "torch.int64" or not per_vertex_out.is_cuda or \
+                    int(per_vertex_out.numel()) != int(n_u) + int(n_v):
+                raise ValueError("per_vertex_out must be an int64 device tensor of n_u + n_v entries")
+            flags |= PER_VERTEX | OUTPUT_ON_DEVICE
+            pv_ptr = per_vertex_out.data_ptr()
+        import torch
+        cur = torch.cuda.current_stream(keep[0].device)
+        if self.stream is None or int(cur.cuda_stream) != int(self.stream):
+            cur.synchronize()
+        out = _CResult()
+        rc = self._lib.bbc_count_noalloc(self._h, int(n_u), int(n_v), int(n), *ptrs, int(flags),
+                                         ctypes.byref(out), pv_ptr)
+        del keep
+        if rc != OK:
+            raise BBCError(rc, self.last_error() or status_string(rc))
+        return Result(int(out.balanced), int(out.unbalanced), int(out.wedges))
 
     def autotune(self, n_u, n_v, edge_offset, eu, ev, sign, repeats: int = 2):
         """bbc_autotune on a batch (or one graph): returns ({chunk_wedges,

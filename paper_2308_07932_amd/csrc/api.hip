@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <mutex>
 #include <vector>
 
 #include "bbc.h"
@@ -98,6 +99,10 @@ struct bbc_context {
         hipGraphExec_t exec = nullptr;
     } seg[2];
     int64_t graph_captures = 0, graph_replays = 0;
+    // an allocation-free call carves its workspace from this device's static
+    // scratch array instead of the arenas (NULL: arenas)
+    char* fixed_base = nullptr;
+    size_t fixed_cap = 0, fixed_used = 0;
     char err[512] = {0};
 };
 
@@ -153,6 +158,53 @@ static bbc_status arena_reserve(bbc_context* c, Arena& a, size_t bytes) {
     a.base = (char*)p;
     a.cap = want;
     return BBC_OK;
+}
+
+// Workspace for one pipeline stage: the arena `a` grown to `bytes`, or, in an
+// allocation-free call, the next `bytes` of the fixed scratch (an error, never
+// an allocation, when it does not fit).
+static bbc_status workspace(bbc_context* c, Arena& a, size_t bytes, char** base) {
+    if (!c->fixed_base) {
+        bbc_status s = arena_reserve(c, a, bytes);
+        *base = a.base;
+        return s;
+    }
+    if (bytes > c->fixed_cap - c->fixed_used)
+        return fail(c, BBC_ERR_TOO_LARGE,
+                    "workspace of %zu bytes exceeds the %zu bytes of allocation-free scratch left",
+                    bytes, c->fixed_cap - c->fixed_used);
+    *base = c->fixed_base + c->fixed_used;
+    c->fixed_used += (bytes + 255) & ~(size_t)255;
+    return BBC_OK;
+}
+
+// The scratch of bbc_count_noalloc: one array per device, held for the life of
+// the process and shared by every allocation-free call on that device.  Host
+// code never uses the symbol itself as an address; it uses the device address
+// that hipGetSymbolAddress returns for the device (resolved once per device in
+// bbc_create, with the device current).
+static __device__ __align__(256) char scratch[BBC_NOALLOC_SCRATCH_BYTES];
+constexpr int kMaxDevices = 64;
+static char* g_scratch_ptr[kMaxDevices];
+static bool g_scratch_done[kMaxDevices];
+static std::mutex g_scratch_mu;
+
+static void resolve_scratch(int device) {
+    if (device < 0 || device >= kMaxDevices) return;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_done[device]) return;
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) == hipSuccess)
+        g_scratch_ptr[device] = (char*)p;
+    else
+        (void)hipGetLastError();  // left NULL: bbc_count_noalloc reports BBC_ERR_DEVICE
+    g_scratch_done[device] = true;
+}
+
+static char* scratch_ptr(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_ptr[device];
 }
 
 // Two-pass layout helper: first pass measures, second pass hands out pointers.
@@ -318,6 +370,7 @@ bbc_status bbc_create(int device, void* hip_stream, bbc_context** out) {
         return BBC_ERR_DEVICE;
     }
     c->host_ctl = (Control*)h;
+    resolve_scratch(device);  // the device is current
     for (int i = 0; i < kNumEv; ++i)
         if (hipEventCreate(&c->ev[i]) != hipSuccess) {
             bbc_destroy(c);
@@ -534,12 +587,13 @@ static bbc_status run_pipeline(bbc_context* c, const RunIn& in, RunOut& ro) {
 
     // ---- workspace
     PrepBufs b;
+    char* prep_base = nullptr;
     {
         Carver probe(nullptr);
         size_t need = carve_prep(probe, b, n, m, copy_in, tb_total);
-        bbc_status s = arena_reserve(c, c->prep, need);
+        bbc_status s = workspace(c, c->prep, need, &prep_base);
         if (s) return s;
-        Carver cv(c->prep.base);
+        Carver cv(prep_base);
         carve_prep(cv, b, n, m, copy_in, tb_total);
     }
     const int32_t* eu = in.eu;
@@ -560,15 +614,18 @@ static bbc_status run_pipeline(bbc_context* c, const RunIn& in, RunOut& ro) {
     const uint32_t g_bits = bt ? bitlen(bt->n_graphs - 1) : 0;
     if (bt && deg_bits + g_bits > 32)
         return fail(c, BBC_ERR_INTERNAL, "batch sort key needs %u bits", deg_bits + g_bits);
-    std::vector<uint64_t> keyA = {n, nu, nv, m, (uint64_t)eu, (uint64_t)ev, (uint64_t)sg,
-                                  (uint64_t)c->prep.base, tb_total, d.hash_target, d.probe_limit,
-                                  d.chunk_min, d.per_vertex, bt_on, deg_bits, g_bits};
-    if (bt) {
+    // replay keys (graph mode only: an allocation-free call builds none)
+    std::vector<uint64_t> keyA;
+    if (c->use_graphs)
+        keyA = {n, nu, nv, m, (uint64_t)eu, (uint64_t)ev, (uint64_t)sg,
+                (uint64_t)prep_base, tb_total, d.hash_target, d.probe_limit,
+                d.chunk_min, d.per_vertex, bt_on, deg_bits, g_bits};
+    if (bt && c->use_graphs) {
         for (uint64_t x : {(uint64_t)bt->n_graphs, (uint64_t)bt->blk[0], (uint64_t)bt->blk[1],
                            (uint64_t)bt->gres, (uint64_t)bt->gerr})
             keyA.push_back(x);
     }
-    if (in.ingest) {
+    if (in.ingest && c->use_graphs) {
         const IngestArgs& ia = *in.ingest;
         for (uint64_t x : {(uint64_t)ia.src_u, (uint64_t)ia.src_v, (uint64_t)ia.src_s,
                            (uint64_t)ia.src_off, (uint64_t)ia.dst_off, (uint64_t)ia.gnu,
@@ -702,6 +759,7 @@ static bbc_status run_pipeline(bbc_context* c, const RunIn& in, RunOut& ro) {
     u64 *pv = nullptr, *pv_out = nullptr;
     void* ortmp;
     const size_t ortmp_bytes = radix_tmp_bytes(n_heavy + 1);
+    char* plan_base = nullptr;
     {
         auto carve_plan = [&](Carver& cv) {
             pieces = cv.take<Piece>((size_t)n_heavy + n_light);
@@ -729,14 +787,16 @@ static bbc_status run_pipeline(bbc_context* c, const RunIn& in, RunOut& ro) {
         };
         Carver probe(nullptr);
         size_t need = carve_plan(probe);
-        bbc_status s = arena_reserve(c, c->plan, need);
+        bbc_status s = workspace(c, c->plan, need, &plan_base);
         if (s) return s;
-        Carver cv(c->plan.base);
+        Carver cv(plan_base);
         carve_plan(cv);
     }
-    std::vector<uint64_t> keyB = keyA;
+    std::vector<uint64_t> keyB;
+    if (c->use_graphs) keyB = keyA;
+    if (c->use_graphs)
     for (uint64_t x : {(uint64_t)n_heavy, (uint64_t)n_light, (uint64_t)n_light_items, (uint64_t)h.tot_g,
-                       (uint64_t)h.tot_sw, (uint64_t)h.tot_tiles, (uint64_t)c->plan.base, (uint64_t)first_long[0],
+                       (uint64_t)h.tot_sw, (uint64_t)h.tot_tiles, (uint64_t)plan_base, (uint64_t)first_long[0],
                        (uint64_t)first_long[1], (uint64_t)in.per_vertex, (uint64_t)in.pv_host})
         keyB.push_back(x);
     if (tm_out) HIPCHECK(c, hipEventRecord(c->ev[kEvPlanB], st));
@@ -918,6 +978,41 @@ bbc_status bbc_count(bbc_context* c, int32_t n_u, int32_t n_v, int64_t n_edges,
     out->unbalanced = (int64_t)h.unbalanced;
     out->wedges = (int64_t)h.wedges;
     return BBC_OK;
+}
+
+bbc_status bbc_count_noalloc(bbc_context* c, int32_t n_u, int32_t n_v, int64_t n_edges,
+                             const int32_t* edge_u, const int32_t* edge_v,
+                             const int8_t* edge_sign, uint32_t flags, bbc_result* out,
+                             int64_t* per_vertex) {
+    if (!c) return BBC_ERR_INVALID_ARG;
+    if (!(flags & BBC_INPUT_ON_DEVICE)) {
+        begin_call(c);
+        return fail(c, BBC_ERR_INVALID_ARG, "bbc_count_noalloc needs BBC_INPUT_ON_DEVICE");
+    }
+    if ((flags & BBC_PER_VERTEX) && !(flags & BBC_OUTPUT_ON_DEVICE)) {
+        begin_call(c);
+        return fail(c, BBC_ERR_INVALID_ARG,
+                    "bbc_count_noalloc: BBC_PER_VERTEX needs BBC_OUTPUT_ON_DEVICE");
+    }
+    char* base = scratch_ptr(c->device);
+    if (!base) {
+        begin_call(c);
+        return fail(c, BBC_ERR_DEVICE, "the allocation-free scratch of device %d has no address",
+                    c->device);
+    }
+    // the same pipeline as bbc_count, on the scratch and without graph replay
+    // (whose capture and key lists allocate)
+    c->fixed_base = base;
+    c->fixed_cap = BBC_NOALLOC_SCRATCH_BYTES;
+    c->fixed_used = 0;
+    const bool graphs = c->use_graphs;
+    c->use_graphs = false;
+    const bbc_status s = bbc_count(c, n_u, n_v, n_edges, edge_u, edge_v, edge_sign, flags, out,
+                                   per_vertex);
+    c->use_graphs = graphs;
+    c->fixed_base = nullptr;
+    c->fixed_cap = c->fixed_used = 0;
+    return s;
 }
 
 // ---------------------------------------------------------------------------

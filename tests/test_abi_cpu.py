@@ -115,3 +115,10 @@ def test_workspace_estimate():
     b = bbc.workspace_bytes(1000, 1000, 100000)
     c = bbc.workspace_bytes(100000, 1000, 100000)
     assert 0 < a < b < c
+
+
+def test_noalloc_scratch_size_matches_header():
+    text = open(bbc.HEADER_PATH).read()
+    m = re.search(r"#define\s+BBC_NOALLOC_SCRATCH_BYTES\s+\((\d+)ull\s*<<\s*(\d+)\)", text)
+    assert m, "BBC_NOALLOC_SCRATCH_BYTES not found in bbc.h"
+    assert int(m.group(1)) << int(m.group(2)) == bbc.NOALLOC_SCRATCH_BYTES
