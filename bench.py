@@ -56,44 +56,141 @@ def measured_traffic(workload: str):
     return d.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(g, W: int, budget_s: float):
-    """Time the CPU oracle (pair enumeration, one thread) on a bounded sample of
-    rows of side U and extrapolate to the whole graph by the exact inner-loop
-    count of each row (sum of the degrees of its neighbours)."""
+def host_threads() -> int:
+    """Threads the CPU baselines use: the host's cores, at most 16 (the share of
+    the host that goes with one GPU)."""
+    return max(1, min(os.cpu_count() or 1, 16))
+
+
+def cpu_baseline(g, W: int, budget_s: float, small: dict):
+    """The oracle timed on the host's cores.
+
+    value: the oracle's bucket route (Algorithm 2 in the paper's order, starts
+    in parallel as in Algorithm 4) over the whole power-law graph on all host
+    threads, W / its wall time (its own relabel and sort included): the same
+    wedges the GPU enumerates, so the two rates compare directly.  Beside it:
+    the bucket route on one thread and on all threads for the small graphs,
+    and the pair enumeration (what the parity tests trust) on all threads,
+    whole for the small graphs and over a bounded prefix of U rows of the
+    power-law graph, extrapolated by each row's exact inner-loop count."""
     import numpy as np
 
     import oracle
+    th = host_threads()
+    t0 = time.perf_counter()
+    b, u, w = oracle.bucket(g, threads=th)
+    t_bucket = time.perf_counter() - t0
+    assert w == W, (w, W)
+    small_runs = {}
+    for name, gs in small.items():
+        row = {}
+        for threads in (1, th):
+            t0 = time.perf_counter()
+            oracle.bucket(gs, threads=threads)
+            row[f"bucket_s_{threads}t"] = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        oracle.pair_count(gs, 0, threads=th)
+        row[f"pairs_u_side_s_{th}t"] = time.perf_counter() - t0
+        small_runs[name] = row
+    # pair enumeration over a bounded prefix of U rows, all threads
     deg_v = np.bincount(g.ev, minlength=g.n_v).astype(np.int64)
     row_cost = np.zeros(g.n_u, np.int64)
     np.add.at(row_cost, g.eu, deg_v[g.ev])
     total = int(row_cost.sum())
     csum = np.cumsum(row_cost)
     t0 = time.perf_counter()
-    oracle.pair_count_rows(g, 0, 0, 0)  # input check + adjacency build only
+    oracle.pair_count_rows(g, 0, 0, 0, threads=th)  # input check + adjacency build only
     setup = time.perf_counter() - t0
-    pilot_rows = int(np.searchsorted(csum, min(total, 3e7)))
+    pilot_rows = int(np.searchsorted(csum, min(total, 3e7 * th)))
     t0 = time.perf_counter()
-    oracle.pair_count_rows(g, 0, 0, pilot_rows)
+    oracle.pair_count_rows(g, 0, 0, pilot_rows, threads=th)
     tp = max(time.perf_counter() - t0 - setup, 1e-3)
     rate = csum[pilot_rows - 1] / tp if pilot_rows > 0 else 1e8
-    want = min(total, rate * budget_s)
-    rows = int(np.searchsorted(csum, want))
+    rows = int(np.searchsorted(csum, min(total, rate * budget_s)))
     rows = max(1, min(rows, g.n_u))
     t0 = time.perf_counter()
-    oracle.pair_count_rows(g, 0, 0, rows)
+    oracle.pair_count_rows(g, 0, 0, rows, threads=th)
     ts = time.perf_counter() - t0 - setup
     cost = int(csum[rows - 1])
     full_s = setup + ts * total / max(cost, 1)
+    log(f"cpu: bucket route {t_bucket:.2f} s on {th} threads (W/s {W / t_bucket:.3g}); pair "
+        f"enumeration est. {full_s:.1f} s on {th} threads")
     return {
-        "value": W / full_s,
+        "value": W / t_bucket,
         "unit": "wedges/s",
-        "cores": 1,
+        "cores": th,
         "kind": "oracle",
-        "sample": f"oracle pair enumeration over U rows 0..{rows - 1} of {g.n_u} "
-                  f"({cost:.3g} of {total:.3g} inner steps, {ts:.1f} s, 1 thread); "
-                  f"extrapolated full oracle time {full_s:.1f} s incl. {setup:.1f} s setup",
-        "oracle_full_seconds_est": full_s,
+        "sample": f"whole power-law graph: the oracle's bucket route (Algorithm 2, starts in "
+                  f"parallel as in Algorithm 4; its own relabel and sort included) on {th} threads, "
+                  f"{t_bucket:.2f} s for the same W the GPU enumerates",
+        "bucket_seconds": t_bucket,
+        "small_graphs": small_runs,
+        "pair_enumeration": {
+            "threads": th,
+            "sample": f"U rows 0..{rows - 1} of {g.n_u} ({cost:.3g} of {total:.3g} inner steps, "
+                      f"{ts:.1f} s)",
+            "full_seconds_est": full_s,
+            "note": "the pair enumeration does sum-of-degree-squared work, not W; its time is "
+                    "extrapolated from the sample by exact per-row step counts",
+        },
     }
+
+
+def bench_small(ctx, name: str, steps: int):
+    """Whole bbc_count calls on a small device-resident workload (uniform or
+    voting): time per call, the wedge kernel's HIP-event time, and its
+    roofline fraction (same algorithmic bytes as the power-law line)."""
+    import numpy as np
+    import torch
+
+    import gen
+    g = gen.workload(name)
+    dev = torch.device("cuda:0")
+    eu, ev, sg = (torch.from_numpy(x).to(dev) for x in (g.eu, g.ev, g.sign))
+    torch.cuda.synchronize()
+    for _ in range(5):
+        r = ctx.count(eu, ev, sg, g.n_u, g.n_v)
+    torch.cuda.synchronize()
+    phase = np.zeros(4)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r = ctx.count(eu, ev, sg, g.n_u, g.n_v)
+        for p in range(4):
+            phase[p] += ctx.phase_ms(p)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    phase /= steps
+    st = ctx.stats()
+    W, m, active = st[2], st[1], st[6]
+    alg = 4 * W + 16 * m + 16 * active
+    log(f"{name}: {ms:.3f} ms per call (wedge kernel {phase[2] * 1e3:.1f} us), W={W}")
+    return {"workload": WORKLOAD_DESC[name], "edges": g.n_edges, "wedges": W,
+            "balanced": r.balanced, "ms_per_call": ms, "wedges_per_s": W / (ms * 1e-3),
+            "phase_ms": {"prep": phase[1], "plan": phase[3], "wedge_kernel": phase[2]},
+            "wedge_kernel_roofline_frac": alg / (phase[2] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "algorithmic_bytes": alg, "steps": steps}
+
+
+def lds_atomic_peaks():
+    """Measured LDS atomic-add ceilings of the device (probe library): adds/s
+    for conflict-free u32, scattered u32 and scattered u64 adds."""
+    import ctypes
+    path = os.path.join(ROOT, "paper_2308_07932_amd", "libbbc_probe.so")
+    lib = ctypes.CDLL(path)
+    f = lib.bbc_probe_lds_atomics
+    f.argtypes = [ctypes.c_int] * 5 + [ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_ulonglong)]
+    f.restype = ctypes.c_int
+    out = {}
+    for pat, name in ((0, "u32_conflict_free"), (1, "u32_scattered"), (2, "u64_scattered")):
+        r, ms, chk = ctypes.c_double(), ctypes.c_double(), ctypes.c_ulonglong()
+        blocks, iters = 1024, 1024
+        rc = f(0, pat, blocks, iters, 3, ctypes.byref(r), ctypes.byref(ms), ctypes.byref(chk))
+        if rc != 0 or chk.value != blocks * 1024 * iters * 8:
+            raise RuntimeError(f"LDS probe pattern {pat} failed (rc {rc})")
+        out[name] = r.value
+    return out
 
 
 def bench_per_vertex(ctx, g, eu, ev, sg, r, steps: int):
@@ -340,9 +437,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="powerlaw", choices=sorted(WORKLOAD_DESC))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-per-vertex", action="store_true")
+    ap.add_argument("--no-small", action="store_true", help="skip the uniform and voting graphs")
     ap.add_argument("--batched-steps", type=int, default=3)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--only-batched", action="store_true",
@@ -437,6 +535,18 @@ def main():
                      "traffic": traffic, "kernel": "bbc::k_wedge",
                      "algorithmic_bytes_per_launch": alg_bytes},
     }
+    peaks = lds_atomic_peaks()
+    adds = W / (phase[2] * 1e-3)  # one LDS add per wedge
+    out["lds_atomics"] = {
+        "achieved_adds_per_s": adds,
+        "peak_adds_per_s": peaks,
+        "frac_of_u32_scattered": adds / peaks["u32_scattered"],
+        "probe": "1024 workgroups of 1024 threads, each with a 128 KiB LDS table, non-returning "
+                 "ds_add (libbbc_probe.so)",
+    }
+    log(f"LDS adds: achieved {adds:.3g}/s; probe peaks {peaks}")
+    if not args.no_small:
+        out["configs"] = {name: bench_small(ctx, name, 50) for name in ("uniform", "voting")}
     if not args.no_per_vertex:
         out["per_vertex"] = bench_per_vertex(ctx, g, eu, ev, sg, r, 5)
     if not args.no_batched:
@@ -446,7 +556,8 @@ def main():
                                            args.serving_requests, args.serving_load)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
-        out["cpu_baseline"] = cpu_baseline(g, W, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(g, W, args.cpu_seconds,
+                                           {n: gen.workload(n) for n in ("uniform", "voting")})
     print(json.dumps(out), flush=True)
     ctx.close()
 

@@ -9,6 +9,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbbc.so")
 SOURCES = ["scan.hip", "prep.hip", "plan.hip", "wedge.hip", "batch.hip", "api.hip", "server.hip"]
+# measurement only: the LDS-atomic throughput probe, a library of its own
+PROBE_LIB = os.path.join(HERE, "libbbc_probe.so")
+PROBE_SOURCES = ["probe_lds.hip"]
 ARCH = os.environ.get("BBC_OFFLOAD_ARCH", "gfx950")
 
 
@@ -28,7 +31,7 @@ def build(verbose: bool = False, jobs: int = 0) -> str:
              "-I", os.path.join(HERE, "..", "include")]
     procs = []
     objs = []
-    for s in SOURCES:
+    for s in SOURCES + PROBE_SOURCES:
         obj = os.path.join(objdir, s.replace(".hip", ".o"))
         objs.append(obj)
         cmd = [hipcc(), *flags, "-c", os.path.join(CSRC, s), "-o", obj]
@@ -46,12 +49,15 @@ def build(verbose: bool = False, jobs: int = 0) -> str:
             sys.stderr.write(text)
     if failed:
         raise RuntimeError(f"hipcc failed for {failed}")
-    tmp = LIB + ".tmp"
-    link = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-Wl,--no-undefined", *objs, "-o", tmp]
-    if verbose:
-        print(" ".join(link), flush=True)
-    subprocess.check_call(link)
-    os.replace(tmp, LIB)
+    for lib, srcs in ((LIB, SOURCES), (PROBE_LIB, PROBE_SOURCES)):
+        tmp = lib + ".tmp"
+        lobjs = [os.path.join(objdir, s.replace(".hip", ".o")) for s in srcs]
+        link = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-Wl,--no-undefined", *lobjs,
+                "-o", tmp]
+        if verbose:
+            print(" ".join(link), flush=True)
+        subprocess.check_call(link)
+        os.replace(tmp, lib)
     return LIB
 
 
