@@ -332,3 +332,27 @@ def test_bucket_method_on_larger_graphs():
         assert (b, u) == oracle.count(g)
         assert w == oracle.wedges(g) == wedge_count_by_degrees(g)
         assert oracle.bucket(g, threads=1) == (b, u, w)
+
+
+def test_batched_golden_rows_by_pair_enumeration():
+    # tests/golden/batched_counts.csv.gz stores the Gram closed form's counts
+    # for all 20,000 graphs of the batched workload; a seeded sample of rows is
+    # recomputed here by the pair enumeration on both sides (Lemma 2), and W by
+    # the explicit wedge enumeration, so the stored file is pinned by a route
+    # that shares nothing with the closed form
+    import gzip
+    path = os.path.join(os.path.dirname(__file__), "golden", "batched_counts.csv.gz")
+    with gzip.open(path, "rt") as f:
+        rows = [list(map(int, line.split(","))) for line in f
+                if not line.startswith("#") and not line.startswith("graph,")]
+    assert len(rows) == 20000
+    nu, nv, ne = gen.batch_graph_params(20000)
+    small = [r for r in rows if 0 < r[3] <= 30000]
+    rng = np.random.default_rng(2024)
+    for k in rng.choice(len(small), size=40, replace=False):
+        i, n_u, n_v, m, bal, unb, w = small[k]
+        assert (n_u, n_v, m) == (nu[i], nv[i], ne[i])
+        g = gen.batch_graph(i, nu[i], nv[i], ne[i])
+        assert oracle.count(g, threads=4) == (bal, unb), i
+        assert oracle.wedges(g, threads=4) == w, i
+    assert all(r[4] == r[5] == r[6] == 0 for r in rows if r[3] == 0)
