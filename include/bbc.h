@@ -182,11 +182,16 @@ int64_t bbc_workspace_bytes(int32_t n_u, int32_t n_v, int64_t n_edges);
  *   - larger jobs go to large_workers workers running bbc_count
  *     concurrently on their own streams, overlapping on the device with the
  *     batches.
- * Admission by device memory: a job reserves its footprint (its input plus
- * bbc_workspace_bytes) while it runs; a worker starts jobs only while the
- * reservations stay within memory_budget, and a job larger than the whole
- * budget finishes with BBC_ERR_OUT_OF_MEMORY.  Results are exact and do not
- * depend on what else runs.
+ * Admission by device memory: each worker reserves what its workspace really
+ * holds (its arenas stay allocated between jobs), and while it runs jobs the
+ * larger of that and their footprint (input plus bbc_workspace_bytes), with
+ * its workspace capped at that grant; a worker starts jobs only while the
+ * reservations stay within memory_budget.  A job whose workspace turns out
+ * larger than its estimate is queued again with the larger footprint; idle
+ * workers release their workspace while a job waits for memory; a job larger
+ * than the whole budget finishes with BBC_ERR_OUT_OF_MEMORY.  Device memory
+ * held by the workers' workspaces therefore stays within memory_budget.
+ * Results are exact and do not depend on what else runs.
  *
  * bbc_server_create: cfg may be NULL for defaults (device 0, 2 large workers,
  * budget 90% of the device memory free at creation, small_side 16384,
@@ -200,10 +205,11 @@ int64_t bbc_workspace_bytes(int32_t n_u, int32_t n_v, int64_t n_edges);
  * *job_status (the bbc_status of the count) and *latency_ms (submission to
  * completion; may be NULL) filled in, after which the ticket is released.
  * INVALID_ARG for an unknown ticket.
- * bbc_server_stats: up to 10 values: [0] jobs submitted, [1] completed,
+ * bbc_server_stats: up to 12 values: [0] jobs submitted, [1] completed,
  * [2] batches run, [3] jobs counted in batches, [4] largest batch, [5] peak
  * reserved bytes, [6] peak jobs running at once, [7] memory budget, [8] jobs
- * waiting now, [9] bytes reserved now.
+ * waiting now, [9] bytes reserved now, [10] workspace releases, [11] jobs
+ * queued again after outgrowing their estimate.
  * bbc_server_destroy: finishes every submitted job, then releases the server
  * (results not polled are dropped).  NULL is a no-op.
  * One server may be used from several threads at once.

@@ -453,10 +453,10 @@ class Server:
                                                int(out.wedges)), float(lat.value))
 
     def stats(self) -> dict:
-        a = (ctypes.c_int64 * 10)()
-        self._lib.bbc_server_stats(self._h, a, 10)
+        a = (ctypes.c_int64 * 12)()
+        self._lib.bbc_server_stats(self._h, a, 12)
         keys = ("submitted", "completed", "batches", "batched_jobs", "max_batch", "peak_reserved",
-                "peak_running", "budget", "waiting", "reserved")
+                "peak_running", "budget", "waiting", "reserved", "trims", "retries")
         return dict(zip(keys, (int(x) for x in a)))
 
     def close(self):

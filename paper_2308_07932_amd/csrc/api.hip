@@ -103,6 +103,7 @@ struct bbc_context {
     // scratch array instead of the arenas (NULL: arenas)
     char* fixed_base = nullptr;
     size_t fixed_cap = 0, fixed_used = 0;
+    size_t last_need = 0;  // arena bytes the last refused growth asked for in total
     char err[512] = {0};
 };
 
@@ -132,6 +133,7 @@ static bbc_status arena_reserve(bbc_context* c, Arena& a, size_t bytes) {
     size_t want = bytes + bytes / 4;
     if (c->budget && total_reserved(c) - a.cap + want > c->budget) {
         want = bytes;
+        c->last_need = total_reserved(c) - a.cap + bytes;
         if (total_reserved(c) - a.cap + want > c->budget)
             return fail(c, BBC_ERR_OUT_OF_MEMORY,
                         "device workspace of %zu bytes exceeds BBC_MAX_DEVICE_BYTES=%zu", bytes,
@@ -159,6 +161,36 @@ static bbc_status arena_reserve(bbc_context* c, Arena& a, size_t bytes) {
     a.cap = want;
     return BBC_OK;
 }
+
+// ---- for the counting service (server.hip): a context's resident arenas,
+// releasing them, and capping their total
+namespace bbc {
+size_t context_resident_bytes(const bbc_context* c) { return total_reserved(c); }
+size_t context_last_need(const bbc_context* c) { return c->last_need; }
+void context_set_budget(bbc_context* c, size_t bytes) {
+    c->budget = bytes;
+    c->last_need = 0;
+}
+bool context_trim(bbc_context* c) {
+    if (hipSetDevice(c->device) != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    for (Arena* a : {&c->prep, &c->plan, &c->batch}) {
+        if (a->base) hipFree(a->base);
+        a->base = nullptr;
+        a->cap = a->used = 0;
+    }
+    for (auto& g : c->seg)  // replay graphs point into the freed arenas
+        if (g.exec) {
+            hipGraphExecDestroy(g.exec);
+            g.exec = nullptr;
+            g.key.clear();
+        }
+    (void)hipGetLastError();
+    return true;
+}
+}  // namespace bbc
 
 // Workspace for one pipeline stage: the arena `a` grown to `bytes`, or, in an
 // allocation-free call, the next `bytes` of the fixed scratch (an error, never

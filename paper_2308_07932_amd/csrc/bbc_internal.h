@@ -234,6 +234,15 @@ struct IngestArgs {
 
 }  // namespace bbc
 
+// ---- context arenas, for the counting service (defined in api.hip) ----------
+struct bbc_context;
+namespace bbc {
+size_t context_resident_bytes(const bbc_context* c);  // device bytes its arenas hold now
+size_t context_last_need(const bbc_context* c);  // total arena bytes a refused growth wanted
+void context_set_budget(bbc_context* c, size_t bytes);  // cap its arenas (0: no cap)
+bool context_trim(bbc_context* c);  // free its arenas (after its stream is idle)
+}  // namespace bbc
+
 // ---- host-side launchers (defined in the .hip files) ------------------------
 namespace bbc {
 hipError_t scan_excl_u32(const uint32_t* in, uint32_t* out, uint32_t n, void* tmp, size_t tmp_bytes,

@@ -9,10 +9,19 @@
 //     next batch;
 //   * large-graph workers run one bbc_count each, concurrently on their own
 //     streams, so their kernels overlap on the device with the batches.
-// Admission: a job holds its estimated device footprint (bbc_workspace_bytes)
-// from start to finish; a worker starts a job only while the footprints of
-// running jobs plus its own stay within the memory budget, else it waits.  A
-// job larger than the whole budget fails with BBC_ERR_OUT_OF_MEMORY.
+// Admission against the device memory the workers really hold.  Each worker's
+// context keeps its arenas between jobs (no allocation for a job that fits
+// them), so the server reserves, per worker, what its arenas hold when idle and,
+// while it runs jobs, the larger of that and the jobs' estimated footprint
+// (input copy plus bbc_workspace_bytes) -- its grant.  The context's arenas
+// are capped at the grant for the run, so they can never outgrow it.  A worker
+// starts jobs only while the sum of the reservations stays within the memory
+// budget.  A job whose estimate turns out too small (the planner's work lists
+// grow with the graph's wedges, which the estimate cannot see) fails inside
+// the grant and is queued again with its footprint raised to what it asked
+// for.  A worker whose job waits for memory, or that finishes while another
+// job waits, releases its arenas.  A job larger than the whole budget fails
+// with BBC_ERR_OUT_OF_MEMORY.
 #include <hip/hip_runtime.h>
 #include <string.h>
 
@@ -26,6 +35,7 @@
 #include <vector>
 
 #include "bbc.h"
+#include "bbc_internal.h"
 
 namespace {
 
@@ -55,6 +65,10 @@ struct bbc_server {
     std::unordered_map<uint64_t, Job*> jobs;
     uint64_t next_id = 1;
     uint64_t budget = 0, reserved = 0, peak_reserved = 0;
+    std::vector<uint64_t> held;  // per worker: bytes reserved for it (see the top of this file)
+    std::vector<char> idle;      // per worker: waiting for jobs
+    bool mem_blocked = false;    // a queued job is waiting for memory
+    int64_t trims = 0, retries = 0;
     int running = 0, peak_running = 0;
     int64_t submitted = 0, completed = 0, batches = 0, batched_jobs = 0, max_batch = 0;
     bool stop = false;
@@ -68,9 +82,11 @@ int64_t elapsed_us(Clock::time_point a, Clock::time_point b) {
     return std::chrono::duration_cast<std::chrono::microseconds>(b - a).count();
 }
 
-// Take jobs from q (front first) whose footprints fit the remaining budget;
-// at most max_jobs and max_edges.  Jobs that can never fit fail here.
-std::vector<Job*> take_jobs(bbc_server* s, std::deque<Job*>& q, size_t max_jobs, uint64_t max_edges) {
+// Take jobs from q (front first) for worker w while the reservations fit the
+// budget; at most max_jobs and max_edges.  Jobs that can never fit fail here.
+// On success the worker's reservation becomes its grant, returned in *grant.
+std::vector<Job*> take_jobs(bbc_server* s, std::deque<Job*>& q, size_t max_jobs, uint64_t max_edges,
+                            int w, uint64_t* grant) {
     std::vector<Job*> out;
     uint64_t fp = 0, edges = 0;
     while (!q.empty() && out.size() < max_jobs) {
@@ -86,14 +102,21 @@ std::vector<Job*> take_jobs(bbc_server* s, std::deque<Job*>& q, size_t max_jobs,
         }
         const uint64_t m = j->eu.size();
         if (!out.empty() && edges + m > max_edges) break;
-        if (s->reserved + fp + j->footprint > s->budget) break;  // wait for memory
+        const uint64_t g = std::max(s->held[w], fp + j->footprint);
+        if (s->reserved - s->held[w] + g > s->budget) {  // wait for memory
+            s->mem_blocked = true;
+            break;
+        }
         q.pop_front();
         out.push_back(j);
         fp += j->footprint;
         edges += m;
     }
     if (!out.empty()) {
-        s->reserved += fp;
+        const uint64_t g = std::max(s->held[w], fp);
+        s->reserved += g - s->held[w];
+        s->held[w] = g;
+        *grant = g;
         s->peak_reserved = std::max(s->peak_reserved, s->reserved);
         s->running += (int)out.size();
         s->peak_running = std::max(s->peak_running, s->running);
@@ -103,16 +126,83 @@ std::vector<Job*> take_jobs(bbc_server* s, std::deque<Job*>& q, size_t max_jobs,
     return out;
 }
 
-void finish(bbc_server* s, std::vector<Job*>& js) {
+// Wait (with the lock held) until worker w's queue yields jobs; an idle worker
+// releases its arenas while a job waits for memory.  Returns no jobs once the
+// server stops and the queue is empty.
+std::vector<Job*> next_jobs(bbc_server* s, std::unique_lock<std::mutex>& lk, std::deque<Job*>& q,
+                            size_t max_jobs, uint64_t max_edges, int w, bbc_context* ctx,
+                            uint64_t* grant) {
+    for (;;) {
+        if (!q.empty()) {
+            std::vector<Job*> js = take_jobs(s, q, max_jobs, max_edges, w, grant);
+            if (!js.empty()) {
+                s->idle[w] = 0;
+                return js;
+            }
+            // blocked on memory: wake idle workers that hold arenas, so they release them
+            bool holder = false;
+            for (size_t x = 0; x < s->held.size(); ++x)
+                holder = holder || ((int)x != w && s->idle[x] && s->held[x] > 0);
+            if (s->mem_blocked && holder) s->cv_work.notify_all();
+        }
+        s->idle[w] = 1;
+        if (s->stop && q.empty()) return {};
+        if (s->mem_blocked && s->held[w] > 0) {
+            lk.unlock();
+            const bool ok = bbc::context_trim(ctx);
+            lk.lock();
+            if (ok) {
+                s->reserved -= s->held[w];
+                s->held[w] = 0;
+                s->trims++;
+            }
+            s->mem_blocked = false;  // the waiting jobs look again
+            s->cv_work.notify_all();
+            continue;
+        }
+        s->cv_work.wait(lk);
+    }
+}
+
+// After worker w ran `js` within `grant` (call status rc): jobs that failed only
+// because their estimate was below what the count asked for go back to the
+// front of their queue with a raised footprint; the rest are done.  The
+// worker's reservation becomes what its arenas now hold, or zero when it
+// releases them because a job waits for memory.
+void finish(bbc_server* s, std::vector<Job*>& js, bbc_context* ctx, int w, uint64_t grant,
+            bbc_status rc, std::deque<Job*>& q) {
+    const uint64_t need = bbc::context_last_need(ctx);
+    const bool retry = rc == BBC_ERR_OUT_OF_MEMORY && need > grant && grant > 0;
+    bbc::context_set_budget(ctx, 0);
+    uint64_t resident = bbc::context_resident_bytes(ctx);
+    bool trim;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        trim = s->mem_blocked || retry;
+    }
+    if (trim && bbc::context_trim(ctx)) resident = 0;
     std::lock_guard<std::mutex> lk(s->mu);
     const auto now = Clock::now();
-    for (Job* j : js) {
-        s->reserved -= j->footprint;
-        s->running--;
-        j->t_done = now;
-        j->done = true;
-        s->completed++;
+    if (trim && resident == 0) s->trims++;
+    s->reserved = s->reserved - s->held[w] + resident;
+    s->held[w] = resident;
+    s->running -= (int)js.size();
+    if (retry) {
+        s->retries++;
+        for (auto it = js.rbegin(); it != js.rend(); ++it) {
+            Job* j = *it;
+            j->footprint = (uint64_t)((double)j->footprint * (double)need / (double)grant) + 1;
+            j->status = BBC_OK;
+            q.push_front(j);
+        }
+    } else {
+        for (Job* j : js) {
+            j->t_done = now;
+            j->done = true;
+            s->completed++;
+        }
     }
+    s->mem_blocked = false;  // memory changed: waiting jobs look again
     s->cv_done.notify_all();
     s->cv_work.notify_all();
 }
@@ -125,16 +215,12 @@ void batch_worker(bbc_server* s, bbc_context* ctx) {
     std::vector<int32_t> st;
     for (;;) {
         std::vector<Job*> js;
+        uint64_t grant = 0;
         {
             std::unique_lock<std::mutex> lk(s->mu);
-            for (;;) {
-                if (!s->q_small.empty()) {
-                    js = take_jobs(s, s->q_small, (size_t)s->cfg.max_batch_graphs, 1ull << 30);
-                    if (!js.empty()) break;
-                }
-                if (s->stop && s->q_small.empty()) return;
-                s->cv_work.wait(lk);
-            }
+            js = next_jobs(s, lk, s->q_small, (size_t)s->cfg.max_batch_graphs, 1ull << 30, 0, ctx,
+                           &grant);
+            if (js.empty()) return;
             s->batches++;
             s->batched_jobs += (int64_t)js.size();
             s->max_batch = std::max<int64_t>(s->max_batch, (int64_t)js.size());
@@ -160,10 +246,12 @@ void batch_worker(bbc_server* s, bbc_context* ctx) {
         }
         res.assign(G, bbc_result{0, 0, 0});
         st.assign(G, BBC_OK);
+        bbc::context_set_budget(ctx, grant);
         const bbc_status rc = bbc_count_batch(ctx, (int32_t)G, nu.data(), nv.data(), off.data(),
                                               eu.data(), ev.data(), sg.data(), 0, res.data(),
                                               st.data());
-        for (size_t i = 0; i < G; ++i) {
+        const bool retry = rc == BBC_ERR_OUT_OF_MEMORY && bbc::context_last_need(ctx) > grant;
+        for (size_t i = 0; i < G && !retry; ++i) {
             js[i]->status = rc == BBC_OK ? st[i] : rc;
             js[i]->res = rc == BBC_OK ? res[i] : bbc_result{0, 0, 0};
             js[i]->batched = true;
@@ -174,37 +262,36 @@ void batch_worker(bbc_server* s, bbc_context* ctx) {
             js[i]->sg.clear();
             js[i]->sg.shrink_to_fit();
         }
-        finish(s, js);
+        finish(s, js, ctx, 0, grant, rc, s->q_small);
     }
 }
 
-void large_worker(bbc_server* s, bbc_context* ctx) {
+void large_worker(bbc_server* s, bbc_context* ctx, int w) {
     for (;;) {
         std::vector<Job*> js;
+        uint64_t grant = 0;
         {
             std::unique_lock<std::mutex> lk(s->mu);
-            for (;;) {
-                if (!s->q_large.empty()) {
-                    js = take_jobs(s, s->q_large, 1, ~0ull);
-                    if (!js.empty()) break;
-                }
-                if (s->stop && s->q_large.empty()) return;
-                s->cv_work.wait(lk);
-            }
+            js = next_jobs(s, lk, s->q_large, 1, ~0ull, w, ctx, &grant);
+            if (js.empty()) return;
         }
         Job* j = js[0];
         bbc_result r = {0, 0, 0};
+        bbc::context_set_budget(ctx, grant);
         const bbc_status rc = bbc_count(ctx, j->n_u, j->n_v, (int64_t)j->eu.size(), j->eu.data(),
                                         j->ev.data(), j->sg.data(), 0, &r, nullptr);
-        j->status = rc;
-        j->res = rc == BBC_OK ? r : bbc_result{0, 0, 0};
-        j->eu.clear();
-        j->eu.shrink_to_fit();
-        j->ev.clear();
-        j->ev.shrink_to_fit();
-        j->sg.clear();
-        j->sg.shrink_to_fit();
-        finish(s, js);
+        const bool retry = rc == BBC_ERR_OUT_OF_MEMORY && bbc::context_last_need(ctx) > grant;
+        if (!retry) {
+            j->status = rc;
+            j->res = rc == BBC_OK ? r : bbc_result{0, 0, 0};
+            j->eu.clear();
+            j->eu.shrink_to_fit();
+            j->ev.clear();
+            j->ev.shrink_to_fit();
+            j->sg.clear();
+            j->sg.shrink_to_fit();
+        }
+        finish(s, js, ctx, w, grant, rc, s->q_large);
     }
 }
 
@@ -247,8 +334,11 @@ bbc_status bbc_server_create(const bbc_server_config* cfg, bbc_server** out) {
         }
         s->ctx.push_back(ctx);
     }
+    s->held.assign(s->ctx.size(), 0);
+    s->idle.assign(s->ctx.size(), 1);
     s->workers.emplace_back(batch_worker, s, s->ctx[0]);
-    for (int i = 0; i < c.large_workers; ++i) s->workers.emplace_back(large_worker, s, s->ctx[1 + i]);
+    for (int i = 0; i < c.large_workers; ++i)
+        s->workers.emplace_back(large_worker, s, s->ctx[1 + i], 1 + i);
     *out = s;
     return BBC_OK;
 }
@@ -312,7 +402,7 @@ bbc_status bbc_server_poll(bbc_server* s, uint64_t ticket, int32_t wait_ms, bbc_
 bbc_status bbc_server_stats(bbc_server* s, int64_t* stats, int n) {
     if (!s || !stats || n < 0) return BBC_ERR_INVALID_ARG;
     std::lock_guard<std::mutex> lk(s->mu);
-    const int64_t v[10] = {s->submitted,
+    const int64_t v[12] = {s->submitted,
                            s->completed,
                            s->batches,
                            s->batched_jobs,
@@ -321,8 +411,10 @@ bbc_status bbc_server_stats(bbc_server* s, int64_t* stats, int n) {
                            s->peak_running,
                            (int64_t)s->budget,
                            (int64_t)(s->q_small.size() + s->q_large.size()),
-                           (int64_t)s->reserved};
-    for (int i = 0; i < n && i < 10; ++i) stats[i] = v[i];
+                           (int64_t)s->reserved,
+                           s->trims,
+                           s->retries};
+    for (int i = 0; i < n && i < 12; ++i) stats[i] = v[i];
     return BBC_OK;
 }
 
