@@ -51,7 +51,7 @@ hipError_t launch_short_wedges(const uint4*, uint32_t, const uint32_t*, const ui
                                const uint32_t*, const uint32_t*, const uint32_t*, const uint32_t*,
                                uint32_t, uint32_t*, uint32_t*, uint32_t*, uint32_t*, bool,
                                hipStream_t);
-hipError_t launch_wedge(const Piece*, const uint32_t*, const uint32_t*, uint32_t, uint32_t,
+hipError_t launch_wedge(const Piece*, const uint32_t*, const uint32_t*, uint32_t, uint32_t, uint32_t,
                         const uint4*, const uint32_t*, const uint32_t*, Dims, const uint32_t[2], u64*,
                         const uint32_t*, const uint32_t*, const uint32_t*, Control*, u64*, u64*,
                         uint32_t, hipStream_t);
@@ -778,6 +778,7 @@ static bbc_status run_pipeline(bbc_context* c, const RunIn& in, RunOut& ro) {
                     (unsigned long long)h.tot_sw, (unsigned long long)h.tot_tiles,
                     (unsigned long long)h.tot_g);
     const uint32_t n_heavy = (uint32_t)h.tot_heavy, n_light = (uint32_t)h.tot_light;
+    const uint32_t n_dense = (uint32_t)std::min<u64>(h.n_dense_pieces, h.tot_heavy);
     const uint64_t n_light_items64 = (h.tot_light_region + d.light_window - 1) / d.light_window;
     const uint32_t n_light_items = (uint32_t)n_light_items64;
     const uint32_t n_items = n_heavy + n_light_items;
@@ -827,7 +828,7 @@ static bbc_status run_pipeline(bbc_context* c, const RunIn& in, RunOut& ro) {
     std::vector<uint64_t> keyB;
     if (c->use_graphs) keyB = keyA;
     if (c->use_graphs)
-    for (uint64_t x : {(uint64_t)n_heavy, (uint64_t)n_light, (uint64_t)n_light_items, (uint64_t)h.tot_g,
+    for (uint64_t x : {(uint64_t)n_heavy, (uint64_t)n_dense, (uint64_t)n_light, (uint64_t)n_light_items, (uint64_t)h.tot_g,
                        (uint64_t)h.tot_sw, (uint64_t)h.tot_tiles, (uint64_t)plan_base, (uint64_t)first_long[0],
                        (uint64_t)first_long[1], (uint64_t)in.per_vertex, (uint64_t)in.pv_host})
         keyB.push_back(x);
@@ -854,13 +855,13 @@ static bbc_status run_pipeline(bbc_context* c, const RunIn& in, RunOut& ro) {
     }
     uint32_t* order = nullptr;
     if (n_heavy > 0)  // heavy pieces, most expensive first
-        HIPCHECK(c, radix_sort_by_key(hkey, n_heavy, 16, ok0, ov0, ok1, ov1, ortmp, ortmp_bytes,
+        HIPCHECK(c, radix_sort_by_key(hkey, n_heavy, 17, ok0, ov0, ok1, ov1, ortmp, ortmp_bytes,
                                       &order, st));
     if (tm) HIPCHECK(c, hipEventRecord(c->ev[kEvPlanC], st));
 
     // ---- wedge enumeration and bucket counting
     if (tm) HIPCHECK(c, hipEventRecord(c->ev[kEvWedgeA], st));
-    HIPCHECK(c, launch_wedge(pieces, order, items_first, n_heavy, n_items, b.recs, b.col, b.tb, d,
+    HIPCHECK(c, launch_wedge(pieces, order, items_first, n_heavy, n_dense, n_items, b.recs, b.col, b.tb, d,
                              first_long, G, sw_off, sw_list, sw_mid, b.ctl,
                              bt ? bt->gres : nullptr, pv,
                              c->num_cus, st));

@@ -110,12 +110,13 @@ struct Control {
     uint32_t queue;      // wedge-kernel work counter
     uint32_t cls[2][kNumClassBounds];  // first row (absolute) with len > class_hi(c), per side
     uint32_t nbig_pairs; // (big row, chunk) pairs for the bitmap sort
-    uint32_t pad;
+    uint32_t queue_dense;  // work counter of the dense-piece wedge kernel
     u64 tot_heavy, tot_light_region, tot_light, tot_g;  // planner totals
     u64 active_starts;   // vertices with W_u > 0
     u64 tot_tiles;       // tile-to-piece map entries of split starts
     u64 tot_sw;          // bucketed short-middle wedges of split starts
     u64 n_dense, n_dense16, n_hashed;  // tile pieces by kind
+    u64 n_dense_pieces;  // heavy pieces with dense counters (small-side chunks and dense tiles)
 };
 
 struct Dims {

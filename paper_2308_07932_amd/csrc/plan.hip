@@ -45,13 +45,14 @@ __device__ inline uint32_t next_pow2(uint32_t x) {
 
 __device__ inline uint32_t log2_pow2(uint32_t x) { return 31u - __clz(x); }
 
-// Sort key putting the most expensive pieces first (ascending key): a 16-bit
+// Sort key of a heavy piece (ascending): pieces with dense counters first
+// (they run in their own kernel), each group most expensive first by a 16-bit
 // log-scale of the estimated cost, 4 units per record visited plus the
 // expected wedges.
-__device__ inline uint32_t cost_key(double wedges, uint32_t nrec) {
+__device__ inline uint32_t cost_key(double wedges, uint32_t nrec, bool dense) {
     const double c = wedges + 4.0 * nrec;
     const double q = log2(1.0 + c) * 2048.0;
-    return 65535u - (uint32_t)fmin(q, 65535.0);
+    return (dense ? 0u : 1u << 16) | (65535u - (uint32_t)fmin(q, 65535.0));
 }
 
 // Tile runs of a start with end-vertex space [0, S) on the side whose rows start
@@ -178,7 +179,7 @@ __global__ void k_plan_count(const u64* __restrict__ wu, const u64* __restrict__
         const StartPlan sp = plan_start(row_ptr, d, r, W, lowcnt[r], chunk);
         const uint32_t side = r >= d.n_u ? 1u : 0u;
         if (sp.cls == kClassTiles && d.n_graphs > 1) atomicOr(&ctl->internal_err, 2u);
-        if (sp.cls == kClassTiles) {  // tile pieces by kind (statistics)
+        if (sp.cls == kClassTiles) {  // tile pieces by kind
             u64 nd = 0, nd16 = 0, nh = 0;
             plan_runs(row_ptr, d.base[side], r - d.base[side], W, d.hash_target,
                       lowcnt[r] < (1u << 16),
@@ -190,6 +191,9 @@ __global__ void k_plan_count(const u64* __restrict__ wu, const u64* __restrict__
             if (nd) atomicAdd(&ctl->n_dense, nd);
             if (nd16) atomicAdd(&ctl->n_dense16, nd16);
             if (nh) atomicAdd(&ctl->n_hashed, nh);
+            if (nd + nd16) atomicAdd(&ctl->n_dense_pieces, nd + nd16);
+        } else if (sp.cls == kClassSmallSide) {
+            atomicAdd(&ctl->n_dense_pieces, (u64)sp.pieces);
         }
         hp[r] = sp.pieces;
         lr[r] = sp.cls == kClassLight ? sp.region : 0u;
@@ -260,7 +264,7 @@ __global__ void k_plan_write(const u64* __restrict__ wu, const uint32_t* __restr
                 p.list = kEmpty;
                 p.graph = sp.graph;
                 pieces[b + i] = p;
-                hkey[b + i] = cost_key((double)W * (c1 - c0) / k, c1 - c0);
+                hkey[b + i] = cost_key((double)W * (c1 - c0) / k, c1 - c0, true);
             }
             continue;
         }
@@ -292,7 +296,7 @@ __global__ void k_plan_write(const u64* __restrict__ wu, const uint32_t* __restr
             p.list = bucketed ? b + i : kEmpty;
             p.graph = 0;
             pieces[b + i] = p;
-            hkey[b + i] = cost_key(est, p.nrec);
+            hkey[b + i] = cost_key(est, p.nrec, dense);
             if (split)
                 for (uint32_t t = t0; t < t1; ++t) tile_piece[tc_off[r] + t] = i;
             ++i;

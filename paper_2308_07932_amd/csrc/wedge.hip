@@ -43,6 +43,8 @@ struct WedgeArgs {
     Control* ctl;
     u64* gres;  // batches: per graph {balanced, unbalanced, wedges, -}; else NULL (totals in ctl)
     u64* pv;    // per-vertex mode: balanced butterflies per row (n entries, zeroed)
+    uint32_t n_dense;  // heavy items 0..n_dense-1 are dense pieces, run by k_wedge_dense
+    uint32_t item0;    // first item k_wedge runs (n_dense, or 0 when it runs them all)
 };
 
 // Thread 0's running totals for one graph at a time; flushed to memory when
@@ -257,7 +259,7 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
     if (tid == 0) {
         s_acc.reset();
         s_pf_item = kEmpty;
-        s_item = atomicAdd(&a.ctl->queue, 1u);
+        s_item = a.item0 + atomicAdd(&a.ctl->queue, 1u);
     }
     for (;;) {
         __syncthreads();  // every thread is done with the previous item; s_item is set
@@ -272,7 +274,7 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
             const uint32_t p0 = a.n_heavy + a.items_first[li];
             np = a.n_heavy + a.items_first[li + 1] - p0;
             if (np == 0 || np > kMaxItemPieces) {  // never planned; uniform across the block
-                if (tid == 0) s_item = atomicAdd(&a.ctl->queue, 1u);
+                if (tid == 0) s_item = a.item0 + atomicAdd(&a.ctl->queue, 1u);
                 continue;
             }
             if (tid < np) s_pc[tid] = a.pieces[p0 + tid];
@@ -615,7 +617,7 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
                 uint32_t f = 1;
                 if (lane == 0) f = atomicAdd(&s_done, 1u);
                 if (lane == 0 && f == 0 && !s_nextok) {
-                    const uint32_t nx = atomicAdd(&a.ctl->queue, 1u);
+                    const uint32_t nx = a.item0 + atomicAdd(&a.ctl->queue, 1u);
                     if (nx < a.n_heavy && s_pf_item != nx) {
                         s_pf = a.pieces[a.order[nx]];
                         s_pf_item = nx;
@@ -905,7 +907,457 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
             }
             if (!more) break;
         }
-        if (tid == 0) s_item = s_nextok ? s_next : atomicAdd(&a.ctl->queue, 1u);
+        if (tid == 0) s_item = s_nextok ? s_next : a.item0 + atomicAdd(&a.ctl->queue, 1u);
+    }
+    if (tid == 0) s_acc.flush(a);
+}
+
+// ---------------------------------------------------------------------------
+// Dense pieces (plain count): one start's records restricted to an end-vertex
+// range [lo, hi) whose counters always fit the table, as u64 l + (m << 32)
+// per end vertex (kDenseW of them) or, for a start with fewer than 2^16
+// middles, u32 l | (m << 16) over two tiles.  The counting is the same as in
+// k_wedge; what differs is how the work is scheduled, because a wave's time
+// here goes to chains of dependent memory loads (record -> tile offsets ->
+// CSR entries), each about a microsecond under load, more than to the adds:
+//   * the CSR entries of the next sweep step (kUnroll windows of 64) are
+//     loaded before the adds of the current step are issued;
+//   * the record and tile offsets of a wave's next grab are loaded while its
+//     current grab is swept, as long as enough records remain for every wave
+//     (a grab claimed early by a busy wave would otherwise leave others idle
+//     at the end of the piece);
+//   * each wave's first grab is fixed (wave w takes records [w*b, (w+1)*b))
+//     and loaded while the table is cleared.
+// A dense piece never overflows, so there is no abandon-and-redo path; the
+// long-interval queue, the bucketed short-middle wedges and the exact merge of
+// record chunks through G work as in k_wedge.
+namespace {
+
+// this lane's record of a grab, and the sub-interval of its middle row
+struct DenseGrab {
+    uint32_t rs, pos, vs, s1;  // record: row start, prefix length, middle sidx, sign(u, v)
+    uint32_t ta, tb;           // tile offsets of the piece's range (long middles of split starts)
+};
+
+// 2 (C(l,2) + C(m,2)) and 2 l m of one u32 bucket l | (m << 16), l + m < 2^16:
+// dot products of the two 16-bit halves
+__device__ inline void bucket16_sums(uint32_t c, u64& q2, u64& lm2) {
+    typedef unsigned short h2 __attribute__((ext_vector_type(2)));
+    const h2 a = __builtin_bit_cast(h2, c);
+    const h2 d = a - (h2){1, 1};  // l - 1, m - 1 (an empty half gives 0 * 0xFFFF = 0)
+    q2 += __builtin_amdgcn_udot2(a, d, 0u, false);
+    lm2 += __builtin_amdgcn_udot2(a, __builtin_bit_cast(h2, __builtin_amdgcn_alignbit(c, c, 16)), 0u,
+                                  false);
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(kWedgeThreads) void k_wedge_dense(WedgeArgs a) {
+    __shared__ u64 s_tab[kDenseW];
+    __shared__ uint32_t s_wadj[kWaves][64], s_waux[kWaves][64];
+    __shared__ uint32_t s_head[kWaves][64];  // head flags, interleaved as in k_wedge
+    __shared__ uint32_t s_qadj[kQueue], s_qlen[kQueue], s_qaux[kQueue];
+    __shared__ Piece s_p, s_pf;
+    __shared__ uint32_t s_item, s_pf_item, s_next, s_nextok, s_done;
+    __shared__ uint32_t s_batch, s_qn, s_qtake, s_swtake;
+    __shared__ u64 s_red[2][kWaves];
+    __shared__ GraphAcc s_acc;
+    uint32_t* s32 = (uint32_t*)s_tab;
+    const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
+    const uint32_t* __restrict__ col = a.col;
+    const u64 le_mask = ~0ull >> (63 - lane);  // lanes 0..lane
+    s_head[wave][lane] = 0;
+    if (tid == 0) {
+        s_acc.reset();
+        s_pf_item = kEmpty;
+        s_item = atomicAdd(&a.ctl->queue_dense, 1u);
+        if (s_item < a.n_dense) s_p = a.pieces[a.order[s_item]];
+    }
+    for (;;) {
+        __syncthreads();  // s_item and s_p are set; the previous item is done
+        const uint32_t item = s_item;
+        if (item >= a.n_dense) break;
+        Piece P;  // wave-uniform: the fields live in scalar registers
+        P.rec0 = __builtin_amdgcn_readfirstlane(s_p.rec0);
+        P.nrec = __builtin_amdgcn_readfirstlane(s_p.nrec);
+        P.lo = __builtin_amdgcn_readfirstlane(s_p.lo);
+        P.hi = __builtin_amdgcn_readfirstlane(s_p.hi);
+        P.t0 = __builtin_amdgcn_readfirstlane(s_p.t0);
+        P.t1 = __builtin_amdgcn_readfirstlane(s_p.t1);
+        P.flags = __builtin_amdgcn_readfirstlane(s_p.flags);
+        P.gbase = __builtin_amdgcn_readfirstlane(s_p.gbase);
+        P.list = __builtin_amdgcn_readfirstlane(s_p.list);
+        P.graph = __builtin_amdgcn_readfirstlane(s_p.graph);
+        const bool d16 = (P.flags & kPieceDense16) != 0;
+        const bool partial = (P.flags & kPiecePartial) != 0;
+        const uint32_t ys = (P.flags & kPieceSideV) ? 0u : 1u;  // side of the middles
+        const uint32_t dlo = P.lo, plo = P.lo, phi = P.hi, dwidth = P.hi - P.lo;
+        const uint32_t total = P.nrec;
+        const uint32_t bsz = partial ? min(32u, max(4u, (total + 31) / 32))
+                                     : min(64u, max(8u, (total + 15) / 16));
+        const uint32_t* tbl = partial ? a.tb + a.d.tb_off[ys] : nullptr;
+        const uint32_t tstride = a.d.ntile[ys ^ 1u] + 1;
+        const uint32_t flong = a.first_long[ys];
+        if (tid == 0) {
+            s_batch = kWaves * bsz;  // grabs beyond every wave's first one
+            s_qn = s_qtake = s_swtake = 0;
+            s_nextok = 0;
+            s_done = 0;
+        }
+        // Loads below are issued by every lane (inactive lanes read a valid
+        // address and drop the value): a load in a per-lane branch makes the
+        // compiler wait for all outstanding loads where the branches meet.
+        // -- a grab's records (issued now, used later); total > 0
+        auto load_rec = [&](uint32_t base, DenseGrab& g) {
+            const uint32_t f = base + lane;
+            const bool act = lane < bsz && f < total;
+            const uint4 rc = a.recs[P.rec0 + (act ? f : 0u)];
+            g.rs = rc.x;
+            g.pos = act ? rc.y >> 1 : 0u;
+            g.s1 = rc.y & 1u;
+            g.vs = rc.z;
+        };
+        // tile offsets of the piece's range in the middle's row (split starts)
+        auto load_tiles = [&](DenseGrab& g) {
+            g.ta = 0;
+            g.tb = g.pos;
+            if (partial) {
+                const bool lng = g.pos > 0 && g.vs >= flong;
+                const uint32_t* t = tbl + (uint64_t)(lng ? g.vs - flong : 0u) * tstride;
+                const uint32_t a0 = t[P.t0], a1 = t[P.t1];
+                if (lng) {
+                    g.ta = a0;
+                    g.tb = a1;
+                }
+            }
+        };
+        DenseGrab cur;
+        uint32_t cur_base = wave * bsz;
+        if (total > 0) load_rec(cur_base, cur);
+        // -- clear the counters of the range (up to a whole 16-byte unit past
+        // its end, which the finalize reads), while the records arrive
+        {
+            const uint32_t words = d16 ? (dwidth + 3) / 4 * 2 : (dwidth + 1) / 2 * 2;
+            for (uint32_t i = tid; i < words; i += kWedgeThreads) s_tab[i] = 0;
+        }
+        if (total > 0) load_tiles(cur);
+        __syncthreads();  // table cleared, s_batch set
+
+        // -- the records, grab by grab
+        bool have = cur_base < total;
+        while (have) {
+            // this lane's sub-interval [ia, ib) of its middle row
+            uint32_t ia = 0, ib = cur.pos, filt = 0;
+            if (partial && cur.pos > 0) {
+                if (cur.vs >= flong) {
+                    ia = min(cur.ta, cur.pos);
+                    ib = min(cur.tb, cur.pos);
+                } else if (cur.pos <= kScanMax) {
+                    filt = 1;  // short prefix: read it all, keep the entries in [lo, hi)
+                } else {
+                    ia = lower_bound_u32(col + cur.rs, cur.pos, plo << 1);
+                    ib = ia + lower_bound_u32(col + cur.rs + ia, cur.pos - ia, phi << 1);
+                }
+            }
+            const uint32_t rs = cur.rs, s1 = cur.s1;
+            // claim the next grab now when enough records remain for every
+            // wave, and start loading it; otherwise claim it after this sweep
+            DenseGrab nxt;
+            uint32_t nxt_base = kEmpty;
+            {
+                uint32_t nb = 0;
+                if (lane == 0) {
+                    const uint32_t seen = __hip_atomic_load(&s_batch, __ATOMIC_RELAXED,
+                                                            __HIP_MEMORY_SCOPE_WORKGROUP);
+                    nb = (seen < total && total - seen > 2 * kWaves * bsz)
+                             ? atomicAdd(&s_batch, bsz) : kEmpty;
+                }
+                nxt_base = __shfl(nb, 0, 64);
+                if (nxt_base != kEmpty) load_rec(nxt_base, nxt);
+            }
+            // a long sub-interval keeps its first kChunk entries; the rest goes to
+            // the LDS queue in chunks of kChunk (as many as fit)
+            if (ib - ia > kChunk) {
+                const uint32_t want = (ib - ia - 1) / kChunk;
+                uint32_t old = s_qn, got = 0;
+                for (;;) {
+                    got = min(want, kQueue - min(old, kQueue));
+                    if (got == 0) break;
+                    const uint32_t seen = atomicCAS(&s_qn, old, old + got);
+                    if (seen == old) break;
+                    old = seen;
+                }
+                if (got > 0) {
+                    const uint32_t keep_end = max(ia + kChunk, ib - got * kChunk);
+                    for (uint32_t c = 0; c < got; ++c) {
+                        const uint32_t c0 = keep_end + c * kChunk;
+                        s_qadj[old + c] = rs + c0;
+                        s_qlen[old + c] = min(kChunk, ib - c0);
+                        s_qaux[old + c] = s1 | (filt << 1);
+                    }
+                    ib = keep_end;
+                }
+            }
+            const uint32_t len = ib - ia;
+            const u64 nz = __ballot(len > 0);
+            const uint32_t excl = wave_incl_scan(len) - len;
+            const uint32_t T = __shfl(excl + len, 63, 64);
+            if (len > 0) {
+                const uint32_t ci = (uint32_t)__popcll(nz & (le_mask >> 1));
+                s_wadj[wave][ci] = rs + ia - excl;
+                s_waux[wave][ci] = s1 | (filt << 1);
+            }
+            // -- sweep the T concatenated wedges, kUnroll windows of 64 per step;
+            // the entries of step j + 1 are loaded before the adds of step j
+            uint32_t before = 0;
+            uint32_t xa[kUnroll], aa[kUnroll];
+            auto step_load = [&](uint32_t j, uint32_t* x, uint32_t* aux) {
+                uint8_t* hb = (uint8_t*)s_head[wave];
+                if (len > 0 && excl >= j && excl < j + 64 * kUnroll) {
+                    const uint32_t hp = excl - j;
+                    hb[(hp & 63u) * kUnroll + (hp >> 6)] = 1;
+                }
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                const uint32_t hd4 = s_head[wave][lane];
+                uint32_t adj[kUnroll];
+#pragma unroll
+                for (uint32_t u = 0; u < kUnroll; ++u) {
+                    const u64 M = __ballot(((hd4 >> (8 * u)) & 0xFFu) != 0);
+                    const uint32_t idx = before + (uint32_t)__popcll(M & le_mask) - 1u;
+                    before += (uint32_t)__popcll(M);
+                    const bool in = j + u * 64 + lane < T;
+                    const uint32_t ii = in ? idx : 0u;
+                    aux[u] = in ? s_waux[wave][ii] : kEmpty;
+                    adj[u] = s_wadj[wave][ii];
+                }
+#pragma unroll
+                for (uint32_t u = 0; u < kUnroll; ++u) {
+                    const uint32_t q = j + u * 64 + lane;
+                    x[u] = col[q < T ? adj[u] + q : 0u];  // aux marks the lanes past T
+                }
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                s_head[wave][lane] = 0;
+            };
+            auto step_add = [&](const uint32_t* x, const uint32_t* aux) {
+#pragma unroll
+                for (uint32_t u = 0; u < kUnroll; ++u) {
+                    if (aux[u] == kEmpty) continue;
+                    const uint32_t w = x[u] >> 1;
+                    if ((aux[u] & 2u) && (w < plo || w >= phi)) continue;
+                    const bool asym = ((x[u] ^ aux[u]) & 1u) != 0;
+                    if (d16)
+                        atomicAdd(&s32[w - dlo], asym ? 0x10000u : 1u);
+                    else
+                        atomicAdd(&s_tab[w - dlo], asym ? (1ull << 32) : 1ull);
+                }
+            };
+            // two register sets take turns (no copies: a copy of a value still
+            // being loaded would wait for the load)
+            // the step after the last is loaded too (to a valid address, all
+            // lanes marked past T), which keeps the loads out of branches
+            uint32_t xb[kUnroll], ab[kUnroll];
+            if (T > 0) {
+                step_load(0, xa, aa);
+                for (uint32_t j = 0;;) {
+                    j += 64 * kUnroll;
+                    step_load(j, xb, ab);
+                    if (j == 64 * kUnroll && nxt_base != kEmpty) load_tiles(nxt);  // records arrived
+                    step_add(xa, aa);
+                    if (j >= T) break;
+                    j += 64 * kUnroll;
+                    step_load(j, xa, aa);
+                    step_add(xb, ab);
+                    if (j >= T) break;
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            // the next grab: loaded above, or claimed now
+            if (nxt_base != kEmpty) {
+                if (T == 0) load_tiles(nxt);
+                cur = nxt;
+                cur_base = nxt_base;
+            } else {
+                uint32_t nb = 0;
+                if (lane == 0) nb = atomicAdd(&s_batch, bsz);
+                cur_base = __shfl(nb, 0, 64);
+                if (cur_base < total) {
+                    load_rec(cur_base, cur);
+                    load_tiles(cur);
+                }
+            }
+            have = cur_base < total;
+        }
+        // -- the bucketed wedges through short middle rows (split starts);
+        // the next chunk's entries are loaded before the current chunk's adds
+        if (partial && P.list != kEmpty) {
+            const uint32_t b0 = a.sw_off[P.list];
+            const uint32_t n_sw = a.sw_off[P.list + 1] - b0;
+            auto take = [&]() {
+                uint32_t c = 0;
+                if (lane == 0) c = atomicAdd(&s_swtake, 64 * kUnroll);
+                return __shfl(c, 0, 64);
+            };
+            auto load = [&](uint32_t c, uint32_t* x) {
+#pragma unroll
+                for (uint32_t u = 0; u < kUnroll; ++u) {
+                    const uint32_t q = c + u * 64 + lane;
+                    const uint32_t v = a.sw_list[b0 + (q < n_sw ? q : 0u)];
+                    x[u] = q < n_sw ? v : kEmpty;
+                }
+            };
+            auto add = [&](const uint32_t* x) {
+#pragma unroll
+                for (uint32_t u = 0; u < kUnroll; ++u) {
+                    if (x[u] == kEmpty) continue;
+                    const uint32_t w = x[u] >> 1;
+                    if (w < plo || w >= phi) continue;
+                    if (d16)
+                        atomicAdd(&s32[w - dlo], (x[u] & 1u) ? 0x10000u : 1u);
+                    else
+                        atomicAdd(&s_tab[w - dlo], (x[u] & 1u) ? (1ull << 32) : 1ull);
+                }
+            };
+            uint32_t xa[kUnroll], xb[kUnroll];
+            uint32_t c = n_sw > 0 ? take() : n_sw;
+            if (c < n_sw) {
+                load(c, xa);
+                for (;;) {
+                    c = take();
+                    load(c, xb);  // past the end: all lanes marked empty
+                    add(xa);
+                    if (c >= n_sw) break;
+                    c = take();
+                    load(c, xa);
+                    add(xb);
+                    if (c >= n_sw) break;
+                }
+            }
+        }
+        // the first wave done takes the next item and fetches its piece
+        {
+            uint32_t f = 1;
+            if (lane == 0) f = atomicAdd(&s_done, 1u);
+            if (lane == 0 && f == 0) {
+                const uint32_t nx = atomicAdd(&a.ctl->queue_dense, 1u);
+                if (nx < a.n_dense) {
+                    s_pf = a.pieces[a.order[nx]];
+                    s_pf_item = nx;
+                }
+                s_next = nx;
+                s_nextok = 1;
+            }
+        }
+        __syncthreads();
+        // -- queued chunks of long sub-intervals: one wave per chunk
+        if (s_qn > 0) {
+            for (;;) {
+                uint32_t c = 0;
+                if (lane == 0) c = atomicAdd(&s_qtake, 1u);
+                c = __shfl(c, 0, 64);
+                if (c >= s_qn) break;
+                const uint32_t adj = s_qadj[c], qlen = s_qlen[c], aux = s_qaux[c];
+                auto load = [&](uint32_t e0, uint32_t* x) {
+#pragma unroll
+                    for (uint32_t u = 0; u < kUnroll; ++u) {
+                        const uint32_t e = e0 + u * 64 + lane;
+                        const uint32_t v = col[adj + (e < qlen ? e : 0u)];
+                        x[u] = e < qlen ? v : kEmpty;
+                    }
+                };
+                auto add = [&](const uint32_t* x) {
+#pragma unroll
+                    for (uint32_t u = 0; u < kUnroll; ++u) {
+                        if (x[u] == kEmpty) continue;
+                        const uint32_t w = x[u] >> 1;
+                        if ((aux & 2u) && (w < plo || w >= phi)) continue;
+                        const bool asym = ((x[u] ^ aux) & 1u) != 0;
+                        if (d16)
+                            atomicAdd(&s32[w - dlo], asym ? 0x10000u : 1u);
+                        else
+                            atomicAdd(&s_tab[w - dlo], asym ? (1ull << 32) : 1ull);
+                    }
+                };
+                uint32_t xa[kUnroll], xb[kUnroll];
+                load(0, xa);
+                for (uint32_t e0 = 0;;) {
+                    e0 += 64 * kUnroll;
+                    load(e0, xb);
+                    add(xa);
+                    if (e0 >= qlen) break;
+                    e0 += 64 * kUnroll;
+                    load(e0, xa);
+                    add(xb);
+                    if (e0 >= qlen) break;
+                }
+            }
+            __syncthreads();
+        }
+        // -- finalize: C(l,2) + C(m,2) and l*m over the range
+        u64 bal = 0, unb = 0;
+        if (d16 && !(P.flags & kPieceMerge)) {
+            // 2 (C(l,2) + C(m,2)) and 2 l m from dot products of the halves
+            // (l + m < 2^16); entries past the range and unreached ones are zero
+            const uint4* t4 = reinterpret_cast<const uint4*>(s32);
+            u64 q2 = 0, lm2 = 0;
+            for (uint32_t g = tid; g < (dwidth + 3) / 4; g += kWedgeThreads) {
+                const uint4 c = t4[g];
+                bucket16_sums(c.x, q2, lm2);
+                bucket16_sums(c.y, q2, lm2);
+                bucket16_sums(c.z, q2, lm2);
+                bucket16_sums(c.w, q2, lm2);
+            }
+            bal = q2 >> 1;  // every term is even: l(l-1) + m(m-1) and 2lm
+            unb = lm2 >> 1;
+        } else if (!(P.flags & kPieceMerge)) {
+            const ulonglong2* t2 = reinterpret_cast<const ulonglong2*>(s_tab);
+            for (uint32_t g = tid; g < (dwidth + 1) / 2; g += kWedgeThreads) {
+                const ulonglong2 c = t2[g];
+                const u64 cc[2] = {c.x, c.y};
+#pragma unroll
+                for (int k = 0; k < 2; ++k) {
+                    const u64 l = cc[k] & 0xFFFFFFFFull, mm = cc[k] >> 32;
+                    bal += choose2(l) + choose2(mm);
+                    unb += l * mm;
+                }
+            }
+        } else {
+            const uint32_t gb = P.gbase;
+            for (uint32_t i = tid; i < dwidth; i += kWedgeThreads) {
+                u64 v;
+                if (d16) {
+                    const uint32_t c = s32[i];
+                    v = (c & 0xFFFFu) | ((u64)(c >> 16) << 32);
+                } else {
+                    v = s_tab[i];
+                }
+                if (v == 0) continue;
+                const u64 l = v & 0xFFFFFFFFull, m = v >> 32;
+                bal += choose2(l) + choose2(m);
+                unb += l * m;
+                const u64 old = atomicAdd(&a.G[(uint64_t)gb + i], v);
+                const u64 ol = old & 0xFFFFFFFFull, om = old >> 32;
+                bal += ol * l + om * m;
+                unb += ol * m + om * l;
+            }
+        }
+        bal = wave_reduce_sum(bal);
+        unb = wave_reduce_sum(unb);
+        if (lane == 0) {
+            s_red[0][wave] = bal;
+            s_red[1][wave] = unb;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            u64 sb = 0, su = 0;
+            for (uint32_t w = 0; w < kWaves; ++w) {
+                sb += s_red[0][w];
+                su += s_red[1][w];
+            }
+            s_acc.add(a, P.graph, sb, su);
+            const uint32_t nx = s_nextok ? s_next : atomicAdd(&a.ctl->queue_dense, 1u);
+            s_item = nx;
+            if (nx < a.n_dense) s_p = (s_pf_item == nx) ? s_pf : a.pieces[a.order[nx]];
+        }
     }
     if (tid == 0) s_acc.flush(a);
 }
@@ -925,8 +1377,10 @@ hipError_t launch_pv_out(const u64* pv, const uint32_t* sidx_of, Dims d, u64* ou
     return hipGetLastError();
 }
 
+// Plain count: the dense heavy items (0..n_dense-1) run in k_wedge_dense, then
+// the rest in k_wedge; per-vertex mode runs every item in k_wedge<true>.
 hipError_t launch_wedge(const Piece* pieces, const uint32_t* order, const uint32_t* items_first,
-                        uint32_t n_heavy,
+                        uint32_t n_heavy, uint32_t n_dense,
                         uint32_t n_items, const uint4* recs, const uint32_t* col, const uint32_t* tb,
                         Dims d, const uint32_t first_long[2], u64* G, const uint32_t* sw_off,
                         const uint32_t* sw_list, const uint32_t* sw_mid, Control* ctl, u64* gres,
@@ -951,9 +1405,16 @@ hipError_t launch_wedge(const Piece* pieces, const uint32_t* order, const uint32
     a.ctl = ctl;
     a.gres = gres;
     a.pv = pv;
+    a.n_dense = pv ? 0 : n_dense;
+    a.item0 = a.n_dense;
+    if (a.n_dense > 0) {
+        const uint32_t grid = min(num_cus, a.n_dense);
+        hipLaunchKernelGGL(k_wedge_dense, dim3(grid), dim3(kWedgeThreads), 0, st, a);
+    }
+    const uint32_t rest = n_items - a.item0;
     uint32_t grid = num_cus;
-    if (grid > n_items) grid = n_items;
-    if (grid == 0) return hipSuccess;
+    if (grid > rest) grid = rest;
+    if (grid == 0) return hipGetLastError();
     if (pv)
         hipLaunchKernelGGL(k_wedge<true>, dim3(grid), dim3(kWedgeThreads), 0, st, a);
     else
