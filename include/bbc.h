@@ -235,15 +235,19 @@ void bbc_server_destroy(bbc_server* srv);
  * Autotuner: pick the work-split tunables for a workload by measurement.
  * The input is laid out as for bbc_count_batch (n_graphs = 1 tunes
  * bbc_count on that graph).  Starting from the context's current settings,
- * a coordinate search tries record-chunk floors {16K, 64K, 256K, 1M, 4M}
- * wedges, hash targets {1024, 2048, 4096, 8192} and probe limits
- * {32, 256, 2048}, timing each setting as the best of `repeats` whole calls
- * (1..100) and keeping a value only for a gain above 3%.  Every call must
- * give the same counts and statuses as the first one (else
- * BBC_ERR_INTERNAL, and the settings are restored).  On success the best
- * settings stay on the context; chosen[0..2] (may be NULL) receives
- * {chunk wedges, hash target, probe limit} and *best_ms (may be NULL) the
- * best call time in milliseconds (host clock).
+ * a coordinate search tries, in this order, record-chunk floors {16K, 64K,
+ * 256K, 1M, 4M} wedges; hash targets {1024, 2048, 4096, 8192} and probe
+ * limits {32, 256, 2048} (only when some graph has more than 16384 vertices
+ * on a side, the only graphs whose starts are cut into end-vertex tiles);
+ * light cuts {512, 1024, 2048}; grab divisors {8, 16, 32}; and, for a batch,
+ * union sizes {2^24, 2^26, 2^28, 2^30} edges.  Each setting is timed as the
+ * best of `repeats` whole calls (1..100) and a value is kept only for a gain
+ * above 3%.  Every call must give the same counts and statuses as the first
+ * one (else BBC_ERR_INTERNAL, and the settings are restored).  On success the
+ * best settings stay on the context; chosen[0..5] (may be NULL; 6 entries)
+ * receives {chunk wedges, hash target, probe limit, light cut, grab divisor,
+ * union edges} and *best_ms (may be NULL) the best call time in milliseconds
+ * (host clock).
  */
 bbc_status bbc_autotune(bbc_context* ctx, int32_t n_graphs, const int32_t* n_u,
                         const int32_t* n_v, const int64_t* edge_offset, const int32_t* edge_u,
@@ -313,6 +317,20 @@ bbc_status bbc_last_stats(const bbc_context* ctx, int64_t* stats, int n);
  *                          the second.  Default 0.
  *   BBC_PARAM_GRAPH_CAPTURES, BBC_PARAM_GRAPH_REPLAYS  (bbc_get_param only)
  *                          segments captured and replayed so far.
+ *   BBC_PARAM_LIGHT_MAX    most wedges of a "light" start: light starts share
+ *                          work items, each with its own region of one on-chip
+ *                          hash table; heavier ones are work items of their
+ *                          own.  Default 2048, range [16, 2048].
+ *   BBC_PARAM_GRAB_DIV     a work item's records are taken by the waves of its
+ *                          workgroup in grabs of about 1/GRAB_DIV of them (light
+ *                          items and starts that are not cut along the end
+ *                          vertices; capped at 64 records).  Default 16, range
+ *                          [4, 64].
+ *   BBC_PARAM_UNION_EDGES  bbc_count_batch counts consecutive small graphs
+ *                          as one union graph of at most this many edges
+ *                          (smaller unions: more passes, but each pass's work
+ *                          arrays fit the on-package cache).  Default 2^30,
+ *                          range [2^16, 2^30].
  * bbc_set_param returns BBC_ERR_INVALID_ARG for a NULL context, an unknown
  * parameter or a value out of range (the setting is then unchanged);
  * bbc_get_param writes the current value to *value.
@@ -323,7 +341,10 @@ enum {
     BBC_PARAM_CHUNK_WEDGES = 3,
     BBC_PARAM_GRAPHS = 4,         /* 0 / 1 */
     BBC_PARAM_GRAPH_CAPTURES = 5, /* read only */
-    BBC_PARAM_GRAPH_REPLAYS = 6   /* read only */
+    BBC_PARAM_GRAPH_REPLAYS = 6,  /* read only */
+    BBC_PARAM_LIGHT_MAX = 7,
+    BBC_PARAM_GRAB_DIV = 8,
+    BBC_PARAM_UNION_EDGES = 9
 };
 bbc_status bbc_set_param(bbc_context* ctx, int param, int64_t value);
 bbc_status bbc_get_param(const bbc_context* ctx, int param, int64_t* value);

@@ -46,6 +46,9 @@ PARAM_CHUNK_WEDGES = 3
 PARAM_GRAPHS = 4
 PARAM_GRAPH_CAPTURES = 5
 PARAM_GRAPH_REPLAYS = 6
+PARAM_LIGHT_MAX = 7
+PARAM_GRAB_DIV = 8
+PARAM_UNION_EDGES = 9
 
 PHASE_TOTAL, PHASE_PREP, PHASE_WEDGE, PHASE_PLAN = 0, 1, 2, 3
 
@@ -315,7 +318,8 @@ class Context:
 
     def autotune(self, n_u, n_v, edge_offset, eu, ev, sign, repeats: int = 2):
         """bbc_autotune on a batch (or one graph): returns ({chunk_wedges,
-        hash_target, probe_limit}, best call ms); the settings stay on the context."""
+        hash_target, probe_limit, light_max, grab_div, union_edges}, best call
+        ms); the settings stay on the context."""
         nu = np.ascontiguousarray(n_u, dtype=np.int32)
         nv = np.ascontiguousarray(n_v, dtype=np.int32)
         off = np.ascontiguousarray(edge_offset, dtype=np.int64)
@@ -325,7 +329,7 @@ class Context:
             cur = torch.cuda.current_stream(keep[0].device)
             if self.stream is None or int(cur.cuda_stream) != int(self.stream):
                 cur.synchronize()
-        ch = (ctypes.c_int64 * 3)()
+        ch = (ctypes.c_int64 * 6)()
         best = ctypes.c_double()
         rc = self._lib.bbc_autotune(self._h, int(nu.shape[0]), nu.ctypes.data, nv.ctypes.data,
                                     off.ctypes.data, *ptrs, INPUT_ON_DEVICE if on_dev else 0,
@@ -334,7 +338,8 @@ class Context:
         if rc != OK:
             raise BBCError(rc, self.last_error() or status_string(rc))
         return {"chunk_wedges": int(ch[0]), "hash_target": int(ch[1]),
-                "probe_limit": int(ch[2])}, float(best.value)
+                "probe_limit": int(ch[2]), "light_max": int(ch[3]), "grab_div": int(ch[4]),
+                "union_edges": int(ch[5])}, float(best.value)
 
     def count_batch(self, n_u, n_v, edge_offset, eu, ev, sign) -> "BatchResult":
         """Count many graphs in one call (bbc_count_batch): n_u, n_v (n_graphs

@@ -91,6 +91,9 @@ struct bbc_context {
     uint32_t hash_target = bbc::kDefaultHashTarget;
     uint32_t probe_limit = bbc::kDefaultProbeLimit;
     uint64_t chunk_min = bbc::kRecordChunkWedges;
+    uint32_t light_max = bbc::kLightMax;
+    uint32_t grab_div = 16;
+    uint64_t union_edges = bbc::kBatchMaxEdges;
     int64_t* pv_host = nullptr;  // pinned staging of per-vertex counts
     size_t pv_host_cap = 0;
     bool use_graphs = false;     // capture the two device segments and replay them
@@ -455,6 +458,18 @@ bbc_status bbc_set_param(bbc_context* c, int param, int64_t value) {
         if (value != 0 && value != 1) return BBC_ERR_INVALID_ARG;
         c->use_graphs = value != 0;
         return BBC_OK;
+    case BBC_PARAM_LIGHT_MAX:
+        if (value < 16 || value > (int64_t)bbc::kLightMax) return BBC_ERR_INVALID_ARG;
+        c->light_max = (uint32_t)value;
+        return BBC_OK;
+    case BBC_PARAM_GRAB_DIV:
+        if (value < 4 || value > 64) return BBC_ERR_INVALID_ARG;
+        c->grab_div = (uint32_t)value;
+        return BBC_OK;
+    case BBC_PARAM_UNION_EDGES:
+        if (value < (1 << 16) || value > (int64_t)bbc::kBatchMaxEdges) return BBC_ERR_INVALID_ARG;
+        c->union_edges = (uint64_t)value;
+        return BBC_OK;
     default:
         return BBC_ERR_INVALID_ARG;
     }
@@ -469,6 +484,9 @@ bbc_status bbc_get_param(const bbc_context* c, int param, int64_t* value) {
     case BBC_PARAM_GRAPHS: *value = c->use_graphs ? 1 : 0; return BBC_OK;
     case BBC_PARAM_GRAPH_CAPTURES: *value = c->graph_captures; return BBC_OK;
     case BBC_PARAM_GRAPH_REPLAYS: *value = c->graph_replays; return BBC_OK;
+    case BBC_PARAM_LIGHT_MAX: *value = c->light_max; return BBC_OK;
+    case BBC_PARAM_GRAB_DIV: *value = c->grab_div; return BBC_OK;
+    case BBC_PARAM_UNION_EDGES: *value = (int64_t)c->union_edges; return BBC_OK;
     default: return BBC_ERR_INVALID_ARG;
     }
 }
@@ -609,6 +627,8 @@ static bbc_status run_pipeline(bbc_context* c, const RunIn& in, RunOut& ro) {
     d.rlist = nullptr;
     d.per_vertex = in.per_vertex ? 1u : 0u;
     d.light_window = kLightWindow16;
+    d.light_max = c->light_max;
+    d.grab_div = c->grab_div;
     // rows of side Y with more than kLongDeg entries: at most m / (kLongDeg + 1) per side
     uint64_t maxlong0 = std::min<uint64_t>(nu, m / (kLongDeg + 1));
     uint64_t maxlong1 = std::min<uint64_t>(nv, m / (kLongDeg + 1));
@@ -651,7 +671,7 @@ static bbc_status run_pipeline(bbc_context* c, const RunIn& in, RunOut& ro) {
     if (c->use_graphs)
         keyA = {n, nu, nv, m, (uint64_t)eu, (uint64_t)ev, (uint64_t)sg,
                 (uint64_t)prep_base, tb_total, d.hash_target, d.probe_limit,
-                d.chunk_min, d.per_vertex, bt_on, deg_bits, g_bits};
+                d.chunk_min, d.per_vertex, bt_on, deg_bits, g_bits, d.light_max, d.grab_div};
     if (bt && c->use_graphs) {
         for (uint64_t x : {(uint64_t)bt->n_graphs, (uint64_t)bt->blk[0], (uint64_t)bt->blk[1],
                            (uint64_t)bt->gres, (uint64_t)bt->gerr})
@@ -1268,7 +1288,7 @@ bbc_status bbc_count_batch(bbc_context* c, int32_t n_graphs, const int32_t* n_u,
             const uint32_t g = small[i];
             const uint64_t mg = (uint64_t)(edge_offset[g + 1] - edge_offset[g]);
             const uint64_t ng = (uint64_t)n_u[g] + (uint64_t)n_v[g];
-            if (!gl.empty() && (me + mg > kBatchMaxEdges || nn + ng > kBatchMaxVertices ||
+            if (!gl.empty() && (me + mg > c->union_edges || nn + ng > kBatchMaxVertices ||
                                 gl.size() >= kBatchMaxGraphs))
                 break;
             gl.push_back(g);
@@ -1351,15 +1371,30 @@ bbc_status bbc_autotune(bbc_context* c, int32_t n_graphs, const int32_t* n_u, co
     TuneInput in{n_graphs, n_u, n_v, edge_offset, edge_u, edge_v, edge_sign, flags};
     std::vector<bbc_result> res((size_t)n_graphs), ref((size_t)n_graphs);
     std::vector<int32_t> st((size_t)n_graphs), ref_st((size_t)n_graphs);
-    const int pids[3] = {BBC_PARAM_CHUNK_WEDGES, BBC_PARAM_HASH_TARGET, BBC_PARAM_PROBE_LIMIT};
-    const std::vector<int64_t> grid[3] = {{16384, 65536, 262144, 1048576, 4194304},
-                                          {1024, 2048, 4096, 8192},
-                                          {32, 256, 2048}};
-    int64_t cur[3];
-    for (int k = 0; k < 3; ++k) bbc_get_param(c, pids[k], &cur[k]);
-    const int64_t saved[3] = {cur[0], cur[1], cur[2]};
+    // Every tunable, in the order of chosen[].  Which ones are searched depends
+    // on the input: only graphs with more than 16384 vertices on a side cut
+    // starts into end-vertex tiles, so only they make the hash target and the
+    // probe limit matter; only a batch is split into unions.
+    constexpr int kN = 6;
+    const int pids[kN] = {BBC_PARAM_CHUNK_WEDGES, BBC_PARAM_HASH_TARGET, BBC_PARAM_PROBE_LIMIT,
+                          BBC_PARAM_LIGHT_MAX, BBC_PARAM_GRAB_DIV, BBC_PARAM_UNION_EDGES};
+    const bool batch = n_graphs > 1;
+    bool tiles = !batch;  // some graph is counted alone (more than 16384 vertices on a side)
+    for (int32_t g = 0; g < n_graphs && !tiles; ++g)
+        tiles = (uint32_t)std::max(n_u[g], n_v[g]) > kBatchSide;
+    const std::vector<int64_t> grid[kN] = {
+        {16384, 65536, 262144, 1048576, 4194304},
+        tiles ? std::vector<int64_t>{1024, 2048, 4096, 8192} : std::vector<int64_t>{},
+        tiles ? std::vector<int64_t>{32, 256, 2048} : std::vector<int64_t>{},
+        {512, 1024, 2048},
+        {8, 16, 32},
+        batch ? std::vector<int64_t>{1 << 24, 1 << 26, 1 << 28, 1 << 30} : std::vector<int64_t>{}};
+    int64_t cur[kN];
+    for (int k = 0; k < kN; ++k) bbc_get_param(c, pids[k], &cur[k]);
+    int64_t saved[kN];
+    for (int k = 0; k < kN; ++k) saved[k] = cur[k];
     auto restore = [&]() {
-        for (int k = 0; k < 3; ++k) bbc_set_param(c, pids[k], saved[k]);
+        for (int k = 0; k < kN; ++k) bbc_set_param(c, pids[k], saved[k]);
     };
     // reference counts and a warm workspace at the current settings
     double ms = 0;
@@ -1385,7 +1420,7 @@ bbc_status bbc_autotune(bbc_context* c, int32_t n_graphs, const int32_t* n_u, co
         restore();
         return s;
     }
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < kN; ++k) {
         int64_t keep = cur[k];
         for (int64_t v : grid[k]) {
             if (v == keep) continue;
@@ -1405,7 +1440,7 @@ bbc_status bbc_autotune(bbc_context* c, int32_t n_graphs, const int32_t* n_u, co
         bbc_set_param(c, pids[k], keep);
     }
     if (chosen)
-        for (int k = 0; k < 3; ++k) chosen[k] = cur[k];
+        for (int k = 0; k < kN; ++k) chosen[k] = cur[k];
     if (best_ms) *best_ms = best;
     return BBC_OK;
 }

@@ -137,6 +137,8 @@ struct Dims {
     // short-middle wedges carry their middles
     uint32_t per_vertex;
     uint32_t light_window;  // H of the light items (kLightWindow16)
+    uint32_t light_max;     // light starts: W_u <= light_max (at most kLightMax)
+    uint32_t grab_div;      // grabs of total / grab_div records (unsplit pieces, light items)
     // rows in ascending (side, length) order, or NULL when the row index order
     // already is (one graph: rows are sorted by degree within each side)
     const uint32_t* rlist;

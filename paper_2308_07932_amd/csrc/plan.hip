@@ -11,7 +11,7 @@
 //
 // Per start with W_u > 0 (S = number of same-side vertices below u, so the
 // end vertices have sidx in [0, S)):
-//   * light   (W_u <= kLightMax): one hashed piece; many light starts share
+//   * light   (W_u <= light_max <= kLightMax): one hashed piece; many light starts share
 //             one work item, each in its own region of the on-chip table;
 //   * small S (S - lo <= kDenseW, lo = the start's graph block start, 0 for
 //             a single graph): dense counters over [lo, S); split into record
@@ -138,7 +138,7 @@ __device__ inline StartPlan plan_start(const uint32_t* __restrict__ row_ptr, con
         sp.lo = d.blk[side][sp.graph];
     }
     if (W == 0) return sp;
-    if (W <= kLightMax) {
+    if (W <= d.light_max) {
         sp.cls = kClassLight;
         sp.region = max(kMinRegion, next_pow2((uint32_t)(2 * W)));
         return sp;

@@ -343,7 +343,7 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
             // starts and light items up to 64 in grabs of total/16 (at least 8).
             const bool varied = (s_pc[0].flags & kPiecePartial) || (heavy && !dense);
             const uint32_t bsz = varied ? min(32u, max(4u, (total + 31) / 32))
-                                        : min(64u, max(8u, (total + 15) / 16));
+                                        : min(64u, max(8u, (total + a.d.grab_div - 1) / a.d.grab_div));
 
             // pass over the piece's records: count (readback = false) or, in
             // per-vertex mode, read the complete buckets back (readback = true)
@@ -994,7 +994,7 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge_dense(WedgeArgs a) {
         const uint32_t dlo = P.lo, plo = P.lo, phi = P.hi, dwidth = P.hi - P.lo;
         const uint32_t total = P.nrec;
         const uint32_t bsz = partial ? min(32u, max(4u, (total + 31) / 32))
-                                     : min(64u, max(8u, (total + 15) / 16));
+                                     : min(64u, max(8u, (total + a.d.grab_div - 1) / a.d.grab_div));
         const uint32_t* tbl = partial ? a.tb + a.d.tb_off[ys] : nullptr;
         const uint32_t tstride = a.d.ntile[ys ^ 1u] + 1;
         const uint32_t flong = a.first_long[ys];

@@ -268,8 +268,14 @@ def test_autotune_keeps_counts(ctx):
     try:
         chosen, best = tctx.autotune(nu, nv, off, eu, ev, sg, repeats=1)
         assert chosen["chunk_wedges"] in (16384, 65536, 262144, 1048576, 4194304)
-        assert chosen["hash_target"] in (1024, 2048, 4096, 8192)
-        assert chosen["probe_limit"] in (32, 256, 2048)
+        # no graph here is cut into end-vertex tiles: hash target and probe
+        # limit are not searched and keep their defaults
+        assert (chosen["hash_target"], chosen["probe_limit"]) == (4096, 256)
+        assert chosen["light_max"] in (512, 1024, 2048)
+        assert chosen["grab_div"] in (8, 16, 32)
+        assert chosen["union_edges"] in (1 << 24, 1 << 26, 1 << 28, 1 << 30)
+        assert tctx.get_param(bbc.PARAM_LIGHT_MAX) == chosen["light_max"]
+        assert tctx.get_param(bbc.PARAM_UNION_EDGES) == chosen["union_edges"]
         assert best > 0
         assert tctx.get_param(bbc.PARAM_CHUNK_WEDGES) == chosen["chunk_wedges"]
         assert tctx.get_param(bbc.PARAM_HASH_TARGET) == chosen["hash_target"]
@@ -284,3 +290,29 @@ def test_autotune_keeps_counts(ctx):
         assert tctx.count(g.eu, g.ev, g.sign, g.n_u, g.n_v) == want
     finally:
         tctx.close()
+
+
+def test_batch_tunables_never_change_counts(ctx):
+    # the light cut, grab size and union size change how the work is cut,
+    # never a count: extreme settings (many tiny unions, almost no light
+    # starts, one-record grabs) give the same per-graph results
+    graphs = mixed_graphs(17, 120)
+    nu, nv, off, eu, ev, sg = bbc.concat_graphs(graphs)
+    want = ctx.count_batch(nu, nv, off, eu, ev, sg)
+    tctx = bbc.Context(0)
+    try:
+        for lm, gd, ue in ((16, 4, 1 << 16), (2048, 64, 1 << 16), (512, 8, 1 << 20), (1024, 32, 1 << 30)):
+            tctx.set_param(bbc.PARAM_LIGHT_MAX, lm)
+            tctx.set_param(bbc.PARAM_GRAB_DIV, gd)
+            tctx.set_param(bbc.PARAM_UNION_EDGES, ue)
+            got = tctx.count_batch(nu, nv, off, eu, ev, sg)
+            for a, b in zip(want, got):
+                assert np.array_equal(a, b), (lm, gd, ue)
+        with pytest.raises(bbc.BBCError):
+            tctx.set_param(bbc.PARAM_LIGHT_MAX, 4096)
+        with pytest.raises(bbc.BBCError):
+            tctx.set_param(bbc.PARAM_UNION_EDGES, 100)
+    finally:
+        tctx.close()
+    for g in graphs[:12]:
+        assert want.result(graphs.index(g)) == expect(g)
