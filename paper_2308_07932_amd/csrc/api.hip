@@ -51,8 +51,8 @@ hipError_t launch_short_wedges(const uint4*, uint32_t, const uint32_t*, const ui
                                const uint32_t*, const uint32_t*, const uint32_t*, const uint32_t*,
                                uint32_t, uint32_t*, uint32_t*, uint32_t*, uint32_t*, bool,
                                hipStream_t);
-hipError_t launch_wedge(const Piece*, const uint32_t*, const uint32_t*, uint32_t, uint32_t, uint32_t,
-                        const uint4*, const uint32_t*, const uint32_t*, Dims, const uint32_t[2], u64*,
+hipError_t launch_wedge(const Piece*, const uint32_t*, const uint32_t*, uint32_t, uint32_t, Piece*,
+                        uint32_t, const uint4*, const uint32_t*, const uint32_t*, Dims, const uint32_t[2], u64*,
                         const uint32_t*, const uint32_t*, const uint32_t*, Control*, u64*, u64*,
                         uint32_t, hipStream_t);
 hipError_t launch_pv_out(const u64*, const uint32_t*, Dims, u64*, hipStream_t);
@@ -804,6 +804,7 @@ static bbc_status run_pipeline(bbc_context* c, const RunIn& in, RunOut& ro) {
     const uint32_t n_items = n_heavy + n_light_items;
     uint32_t first_long[2] = {h.cls[0][4] - d.base[0], h.cls[1][4] - d.base[1]};
     Piece* pieces;
+    Piece* redo;  // halves of hashed pieces given up on: at most two per hashed piece
     u64* light_off;
     uint32_t* items_first;
     u64* G;
@@ -816,6 +817,7 @@ static bbc_status run_pipeline(bbc_context* c, const RunIn& in, RunOut& ro) {
     {
         auto carve_plan = [&](Carver& cv) {
             pieces = cv.take<Piece>((size_t)n_heavy + n_light);
+            redo = cv.take<Piece>(2 * (size_t)(n_heavy - n_dense) + 1);
             light_off = cv.take<u64>((size_t)n_light + 1);
             items_first = cv.take<uint32_t>((size_t)n_light_items + 2);
             G = cv.take<u64>((size_t)h.tot_g + 1);
@@ -881,7 +883,7 @@ static bbc_status run_pipeline(bbc_context* c, const RunIn& in, RunOut& ro) {
 
     // ---- wedge enumeration and bucket counting
     if (tm) HIPCHECK(c, hipEventRecord(c->ev[kEvWedgeA], st));
-    HIPCHECK(c, launch_wedge(pieces, order, items_first, n_heavy, n_dense, n_items, b.recs, b.col, b.tb, d,
+    HIPCHECK(c, launch_wedge(pieces, order, items_first, n_heavy, n_dense, redo, n_items, b.recs, b.col, b.tb, d,
                              first_long, G, sw_off, sw_list, sw_mid, b.ctl,
                              bt ? bt->gres : nullptr, pv,
                              c->num_cus, st));

@@ -117,6 +117,8 @@ struct Control {
     u64 tot_sw;          // bucketed short-middle wedges of split starts
     u64 n_dense, n_dense16, n_hashed;  // tile pieces by kind
     u64 n_dense_pieces;  // heavy pieces with dense counters (small-side chunks and dense tiles)
+    uint32_t queue_hash;  // work counter of the hashed-piece wedge kernel
+    uint32_t redo_n;      // halves of hashed pieces to redo (in the redo list)
 };
 
 struct Dims {

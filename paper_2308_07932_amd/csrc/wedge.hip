@@ -43,8 +43,10 @@ struct WedgeArgs {
     Control* ctl;
     u64* gres;  // batches: per graph {balanced, unbalanced, wedges, -}; else NULL (totals in ctl)
     u64* pv;    // per-vertex mode: balanced butterflies per row (n entries, zeroed)
-    uint32_t n_dense;  // heavy items 0..n_dense-1 are dense pieces, run by k_wedge_dense
-    uint32_t item0;    // first item k_wedge runs (n_dense, or 0 when it runs them all)
+    uint32_t n_dense;  // heavy items 0..n_dense-1 are dense pieces, n_dense..n_heavy-1 hashed
+    uint32_t item0;    // first item k_wedge runs (n_heavy, or 0 when it runs them all)
+    Piece* redo;       // halves of hashed pieces k_wedge_pieces<true> gave up on (ctl->redo_n),
+                       // run by k_wedge as items n_items, n_items + 1, ...
 };
 
 // Thread 0's running totals for one graph at a time; flushed to memory when
@@ -255,20 +257,28 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
 
     __shared__ GraphAcc s_acc;     // this workgroup's totals (thread 0)
     __shared__ Piece s_pf;         // the next heavy item's piece, fetched ahead
-    __shared__ uint32_t s_pf_item;
+    __shared__ uint32_t s_pf_item, s_nredo;
     if (tid == 0) {
         s_acc.reset();
         s_pf_item = kEmpty;
         s_item = a.item0 + atomicAdd(&a.ctl->queue, 1u);
+        // halves left by the hashed-piece kernel (it ran before this launch)
+        s_nredo = a.redo ? a.ctl->redo_n : 0u;
     }
+    // items: heavy pieces [0, n_heavy), light items [n_heavy, n_items), redo
+    // halves [n_items, n_items + s_nredo)
+    auto is_heavy = [&](uint32_t it) { return it < a.n_heavy || it >= a.n_items; };
+    auto heavy_piece = [&](uint32_t it) {
+        return it < a.n_heavy ? a.pieces[a.order[it]] : a.redo[it - a.n_items];
+    };
     for (;;) {
         __syncthreads();  // every thread is done with the previous item; s_item is set
         const uint32_t item = s_item;
-        if (item >= a.n_items) break;
+        if (item >= a.n_items + s_nredo) break;
         if (tid == 0) s_nextok = 0;  // the next item is taken during this one
         uint32_t np = 1;
-        if (item < a.n_heavy) {
-            if (tid == 0) s_pc[0] = (s_pf_item == item) ? s_pf : a.pieces[a.order[item]];
+        if (is_heavy(item)) {
+            if (tid == 0) s_pc[0] = (s_pf_item == item) ? s_pf : heavy_piece(item);
         } else {
             const uint32_t li = item - a.n_heavy;
             const uint32_t p0 = a.n_heavy + a.items_first[li];
@@ -280,7 +290,7 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
             if (tid < np) s_pc[tid] = a.pieces[p0 + tid];
         }
         if (tid == 0) s_sp = 0;
-        const bool heavy = item < a.n_heavy;
+        const bool heavy = is_heavy(item);
 
         for (;;) {  // the item's pieces, then any re-split halves (heavy items only)
             __syncthreads();
@@ -618,8 +628,8 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
                 if (lane == 0) f = atomicAdd(&s_done, 1u);
                 if (lane == 0 && f == 0 && !s_nextok) {
                     const uint32_t nx = a.item0 + atomicAdd(&a.ctl->queue, 1u);
-                    if (nx < a.n_heavy && s_pf_item != nx) {
-                        s_pf = a.pieces[a.order[nx]];
+                    if (nx < a.n_items + s_nredo && is_heavy(nx) && s_pf_item != nx) {
+                        s_pf = heavy_piece(nx);
                         s_pf_item = nx;
                     }
                     s_next = nx;
@@ -952,31 +962,43 @@ __device__ inline void bucket16_sums(uint32_t c, u64& q2, u64& lm2) {
 
 }  // namespace
 
-__global__ __launch_bounds__(kWedgeThreads) void k_wedge_dense(WedgeArgs a) {
+template <bool HASH>
+__global__ __launch_bounds__(kWedgeThreads) void k_wedge_pieces(WedgeArgs a) {
     __shared__ u64 s_tab[kDenseW];
     __shared__ uint32_t s_wadj[kWaves][64], s_waux[kWaves][64];
     __shared__ uint32_t s_head[kWaves][64];  // head flags, interleaved as in k_wedge
     __shared__ uint32_t s_qadj[kQueue], s_qlen[kQueue], s_qaux[kQueue];
     __shared__ Piece s_p, s_pf;
     __shared__ uint32_t s_item, s_pf_item, s_next, s_nextok, s_done;
-    __shared__ uint32_t s_batch, s_qn, s_qtake, s_swtake;
+    __shared__ uint32_t s_batch, s_qn, s_qtake, s_swtake, s_abort;
     __shared__ u64 s_red[2][kWaves];
     __shared__ GraphAcc s_acc;
     uint32_t* s32 = (uint32_t*)s_tab;
+    uint32_t* keys = (uint32_t*)s_tab;  // 64-bit hashed layout: keys, then counters
+    u64* hvals = s_tab + kHashSlots / 2;
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
+    // dense pieces are heavy items 0 .. n_dense-1, hashed ones n_dense .. n_heavy-1
+    auto fetch = [&]() -> uint32_t {
+        if (HASH) {
+            const uint32_t i = a.n_dense + atomicAdd(&a.ctl->queue_hash, 1u);
+            return i < a.n_heavy ? i : kEmpty;
+        }
+        const uint32_t i = atomicAdd(&a.ctl->queue_dense, 1u);
+        return i < a.n_dense ? i : kEmpty;
+    };
     const uint32_t* __restrict__ col = a.col;
     const u64 le_mask = ~0ull >> (63 - lane);  // lanes 0..lane
     s_head[wave][lane] = 0;
     if (tid == 0) {
         s_acc.reset();
         s_pf_item = kEmpty;
-        s_item = atomicAdd(&a.ctl->queue_dense, 1u);
-        if (s_item < a.n_dense) s_p = a.pieces[a.order[s_item]];
+        s_item = fetch();
+        if (s_item != kEmpty) s_p = a.pieces[a.order[s_item]];
     }
     for (;;) {
         __syncthreads();  // s_item and s_p are set; the previous item is done
         const uint32_t item = s_item;
-        if (item >= a.n_dense) break;
+        if (item == kEmpty) break;
         Piece P;  // wave-uniform: the fields live in scalar registers
         P.rec0 = __builtin_amdgcn_readfirstlane(s_p.rec0);
         P.nrec = __builtin_amdgcn_readfirstlane(s_p.nrec);
@@ -988,7 +1010,12 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge_dense(WedgeArgs a) {
         P.gbase = __builtin_amdgcn_readfirstlane(s_p.gbase);
         P.list = __builtin_amdgcn_readfirstlane(s_p.list);
         P.graph = __builtin_amdgcn_readfirstlane(s_p.graph);
-        const bool d16 = (P.flags & kPieceDense16) != 0;
+        P.region = __builtin_amdgcn_readfirstlane(s_p.region);
+        const bool d16 = !HASH && (P.flags & kPieceDense16) != 0;
+        const bool h16 = HASH && (P.flags & kPieceHash16) != 0;  // else u32 keys + u64 counters
+        // a split piece's hash table may give up (the piece is then redone in
+        // halves by k_wedge); an unsplit one holds at most kHashSlots/2 ends
+        const uint32_t lim = (P.flags & kPiecePartial) ? a.d.probe_limit : kHashSlots;
         const bool partial = (P.flags & kPiecePartial) != 0;
         const uint32_t ys = (P.flags & kPieceSideV) ? 0u : 1u;  // side of the middles
         const uint32_t dlo = P.lo, plo = P.lo, phi = P.hi, dwidth = P.hi - P.lo;
@@ -1003,6 +1030,7 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge_dense(WedgeArgs a) {
             s_qn = s_qtake = s_swtake = 0;
             s_nextok = 0;
             s_done = 0;
+            s_abort = 0;
         }
         // Loads below are issued by every lane (inactive lanes read a valid
         // address and drop the value): a load in a per-lane branch makes the
@@ -1031,14 +1059,38 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge_dense(WedgeArgs a) {
                 }
             }
         };
+        // one wedge into the bucket of end vertex w; false when a hashed table
+        // has no room for w within the probe limit
+        auto add_one = [&](uint32_t w, bool asym) -> bool {
+            if (!HASH) {
+                if (d16)
+                    atomicAdd(&s32[w - dlo], asym ? 0x10000u : 1u);
+                else
+                    atomicAdd(&s_tab[w - dlo], asym ? (1ull << 32) : 1ull);
+                return true;
+            }
+            if (h16) return bucket_add16(s32, lim, w, asym ? 0x10000u : 1u);
+            return bucket_add(s_tab, keys, hvals, false, 0, P.region, lim, w,
+                              asym ? (1ull << 32) : 1ull);
+        };
         DenseGrab cur;
         uint32_t cur_base = wave * bsz;
         if (total > 0) load_rec(cur_base, cur);
         // -- clear the counters of the range (up to a whole 16-byte unit past
         // its end, which the finalize reads), while the records arrive
-        {
+        if (!HASH) {
             const uint32_t words = d16 ? (dwidth + 3) / 4 * 2 : (dwidth + 1) / 2 * 2;
             for (uint32_t i = tid; i < words; i += kWedgeThreads) s_tab[i] = 0;
+        } else if (h16) {
+            for (uint32_t i = tid; i < kHash16Slots; i += kWedgeThreads) {
+                s32[i] = kEmpty;
+                s32[kHash16Slots + i] = 0;
+            }
+        } else {
+            for (uint32_t i = tid; i < kHashSlots; i += kWedgeThreads) {
+                keys[i] = kEmpty;
+                hvals[i] = 0;
+            }
         }
         if (total > 0) load_tiles(cur);
         __syncthreads();  // table cleared, s_batch set
@@ -1138,38 +1190,40 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge_dense(WedgeArgs a) {
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
                 s_head[wave][lane] = 0;
             };
-            auto step_add = [&](const uint32_t* x, const uint32_t* aux) {
+            // the adds of one step; false (for the whole wave) when a hashed
+            // table found no room
+            auto step_add = [&](const uint32_t* x, const uint32_t* aux) -> bool {
+                bool lok = true;
 #pragma unroll
                 for (uint32_t u = 0; u < kUnroll; ++u) {
-                    if (aux[u] == kEmpty) continue;
+                    if (aux[u] == kEmpty || !lok) continue;
                     const uint32_t w = x[u] >> 1;
                     if ((aux[u] & 2u) && (w < plo || w >= phi)) continue;
-                    const bool asym = ((x[u] ^ aux[u]) & 1u) != 0;
-                    if (d16)
-                        atomicAdd(&s32[w - dlo], asym ? 0x10000u : 1u);
-                    else
-                        atomicAdd(&s_tab[w - dlo], asym ? (1ull << 32) : 1ull);
+                    lok = add_one(w, ((x[u] ^ aux[u]) & 1u) != 0);
                 }
+                return !HASH || __ballot(!lok) == 0;
             };
             // two register sets take turns (no copies: a copy of a value still
             // being loaded would wait for the load)
             // the step after the last is loaded too (to a valid address, all
             // lanes marked past T), which keeps the loads out of branches
             uint32_t xb[kUnroll], ab[kUnroll];
+            bool ok = true;
             if (T > 0) {
                 step_load(0, xa, aa);
                 for (uint32_t j = 0;;) {
                     j += 64 * kUnroll;
                     step_load(j, xb, ab);
                     if (j == 64 * kUnroll && nxt_base != kEmpty) load_tiles(nxt);  // records arrived
-                    step_add(xa, aa);
-                    if (j >= T) break;
+                    ok = step_add(xa, aa);
+                    if (j >= T || !ok) break;
                     j += 64 * kUnroll;
                     step_load(j, xa, aa);
-                    step_add(xb, ab);
-                    if (j >= T) break;
+                    ok = step_add(xb, ab);
+                    if (j >= T || !ok) break;
                 }
             }
+            if (!ok) s_abort = 1;  // the piece is abandoned
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             // the next grab: loaded above, or claimed now
             if (nxt_base != kEmpty) {
@@ -1185,7 +1239,7 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge_dense(WedgeArgs a) {
                     load_tiles(cur);
                 }
             }
-            have = cur_base < total;
+            have = cur_base < total && !(HASH && s_abort);
         }
         // -- the bucketed wedges through short middle rows (split starts);
         // the next chunk's entries are loaded before the current chunk's adds
@@ -1205,41 +1259,42 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge_dense(WedgeArgs a) {
                     x[u] = q < n_sw ? v : kEmpty;
                 }
             };
-            auto add = [&](const uint32_t* x) {
+            auto add = [&](const uint32_t* x) -> bool {
+                bool lok = true;
 #pragma unroll
                 for (uint32_t u = 0; u < kUnroll; ++u) {
-                    if (x[u] == kEmpty) continue;
+                    if (x[u] == kEmpty || !lok) continue;
                     const uint32_t w = x[u] >> 1;
                     if (w < plo || w >= phi) continue;
-                    if (d16)
-                        atomicAdd(&s32[w - dlo], (x[u] & 1u) ? 0x10000u : 1u);
-                    else
-                        atomicAdd(&s_tab[w - dlo], (x[u] & 1u) ? (1ull << 32) : 1ull);
+                    lok = add_one(w, (x[u] & 1u) != 0);
                 }
+                return !HASH || __ballot(!lok) == 0;
             };
             uint32_t xa[kUnroll], xb[kUnroll];
-            uint32_t c = n_sw > 0 ? take() : n_sw;
+            uint32_t c = (n_sw > 0 && !(HASH && s_abort)) ? take() : n_sw;
+            bool ok = true;
             if (c < n_sw) {
                 load(c, xa);
                 for (;;) {
                     c = take();
                     load(c, xb);  // past the end: all lanes marked empty
-                    add(xa);
-                    if (c >= n_sw) break;
+                    ok = add(xa);
+                    if (c >= n_sw || !ok) break;
                     c = take();
                     load(c, xa);
-                    add(xb);
-                    if (c >= n_sw) break;
+                    ok = add(xb);
+                    if (c >= n_sw || !ok) break;
                 }
             }
+            if (!ok) s_abort = 1;
         }
         // the first wave done takes the next item and fetches its piece
         {
             uint32_t f = 1;
             if (lane == 0) f = atomicAdd(&s_done, 1u);
             if (lane == 0 && f == 0) {
-                const uint32_t nx = atomicAdd(&a.ctl->queue_dense, 1u);
-                if (nx < a.n_dense) {
+                const uint32_t nx = fetch();
+                if (nx != kEmpty) {
                     s_pf = a.pieces[a.order[nx]];
                     s_pf_item = nx;
                 }
@@ -1249,12 +1304,12 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge_dense(WedgeArgs a) {
         }
         __syncthreads();
         // -- queued chunks of long sub-intervals: one wave per chunk
-        if (s_qn > 0) {
+        if (s_qn > 0 && !(HASH && s_abort)) {
             for (;;) {
                 uint32_t c = 0;
                 if (lane == 0) c = atomicAdd(&s_qtake, 1u);
                 c = __shfl(c, 0, 64);
-                if (c >= s_qn) break;
+                if (c >= s_qn || (HASH && s_abort)) break;
                 const uint32_t adj = s_qadj[c], qlen = s_qlen[c], aux = s_qaux[c];
                 auto load = [&](uint32_t e0, uint32_t* x) {
 #pragma unroll
@@ -1264,37 +1319,66 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge_dense(WedgeArgs a) {
                         x[u] = e < qlen ? v : kEmpty;
                     }
                 };
-                auto add = [&](const uint32_t* x) {
+                auto add = [&](const uint32_t* x) -> bool {
+                    bool lok = true;
 #pragma unroll
                     for (uint32_t u = 0; u < kUnroll; ++u) {
-                        if (x[u] == kEmpty) continue;
+                        if (x[u] == kEmpty || !lok) continue;
                         const uint32_t w = x[u] >> 1;
                         if ((aux & 2u) && (w < plo || w >= phi)) continue;
-                        const bool asym = ((x[u] ^ aux) & 1u) != 0;
-                        if (d16)
-                            atomicAdd(&s32[w - dlo], asym ? 0x10000u : 1u);
-                        else
-                            atomicAdd(&s_tab[w - dlo], asym ? (1ull << 32) : 1ull);
+                        lok = add_one(w, ((x[u] ^ aux) & 1u) != 0);
                     }
+                    return !HASH || __ballot(!lok) == 0;
                 };
                 uint32_t xa[kUnroll], xb[kUnroll];
+                bool ok = true;
                 load(0, xa);
                 for (uint32_t e0 = 0;;) {
                     e0 += 64 * kUnroll;
                     load(e0, xb);
-                    add(xa);
-                    if (e0 >= qlen) break;
+                    ok = add(xa);
+                    if (e0 >= qlen || !ok) break;
                     e0 += 64 * kUnroll;
                     load(e0, xa);
-                    add(xb);
-                    if (e0 >= qlen) break;
+                    ok = add(xb);
+                    if (e0 >= qlen || !ok) break;
                 }
+                if (!ok) s_abort = 1;
             }
-            __syncthreads();
         }
+        __syncthreads();  // every wave is done with the piece's wedges; s_abort is final
+        const bool aborted = HASH && s_abort;
         // -- finalize: C(l,2) + C(m,2) and l*m over the range
         u64 bal = 0, unb = 0;
-        if (d16 && !(P.flags & kPieceMerge)) {
+        if (aborted) {
+            // counts abandoned: the piece is redone in halves by k_wedge
+        } else if (HASH && h16) {
+            // counters of empty slots are zero; l + m < 2^16 (a start with
+            // fewer than 2^16 middles)
+            const uint4* c4 = reinterpret_cast<const uint4*>(s32 + kHash16Slots);
+            u64 q2 = 0, lm2 = 0;
+            for (uint32_t g = tid; g < kHash16Slots / 4; g += kWedgeThreads) {
+                const uint4 c = c4[g];
+                bucket16_sums(c.x, q2, lm2);
+                bucket16_sums(c.y, q2, lm2);
+                bucket16_sums(c.z, q2, lm2);
+                bucket16_sums(c.w, q2, lm2);
+            }
+            bal = q2 >> 1;
+            unb = lm2 >> 1;
+        } else if (HASH) {
+            const ulonglong2* v2 = reinterpret_cast<const ulonglong2*>(hvals);
+            for (uint32_t g = tid; g < kHashSlots / 2; g += kWedgeThreads) {
+                const ulonglong2 c = v2[g];
+                const u64 cc[2] = {c.x, c.y};
+#pragma unroll
+                for (int k = 0; k < 2; ++k) {
+                    const u64 l = cc[k] & 0xFFFFFFFFull, mm = cc[k] >> 32;
+                    bal += choose2(l) + choose2(mm);
+                    unb += l * mm;
+                }
+            }
+        } else if (d16 && !(P.flags & kPieceMerge)) {
             // 2 (C(l,2) + C(m,2)) and 2 l m from dot products of the halves
             // (l + m < 2^16); entries past the range and unreached ones are zero
             const uint4* t4 = reinterpret_cast<const uint4*>(s32);
@@ -1353,10 +1437,33 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge_dense(WedgeArgs a) {
                 sb += s_red[0][w];
                 su += s_red[1][w];
             }
-            s_acc.add(a, P.graph, sb, su);
-            const uint32_t nx = s_nextok ? s_next : atomicAdd(&a.ctl->queue_dense, 1u);
+            if (!aborted) {
+                s_acc.add(a, P.graph, sb, su);
+            } else {
+                // redo as the two halves of its tile run, or, for a single tile,
+                // with dense counters (which always fit): k_wedge runs them
+                atomicAdd(&a.ctl->resplits, 1ull);
+                Piece Q = s_p;
+                if (!(Q.flags & kPiecePartial)) {
+                    atomicOr(&a.ctl->internal_err, 1u);  // cannot happen by construction
+                } else if (Q.t1 - Q.t0 > 1) {
+                    const uint32_t tm = (Q.t0 + Q.t1) >> 1;
+                    Piece hi = Q;
+                    hi.t0 = tm;
+                    hi.lo = tm * kTile;
+                    Q.t1 = tm;
+                    Q.hi = min(Q.hi, tm * kTile);
+                    const uint32_t r = atomicAdd(&a.ctl->redo_n, 2u);
+                    a.redo[r] = Q;
+                    a.redo[r + 1] = hi;
+                } else {
+                    Q.flags |= kPieceDense;
+                    a.redo[atomicAdd(&a.ctl->redo_n, 1u)] = Q;
+                }
+            }
+            const uint32_t nx = s_nextok ? s_next : fetch();
             s_item = nx;
-            if (nx < a.n_dense) s_p = (s_pf_item == nx) ? s_pf : a.pieces[a.order[nx]];
+            if (nx != kEmpty) s_p = (s_pf_item == nx) ? s_pf : a.pieces[a.order[nx]];
         }
     }
     if (tid == 0) s_acc.flush(a);
@@ -1377,10 +1484,12 @@ hipError_t launch_pv_out(const u64* pv, const uint32_t* sidx_of, Dims d, u64* ou
     return hipGetLastError();
 }
 
-// Plain count: the dense heavy items (0..n_dense-1) run in k_wedge_dense, then
-// the rest in k_wedge; per-vertex mode runs every item in k_wedge<true>.
+// Plain count: the dense heavy items (0..n_dense-1) run in k_wedge_pieces<false>,
+// the hashed ones in k_wedge_pieces<true>, then the light items and the halves
+// of hashed pieces redone in k_wedge; per-vertex mode runs every item in
+// k_wedge<true>.
 hipError_t launch_wedge(const Piece* pieces, const uint32_t* order, const uint32_t* items_first,
-                        uint32_t n_heavy, uint32_t n_dense,
+                        uint32_t n_heavy, uint32_t n_dense, Piece* redo,
                         uint32_t n_items, const uint4* recs, const uint32_t* col, const uint32_t* tb,
                         Dims d, const uint32_t first_long[2], u64* G, const uint32_t* sw_off,
                         const uint32_t* sw_list, const uint32_t* sw_mid, Control* ctl, u64* gres,
@@ -1406,14 +1515,20 @@ hipError_t launch_wedge(const Piece* pieces, const uint32_t* order, const uint32
     a.gres = gres;
     a.pv = pv;
     a.n_dense = pv ? 0 : n_dense;
-    a.item0 = a.n_dense;
-    if (a.n_dense > 0) {
-        const uint32_t grid = min(num_cus, a.n_dense);
-        hipLaunchKernelGGL(k_wedge_dense, dim3(grid), dim3(kWedgeThreads), 0, st, a);
+    a.item0 = pv ? 0 : n_heavy;
+    a.redo = pv ? nullptr : redo;
+    if (!pv && n_dense > 0) {
+        const uint32_t grid = min(num_cus, n_dense);
+        hipLaunchKernelGGL(k_wedge_pieces<false>, dim3(grid), dim3(kWedgeThreads), 0, st, a);
     }
+    if (!pv && n_heavy > n_dense) {
+        const uint32_t grid = min(num_cus, n_heavy - n_dense);
+        hipLaunchKernelGGL(k_wedge_pieces<true>, dim3(grid), dim3(kWedgeThreads), 0, st, a);
+    }
+    // light items, and any halves the hashed pieces left
     const uint32_t rest = n_items - a.item0;
     uint32_t grid = num_cus;
-    if (grid > rest) grid = rest;
+    if (grid > rest && (pv || n_heavy == n_dense)) grid = rest;
     if (grid == 0) return hipGetLastError();
     if (pv)
         hipLaunchKernelGGL(k_wedge<true>, dim3(grid), dim3(kWedgeThreads), 0, st, a);
