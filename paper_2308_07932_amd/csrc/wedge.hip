@@ -22,6 +22,8 @@
 // fills up is abandoned (its counts are never added) and redone as two halves
 // of its tile run; a single tile is redone with dense counters, which always
 // fit, so every piece ends exact.
+#include <type_traits>
+
 #include "bbc_internal.h"
 
 namespace bbc {
@@ -1095,20 +1097,24 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge_pieces(WedgeArgs a) {
         if (total > 0) load_tiles(cur);
         __syncthreads();  // table cleared, s_batch set
 
-        // -- the records, grab by grab
+        // -- the records, grab by grab; the sweep is compiled once per counter
+        // width (D16: u32 l | m << 16, else u64), chosen per piece
+        auto records = [&](auto d16tag) {
+        constexpr bool D16 = decltype(d16tag)::value;
         bool have = cur_base < total;
         while (have) {
-            // this lane's sub-interval [ia, ib) of its middle row
-            uint32_t ia = 0, ib = cur.pos, filt = 0;
+            // this lane's sub-interval [ia, ib) of its middle row.  A split
+            // start's pieces hold its long-middle records only (the planner
+            // gives them the records before its first short one), and every
+            // long middle row has a tile table.
+            uint32_t ia = 0, ib = cur.pos;
             if (partial && cur.pos > 0) {
                 if (cur.vs >= flong) {
                     ia = min(cur.ta, cur.pos);
                     ib = min(cur.tb, cur.pos);
-                } else if (cur.pos <= kScanMax) {
-                    filt = 1;  // short prefix: read it all, keep the entries in [lo, hi)
                 } else {
-                    ia = lower_bound_u32(col + cur.rs, cur.pos, plo << 1);
-                    ib = ia + lower_bound_u32(col + cur.rs + ia, cur.pos - ia, phi << 1);
+                    ib = 0;
+                    atomicOr(&a.ctl->internal_err, 4u);  // cannot happen by construction
                 }
             }
             const uint32_t rs = cur.rs, s1 = cur.s1;
@@ -1145,7 +1151,7 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge_pieces(WedgeArgs a) {
                         const uint32_t c0 = keep_end + c * kChunk;
                         s_qadj[old + c] = rs + c0;
                         s_qlen[old + c] = min(kChunk, ib - c0);
-                        s_qaux[old + c] = s1 | (filt << 1);
+                        s_qaux[old + c] = s1;
                     }
                     ib = keep_end;
                 }
@@ -1157,7 +1163,7 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge_pieces(WedgeArgs a) {
             if (len > 0) {
                 const uint32_t ci = (uint32_t)__popcll(nz & (le_mask >> 1));
                 s_wadj[wave][ci] = rs + ia - excl;
-                s_waux[wave][ci] = s1 | (filt << 1);
+                s_waux[wave][ci] = s1;
             }
             // -- sweep the T concatenated wedges, kUnroll windows of 64 per step;
             // the entries of step j + 1 are loaded before the adds of step j
@@ -1174,12 +1180,16 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge_pieces(WedgeArgs a) {
                 uint32_t adj[kUnroll];
 #pragma unroll
                 for (uint32_t u = 0; u < kUnroll; ++u) {
-                    const u64 M = __ballot(((hd4 >> (8 * u)) & 0xFFu) != 0);
-                    const uint32_t idx = before + (uint32_t)__popcll(M & le_mask) - 1u;
+                    // owner = heads before the window + heads at or before this lane - 1
+                    const bool own = ((hd4 >> (8 * u)) & 0xFFu) != 0;
+                    const u64 M = __ballot(own);
+                    const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+                        (uint32_t)(M >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)M, 0u));
+                    const uint32_t idx = before + below + (own ? 1u : 0u) - 1u;
                     before += (uint32_t)__popcll(M);
                     const bool in = j + u * 64 + lane < T;
                     const uint32_t ii = in ? idx : 0u;
-                    aux[u] = in ? s_waux[wave][ii] : kEmpty;
+                    aux[u] = in ? s_waux[wave][ii] : 2u;  // bit 1: past the end
                     adj[u] = s_wadj[wave][ii];
                 }
 #pragma unroll
@@ -1193,15 +1203,27 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge_pieces(WedgeArgs a) {
             // the adds of one step; false (for the whole wave) when a hashed
             // table found no room
             auto step_add = [&](const uint32_t* x, const uint32_t* aux) -> bool {
+                if (!HASH) {
+                    // no branches: a lane past the end adds 0 to a word of its own
+#pragma unroll
+                    for (uint32_t u = 0; u < kUnroll; ++u) {
+                        const bool v = (aux[u] & 2u) == 0;
+                        const bool asym = ((x[u] ^ aux[u]) & 1u) != 0;
+                        const uint32_t at = v ? (x[u] >> 1) - dlo : lane;
+                        if (D16)
+                            atomicAdd(&s32[at], v ? (asym ? 0x10000u : 1u) : 0u);
+                        else
+                            atomicAdd(&s_tab[at], v ? (asym ? (1ull << 32) : 1ull) : 0ull);
+                    }
+                    return true;
+                }
                 bool lok = true;
 #pragma unroll
                 for (uint32_t u = 0; u < kUnroll; ++u) {
-                    if (aux[u] == kEmpty || !lok) continue;
-                    const uint32_t w = x[u] >> 1;
-                    if ((aux[u] & 2u) && (w < plo || w >= phi)) continue;
-                    lok = add_one(w, ((x[u] ^ aux[u]) & 1u) != 0);
+                    if ((aux[u] & 2u) || !lok) continue;
+                    lok = add_one(x[u] >> 1, ((x[u] ^ aux[u]) & 1u) != 0);
                 }
-                return !HASH || __ballot(!lok) == 0;
+                return __ballot(!lok) == 0;
             };
             // two register sets take turns (no copies: a copy of a value still
             // being loaded would wait for the load)
@@ -1241,6 +1263,11 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge_pieces(WedgeArgs a) {
             }
             have = cur_base < total && !(HASH && s_abort);
         }
+        };
+        if (!HASH && d16)
+            records(std::integral_constant<bool, true>());
+        else
+            records(std::integral_constant<bool, false>());
         // -- the bucketed wedges through short middle rows (split starts);
         // the next chunk's entries are loaded before the current chunk's adds
         if (partial && P.list != kEmpty) {
@@ -1325,7 +1352,6 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge_pieces(WedgeArgs a) {
                     for (uint32_t u = 0; u < kUnroll; ++u) {
                         if (x[u] == kEmpty || !lok) continue;
                         const uint32_t w = x[u] >> 1;
-                        if ((aux & 2u) && (w < plo || w >= phi)) continue;
                         lok = add_one(w, ((x[u] ^ aux) & 1u) != 0);
                     }
                     return !HASH || __ballot(!lok) == 0;
