@@ -283,10 +283,11 @@ bbc_status bbc_last_phase_ms(const bbc_context* ctx, int phase, double* ms);
  * u->v with v below u), [4] = work items run by the wedge kernel,
  * [5] = hashed work pieces whose on-chip table overflowed and that were
  * redone in smaller parts, [6] = start vertices with at least one wedge,
- * [7] = heavy work items (one piece of one start each), [8], [9], [10] =
- * pieces of starts cut into end-vertex tiles: one dense tile, two dense
- * tiles with 16-bit counters, a hashed run of tiles.  `n` is the capacity of
- * `stats`; up to 11 values are written.
+ * [7] = heavy work items (one piece of one start each), [8], [9], [10],
+ * [11], [12] = pieces of starts cut into end-vertex tiles: one dense tile
+ * (32-bit counters), two dense tiles with 16-bit counters, a hashed run of
+ * tiles, four dense tiles with 8-bit counters, eight dense tiles with 4-bit
+ * counters.  `n` is the capacity of `stats`; up to 13 values are written.
  */
 bbc_status bbc_last_stats(const bbc_context* ctx, int64_t* stats, int n);
 

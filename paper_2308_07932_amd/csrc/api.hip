@@ -87,7 +87,7 @@ struct bbc_context {
     bool timing = false;
     bool timing_valid = false;
     double phase_ms[4] = {0, 0, 0, 0};
-    int64_t stats[11] = {0};
+    int64_t stats[13] = {0};
     uint32_t hash_target = bbc::kDefaultHashTarget;
     uint32_t probe_limit = bbc::kDefaultProbeLimit;
     uint64_t chunk_min = bbc::kRecordChunkWedges;
@@ -499,7 +499,7 @@ bbc_status bbc_last_phase_ms(const bbc_context* c, int phase, double* ms) {
 
 bbc_status bbc_last_stats(const bbc_context* c, int64_t* stats, int n) {
     if (!c || !stats || n < 0) return BBC_ERR_INVALID_ARG;
-    for (int i = 0; i < n && i < 11; ++i) stats[i] = c->stats[i];
+    for (int i = 0; i < n && i < 13; ++i) stats[i] = c->stats[i];
     return BBC_OK;
 }
 
@@ -902,7 +902,11 @@ static bbc_status run_pipeline(bbc_context* c, const RunIn& in, RunOut& ro) {
     h = *c->host_ctl;
     ro.h = h;
     if (h.internal_err)
-        return fail(c, BBC_ERR_INTERNAL, "a hashed work piece could not be split further");
+        return fail(c, BBC_ERR_INTERNAL,
+                    "wedge kernel invariant broken (flags %u: 1 = an unsplit hashed piece gave up, "
+                    "4 = a split piece met a short-middle record, 8 = a packed piece reached the "
+                    "general kernel)",
+                    h.internal_err);
     if (tm_out && !c->use_graphs) {
         c->phase_ms[0] += ev_ms(c, kEvStart, kEvEnd);
         c->phase_ms[1] += ev_ms(c, kEvStart, kEvPrepEnd);
@@ -930,6 +934,8 @@ static void add_stats(bbc_context* c, const RunOut& ro, uint64_t m) {
     c->stats[8] += (int64_t)ro.h.n_dense;
     c->stats[9] += (int64_t)ro.h.n_dense16;
     c->stats[10] += (int64_t)ro.h.n_hashed;
+    c->stats[11] += (int64_t)ro.h.n_dense8;
+    c->stats[12] += (int64_t)ro.h.n_dense4;
 }
 
 static void begin_call(bbc_context* c) {
@@ -1275,10 +1281,10 @@ bbc_status bbc_count_batch(bbc_context* c, int32_t n_graphs, const int32_t* n_u,
         else
             small.push_back((uint32_t)g);
     }
-    int64_t stats[11] = {0};
+    int64_t stats[13] = {0};
     double ph[4] = {0, 0, 0, 0};
     auto keep_stats = [&]() {
-        for (int i = 0; i < 11; ++i) stats[i] += c->stats[i];
+        for (int i = 0; i < 13; ++i) stats[i] += c->stats[i];
         for (int i = 0; i < 4; ++i) ph[i] += c->phase_ms[i];
     };
     // unions: consecutive small graphs up to the size limits

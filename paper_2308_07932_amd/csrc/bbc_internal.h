@@ -77,6 +77,12 @@ constexpr uint32_t kPiecePartial = 4u;  // w-range is a tile range: look up sub-
 constexpr uint32_t kPieceSideV = 8u;    // the start vertex lies on side V
 constexpr uint32_t kPieceDense16 = 16u; // dense with 16-bit l | m halves (two tiles wide)
 constexpr uint32_t kPieceHash16 = 32u;  // hashed with 16-bit l | m halves (2 x kHashSlots slots)
+// Packed dense counters.  l + m <= |N(u) & N(w)| <= deg(w), so over end
+// vertices of degree at most 2^b - 1 both counts fit in b bits: a u32 word
+// then holds 32 / 2b end vertices and one 128 KiB table spans more tiles.
+constexpr uint32_t kPieceDense8 = 64u;   // l | m << 8 per end vertex, two per word (four tiles)
+constexpr uint32_t kPieceDense4 = 128u;  // l | m << 4 per end vertex, four per word (eight tiles)
+constexpr uint32_t kDensePacked = kPieceDense8 | kPieceDense4;
 
 // One unit of counting: records [rec0, rec0 + nrec) of one start vertex,
 // restricted to end vertices with sidx in [lo, hi).
@@ -119,6 +125,7 @@ struct Control {
     u64 n_dense_pieces;  // heavy pieces with dense counters (small-side chunks and dense tiles)
     uint32_t queue_hash;  // work counter of the hashed-piece wedge kernel
     uint32_t redo_n;      // halves of hashed pieces to redo (in the redo list)
+    u64 n_dense8, n_dense4;  // tile pieces with packed 8- and 4-bit counters
 };
 
 struct Dims {

@@ -55,48 +55,67 @@ __device__ inline uint32_t cost_key(double wedges, uint32_t nrec, bool dense) {
     return (dense ? 0u : 1u << 16) | (65535u - (uint32_t)fmin(q, 65535.0));
 }
 
+// Kinds of the pieces of a split start
+enum : uint32_t { kRunHash = 0, kRunD32, kRunD16, kRunD8, kRunD4 };
+
 // Tile runs of a start with end-vertex space [0, S) on the side whose rows start
-// at `base`; calls emit(t0, t1, dense, expected wedges) per run and returns the
-// number of runs.  A tile of degree mass x is expected to hold W * x / tot
-// wedges; "more than target" is tested exactly as x * W > target * tot.  With
-// `pair` (the start has fewer than 2^16 middles, so no bucket can reach 2^16
-// and 16-bit counter halves suffice), two neighbouring dense tiles share one
-// dense piece (t1 = t0 + 2), and hashed runs, whose table then has twice the
-// slots, may hold twice the target.
+// at `base`; calls emit(t0, t1, kind, expected wedges) per run and returns the
+// number of runs.  A range of degree mass x is expected to hold W * x / tot
+// wedges; "more than target" is tested exactly as x * W > target * tot.
+//
+// From tile t the widest dense counters that fit are chosen: a bucket's counts
+// satisfy l + m <= min(k, deg(w)) (k = the start's middles), and rows are
+// sorted by degree, so the last end vertex of a range bounds them all.  With
+// `pack`, counters of 4 bits (eight tiles per piece) or 8 bits (four tiles)
+// per half are tried first; then 16 bits (two tiles), else 32 (one tile).
+// When the range is expected to hold more than the target it becomes one
+// dense piece; otherwise tile t joins the open hashed run, which holds up to
+// the target (twice that with 16-bit table halves, k < 2^16).
 template <typename F>
 __device__ uint32_t plan_runs(const uint32_t* __restrict__ row_ptr, uint32_t base, uint32_t S,
-                              u64 W, uint32_t target, bool pair, F emit) {
+                              u64 W, uint32_t k, uint32_t target, bool pack, F emit) {
     using u128 = unsigned __int128;
     const uint32_t T = (S + kTile - 1) / kTile;
     const u64 tot = row_ptr[base + S] - row_ptr[base];
     const u128 lim = (u128)target * tot;
-    const u128 lim_run = pair ? 2 * lim : lim;
+    const u128 lim_run = k < (1u << 16) ? 2 * lim : lim;
     auto est = [&](u64 x) { return tot > 0 ? (double)x * (double)W / (double)tot : 0.0; };
+    // the largest possible count of a bucket whose end vertex is below sidx hi
+    auto bound = [&](uint32_t hi) {
+        const uint32_t dg = row_ptr[base + hi] - row_ptr[base + hi - 1];
+        return min(k, dg);
+    };
     uint32_t n = 0, rs = kNoTile;
     u64 rx = 0;  // degree mass of the open run
-    for (uint32_t t = 0; t < T; ++t) {
-        const uint32_t lo = t * kTile, hi = min(S, lo + kTile);
-        const u64 x = row_ptr[base + hi] - row_ptr[base + lo];
-        if ((u128)x * W > lim) {
+    for (uint32_t t = 0; t < T;) {
+        uint32_t span = 1, kind = kRunD32;
+        if (pack && bound(min(S, (t + 8) * kTile)) <= 15u) {
+            span = 8;
+            kind = kRunD4;
+        } else if (pack && bound(min(S, (t + 4) * kTile)) <= 255u) {
+            span = 4;
+            kind = kRunD8;
+        } else if (bound(min(S, (t + 2) * kTile)) <= 65535u) {
+            span = 2;
+            kind = kRunD16;
+        }
+        const uint32_t t1 = min(T, t + span);
+        const uint32_t lo = t * kTile;
+        const u64 xs = row_ptr[base + min(S, t1 * kTile)] - row_ptr[base + lo];
+        if ((u128)xs * W > lim) {
             if (rs != kNoTile) {
-                emit(rs, t, false, est(rx));
+                emit(rs, t, kRunHash, est(rx));
                 ++n;
                 rs = kNoTile;
             }
-            if (pair && t + 1 < T) {
-                const uint32_t hi2 = min(S, hi + kTile);
-                const u64 x2 = row_ptr[base + hi2] - row_ptr[base + hi];
-                if ((u128)x2 * W > lim) {
-                    emit(t, t + 2, true, est(x + x2));
-                    ++n;
-                    ++t;
-                    continue;
-                }
-            }
-            emit(t, t + 1, true, est(x));
+            emit(t, t1, kind, est(xs));
             ++n;
-        } else if (rs != kNoTile && (u128)(rx + x) * W > lim_run) {
-            emit(rs, t, false, est(rx));
+            t = t1;
+            continue;
+        }
+        const u64 x = row_ptr[base + min(S, lo + kTile)] - row_ptr[base + lo];
+        if (rs != kNoTile && (u128)(rx + x) * W > lim_run) {
+            emit(rs, t, kRunHash, est(rx));
             ++n;
             rs = t;
             rx = x;
@@ -107,9 +126,10 @@ __device__ uint32_t plan_runs(const uint32_t* __restrict__ row_ptr, uint32_t bas
             }
             rx += x;
         }
+        ++t;
     }
     if (rs != kNoTile) {
-        emit(rs, T, false, est(rx));
+        emit(rs, T, kRunHash, est(rx));
         ++n;
     }
     return n;
@@ -155,9 +175,9 @@ __device__ inline StartPlan plan_start(const uint32_t* __restrict__ row_ptr, con
     const uint32_t T = (S + kTile - 1) / kTile;
     bool whole = false;
     sp.cls = kClassTiles;
-    sp.pieces = plan_runs(row_ptr, d.base[side], S, W, d.hash_target,
-                          k < (1u << 16), [&](uint32_t t0, uint32_t t1, bool dense, double) {
-                              whole = whole || (t0 == 0 && t1 == T && !dense);
+    sp.pieces = plan_runs(row_ptr, d.base[side], S, W, k, d.hash_target, !d.per_vertex,
+                          [&](uint32_t t0, uint32_t t1, uint32_t kind, double) {
+                              whole = whole || (t0 == 0 && t1 == T && kind == kRunHash);
                           });
     // One hashed run over everything is left unsplit only when its W wedges
     // cannot fill the table (at most W distinct ends); otherwise it keeps its
@@ -180,18 +200,17 @@ __global__ void k_plan_count(const u64* __restrict__ wu, const u64* __restrict__
         const uint32_t side = r >= d.n_u ? 1u : 0u;
         if (sp.cls == kClassTiles && d.n_graphs > 1) atomicOr(&ctl->internal_err, 2u);
         if (sp.cls == kClassTiles) {  // tile pieces by kind
-            u64 nd = 0, nd16 = 0, nh = 0;
-            plan_runs(row_ptr, d.base[side], r - d.base[side], W, d.hash_target,
-                      lowcnt[r] < (1u << 16),
-                      [&](uint32_t t0, uint32_t t1, bool dense, double) {
-                          if (!dense) ++nh;
-                          else if (t1 - t0 == 2) ++nd16;
-                          else ++nd;
-                      });
-            if (nd) atomicAdd(&ctl->n_dense, nd);
-            if (nd16) atomicAdd(&ctl->n_dense16, nd16);
-            if (nh) atomicAdd(&ctl->n_hashed, nh);
-            if (nd + nd16) atomicAdd(&ctl->n_dense_pieces, nd + nd16);
+            u64 nk[5] = {0, 0, 0, 0, 0};  // by kind
+            plan_runs(row_ptr, d.base[side], r - d.base[side], W, lowcnt[r], d.hash_target,
+                      !d.per_vertex,
+                      [&](uint32_t, uint32_t, uint32_t kind, double) { ++nk[kind]; });
+            if (nk[kRunD32]) atomicAdd(&ctl->n_dense, nk[kRunD32]);
+            if (nk[kRunD16]) atomicAdd(&ctl->n_dense16, nk[kRunD16]);
+            if (nk[kRunD8]) atomicAdd(&ctl->n_dense8, nk[kRunD8]);
+            if (nk[kRunD4]) atomicAdd(&ctl->n_dense4, nk[kRunD4]);
+            if (nk[kRunHash]) atomicAdd(&ctl->n_hashed, nk[kRunHash]);
+            const u64 ndense = nk[kRunD32] + nk[kRunD16] + nk[kRunD8] + nk[kRunD4];
+            if (ndense) atomicAdd(&ctl->n_dense_pieces, ndense);
         } else if (sp.cls == kClassSmallSide) {
             atomicAdd(&ctl->n_dense_pieces, (u64)sp.pieces);
         }
@@ -276,9 +295,10 @@ __global__ void k_plan_write(const u64* __restrict__ wu, const uint32_t* __restr
         const bool bucketed = split;
         const uint32_t nlong = front[r] - m0;
         uint32_t i = 0;
-        plan_runs(row_ptr, d.base[side], S, W, d.hash_target, k < (1u << 16),
-                  [&](uint32_t t0, uint32_t t1, bool dense, double est) {
+        plan_runs(row_ptr, d.base[side], S, W, k, d.hash_target, !d.per_vertex,
+                  [&](uint32_t t0, uint32_t t1, uint32_t kind, double est) {
             if (i >= h) return;
+            const bool dense = kind != kRunHash;
             Piece p;
             p.rec0 = m0;
             p.nrec = bucketed ? nlong : k;
@@ -289,7 +309,8 @@ __global__ void k_plan_write(const u64* __restrict__ wu, const uint32_t* __restr
             p.region = log2_pow2(kHashSlots) << 16;
             const bool pair = k < (1u << 16);
             p.flags = (split ? kPiecePartial : 0u) | (dense ? kPieceDense : 0u) |
-                      ((dense && t1 - t0 == 2) ? kPieceDense16 : 0u) |
+                      (kind == kRunD16 ? kPieceDense16 : 0u) | (kind == kRunD8 ? kPieceDense8 : 0u) |
+                      (kind == kRunD4 ? kPieceDense4 : 0u) |
                       ((!dense && split && pair) ? kPieceHash16 : 0u) | sideflag;
             p.gbase = kEmpty;
             p.start_row = r;

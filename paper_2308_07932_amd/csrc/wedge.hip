@@ -323,6 +323,9 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
             }
             const bool dense = (s_pc[0].flags & kPieceDense) != 0;
             const bool d16 = (s_pc[0].flags & kPieceDense16) != 0;  // u32 counters l | m << 16
+            // packed counters run in k_wedge_pieces only (never planned in
+            // per-vertex mode, and a redone piece is hashed or 32-bit dense)
+            if (tid == 0 && (s_pc[0].flags & kDensePacked)) atomicOr(&a.ctl->internal_err, 8u);
             const bool h16 = !dense && (s_pc[0].flags & kPieceHash16) != 0;
             const uint32_t dlo = s_pc[0].lo;
             const uint32_t dwidth = s_pc[0].hi - s_pc[0].lo;
@@ -962,6 +965,27 @@ __device__ inline void bucket16_sums(uint32_t c, u64& q2, u64& lm2) {
                                   false);
 }
 
+// The same sums over a word of two 8-bit-half buckets (bytes l0, m0, l1, m1):
+// every byte squared minus every byte, and each byte times its partner
+__device__ inline void bucket8_sums(uint32_t c, uint32_t& q2, uint32_t& lm2) {
+    const uint32_t sw = ((c >> 8) & 0x00FF00FFu) | ((c & 0x00FF00FFu) << 8);
+    q2 += __builtin_amdgcn_udot4(c, c, 0u, false) - __builtin_amdgcn_udot4(c, 0x01010101u, 0u, false);
+    lm2 += __builtin_amdgcn_udot4(c, sw, 0u, false);
+}
+
+// ... and over a word of four 4-bit-half buckets (byte i = l_i | m_i << 4,
+// l_i + m_i <= 15): the l and m nibbles split into bytes first
+__device__ inline void bucket4_sums(uint32_t c, uint32_t& q2, uint32_t& lm2) {
+    const uint32_t l = c & 0x0F0F0F0Fu, m = (c >> 4) & 0x0F0F0F0Fu;
+    q2 += __builtin_amdgcn_udot4(l, l, 0u, false) + __builtin_amdgcn_udot4(m, m, 0u, false) -
+          __builtin_amdgcn_udot4(l + m, 0x01010101u, 0u, false);
+    lm2 += 2u * __builtin_amdgcn_udot4(l, m, 0u, false);
+}
+
+// dense counter layouts of k_wedge_pieces (log2 of end vertices per u32 word
+// for the packed ones)
+enum : int { kD32 = 0, kD16, kD8, kD4 };
+
 }  // namespace
 
 template <bool HASH>
@@ -1013,7 +1037,12 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge_pieces(WedgeArgs a) {
         P.list = __builtin_amdgcn_readfirstlane(s_p.list);
         P.graph = __builtin_amdgcn_readfirstlane(s_p.graph);
         P.region = __builtin_amdgcn_readfirstlane(s_p.region);
-        const bool d16 = !HASH && (P.flags & kPieceDense16) != 0;
+        const int dk = HASH ? kD32
+                            : (P.flags & kPieceDense4) ? kD4
+                            : (P.flags & kPieceDense8) ? kD8
+                            : (P.flags & kPieceDense16) ? kD16 : kD32;
+        const bool d16 = dk != kD32;  // u32 words of l | m halves (16, 8 or 4 bits each)
+        const uint32_t wlog = dk == kD4 ? 2u : dk == kD8 ? 1u : 0u;  // log2 ends per word
         const bool h16 = HASH && (P.flags & kPieceHash16) != 0;  // else u32 keys + u64 counters
         // a split piece's hash table may give up (the piece is then redone in
         // halves by k_wedge); an unsplit one holds at most kHashSlots/2 ends
@@ -1065,10 +1094,15 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge_pieces(WedgeArgs a) {
         // has no room for w within the probe limit
         auto add_one = [&](uint32_t w, bool asym) -> bool {
             if (!HASH) {
-                if (d16)
-                    atomicAdd(&s32[w - dlo], asym ? 0x10000u : 1u);
-                else
-                    atomicAdd(&s_tab[w - dlo], asym ? (1ull << 32) : 1ull);
+                const uint32_t off = w - dlo;
+                if (d16) {
+                    // half width 16 >> wlog bits; this end's field at (off mod 2^wlog)
+                    const uint32_t inc = (asym ? 1u << (16u >> wlog) : 1u)
+                                         << ((off & ((1u << wlog) - 1u)) << (5u - wlog));
+                    atomicAdd(&s32[off >> wlog], inc);
+                } else {
+                    atomicAdd(&s_tab[off], asym ? (1ull << 32) : 1ull);
+                }
                 return true;
             }
             if (h16) return bucket_add16(s32, lim, w, asym ? 0x10000u : 1u);
@@ -1081,7 +1115,8 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge_pieces(WedgeArgs a) {
         // -- clear the counters of the range (up to a whole 16-byte unit past
         // its end, which the finalize reads), while the records arrive
         if (!HASH) {
-            const uint32_t words = d16 ? (dwidth + 3) / 4 * 2 : (dwidth + 1) / 2 * 2;
+            const uint32_t words =
+                d16 ? (((dwidth + (1u << wlog) - 1u) >> wlog) + 3) / 4 * 2 : (dwidth + 1) / 2 * 2;
             for (uint32_t i = tid; i < words; i += kWedgeThreads) s_tab[i] = 0;
         } else if (h16) {
             for (uint32_t i = tid; i < kHash16Slots; i += kWedgeThreads) {
@@ -1097,10 +1132,10 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge_pieces(WedgeArgs a) {
         if (total > 0) load_tiles(cur);
         __syncthreads();  // table cleared, s_batch set
 
-        // -- the records, grab by grab; the sweep is compiled once per counter
-        // width (D16: u32 l | m << 16, else u64), chosen per piece
-        auto records = [&](auto d16tag) {
-        constexpr bool D16 = decltype(d16tag)::value;
+        // -- the records, grab by grab; the sweep is compiled once per dense
+        // counter layout (DK), chosen per piece
+        auto records = [&](auto dktag) {
+        constexpr int DK = decltype(dktag)::value;
         bool have = cur_base < total;
         while (have) {
             // this lane's sub-interval [ia, ib) of its middle row.  A split
@@ -1209,11 +1244,18 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge_pieces(WedgeArgs a) {
                     for (uint32_t u = 0; u < kUnroll; ++u) {
                         const bool v = (aux[u] & 2u) == 0;
                         const bool asym = ((x[u] ^ aux[u]) & 1u) != 0;
-                        const uint32_t at = v ? (x[u] >> 1) - dlo : lane;
-                        if (D16)
-                            atomicAdd(&s32[at], v ? (asym ? 0x10000u : 1u) : 0u);
-                        else
-                            atomicAdd(&s_tab[at], v ? (asym ? (1ull << 32) : 1ull) : 0ull);
+                        const uint32_t off = (x[u] >> 1) - dlo;
+                        if (DK == kD32) {
+                            atomicAdd(&s_tab[v ? off : lane], v ? (asym ? (1ull << 32) : 1ull) : 0ull);
+                        } else if (DK == kD16) {
+                            atomicAdd(&s32[v ? off : lane], v ? (asym ? 0x10000u : 1u) : 0u);
+                        } else if (DK == kD8) {
+                            const uint32_t inc = (asym ? 0x100u : 1u) << ((off & 1u) << 4);
+                            atomicAdd(&s32[v ? off >> 1 : lane], v ? inc : 0u);
+                        } else {
+                            const uint32_t inc = (asym ? 0x10u : 1u) << ((off & 3u) << 3);
+                            atomicAdd(&s32[v ? off >> 2 : lane], v ? inc : 0u);
+                        }
                     }
                     return true;
                 }
@@ -1264,10 +1306,18 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge_pieces(WedgeArgs a) {
             have = cur_base < total && !(HASH && s_abort);
         }
         };
-        if (!HASH && d16)
-            records(std::integral_constant<bool, true>());
-        else
-            records(std::integral_constant<bool, false>());
+        if constexpr (!HASH) {
+            if (dk == kD16)
+                records(std::integral_constant<int, kD16>());
+            else if (dk == kD8)
+                records(std::integral_constant<int, kD8>());
+            else if (dk == kD4)
+                records(std::integral_constant<int, kD4>());
+            else
+                records(std::integral_constant<int, kD32>());
+        } else {
+            records(std::integral_constant<int, kD32>());
+        }
         // -- the bucketed wedges through short middle rows (split starts);
         // the next chunk's entries are loaded before the current chunk's adds
         if (partial && P.list != kEmpty) {
@@ -1404,6 +1454,31 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge_pieces(WedgeArgs a) {
                     unb += l * mm;
                 }
             }
+        } else if (dk == kD8 || dk == kD4) {
+            // packed halves: per-word sums stay far below 2^32 (at most
+            // 4 * 255^2 per word), summed per group of four words into 64 bits
+            const uint4* t4 = reinterpret_cast<const uint4*>(s32);
+            const uint32_t groups = (((dwidth + (1u << wlog) - 1u) >> wlog) + 3) / 4;
+            u64 q2 = 0, lm2 = 0;
+            for (uint32_t g = tid; g < groups; g += kWedgeThreads) {
+                const uint4 c = t4[g];
+                uint32_t q = 0, lm = 0;
+                if (dk == kD8) {
+                    bucket8_sums(c.x, q, lm);
+                    bucket8_sums(c.y, q, lm);
+                    bucket8_sums(c.z, q, lm);
+                    bucket8_sums(c.w, q, lm);
+                } else {
+                    bucket4_sums(c.x, q, lm);
+                    bucket4_sums(c.y, q, lm);
+                    bucket4_sums(c.z, q, lm);
+                    bucket4_sums(c.w, q, lm);
+                }
+                q2 += q;
+                lm2 += lm;
+            }
+            bal = q2 >> 1;
+            unb = lm2 >> 1;
         } else if (d16 && !(P.flags & kPieceMerge)) {
             // 2 (C(l,2) + C(m,2)) and 2 l m from dot products of the halves
             // (l + m < 2^16); entries past the range and unreached ones are zero

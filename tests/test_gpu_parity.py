@@ -124,9 +124,9 @@ def test_small_powerlaw(ctx):
 def test_resplit_path(ctx):
     # A hub start whose first end-vertex tile holds 16000 degree-2 leaves (each
     # sharing two middles with the hub) while most degree mass sits in 100
-    # heavy vertices the hub cannot reach: the mass estimate sends the leaf
-    # tile to a hashed piece, the table overflows, and the piece must be redone
-    # (here with dense counters) and still count exactly.
+    # heavy vertices the hub cannot reach: the leaf tile goes to a hashed
+    # piece, the table overflows, and the piece must be redone (here with
+    # dense counters) and still count exactly.
     n_iso, n_leaf, n_heavy, n_mid = 384, 16000, 100, 20
     leaf0, heavy0 = n_iso, n_iso + n_leaf
     hub = heavy0 + n_heavy
@@ -153,20 +153,25 @@ def test_resplit_path(ctx):
     assert r.balanced > 0
     # A hashed run of one tile can no longer overflow by capacity when its
     # start has fewer than 2^16 middles (16-bit halves give as many slots as
-    # the tile has vertices), so the redo is forced by a short probe limit.
+    # the tile has vertices), so the redo is forced by a short probe limit;
+    # a hash target above the hub's 32,000 wedges keeps its two tiles out of
+    # a dense piece, in one hashed run.
     ctx.set_param(bbc.PARAM_PROBE_LIMIT, 8)
+    ctx.set_param(bbc.PARAM_HASH_TARGET, 65536)
     try:
         assert run(ctx, g) == r
         assert ctx.stats()[5] > 0, "expected a hashed piece to be redone"
     finally:
         ctx.set_param(bbc.PARAM_PROBE_LIMIT, 256)
+        ctx.set_param(bbc.PARAM_HASH_TARGET, 4096)
 
 
 def test_forced_resplits_stay_exact(ctx):
     # A probe limit of a few slots makes nearly every hashed piece of a heavy
     # start overflow, so the halving and dense-redo paths run thousands of
     # times, interleaved with normal pieces on the same workgroups.  A smaller
-    # and a larger hash target change the piece layout itself.
+    # and a larger hash target change the piece layout itself (at 512 hardly
+    # any range stays hashed).
     g = gen.chung_lu_graph(seed=21, n_u=200000, n_v=60000, n_edges=1500000, alpha=2.1, p_neg=0.2)
     want = expect(g)
     base = run(ctx, g)
@@ -178,11 +183,48 @@ def test_forced_resplits_stay_exact(ctx):
             for _ in range(2):
                 got = run(ctx, g)
                 assert got == want, (target, probes, got, want)
-            if probes <= 4:
+            if probes <= 4 and target >= 4096:
                 assert ctx.stats()[5] > 100, (target, probes, ctx.stats())
+            if target == 512:  # nearly every range is dense, most of them packed
+                assert ctx.stats()[11] + ctx.stats()[12] > ctx.stats()[10], ctx.stats()
     finally:
         ctx.set_param(bbc.PARAM_HASH_TARGET, 4096)
         ctx.set_param(bbc.PARAM_PROBE_LIMIT, 256)
+
+
+def saturated_graph(n_end, end_deg, n_mid, n_pad=0, pad_deg=2, seed=0):
+    """A hub on side U adjacent to every one of n_mid middles, and n_end end
+    vertices of degree end_deg whose middles are all the hub's: every (hub, w)
+    bucket has l + m = end_deg, the most its packed counters may hold.  A third
+    of the ends have l = end_deg, a third m = end_deg, a third a mix; n_pad
+    ends of degree pad_deg sit below them."""
+    rng = np.random.default_rng(seed)
+    eu, ev, sg = [0] * n_mid, list(range(n_mid)), [1] * n_mid
+    for i in range(n_end + n_pad):
+        d = end_deg if i < n_end else pad_deg
+        mids = rng.choice(n_mid, size=d, replace=False)
+        if i < n_end and i % 3 < 2:
+            s = [1 - 2 * (i % 3)] * d
+        else:
+            s = rng.choice([1, -1], size=d).tolist()
+        eu += [1 + i] * d
+        ev += mids.tolist()
+        sg += s
+    return SignedBipartiteGraph(1 + n_end + n_pad, n_mid, np.array(eu, np.int32),
+                                np.array(ev, np.int32), np.array(sg, np.int8),
+                                f"saturated{end_deg}")
+
+
+def test_packed_counters_at_their_limits(ctx):
+    # 4-bit halves: 40,000 ends of degree 15 below a hub of degree 1000, one
+    # piece of eight tiles (cut to the three the hub has); 8-bit halves: 100
+    # ends of degree 255 above 20,000 of degree 2
+    g4 = saturated_graph(40000, 15, 1000)
+    check(ctx, g4)
+    assert ctx.stats()[12] >= 1, ctx.stats()
+    g8 = saturated_graph(100, 255, 400, n_pad=20000)
+    check(ctx, g8)
+    assert ctx.stats()[11] >= 1, ctx.stats()
 
 
 def test_param_checks(ctx):
