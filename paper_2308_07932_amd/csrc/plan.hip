@@ -58,6 +58,21 @@ __device__ inline uint32_t cost_key(double wedges, uint32_t nrec, bool dense) {
 // Kinds of the pieces of a split start
 enum : uint32_t { kRunHash = 0, kRunD32, kRunD16, kRunD8, kRunD4 };
 
+// First tile of a start's end-vertex space [0, S) holding an end vertex of
+// degree at least 2: an end w of degree 1 has l + m <= 1, so it lies in no
+// butterfly, and the tiles below (rows are sorted by degree) get no piece.
+__device__ inline uint32_t first_live_tile(const uint32_t* __restrict__ row_ptr, uint32_t base,
+                                           uint32_t S) {
+    const uint32_t T = (S + kTile - 1) / kTile;
+    uint32_t t = 0;
+    while (t < T) {
+        const uint32_t last = base + min(S, (t + 1) * kTile) - 1;
+        if (row_ptr[last + 1] - row_ptr[last] > 1) break;
+        ++t;
+    }
+    return t;
+}
+
 // Tile runs of a start with end-vertex space [0, S) on the side whose rows start
 // at `base`; calls emit(t0, t1, kind, expected wedges) per run and returns the
 // number of runs.  A range of degree mass x is expected to hold W * x / tot
@@ -70,7 +85,8 @@ enum : uint32_t { kRunHash = 0, kRunD32, kRunD16, kRunD8, kRunD4 };
 // per half are tried first; then 16 bits (two tiles), else 32 (one tile).
 // When the range is expected to hold more than the target it becomes one
 // dense piece; otherwise tile t joins the open hashed run, which holds up to
-// the target (twice that with 16-bit table halves, k < 2^16).
+// the target (twice that with 16-bit table halves, k < 2^16).  Runs start at
+// the first live tile.
 template <typename F>
 __device__ uint32_t plan_runs(const uint32_t* __restrict__ row_ptr, uint32_t base, uint32_t S,
                               u64 W, uint32_t k, uint32_t target, bool pack, F emit) {
@@ -87,7 +103,7 @@ __device__ uint32_t plan_runs(const uint32_t* __restrict__ row_ptr, uint32_t bas
     };
     uint32_t n = 0, rs = kNoTile;
     u64 rx = 0;  // degree mass of the open run
-    for (uint32_t t = 0; t < T;) {
+    for (uint32_t t = first_live_tile(row_ptr, base, S); t < T;) {
         uint32_t span = 1, kind = kRunD32;
         if (pack && bound(min(S, (t + 8) * kTile)) <= 15u) {
             span = 8;
@@ -175,9 +191,10 @@ __device__ inline StartPlan plan_start(const uint32_t* __restrict__ row_ptr, con
     const uint32_t T = (S + kTile - 1) / kTile;
     bool whole = false;
     sp.cls = kClassTiles;
+    const uint32_t t_live = first_live_tile(row_ptr, d.base[side], S);
     sp.pieces = plan_runs(row_ptr, d.base[side], S, W, k, d.hash_target, !d.per_vertex,
                           [&](uint32_t t0, uint32_t t1, uint32_t kind, double) {
-                              whole = whole || (t0 == 0 && t1 == T && kind == kRunHash);
+                              whole = whole || (t0 == t_live && t1 == T && kind == kRunHash);
                           });
     // One hashed run over everything is left unsplit only when its W wedges
     // cannot fill the table (at most W distinct ends); otherwise it keeps its
@@ -294,6 +311,9 @@ __global__ void k_plan_write(const u64* __restrict__ wu, const uint32_t* __restr
         const bool split = sp.tiles > 0;
         const bool bucketed = split;
         const uint32_t nlong = front[r] - m0;
+        if (split)  // tiles of ends of degree <= 1: no piece
+            for (uint32_t t = 0, t1 = first_live_tile(row_ptr, d.base[side], S); t < t1; ++t)
+                tile_piece[tc_off[r] + t] = kEmpty;
         uint32_t i = 0;
         plan_runs(row_ptr, d.base[side], S, W, k, d.hash_target, !d.per_vertex,
                   [&](uint32_t t0, uint32_t t1, uint32_t kind, double est) {
@@ -302,7 +322,7 @@ __global__ void k_plan_write(const u64* __restrict__ wu, const uint32_t* __restr
             Piece p;
             p.rec0 = m0;
             p.nrec = bucketed ? nlong : k;
-            p.lo = t0 * kTile;
+            p.lo = split ? t0 * kTile : 0u;  // an unsplit run takes every end
             p.hi = min(S, t1 * kTile);
             p.t0 = t0;
             p.t1 = t1;
@@ -439,9 +459,9 @@ __global__ __launch_bounds__(kSwThreads) void k_short_wedges(
 #pragma unroll
                 for (uint32_t u = 0; u < kSwUnroll; ++u) {
                     const uint32_t q = w0 + u * 64 + lane;
-                    gp[u] = q < T ? s_pb[wave][idx[u]] +
-                                        tile_piece[s_tb[wave][idx[u]] + (x[u] >> 1) / kTile]
-                                  : kEmpty;
+                    const uint32_t tp =
+                        q < T ? tile_piece[s_tb[wave][idx[u]] + (x[u] >> 1) / kTile] : kEmpty;
+                    gp[u] = tp != kEmpty ? s_pb[wave][idx[u]] + tp : kEmpty;
                     s_head[wave][u * 64 + lane] = 0;
                 }
 #pragma unroll
@@ -462,7 +482,7 @@ __global__ __launch_bounds__(kSwThreads) void k_short_wedges(
                         rlen = later ? (uint32_t)__builtin_ctzll(later) + 1u : nvalid - lane;
                     }
                     uint32_t at = kEmpty;  // the run's first slot, if this pass writes it
-                    if (rlen) {
+                    if (rlen && gp[u] != kEmpty) {  // (a run of ends in no piece is dropped)
                         const int sl = sw_slot(keys, gp[u], s_used, &s_nused);
                         if (!place) {
                             if (sl >= 0)

@@ -227,6 +227,35 @@ def test_packed_counters_at_their_limits(ctx):
     assert ctx.stats()[11] >= 1, ctx.stats()
 
 
+def test_tiles_of_degree_one_ends(ctx):
+    # A hub adjacent to 2000 middles, each with private leaves of degree 1
+    # (80 per middle for the first 100, whose rows are then long, 30 for the
+    # rest): the leaves fill the hub's first tiles, which get no piece.  Alone
+    # they give no butterfly at all; with 500 ends of degree 2 above them the
+    # last tile is live and must still be counted exactly.
+    rng = np.random.default_rng(8)
+    n_mid = 2000
+    per = [80] * 100 + [30] * (n_mid - 100)
+    n_leaf = sum(per)
+    for n_live in (0, 500):
+        eu, ev = [0] * n_mid, list(range(n_mid))
+        w = 1
+        for v, c in enumerate(per):
+            eu += range(w, w + c)
+            ev += [v] * c
+            w += c
+        for i in range(n_live):
+            eu += [w + i] * 2
+            ev += rng.choice(n_mid, size=2, replace=False).tolist()
+        g = SignedBipartiteGraph(1 + n_leaf + n_live, n_mid, np.array(eu, np.int32),
+                                 np.array(ev, np.int32),
+                                 rng.choice([1, -1], size=len(eu)).astype(np.int8),
+                                 f"dead_tiles_{n_live}")
+        r = check(ctx, g)
+        assert (r.balanced + r.unbalanced > 0) == (n_live > 0)
+        assert r.wedges >= n_leaf
+
+
 def test_param_checks(ctx):
     assert ctx.get_param(bbc.PARAM_HASH_TARGET) == 4096
     assert ctx.get_param(bbc.PARAM_PROBE_LIMIT) == 256
