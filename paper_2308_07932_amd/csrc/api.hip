@@ -54,7 +54,7 @@ hipError_t launch_short_wedges(const uint4*, uint32_t, const uint32_t*, const ui
 hipError_t launch_wedge(const Piece*, const uint32_t*, const uint32_t*, uint32_t, uint32_t, Piece*,
                         uint32_t, const uint4*, const uint32_t*, const uint32_t*, Dims, const uint32_t[2], u64*,
                         const uint32_t*, const uint32_t*, const uint32_t*, Control*, u64*, u64*,
-                        uint32_t, hipStream_t);
+                        uint32_t, uint32_t, hipStream_t);
 hipError_t launch_pv_out(const u64*, const uint32_t*, Dims, u64*, hipStream_t);
 hipError_t launch_ingest(const IngestArgs&, hipStream_t);
 hipError_t launch_batch_keys(const uint32_t*, Dims, uint32_t, uint32_t*, hipStream_t);
@@ -294,7 +294,7 @@ static size_t carve_prep(Carver& cv, PrepBufs& b, uint32_t n, uint64_t m, bool c
     b.cursor = cv.take<uint32_t>(n);
     b.vx = cv.take<uint2>(n);
     b.col_in = cv.take<uint32_t>(2 * m);
-    b.col = cv.take<uint32_t>(2 * m);
+    b.col = cv.take<uint32_t>(2 * m + kColPad);
     b.lowcnt = cv.take<uint32_t>(n);
     b.mptr = cv.take<uint32_t>(n + 1);
     b.recs = cv.take<uint4>(m);
@@ -705,6 +705,7 @@ static bbc_status run_pipeline(bbc_context* c, const RunIn& in, RunOut& ro) {
 
     // ---- 1. degrees + validation
     HIPCHECK(c, fill_u32(b.deg, 0, n, st));
+    HIPCHECK(c, fill_u32(b.col + 2 * m, kColPadValue, kColPad, st));
     // every edge's slots in its two rows go to b.raw (free until the records)
     uint2* slots = reinterpret_cast<uint2*>(b.raw);
     HIPCHECK(c, launch_degree(eu, ev, sg, m, nu, nv, b.deg, slots, b.ctl, st));
@@ -885,7 +886,7 @@ static bbc_status run_pipeline(bbc_context* c, const RunIn& in, RunOut& ro) {
     if (tm) HIPCHECK(c, hipEventRecord(c->ev[kEvWedgeA], st));
     HIPCHECK(c, launch_wedge(pieces, order, items_first, n_heavy, n_dense, redo, n_items, b.recs, b.col, b.tb, d,
                              first_long, G, sw_off, sw_list, sw_mid, b.ctl,
-                             bt ? bt->gres : nullptr, pv,
+                             bt ? bt->gres : nullptr, pv, (uint32_t)(2 * m),
                              c->num_cus, st));
     if (tm) HIPCHECK(c, hipEventRecord(c->ev[kEvWedgeB], st));
     if (pv) {

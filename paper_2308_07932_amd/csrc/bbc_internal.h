@@ -61,6 +61,11 @@ constexpr uint32_t kLightWindow16 = 2 * kHashSlots - 2 * kLightMax;
 // offsets of one window lie at least kMinRegion apart
 constexpr uint32_t kMaxItemPieces = kLightWindow16 / kMinRegion + 1;
 constexpr uint32_t kTile = 16384;             // end-vertex tile width (sidx units)
+// The CSR column array carries kColPad entries of kColPadValue past its 2m
+// entries: the wedge sweep points the lanes past the end of a grab there, and
+// that end vertex lies outside every counter table.
+constexpr uint32_t kColPad = 1024;
+constexpr uint32_t kColPadValue = 0xFFFFFFFEu;
 constexpr u64 kRecordChunkWedges = 65536;     // min wedges per record chunk of a small-side start
 constexpr uint32_t kChunkDiv = 2048;          // ... and at least W_total / kChunkDiv
 constexpr uint32_t kBatchSide = kDenseW;          // batches: graphs up to this many vertices

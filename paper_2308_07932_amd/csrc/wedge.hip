@@ -49,6 +49,7 @@ struct WedgeArgs {
     uint32_t item0;    // first item k_wedge runs (n_heavy, or 0 when it runs them all)
     Piece* redo;       // halves of hashed pieces k_wedge_pieces<true> gave up on (ctl->redo_n),
                        // run by k_wedge as items n_items, n_items + 1, ...
+    uint32_t col_pad;  // index of col's first pad entry (kColPad entries of kColPadValue)
 };
 
 // Thread 0's running totals for one graph at a time; flushed to memory when
@@ -985,13 +986,19 @@ __device__ inline void bucket4_sums(uint32_t c, uint32_t& q2, uint32_t& lm2) {
 // dense counter layouts of k_wedge_pieces (log2 of end vertices per u32 word
 // for the packed ones)
 enum : int { kD32 = 0, kD16, kD8, kD4 };
+static_assert(kTile % 4 == 0, "a packed piece's base keeps the field of w in its low bits");
+static_assert(3 * 64 * kUnroll <= kColPad, "the sweep's loads past a grab stay in the pad");
 
 }  // namespace
 
 template <bool HASH>
 __global__ __launch_bounds__(kWedgeThreads) void k_wedge_pieces(WedgeArgs a) {
-    __shared__ u64 s_tab[kDenseW];
-    __shared__ uint32_t s_wadj[kWaves][64], s_waux[kWaves][64];
+    // the counters, then 64 junk words that the lanes past a grab's end add to
+    // (one per lane, so that they do not contend)
+    __shared__ u64 s_tab[kDenseW + 32];
+    // per non-empty sub-interval of a grab (address - first position, sign),
+    // then the sentinel that owns the positions from T on: (pad - T, 2)
+    __shared__ uint2 s_wrec[kWaves][65];
     __shared__ uint32_t s_head[kWaves][64];  // head flags, interleaved as in k_wedge
     __shared__ uint32_t s_qadj[kQueue], s_qlen[kQueue], s_qaux[kQueue];
     __shared__ Piece s_p, s_pf;
@@ -1002,7 +1009,8 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge_pieces(WedgeArgs a) {
     uint32_t* s32 = (uint32_t*)s_tab;
     uint32_t* keys = (uint32_t*)s_tab;  // 64-bit hashed layout: keys, then counters
     u64* hvals = s_tab + kHashSlots / 2;
-    const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
+    const uint32_t tid = threadIdx.x, lane = lane_id();
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // (uniform: LDS bases in SGPRs)
     // dense pieces are heavy items 0 .. n_dense-1, hashed ones n_dense .. n_heavy-1
     auto fetch = [&]() -> uint32_t {
         if (HASH) {
@@ -1056,6 +1064,7 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge_pieces(WedgeArgs a) {
         const uint32_t* tbl = partial ? a.tb + a.d.tb_off[ys] : nullptr;
         const uint32_t tstride = a.d.ntile[ys ^ 1u] + 1;
         const uint32_t flong = a.first_long[ys];
+        const uint32_t junk32 = 2 * kDenseW + lane, junk64 = kDenseW + (lane >> 1);
         if (tid == 0) {
             s_batch = kWaves * bsz;  // grabs beyond every wave's first one
             s_qn = s_qtake = s_swtake = 0;
@@ -1194,20 +1203,28 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge_pieces(WedgeArgs a) {
             const uint32_t len = ib - ia;
             const u64 nz = __ballot(len > 0);
             const uint32_t excl = wave_incl_scan(len) - len;
-            const uint32_t T = __shfl(excl + len, 63, 64);
+            const uint32_t T = __builtin_amdgcn_readfirstlane(__shfl(excl + len, 63, 64));
             if (len > 0) {
                 const uint32_t ci = (uint32_t)__popcll(nz & (le_mask >> 1));
-                s_wadj[wave][ci] = rs + ia - excl;
-                s_waux[wave][ci] = s1;
+                s_wrec[wave][ci] = make_uint2(rs + ia - excl, s1);
             }
+            // the sentinel: positions q >= T read col[pad + q - T] (the steps
+            // loaded past the last reach q < T + 3 * 64 * kUnroll <= T + kColPad)
+            if (lane == 0) s_wrec[wave][__popcll(nz)] = make_uint2(a.col_pad - T, 2u);
             // -- sweep the T concatenated wedges, kUnroll windows of 64 per step;
             // the entries of step j + 1 are loaded before the adds of step j
             uint32_t before = 0;
             uint32_t xa[kUnroll], aa[kUnroll];
+            // Every position has an owner (the sentinel from T on), so no
+            // lane needs a bound check.
             auto step_load = [&](uint32_t j, uint32_t* x, uint32_t* aux) {
                 uint8_t* hb = (uint8_t*)s_head[wave];
                 if (len > 0 && excl >= j && excl < j + 64 * kUnroll) {
                     const uint32_t hp = excl - j;
+                    hb[(hp & 63u) * kUnroll + (hp >> 6)] = 1;
+                }
+                if (lane == 0 && T >= j && T < j + 64 * kUnroll) {
+                    const uint32_t hp = T - j;
                     hb[(hp & 63u) * kUnroll + (hp >> 6)] = 1;
                 }
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -1215,46 +1232,56 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge_pieces(WedgeArgs a) {
                 uint32_t adj[kUnroll];
 #pragma unroll
                 for (uint32_t u = 0; u < kUnroll; ++u) {
-                    // owner = heads before the window + heads at or before this lane - 1
+                    // owner = heads before the window + heads at or before this
+                    // lane - 1; the heads of lanes 1..lane are the bits below
+                    // this lane of M >> 1 (one mbcnt), lane 0's is scalar
                     const bool own = ((hd4 >> (8 * u)) & 0xFFu) != 0;
                     const u64 M = __ballot(own);
-                    const uint32_t below = __builtin_amdgcn_mbcnt_hi(
-                        (uint32_t)(M >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)M, 0u));
-                    const uint32_t idx = before + below + (own ? 1u : 0u) - 1u;
+                    const u64 Ms = M >> 1;
+                    const uint32_t upto = __builtin_amdgcn_mbcnt_hi(
+                        (uint32_t)(Ms >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)Ms, 0u));
+                    const uint32_t idx = (before + (uint32_t)(M & 1u) - 1u) + upto;
                     before += (uint32_t)__popcll(M);
-                    const bool in = j + u * 64 + lane < T;
-                    const uint32_t ii = in ? idx : 0u;
-                    aux[u] = in ? s_waux[wave][ii] : 2u;  // bit 1: past the end
-                    adj[u] = s_wadj[wave][ii];
+                    const uint2 r = s_wrec[wave][idx];
+                    adj[u] = r.x;
+                    aux[u] = r.y;
                 }
 #pragma unroll
-                for (uint32_t u = 0; u < kUnroll; ++u) {
-                    const uint32_t q = j + u * 64 + lane;
-                    x[u] = col[q < T ? adj[u] + q : 0u];  // aux marks the lanes past T
-                }
+                for (uint32_t u = 0; u < kUnroll; ++u) x[u] = col[adj[u] + j + u * 64 + lane];
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
                 s_head[wave][lane] = 0;
+                // keep the previous step's adds below these loads: hoisted
+                // above them they would wait for that step's entries first
+                __builtin_amdgcn_sched_barrier(0);
             };
             // the adds of one step; false (for the whole wave) when a hashed
             // table found no room
             auto step_add = [&](const uint32_t* x, const uint32_t* aux) -> bool {
                 if (!HASH) {
-                    // no branches: a lane past the end adds 0 to a word of its own
+                    // No branches: the pad entries past a grab's end (end
+                    // vertex 2^31 - 1) fall on the junk word behind the table.
+                    // An entry x = w << 1 | sign(v, w) adds 1 to the l half of
+                    // w's counter, or to the m half when sign(v, w) differs
+                    // from the record's sign(u, v), s1.  With y = x ^ s1, bit 0
+                    // of y selects the half, and the bits above it the end's
+                    // slot in a packed word (dlo is a multiple of kTile, so
+                    // w's low bits give the slot): the field is y's low
+                    // 1 / 2 / 3 bits, each field 16 / 8 / 4 bits wide.
 #pragma unroll
                     for (uint32_t u = 0; u < kUnroll; ++u) {
-                        const bool v = (aux[u] & 2u) == 0;
-                        const bool asym = ((x[u] ^ aux[u]) & 1u) != 0;
-                        const uint32_t off = (x[u] >> 1) - dlo;
+                        const uint32_t y = x[u] ^ aux[u];
                         if (DK == kD32) {
-                            atomicAdd(&s_tab[v ? off : lane], v ? (asym ? (1ull << 32) : 1ull) : 0ull);
+                            const uint32_t at = min((x[u] >> 1) - dlo, junk64);
+                            atomicAdd(&s_tab[at], (u64)1 << ((y & 1u) << 5));
                         } else if (DK == kD16) {
-                            atomicAdd(&s32[v ? off : lane], v ? (asym ? 0x10000u : 1u) : 0u);
+                            const uint32_t at = min((x[u] >> 1) - dlo, junk32);
+                            atomicAdd(&s32[at], 1u << ((y & 1u) << 4));
                         } else if (DK == kD8) {
-                            const uint32_t inc = (asym ? 0x100u : 1u) << ((off & 1u) << 4);
-                            atomicAdd(&s32[v ? off >> 1 : lane], v ? inc : 0u);
+                            const uint32_t at = min((x[u] >> 2) - (dlo >> 1), junk32);
+                            atomicAdd(&s32[at], 1u << ((y & 3u) << 3));
                         } else {
-                            const uint32_t inc = (asym ? 0x10u : 1u) << ((off & 3u) << 3);
-                            atomicAdd(&s32[v ? off >> 2 : lane], v ? inc : 0u);
+                            const uint32_t at = min((x[u] >> 3) - (dlo >> 2), junk32);
+                            atomicAdd(&s32[at], 1u << ((y & 7u) << 2));
                         }
                     }
                     return true;
@@ -1268,30 +1295,53 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge_pieces(WedgeArgs a) {
                 return __ballot(!lok) == 0;
             };
             // two register sets take turns (no copies: a copy of a value still
-            // being loaded would wait for the load)
-            // the step after the last is loaded too (to a valid address, all
-            // lanes marked past T), which keeps the loads out of branches
+            // being loaded would wait for the load); the step after the last
+            // is loaded too (pad entries), which keeps the loads out of branches
             uint32_t xb[kUnroll], ab[kUnroll];
             bool ok = true;
+            bool tiles_pending = nxt_base != kEmpty;  // uniform
             if (T > 0) {
-                step_load(0, xa, aa);
-                for (uint32_t j = 0;;) {
-                    j += 64 * kUnroll;
-                    step_load(j, xb, ab);
-                    if (j == 64 * kUnroll && nxt_base != kEmpty) load_tiles(nxt);  // records arrived
-                    ok = step_add(xa, aa);
-                    if (j >= T || !ok) break;
-                    j += 64 * kUnroll;
-                    step_load(j, xa, aa);
+                // Steps go in pairs (a, then b) with one exit, after b: an
+                // exit after a would leave b's loads pending on a path back
+                // to the loop head as the wait-count analysis sees it, and
+                // every step would then wait for the previous step's loads
+                // before reusing their registers.  An odd number of steps
+                // peels the first one.
+                constexpr uint32_t S = 64 * kUnroll;
+                const uint32_t nsteps = (T + S - 1) / S;
+                uint32_t j = 0;
+                if (nsteps & 1u) {
+                    step_load(0, xb, ab);
+                    step_load(S, xa, aa);  // (past T when nsteps == 1: pad entries)
+                    if (tiles_pending) {
+                        load_tiles(nxt);  // the next grab's records have arrived
+                        tiles_pending = false;
+                    }
                     ok = step_add(xb, ab);
-                    if (j >= T || !ok) break;
+                    j = S;
+                } else {
+                    step_load(0, xa, aa);
+                }
+                if (j < T && ok) {
+                    for (;;) {
+                        step_load(j + S, xb, ab);
+                        if (tiles_pending) {
+                            load_tiles(nxt);
+                            tiles_pending = false;
+                        }
+                        ok = step_add(xa, aa) && ok;
+                        step_load(j + 2 * S, xa, aa);
+                        ok = step_add(xb, ab) && ok;
+                        j += 2 * S;
+                        if (j >= T || !ok) break;
+                    }
                 }
             }
             if (!ok) s_abort = 1;  // the piece is abandoned
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             // the next grab: loaded above, or claimed now
             if (nxt_base != kEmpty) {
-                if (T == 0) load_tiles(nxt);
+                if (tiles_pending) load_tiles(nxt);
                 cur = nxt;
                 cur_base = nxt_base;
             } else {
@@ -1594,9 +1644,10 @@ hipError_t launch_wedge(const Piece* pieces, const uint32_t* order, const uint32
                         uint32_t n_items, const uint4* recs, const uint32_t* col, const uint32_t* tb,
                         Dims d, const uint32_t first_long[2], u64* G, const uint32_t* sw_off,
                         const uint32_t* sw_list, const uint32_t* sw_mid, Control* ctl, u64* gres,
-                        u64* pv,
+                        u64* pv, uint32_t col_pad,
                         uint32_t num_cus, hipStream_t st) {
     WedgeArgs a;
+    a.col_pad = col_pad;
     a.pieces = pieces;
     a.order = order;
     a.items_first = items_first;
