@@ -195,6 +195,16 @@ __device__ inline T wave_reduce_sum(T v) {
     return v;
 }
 
+__device__ inline uint32_t wave_reduce_min(uint32_t v) {
+    for (int off = 32; off > 0; off >>= 1) v = min(v, (uint32_t)__shfl_xor(v, off, 64));
+    return v;
+}
+
+__device__ inline uint32_t wave_reduce_max(uint32_t v) {
+    for (int off = 32; off > 0; off >>= 1) v = max(v, (uint32_t)__shfl_xor(v, off, 64));
+    return v;
+}
+
 // inclusive scan across the 64 lanes of a wave
 template <typename T>
 __device__ inline T wave_incl_scan(T v) {

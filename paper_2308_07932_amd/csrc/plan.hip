@@ -406,6 +406,11 @@ __global__ __launch_bounds__(kSwThreads) void k_short_wedges(
     __shared__ uint8_t s_head[kSwWaves][64 * kSwUnroll];
     __shared__ uint32_t s_used[kSwSlots];  // table slots taken in this chunk
     __shared__ uint32_t s_nused;
+    // a chunk whose short records all belong to one start with at most
+    // kSwSlots tiles maps tiles to that start's pieces from LDS, and counts
+    // per piece directly (index = piece - the start's first piece)
+    __shared__ uint32_t s_tp[kSwSlots];
+    __shared__ uint32_t s_umin[kSwWaves], s_umax[kSwWaves];
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
     const u64 le_mask = ~0ull >> (63 - lane);  // lanes 0..lane
     for (uint32_t u = 0; u < kSwUnroll; ++u) s_head[wave][u * 64 + lane] = 0;
@@ -439,7 +444,29 @@ __global__ __launch_bounds__(kSwThreads) void k_short_wedges(
             s_s1[wave][ci] = rc.y & 1u;
             s_mid[wave][ci] = (rc.w < n_u ? n_u : 0u) + rc.z;  // v lies on the other side
         }
+        {
+            const uint32_t umin = wave_reduce_min(len > 0 ? rc.w : kEmpty);
+            const uint32_t umax = wave_reduce_max(len > 0 ? rc.w : 0u);
+            if (lane == 0) {
+                s_umin[wave] = umin;
+                s_umax[wave] = umax;
+            }
+        }
         __syncthreads();
+        uint32_t u0 = kEmpty, u1 = 0;
+        for (uint32_t w = 0; w < kSwWaves; ++w) {
+            u0 = min(u0, s_umin[w]);
+            u1 = max(u1, s_umax[w]);
+        }
+        const bool fast = u0 == u1 && tc[u0] <= kSwSlots;  // uniform over the workgroup
+        uint32_t pb0 = 0, h0 = 0;
+        if (fast) {
+            pb0 = hp_off[u0];
+            h0 = hp_off[u0 + 1] - pb0;
+            const uint32_t tb0 = tc_off[u0], nt = tc[u0];
+            for (uint32_t t = tid; t < nt; t += kSwThreads) s_tp[t] = tile_piece[tb0 + t];
+            __syncthreads();
+        }
         // place = false: count runs per piece; place = true (fill pass): each
         // run takes consecutive slots from its piece's reserved range
         auto walk = [&](const bool place) {
@@ -459,9 +486,13 @@ __global__ __launch_bounds__(kSwThreads) void k_short_wedges(
 #pragma unroll
                 for (uint32_t u = 0; u < kSwUnroll; ++u) {
                     const uint32_t q = w0 + u * 64 + lane;
-                    const uint32_t tp =
-                        q < T ? tile_piece[s_tb[wave][idx[u]] + (x[u] >> 1) / kTile] : kEmpty;
-                    gp[u] = tp != kEmpty ? s_pb[wave][idx[u]] + tp : kEmpty;
+                    if (fast) {  // gp: the piece's index among the start's pieces
+                        gp[u] = q < T ? s_tp[(x[u] >> 1) / kTile] : kEmpty;
+                    } else {
+                        const uint32_t tp =
+                            q < T ? tile_piece[s_tb[wave][idx[u]] + (x[u] >> 1) / kTile] : kEmpty;
+                        gp[u] = tp != kEmpty ? s_pb[wave][idx[u]] + tp : kEmpty;
+                    }
                     s_head[wave][u * 64 + lane] = 0;
                 }
 #pragma unroll
@@ -483,7 +514,7 @@ __global__ __launch_bounds__(kSwThreads) void k_short_wedges(
                     }
                     uint32_t at = kEmpty;  // the run's first slot, if this pass writes it
                     if (rlen && gp[u] != kEmpty) {  // (a run of ends in no piece is dropped)
-                        const int sl = sw_slot(keys, gp[u], s_used, &s_nused);
+                        const int sl = fast ? (int)gp[u] : sw_slot(keys, gp[u], s_used, &s_nused);
                         if (!place) {
                             if (sl >= 0)
                                 atomicAdd(&cnt[sl], rlen);
@@ -508,6 +539,25 @@ __global__ __launch_bounds__(kSwThreads) void k_short_wedges(
         };
         walk(false);
         __syncthreads();
+        if (fast) {
+            for (uint32_t i = tid; i < h0; i += kSwThreads) {
+                const uint32_t c = cnt[i];
+                if (c == 0) continue;
+                if (!kFill)
+                    atomicAdd(&counts[pb0 + i], c);
+                else
+                    base[i] = atomicAdd(&cursor[pb0 + i], c);
+                cnt[i] = 0;
+            }
+            __syncthreads();
+            if (kFill) {
+                walk(true);
+                __syncthreads();
+                for (uint32_t i = tid; i < h0; i += kSwThreads) cnt[i] = 0;
+                __syncthreads();
+            }
+            continue;
+        }
         const uint32_t nused = s_nused;
         for (uint32_t k = tid; k < nused; k += kSwThreads) {
             const uint32_t i = s_used[k];
