@@ -49,8 +49,9 @@ hipError_t launch_plan_write(const u64*, const uint32_t*, const uint32_t*, const
                              hipStream_t);
 hipError_t launch_short_wedges(const uint4*, uint32_t, const uint32_t*, const uint32_t*,
                                const uint32_t*, const uint32_t*, const uint32_t*, const uint32_t*,
-                               uint32_t, uint32_t*, uint32_t*, uint32_t*, uint32_t*, bool,
-                               hipStream_t);
+                               uint32_t, uint32_t*, uint32_t*, uint32_t*, uint32_t*, uint16_t*,
+                               bool, hipStream_t);
+size_t short_wedge_chunk_slots(uint64_t m);
 hipError_t launch_wedge(const Piece*, const uint32_t*, const uint32_t*, uint32_t, uint32_t, Piece*,
                         uint32_t, const uint4*, const uint32_t*, const uint32_t*, Dims, const uint32_t[2], u64*,
                         const uint32_t*, const uint32_t*, const uint32_t*, Control*, u64*, u64*,
@@ -517,7 +518,7 @@ int64_t bbc_workspace_bytes(int32_t n_u, int32_t n_v, int64_t n_edges) {
     const size_t prep = carve_prep(probe, b, n, m, true, tb);
     // planning workspace: about one piece per start plus record chunks and
     // merge rows; taken generously as 96 bytes per vertex and 8 per edge
-    const size_t plan = 96ull * n + 8ull * m + (1u << 20);
+    const size_t plan = 96ull * n + 8ull * m + 2 * short_wedge_chunk_slots(m) + (1u << 20);
     return (int64_t)(prep + plan);
 }
 }  // extern "C"
@@ -811,6 +812,7 @@ static bbc_status run_pipeline(bbc_context* c, const RunIn& in, RunOut& ro) {
     u64* G;
     uint32_t *hkey, *ok0, *ov0, *ok1, *ov1, *tile_piece, *sw_cnt, *sw_off, *sw_cur, *sw_list;
     uint32_t* sw_mid = nullptr;  // per-vertex mode: the middle row of each listed wedge
+    uint16_t* sw_chunk;  // per-piece counts of single-start record chunks (count pass -> fill pass)
     u64 *pv = nullptr, *pv_out = nullptr;
     void* ortmp;
     const size_t ortmp_bytes = radix_tmp_bytes(n_heavy + 1);
@@ -833,6 +835,7 @@ static bbc_status run_pipeline(bbc_context* c, const RunIn& in, RunOut& ro) {
             sw_off = cv.take<uint32_t>((size_t)n_heavy + 1);
             sw_cur = cv.take<uint32_t>((size_t)n_heavy + 1);
             sw_list = cv.take<uint32_t>((size_t)h.tot_sw + 1);
+            sw_chunk = cv.take<uint16_t>(short_wedge_chunk_slots(m));
             if (in.per_vertex) {
                 pv = cv.take<u64>(n);
                 pv_out = cv.take<u64>(n);
@@ -867,14 +870,14 @@ static bbc_status run_pipeline(bbc_context* c, const RunIn& in, RunOut& ro) {
     if (h.tot_sw > 0) {
         HIPCHECK(c, launch_short_wedges(b.recs, (uint32_t)m, b.col, b.cursor, b.tc, b.tc_off,
                                         b.hp_off, tile_piece, nu, sw_cnt, sw_cur, sw_list, sw_mid,
-                                        false, st));
+                                        sw_chunk, false, st));
     }
     HIPCHECK(c, scan_excl_u32(sw_cnt, sw_off, n_heavy, ortmp, ortmp_bytes, st));
     if (h.tot_sw > 0) {
         HIPCHECK(c, copy_u32(sw_off, sw_cur, n_heavy, st));
         HIPCHECK(c, launch_short_wedges(b.recs, (uint32_t)m, b.col, b.cursor, b.tc, b.tc_off,
                                         b.hp_off, tile_piece, nu, sw_cnt, sw_cur, sw_list, sw_mid,
-                                        true, st));
+                                        sw_chunk, true, st));
     }
     uint32_t* order = nullptr;
     if (n_heavy > 0)  // heavy pieces, most expensive first

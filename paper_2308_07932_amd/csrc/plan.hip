@@ -366,6 +366,12 @@ constexpr uint32_t kSwWaves = kSwThreads / 64;
 constexpr uint32_t kSwLog2 = 9;
 constexpr uint32_t kSwSlots = 1u << kSwLog2;
 constexpr uint32_t kSwUnroll = 4;  // windows of 64 entries loaded together
+// per-piece counts a chunk keeps between the passes (a chunk holds at most
+// 256 records of at most kLongDeg entries each, so a count fits 16 bits)
+constexpr uint32_t kSwKept = 64;
+static_assert(kSwThreads * kLongDeg < (1u << 16), "chunk counts fit 16 bits");
+
+size_t short_wedge_chunk_slots(uint64_t m) { return (size_t)((m + kSwThreads - 1) / kSwThreads) * kSwKept; }
 
 // Slot of `key` in the chunk's LDS table (inserting it), or -1 after 8 probes;
 // a newly taken slot is appended to `used`, so that the flush and the reset
@@ -394,7 +400,8 @@ __global__ __launch_bounds__(kSwThreads) void k_short_wedges(
     const uint32_t* __restrict__ front, const uint32_t* __restrict__ tc,
     const uint32_t* __restrict__ tc_off, const uint32_t* __restrict__ hp_off,
     const uint32_t* __restrict__ tile_piece, uint32_t n_u, uint32_t* __restrict__ counts,
-    uint32_t* __restrict__ cursor, uint32_t* __restrict__ list, uint32_t* __restrict__ mids) {
+    uint32_t* __restrict__ cursor, uint32_t* __restrict__ list, uint32_t* __restrict__ mids,
+    uint16_t* __restrict__ chunk_cnt) {
     __shared__ uint32_t keys[kSwSlots];
     __shared__ uint32_t cnt[kSwSlots];
     __shared__ uint32_t base[kSwSlots];
@@ -537,11 +544,18 @@ __global__ __launch_bounds__(kSwThreads) void k_short_wedges(
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             }
         };
-        walk(false);
-        __syncthreads();
+        // a single-start chunk of at most kSwKept pieces keeps its per-piece
+        // counts from the count pass, so the fill pass walks its entries once
+        const bool kept = fast && h0 <= kSwKept;
+        uint16_t* kc = chunk_cnt + (size_t)(c0 / kSwThreads) * kSwKept;
+        if (!(kFill && kept)) {
+            walk(false);
+            __syncthreads();
+        }
         if (fast) {
             for (uint32_t i = tid; i < h0; i += kSwThreads) {
-                const uint32_t c = cnt[i];
+                const uint32_t c = (kFill && kept) ? kc[i] : cnt[i];
+                if (!kFill && kept) kc[i] = (uint16_t)c;
                 if (c == 0) continue;
                 if (!kFill)
                     atomicAdd(&counts[pb0 + i], c);
@@ -684,15 +698,15 @@ hipError_t launch_short_wedges(const uint4* recs, uint32_t m, const uint32_t* co
                                const uint32_t* front, const uint32_t* tc, const uint32_t* tc_off,
                                const uint32_t* hp_off, const uint32_t* tile_piece, uint32_t n_u,
                                uint32_t* counts, uint32_t* cursor, uint32_t* list, uint32_t* mids,
-                               bool fill, hipStream_t st) {
+                               uint16_t* chunk_cnt, bool fill, hipStream_t st) {
     if (fill)
         hipLaunchKernelGGL(k_short_wedges<true>, grid_n(m, kSwThreads, 8192), dim3(kSwThreads), 0, st,
                            recs, m, col, front, tc, tc_off, hp_off, tile_piece, n_u, counts, cursor,
-                           list, mids);
+                           list, mids, chunk_cnt);
     else
         hipLaunchKernelGGL(k_short_wedges<false>, grid_n(m, kSwThreads, 8192), dim3(kSwThreads), 0,
                            st, recs, m, col, front, tc, tc_off, hp_off, tile_piece, n_u, counts,
-                           cursor, list, mids);
+                           cursor, list, mids, chunk_cnt);
     return hipGetLastError();
 }
 
