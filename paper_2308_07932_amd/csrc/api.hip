@@ -743,8 +743,11 @@ static bbc_status run_pipeline(bbc_context* c, const RunIn& in, RunOut& ro) {
     if (bt) HIPCHECK(c, launch_dup_graphs(b.row_ptr, b.col, d, b.ctl, st));
     // ---- 5. middle counts, 6. records and W_u, 7. tile tables
     HIPCHECK(c, launch_lowcount(b.row_ptr, b.col, b.rowcross, n, b.lowcnt, b.upcnt, st));
-    HIPCHECK(c, scan_excl_u32(b.lowcnt, b.mptr, n, b.stmp, b.stmp_bytes, st));
-    HIPCHECK(c, scan_excl_u32(b.upcnt, b.uptr, n, b.stmp, b.stmp_bytes, st));
+    {
+        const uint32_t* ins[2] = {b.lowcnt, b.upcnt};
+        uint32_t* outs[2] = {b.mptr, b.uptr};
+        HIPCHECK(c, scan_excl_u32_set(ins, outs, 2, n, b.stmp, b.stmp_bytes, st));
+    }
     // records in row-v order with their (start, short) keys, sorted by key,
     // gathered into [mptr[u], mptr[u+1]) per start with the long-middle ones
     // first; front[u] (kept in b.cursor) is where u's short ones begin
@@ -767,12 +770,14 @@ static bbc_status run_pipeline(bbc_context* c, const RunIn& in, RunOut& ro) {
     HIPCHECK(c, launch_plan_count(b.wu, b.wsu, b.lowcnt, b.row_ptr, d, b.hp, b.lr, b.lf, b.gs, b.tc,
                                   b.swc, &b.ctl->wedges, &b.ctl->active_starts, b.ctl, st));
     if (bt) HIPCHECK(c, launch_graph_wedges(b.wu, d, bt->gres, st));
-    HIPCHECK(c, scan_excl_u32(b.hp, b.hp_off, n, b.stmp, b.stmp_bytes, st));
-    HIPCHECK(c, scan_excl_u64(b.lr, b.lr_off, n, b.stmp, b.stmp_bytes, st));
-    HIPCHECK(c, scan_excl_u32(b.lf, b.lf_off, n, b.stmp, b.stmp_bytes, st));
-    HIPCHECK(c, scan_excl_u32(b.gs, b.gs_off, n, b.stmp, b.stmp_bytes, st));
-    HIPCHECK(c, scan_excl_u32(b.tc, b.tc_off, n, b.stmp, b.stmp_bytes, st));
-    HIPCHECK(c, scan_excl_u64(b.swc, b.swc_off, n, b.stmp, b.stmp_bytes, st));
+    {
+        const uint32_t* ins[4] = {b.hp, b.lf, b.gs, b.tc};
+        uint32_t* outs[4] = {b.hp_off, b.lf_off, b.gs_off, b.tc_off};
+        HIPCHECK(c, scan_excl_u32_set(ins, outs, 4, n, b.stmp, b.stmp_bytes, st));
+        const u64* ins64[2] = {b.lr, b.swc};
+        u64* outs64[2] = {b.lr_off, b.swc_off};
+        HIPCHECK(c, scan_excl_u64_set(ins64, outs64, 2, n, b.stmp, b.stmp_bytes, st));
+    }
     HIPCHECK(c, launch_gather_totals(b.hp_off, b.lr_off, b.lf_off, b.gs_off, b.tc_off, b.swc_off, n,
                                      b.ctl, st));
     if (tm) HIPCHECK(c, hipEventRecord(c->ev[kEvPlanA], st));
@@ -881,7 +886,7 @@ static bbc_status run_pipeline(bbc_context* c, const RunIn& in, RunOut& ro) {
     }
     uint32_t* order = nullptr;
     if (n_heavy > 0)  // heavy pieces, most expensive first
-        HIPCHECK(c, radix_sort_by_key(hkey, n_heavy, 17, ok0, ov0, ok1, ov1, ortmp, ortmp_bytes,
+        HIPCHECK(c, radix_sort_by_key(hkey, n_heavy, 8, ok0, ov0, ok1, ov1, ortmp, ortmp_bytes,
                                       &order, st));
     if (tm) HIPCHECK(c, hipEventRecord(c->ev[kEvPlanC], st));
 

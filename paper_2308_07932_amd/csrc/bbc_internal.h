@@ -278,6 +278,12 @@ hipError_t scan_excl_u64(const u64* in, u64* out, uint32_t n, void* tmp, size_t 
                          hipStream_t st);
 size_t scan_tmp_bytes(uint32_t n);
 hipError_t fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t st);
+// k <= kMaxScanSet scans of length n in one pair of launches (else one by one)
+constexpr uint32_t kMaxScanSet = 4;
+hipError_t scan_excl_u32_set(const uint32_t* const* ins, uint32_t* const* outs, uint32_t k,
+                             uint32_t n, void* tmp, size_t tmp_bytes, hipStream_t st);
+hipError_t scan_excl_u64_set(const u64* const* ins, u64* const* outs, uint32_t k, uint32_t n,
+                             void* tmp, size_t tmp_bytes, hipStream_t st);
 hipError_t fill_u64(u64* p, u64 v, size_t n, hipStream_t st);
 hipError_t copy_u32(const uint32_t* src, uint32_t* dst, size_t n, hipStream_t st);
 }  // namespace bbc

@@ -45,14 +45,15 @@ __device__ inline uint32_t next_pow2(uint32_t x) {
 
 __device__ inline uint32_t log2_pow2(uint32_t x) { return 31u - __clz(x); }
 
-// Sort key of a heavy piece (ascending): pieces with dense counters first
-// (they run in their own kernel), each group most expensive first by a 16-bit
-// log-scale of the estimated cost, 4 units per record visited plus the
-// expected wedges.
+// Sort key of a heavy piece (ascending, 8 bits: one radix pass): pieces with
+// dense counters first (they run in their own kernel), each group most
+// expensive first by a 7-bit log-scale of the estimated cost (quarter
+// doublings), 4 units per record visited plus the expected wedges.
+constexpr uint32_t kCostKeyBits = 8;
 __device__ inline uint32_t cost_key(double wedges, uint32_t nrec, bool dense) {
     const double c = wedges + 4.0 * nrec;
-    const double q = log2(1.0 + c) * 2048.0;
-    return (dense ? 0u : 1u << 16) | (65535u - (uint32_t)fmin(q, 65535.0));
+    const double q = log2(1.0 + c) * 4.0;
+    return (dense ? 0u : 1u << 7) | (127u - (uint32_t)fmin(q, 127.0));
 }
 
 // Kinds of the pieces of a split start

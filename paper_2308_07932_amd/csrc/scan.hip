@@ -126,7 +126,7 @@ __global__ __launch_bounds__(kScanThreads) void k_tile_scan_few(const T* in, T* 
 
 size_t scan_tmp_bytes(uint32_t n) {
     size_t nb = (size_t)(n + kScanTile - 1) / kScanTile + 1;
-    return (nb + 2) * sizeof(u64) + 256;
+    return (size_t)kMaxScanSet * (nb + 2) * sizeof(u64) + 256;
 }
 
 template <typename T>
@@ -147,6 +147,90 @@ static hipError_t scan_impl(const T* in, T* out, uint32_t n, void* tmp, size_t t
     hipLaunchKernelGGL(k_tile_scan<T>, dim3(nb), dim3(kScanThreads), 0, st, in, out, n,
                        (const T*)sums, (const T*)total);
     return hipGetLastError();
+}
+
+// Several scans of the same length in one pair of launches (blockIdx.y picks
+// the array), for the groups of per-vertex scans the pipeline runs together.
+template <typename T>
+struct ScanSet {
+    const T* in[kMaxScanSet];
+    T* out[kMaxScanSet];
+};
+
+template <typename T>
+__global__ __launch_bounds__(kScanThreads) void k_tile_sums_set(ScanSet<T> set, uint32_t n,
+                                                                T* sums) {
+    __shared__ T s_wave[kScanThreads / 64];
+    const T* in = set.in[blockIdx.y];
+    const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
+    T acc = 0;
+    for (int i = 0; i < kScanItems; ++i) {
+        uint64_t idx = base + (uint64_t)i * kScanThreads + threadIdx.x;
+        if (idx < n) acc += in[idx];
+    }
+    T tot;
+    block_excl_scan(acc, s_wave, &tot);
+    if (threadIdx.x == 0) sums[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = tot;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kScanThreads) void k_tile_scan_few_set(ScanSet<T> set, uint32_t n,
+                                                                    const T* sums_all) {
+    __shared__ T s_wave[kScanThreads / 64];
+    const T* in = set.in[blockIdx.y];
+    T* out = set.out[blockIdx.y];
+    const T* sums = sums_all + (size_t)blockIdx.y * gridDim.x;
+    const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
+    T pre = 0;
+    for (uint32_t i = threadIdx.x; i < blockIdx.x; i += kScanThreads) pre += sums[i];
+    T v[kScanItems];
+    T acc = 0;
+    const uint64_t my = base + (uint64_t)threadIdx.x * kScanItems;
+    for (int i = 0; i < kScanItems; ++i) {
+        v[i] = (my + i < n) ? in[my + i] : 0;
+        acc += v[i];
+    }
+    T off, tot;
+    block_excl_scan(pre, s_wave, &off);
+    T run = block_excl_scan(acc, s_wave, &tot) + off;
+    for (int i = 0; i < kScanItems; ++i) {
+        if (my + i < n) out[my + i] = run;
+        run += v[i];
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = off + tot;
+}
+
+template <typename T>
+static hipError_t scan_set_impl(const T* const* ins, T* const* outs, uint32_t k, uint32_t n,
+                                void* tmp, size_t tmp_bytes, hipStream_t st) {
+    uint32_t nb = (n + kScanTile - 1) / kScanTile;
+    if (nb == 0) nb = 1;
+    if (k == 0 || k > kMaxScanSet || nb > kScanFewTiles || (size_t)k * nb * sizeof(T) > tmp_bytes) {
+        for (uint32_t i = 0; i < k; ++i) {  // one scan at a time
+            hipError_t e = scan_impl<T>(ins[i], outs[i], n, tmp, tmp_bytes, st);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
+    ScanSet<T> set;
+    for (uint32_t i = 0; i < kMaxScanSet; ++i) {
+        set.in[i] = i < k ? ins[i] : nullptr;
+        set.out[i] = i < k ? outs[i] : nullptr;
+    }
+    hipLaunchKernelGGL(k_tile_sums_set<T>, dim3(nb, k), dim3(kScanThreads), 0, st, set, n, (T*)tmp);
+    hipLaunchKernelGGL(k_tile_scan_few_set<T>, dim3(nb, k), dim3(kScanThreads), 0, st, set, n,
+                       (const T*)tmp);
+    return hipGetLastError();
+}
+
+hipError_t scan_excl_u32_set(const uint32_t* const* ins, uint32_t* const* outs, uint32_t k,
+                             uint32_t n, void* tmp, size_t tmp_bytes, hipStream_t st) {
+    return scan_set_impl<uint32_t>(ins, outs, k, n, tmp, tmp_bytes, st);
+}
+
+hipError_t scan_excl_u64_set(const u64* const* ins, u64* const* outs, uint32_t k, uint32_t n,
+                             void* tmp, size_t tmp_bytes, hipStream_t st) {
+    return scan_set_impl<u64>(ins, outs, k, n, tmp, tmp_bytes, st);
 }
 
 hipError_t scan_excl_u32(const uint32_t* in, uint32_t* out, uint32_t n, void* tmp,
