@@ -287,7 +287,8 @@ bbc_status bbc_last_phase_ms(const bbc_context* ctx, int phase, double* ms);
  * [11], [12] = pieces of starts cut into end-vertex tiles: one dense tile
  * (32-bit counters), two dense tiles with 16-bit counters, a hashed run of
  * tiles, four dense tiles with 8-bit counters, eight dense tiles with 4-bit
- * counters.  `n` is the capacity of `stats`; up to 13 values are written.
+ * counters; [13] = starts counted by one wavefront alone (small end ranges).
+ * `n` is the capacity of `stats`; up to 14 values are written.
  */
 bbc_status bbc_last_stats(const bbc_context* ctx, int64_t* stats, int n);
 

@@ -239,8 +239,8 @@ class Context:
         return float(v.value)
 
     def stats(self) -> list[int]:
-        a = (ctypes.c_int64 * 13)()
-        self._lib.bbc_last_stats(self._h, a, 13)
+        a = (ctypes.c_int64 * 14)()
+        self._lib.bbc_last_stats(self._h, a, 14)
         return list(a)
 
     def last_error(self) -> str:

@@ -52,7 +52,7 @@ hipError_t launch_short_wedges(const uint4*, uint32_t, const uint32_t*, const ui
                                uint32_t, uint32_t*, uint32_t*, uint32_t*, uint32_t*, uint16_t*,
                                bool, hipStream_t);
 size_t short_wedge_chunk_slots(uint64_t m);
-hipError_t launch_wedge(const Piece*, const uint32_t*, const uint32_t*, uint32_t, uint32_t, Piece*,
+hipError_t launch_wedge(const Piece*, const uint32_t*, const uint32_t*, uint32_t, uint32_t, uint32_t, Piece*,
                         uint32_t, const uint4*, const uint32_t*, const uint32_t*, Dims, const uint32_t[2], u64*,
                         const uint32_t*, const uint32_t*, const uint32_t*, Control*, u64*, u64*,
                         uint32_t, uint32_t, hipStream_t);
@@ -88,7 +88,7 @@ struct bbc_context {
     bool timing = false;
     bool timing_valid = false;
     double phase_ms[4] = {0, 0, 0, 0};
-    int64_t stats[13] = {0};
+    int64_t stats[14] = {0};
     uint32_t hash_target = bbc::kDefaultHashTarget;
     uint32_t probe_limit = bbc::kDefaultProbeLimit;
     uint64_t chunk_min = bbc::kRecordChunkWedges;
@@ -500,7 +500,7 @@ bbc_status bbc_last_phase_ms(const bbc_context* c, int phase, double* ms) {
 
 bbc_status bbc_last_stats(const bbc_context* c, int64_t* stats, int n) {
     if (!c || !stats || n < 0) return BBC_ERR_INVALID_ARG;
-    for (int i = 0; i < n && i < 13; ++i) stats[i] = c->stats[i];
+    for (int i = 0; i < n && i < 14; ++i) stats[i] = c->stats[i];
     return BBC_OK;
 }
 
@@ -805,7 +805,8 @@ static bbc_status run_pipeline(bbc_context* c, const RunIn& in, RunOut& ro) {
                     (unsigned long long)h.tot_sw, (unsigned long long)h.tot_tiles,
                     (unsigned long long)h.tot_g);
     const uint32_t n_heavy = (uint32_t)h.tot_heavy, n_light = (uint32_t)h.tot_light;
-    const uint32_t n_dense = (uint32_t)std::min<u64>(h.n_dense_pieces, h.tot_heavy);
+    const uint32_t n_wave = (uint32_t)std::min<u64>(h.n_wave, h.tot_heavy);
+    const uint32_t n_dense = (uint32_t)std::min<u64>(h.n_dense_pieces, h.tot_heavy - n_wave);
     const uint64_t n_light_items64 = (h.tot_light_region + d.light_window - 1) / d.light_window;
     const uint32_t n_light_items = (uint32_t)n_light_items64;
     const uint32_t n_items = n_heavy + n_light_items;
@@ -859,7 +860,7 @@ static bbc_status run_pipeline(bbc_context* c, const RunIn& in, RunOut& ro) {
     std::vector<uint64_t> keyB;
     if (c->use_graphs) keyB = keyA;
     if (c->use_graphs)
-    for (uint64_t x : {(uint64_t)n_heavy, (uint64_t)n_dense, (uint64_t)n_light, (uint64_t)n_light_items, (uint64_t)h.tot_g,
+    for (uint64_t x : {(uint64_t)n_heavy, (uint64_t)n_dense, (uint64_t)n_wave, (uint64_t)n_light, (uint64_t)n_light_items, (uint64_t)h.tot_g,
                        (uint64_t)h.tot_sw, (uint64_t)h.tot_tiles, (uint64_t)plan_base, (uint64_t)first_long[0],
                        (uint64_t)first_long[1], (uint64_t)in.per_vertex, (uint64_t)in.pv_host})
         keyB.push_back(x);
@@ -892,7 +893,7 @@ static bbc_status run_pipeline(bbc_context* c, const RunIn& in, RunOut& ro) {
 
     // ---- wedge enumeration and bucket counting
     if (tm) HIPCHECK(c, hipEventRecord(c->ev[kEvWedgeA], st));
-    HIPCHECK(c, launch_wedge(pieces, order, items_first, n_heavy, n_dense, redo, n_items, b.recs, b.col, b.tb, d,
+    HIPCHECK(c, launch_wedge(pieces, order, items_first, n_heavy, n_dense, n_wave, redo, n_items, b.recs, b.col, b.tb, d,
                              first_long, G, sw_off, sw_list, sw_mid, b.ctl,
                              bt ? bt->gres : nullptr, pv, (uint32_t)(2 * m),
                              c->num_cus, st));
@@ -914,7 +915,7 @@ static bbc_status run_pipeline(bbc_context* c, const RunIn& in, RunOut& ro) {
         return fail(c, BBC_ERR_INTERNAL,
                     "wedge kernel invariant broken (flags %u: 1 = an unsplit hashed piece gave up, "
                     "4 = a split piece met a short-middle record, 8 = a packed piece reached the "
-                    "general kernel)",
+                    "general kernel, 16 = a one-wave piece exceeds its counter slice)",
                     h.internal_err);
     if (tm_out && !c->use_graphs) {
         c->phase_ms[0] += ev_ms(c, kEvStart, kEvEnd);
@@ -945,6 +946,7 @@ static void add_stats(bbc_context* c, const RunOut& ro, uint64_t m) {
     c->stats[10] += (int64_t)ro.h.n_hashed;
     c->stats[11] += (int64_t)ro.h.n_dense8;
     c->stats[12] += (int64_t)ro.h.n_dense4;
+    c->stats[13] += (int64_t)ro.h.n_wave;
 }
 
 static void begin_call(bbc_context* c) {
@@ -1290,10 +1292,10 @@ bbc_status bbc_count_batch(bbc_context* c, int32_t n_graphs, const int32_t* n_u,
         else
             small.push_back((uint32_t)g);
     }
-    int64_t stats[13] = {0};
+    int64_t stats[14] = {0};
     double ph[4] = {0, 0, 0, 0};
     auto keep_stats = [&]() {
-        for (int i = 0; i < 13; ++i) stats[i] += c->stats[i];
+        for (int i = 0; i < 14; ++i) stats[i] += c->stats[i];
         for (int i = 0; i < 4; ++i) ph[i] += c->phase_ms[i];
     };
     // unions: consecutive small graphs up to the size limits

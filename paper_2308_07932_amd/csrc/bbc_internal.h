@@ -88,6 +88,12 @@ constexpr uint32_t kPieceHash16 = 32u;  // hashed with 16-bit l | m halves (2 x 
 constexpr uint32_t kPieceDense8 = 64u;   // l | m << 8 per end vertex, two per word (four tiles)
 constexpr uint32_t kPieceDense4 = 128u;  // l | m << 4 per end vertex, four per word (eight tiles)
 constexpr uint32_t kDensePacked = kPieceDense8 | kPieceDense4;
+constexpr uint32_t kPieceWave = 256u;  // counted by one wave alone (k_wedge_wave)
+// One-wave pieces: each wave of a workgroup owns kWaveWords u32 counters
+// (l | m halves of 16, 8 or 4 bits, so 1, 2 or 4 end vertices per word), and
+// takes starts of at most kWaveMaxW wedges
+constexpr uint32_t kWaveWords = 2048;
+constexpr u64 kWaveMaxW = 1u << 16;
 
 // One unit of counting: records [rec0, rec0 + nrec) of one start vertex,
 // restricted to end vertices with sidx in [lo, hi).
@@ -131,6 +137,9 @@ struct Control {
     uint32_t queue_hash;  // work counter of the hashed-piece wedge kernel
     uint32_t redo_n;      // halves of hashed pieces to redo (in the redo list)
     u64 n_dense8, n_dense4;  // tile pieces with packed 8- and 4-bit counters
+    u64 n_wave;              // one-wave pieces (the last n_wave heavy items)
+    uint32_t queue_wave;     // work counter of the one-wave kernel
+    uint32_t pad1;
 };
 
 struct Dims {

@@ -45,15 +45,16 @@ __device__ inline uint32_t next_pow2(uint32_t x) {
 
 __device__ inline uint32_t log2_pow2(uint32_t x) { return 31u - __clz(x); }
 
-// Sort key of a heavy piece (ascending, 8 bits: one radix pass): pieces with
-// dense counters first (they run in their own kernel), each group most
-// expensive first by a 7-bit log-scale of the estimated cost (quarter
-// doublings), 4 units per record visited plus the expected wedges.
-constexpr uint32_t kCostKeyBits = 8;
-__device__ inline uint32_t cost_key(double wedges, uint32_t nrec, bool dense) {
+// Sort key of a heavy piece (ascending, 8 bits: one radix pass): by the
+// kernel that runs it (workgroup pieces with dense counters, then hashed
+// ones, then one-wave pieces), each group most expensive first by a 6-bit
+// log-scale of the estimated cost (half doublings), 4 units per record
+// visited plus the expected wedges.
+enum : uint32_t { kGroupDense = 0, kGroupHashed = 1, kGroupWave = 2 };
+__device__ inline uint32_t cost_key(double wedges, uint32_t nrec, uint32_t group) {
     const double c = wedges + 4.0 * nrec;
-    const double q = log2(1.0 + c) * 4.0;
-    return (dense ? 0u : 1u << 7) | (127u - (uint32_t)fmin(q, 127.0));
+    const double q = log2(1.0 + c) * 2.0;
+    return (group << 6) | (63u - (uint32_t)fmin(q, 63.0));
 }
 
 // Kinds of the pieces of a split start
@@ -152,12 +153,28 @@ __device__ uint32_t plan_runs(const uint32_t* __restrict__ row_ptr, uint32_t bas
     return n;
 }
 
-enum : uint32_t { kClassNone = 0, kClassLight, kClassSmallSide, kClassTiles };
+enum : uint32_t { kClassNone = 0, kClassLight, kClassSmallSide, kClassTiles, kClassWave };
 
 struct StartPlan {
     uint32_t cls, pieces, region, tiles;  // tiles > 0: a split start with T tiles
     uint32_t graph, lo;                   // the start's graph and its sidx block start
+    uint32_t wlog;                        // one-wave pieces: log2 of ends per counter word
 };
+
+// The layout of a one-wave piece over end vertices [lo & ~3, S): the widest
+// packing the range's last end vertex allows (l + m <= min(k, deg(w))), if the
+// range then fits one wave's counter slice; else kEmpty.
+__device__ inline uint32_t wave_layout(const uint32_t* __restrict__ row_ptr, uint32_t base,
+                                       uint32_t lo, uint32_t S, uint32_t k) {
+    // an empty end range has no last vertex (W > 0 there only with invalid
+    // input: a duplicate pair puts u into its own prefix)
+    if (S <= lo) return kEmpty;
+    const uint32_t dg = row_ptr[base + S] - row_ptr[base + S - 1];
+    const uint32_t bound = min(k, dg);
+    const uint32_t wl = bound <= 15u ? 2u : bound <= 255u ? 1u : bound <= 65535u ? 0u : kEmpty;
+    if (wl == kEmpty || S - (lo & ~3u) > (kWaveWords << wl)) return kEmpty;
+    return wl;
+}
 
 // wedges per record chunk of a small-side start
 __device__ inline u64 chunk_wedges(const Dims& d, const Control* ctl) {
@@ -167,7 +184,7 @@ __device__ inline u64 chunk_wedges(const Dims& d, const Control* ctl) {
 
 __device__ inline StartPlan plan_start(const uint32_t* __restrict__ row_ptr, const Dims& d,
                                        uint32_t r, u64 W, uint32_t k, u64 chunk) {
-    StartPlan sp = {kClassNone, 0, 0, 0, 0, 0};
+    StartPlan sp = {kClassNone, 0, 0, 0, 0, 0, 0};
     const uint32_t side = r >= d.n_u ? 1u : 0u;
     const uint32_t S = r - d.base[side];
     if (d.n_graphs > 1) {
@@ -175,6 +192,17 @@ __device__ inline StartPlan plan_start(const uint32_t* __restrict__ row_ptr, con
         sp.lo = d.blk[side][sp.graph];
     }
     if (W == 0) return sp;
+    // a small start whose end range fits one wave's packed counters: one wave
+    // counts it alone (no workgroup barriers, no hashing)
+    if (!d.per_vertex && W <= kWaveMaxW) {
+        const uint32_t wl = wave_layout(row_ptr, d.base[side], sp.lo, S, k);
+        if (wl != kEmpty) {
+            sp.cls = kClassWave;
+            sp.pieces = 1;
+            sp.wlog = wl;
+            return sp;
+        }
+    }
     if (W <= d.light_max) {
         sp.cls = kClassLight;
         sp.region = max(kMinRegion, next_pow2((uint32_t)(2 * W)));
@@ -212,9 +240,11 @@ __global__ void k_plan_count(const u64* __restrict__ wu, const u64* __restrict__
                              uint32_t* __restrict__ lf, uint32_t* __restrict__ gs,
                              uint32_t* __restrict__ tc, u64* __restrict__ swc, Control* ctl) {
     const u64 chunk = chunk_wedges(d, ctl);
+    u64 n_wave = 0;
     for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < d.n; r += gridDim.x * blockDim.x) {
         const u64 W = wu[r];
         const StartPlan sp = plan_start(row_ptr, d, r, W, lowcnt[r], chunk);
+        n_wave += sp.cls == kClassWave ? 1u : 0u;
         const uint32_t side = r >= d.n_u ? 1u : 0u;
         if (sp.cls == kClassTiles && d.n_graphs > 1) atomicOr(&ctl->internal_err, 2u);
         if (sp.cls == kClassTiles) {  // tile pieces by kind
@@ -239,6 +269,8 @@ __global__ void k_plan_count(const u64* __restrict__ wu, const u64* __restrict__
         tc[r] = sp.tiles;
         swc[r] = sp.tiles ? wsu[r] : 0ull;
     }
+    n_wave = wave_reduce_sum(n_wave);
+    if (lane_id() == 0 && n_wave) atomicAdd(&ctl->n_wave, n_wave);
 }
 
 __global__ void k_plan_write(const u64* __restrict__ wu, const uint32_t* __restrict__ lowcnt,
@@ -284,6 +316,25 @@ __global__ void k_plan_write(const u64* __restrict__ wu, const uint32_t* __restr
         }
         const uint32_t h = sp.pieces;
         const uint32_t b = hp_off[r];
+        if (sp.cls == kClassWave) {
+            Piece p;
+            p.rec0 = m0;
+            p.nrec = k;
+            p.lo = sp.lo & ~3u;  // (so that w's low bits give its slot in a packed word)
+            p.hi = S;
+            p.t0 = kNoTile;
+            p.t1 = kNoTile;
+            p.region = 0;
+            p.flags = kPieceDense | kPieceWave | sideflag |
+                      (sp.wlog == 2 ? kPieceDense4 : sp.wlog == 1 ? kPieceDense8 : kPieceDense16);
+            p.gbase = kEmpty;
+            p.start_row = r;
+            p.list = kEmpty;
+            p.graph = sp.graph;
+            pieces[b] = p;
+            hkey[b] = cost_key((double)W, k, kGroupWave);
+            continue;
+        }
         if (sp.cls == kClassSmallSide) {
             for (uint32_t i = 0; i < h; ++i) {
                 const uint32_t c0 = (uint32_t)((u64)k * i / h), c1 = (uint32_t)((u64)k * (i + 1) / h);
@@ -301,7 +352,7 @@ __global__ void k_plan_write(const u64* __restrict__ wu, const uint32_t* __restr
                 p.list = kEmpty;
                 p.graph = sp.graph;
                 pieces[b + i] = p;
-                hkey[b + i] = cost_key((double)W * (c1 - c0) / k, c1 - c0, true);
+                hkey[b + i] = cost_key((double)W * (c1 - c0) / k, c1 - c0, kGroupDense);
             }
             continue;
         }
@@ -338,7 +389,7 @@ __global__ void k_plan_write(const u64* __restrict__ wu, const uint32_t* __restr
             p.list = bucketed ? b + i : kEmpty;
             p.graph = 0;
             pieces[b + i] = p;
-            hkey[b + i] = cost_key(est, p.nrec, dense);
+            hkey[b + i] = cost_key(est, p.nrec, dense ? kGroupDense : kGroupHashed);
             if (split)
                 for (uint32_t t = t0; t < t1; ++t) tile_piece[tc_off[r] + t] = i;
             ++i;

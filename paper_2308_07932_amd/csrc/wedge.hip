@@ -45,7 +45,9 @@ struct WedgeArgs {
     Control* ctl;
     u64* gres;  // batches: per graph {balanced, unbalanced, wedges, -}; else NULL (totals in ctl)
     u64* pv;    // per-vertex mode: balanced butterflies per row (n entries, zeroed)
-    uint32_t n_dense;  // heavy items 0..n_dense-1 are dense pieces, n_dense..n_heavy-1 hashed
+    uint32_t n_dense;  // heavy items 0..n_dense-1 are dense pieces, n_dense..n_heavy-n_wave-1
+                       // hashed, the last n_wave one-wave pieces
+    uint32_t n_wave;
     uint32_t item0;    // first item k_wedge runs (n_heavy, or 0 when it runs them all)
     Piece* redo;       // halves of hashed pieces k_wedge_pieces<true> gave up on (ctl->redo_n),
                        // run by k_wedge as items n_items, n_items + 1, ...
@@ -1015,7 +1017,7 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge_pieces(WedgeArgs a) {
     auto fetch = [&]() -> uint32_t {
         if (HASH) {
             const uint32_t i = a.n_dense + atomicAdd(&a.ctl->queue_hash, 1u);
-            return i < a.n_heavy ? i : kEmpty;
+            return i < a.n_heavy - a.n_wave ? i : kEmpty;
         }
         const uint32_t i = atomicAdd(&a.ctl->queue_dense, 1u);
         return i < a.n_dense ? i : kEmpty;
@@ -1620,6 +1622,219 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge_pieces(WedgeArgs a) {
     if (tid == 0) s_acc.flush(a);
 }
 
+
+// ---------------------------------------------------------------------------
+// One-wave pieces (k_wedge_wave): a start with at most kWaveMaxW wedges whose
+// end vertices [lo, S) fit kWaveWords packed counters is counted by one wave
+// alone, in a slice of the workgroup's LDS: the wave clears its slice, sweeps
+// the start's records 64 at a time (each record's whole prefix, the same
+// concatenated sweep as k_wedge_pieces: head flags, a sentinel past the end,
+// steps in pairs), and sums C(l,2) + C(m,2) and l m over its slice.  Waves take
+// pieces from a global counter and never wait for one another (Section 4.1's
+// per-start buckets, one start per wavefront).
+__global__ __launch_bounds__(kWedgeThreads) void k_wedge_wave(WedgeArgs a) {
+    // per wave: kWaveWords counters, then 64 junk words for the lanes past a
+    // grab's end (and, with invalid input, for ends outside the range)
+    constexpr uint32_t kSlice = kWaveWords + 64;
+    __shared__ __align__(16) uint32_t s_cnt[kWaves * kSlice];
+    __shared__ uint2 s_rec[kWaves][65];
+    __shared__ uint32_t s_hd[kWaves][64];
+    const uint32_t lane = lane_id();
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    uint32_t* slice = s_cnt + wave * kSlice;
+    const uint32_t junk = kWaveWords + lane;  // relative to slice
+    const uint32_t* __restrict__ col = a.col;
+    const u64 le_mask = ~0ull >> (63 - lane);
+    const uint32_t first = a.n_heavy - a.n_wave;
+    uint32_t g = 0;
+    u64 bal = 0, unb = 0;  // this wave's totals for graph g
+    auto flush = [&]() {
+        if (lane == 0 && (bal | unb)) {
+            u64* dst = a.gres ? a.gres + 4ull * g : &a.ctl->balanced;
+            atomicAdd(dst, bal);
+            atomicAdd(dst + 1, unb);
+        }
+        bal = unb = 0;
+    };
+    s_hd[wave][lane] = 0;
+    // a wave takes runs of G consecutive pieces (most expensive first): one
+    // atomic per run keeps the shared counter cold when there are millions of
+    // small pieces, and runs of 1 balance the few large ones
+    const uint32_t G = max(1u, a.n_wave / (gridDim.x * kWaves * 8u));
+    uint32_t it = 0, it_end = 0;
+    for (;;) {
+        if (it == it_end) {
+            uint32_t b = 0;
+            if (lane == 0) b = atomicAdd(&a.ctl->queue_wave, G);
+            it = __builtin_amdgcn_readfirstlane(__shfl(b, 0, 64));
+            if (it >= a.n_wave) break;
+            it_end = min(it + G, a.n_wave);
+        }
+        const Piece* pp = a.pieces + a.order[first + it];
+        ++it;
+        const uint32_t rec0 = __builtin_amdgcn_readfirstlane(pp->rec0);
+        const uint32_t nrec = __builtin_amdgcn_readfirstlane(pp->nrec);
+        const uint32_t dlo = __builtin_amdgcn_readfirstlane(pp->lo);
+        const uint32_t dhi = __builtin_amdgcn_readfirstlane(pp->hi);
+        const uint32_t flags = __builtin_amdgcn_readfirstlane(pp->flags);
+        const uint32_t graph = __builtin_amdgcn_readfirstlane(pp->graph);
+        const int dk = (flags & kPieceDense4) ? kD4 : (flags & kPieceDense8) ? kD8 : kD16;
+        const uint32_t wlog = dk == kD4 ? 2u : dk == kD8 ? 1u : 0u;
+        const uint32_t groups = (((dhi - dlo + (1u << wlog) - 1u) >> wlog) + 3u) / 4u;
+        if (groups > kWaveWords / 4 || dhi <= dlo) {  // cannot happen by construction
+            if (lane == 0) atomicOr(&a.ctl->internal_err, 16u);
+            continue;
+        }
+        // the first 64 records load while the slice is cleared
+        auto load_rec = [&](uint32_t base, uint32_t& rs, uint32_t& pos, uint32_t& s1) {
+            const bool act = base + lane < nrec;
+            const uint4 rc = a.recs[rec0 + (act ? base + lane : 0u)];
+            rs = rc.x;
+            pos = act ? rc.y >> 1 : 0u;
+            s1 = rc.y & 1u;
+        };
+        uint32_t rs, pos, s1;
+        load_rec(0, rs, pos, s1);
+        uint4* s4 = reinterpret_cast<uint4*>(slice);
+        for (uint32_t i = lane; i < groups; i += 64) s4[i] = make_uint4(0, 0, 0, 0);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        auto sweep = [&](auto dktag) {
+            constexpr int DK = decltype(dktag)::value;
+            for (uint32_t base = 0; base < nrec; base += 64) {
+                // next 64 records, loaded during this sweep
+                uint32_t nrs = 0, npos = 0, ns1 = 0;
+                if (base + 64 < nrec) load_rec(base + 64, nrs, npos, ns1);
+                const uint32_t len = pos;
+                const u64 nz = __ballot(len > 0);
+                const uint32_t excl = wave_incl_scan(len) - len;
+                const uint32_t T = __builtin_amdgcn_readfirstlane(__shfl(excl + len, 63, 64));
+                if (len > 0) s_rec[wave][__popcll(nz & (le_mask >> 1))] = make_uint2(rs - excl, s1);
+                if (lane == 0) s_rec[wave][__popcll(nz)] = make_uint2(a.col_pad - T, 2u);
+                uint32_t before = 0;
+                auto step_load = [&](uint32_t j, uint32_t* x, uint32_t* aux) {
+                    uint8_t* hb = (uint8_t*)s_hd[wave];
+                    if (len > 0 && excl >= j && excl < j + 64 * kUnroll) {
+                        const uint32_t hp = excl - j;
+                        hb[(hp & 63u) * kUnroll + (hp >> 6)] = 1;
+                    }
+                    if (lane == 0 && T >= j && T < j + 64 * kUnroll) {
+                        const uint32_t hp = T - j;
+                        hb[(hp & 63u) * kUnroll + (hp >> 6)] = 1;
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                    const uint32_t hd4 = s_hd[wave][lane];
+                    uint32_t adj[kUnroll];
+#pragma unroll
+                    for (uint32_t u = 0; u < kUnroll; ++u) {
+                        const bool own = ((hd4 >> (8 * u)) & 0xFFu) != 0;
+                        const u64 M = __ballot(own);
+                        const u64 Ms = M >> 1;
+                        const uint32_t upto = __builtin_amdgcn_mbcnt_hi(
+                            (uint32_t)(Ms >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)Ms, 0u));
+                        const uint32_t idx = (before + (uint32_t)(M & 1u) - 1u) + upto;
+                        before += (uint32_t)__popcll(M);
+                        const uint2 r = s_rec[wave][idx];
+                        adj[u] = r.x;
+                        aux[u] = r.y;
+                    }
+#pragma unroll
+                    for (uint32_t u = 0; u < kUnroll; ++u) x[u] = col[adj[u] + j + u * 64 + lane];
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                    s_hd[wave][lane] = 0;
+                    __builtin_amdgcn_sched_barrier(0);
+                };
+                auto step_add = [&](const uint32_t* x, const uint32_t* aux) {
+#pragma unroll
+                    for (uint32_t u = 0; u < kUnroll; ++u) {
+                        const uint32_t y = x[u] ^ aux[u];
+                        if (DK == kD16) {
+                            const uint32_t at = min((x[u] >> 1) - dlo, junk);
+                            atomicAdd(&slice[at], 1u << ((y & 1u) << 4));
+                        } else if (DK == kD8) {
+                            const uint32_t at = min((x[u] >> 2) - (dlo >> 1), junk);
+                            atomicAdd(&slice[at], 1u << ((y & 3u) << 3));
+                        } else {
+                            const uint32_t at = min((x[u] >> 3) - (dlo >> 2), junk);
+                            atomicAdd(&slice[at], 1u << ((y & 7u) << 2));
+                        }
+                    }
+                };
+                if (T > 0) {
+                    constexpr uint32_t S = 64 * kUnroll;
+                    const uint32_t nsteps = (T + S - 1) / S;
+                    uint32_t xa[kUnroll], aa[kUnroll], xb[kUnroll], ab[kUnroll];
+                    uint32_t j = 0;
+                    if (nsteps & 1u) {
+                        step_load(0, xb, ab);
+                        step_load(S, xa, aa);
+                        step_add(xb, ab);
+                        j = S;
+                    } else {
+                        step_load(0, xa, aa);
+                    }
+                    if (j < T) {
+                        for (;;) {
+                            step_load(j + S, xb, ab);
+                            step_add(xa, aa);
+                            step_load(j + 2 * S, xa, aa);
+                            step_add(xb, ab);
+                            j += 2 * S;
+                            if (j >= T) break;
+                        }
+                    }
+                }
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                rs = nrs;
+                pos = npos;
+                s1 = ns1;
+            }
+        };
+        if (dk == kD16)
+            sweep(std::integral_constant<int, kD16>());
+        else if (dk == kD8)
+            sweep(std::integral_constant<int, kD8>());
+        else
+            sweep(std::integral_constant<int, kD4>());
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        // finalize over the slice: 2 (C(l,2) + C(m,2)) and 2 l m
+        u64 q2 = 0, lm2 = 0;
+        for (uint32_t i = lane; i < groups; i += 64) {
+            const uint4 c = s4[i];
+            if (dk == kD16) {
+                bucket16_sums(c.x, q2, lm2);
+                bucket16_sums(c.y, q2, lm2);
+                bucket16_sums(c.z, q2, lm2);
+                bucket16_sums(c.w, q2, lm2);
+            } else {
+                uint32_t q = 0, lm = 0;
+                if (dk == kD8) {
+                    bucket8_sums(c.x, q, lm);
+                    bucket8_sums(c.y, q, lm);
+                    bucket8_sums(c.z, q, lm);
+                    bucket8_sums(c.w, q, lm);
+                } else {
+                    bucket4_sums(c.x, q, lm);
+                    bucket4_sums(c.y, q, lm);
+                    bucket4_sums(c.z, q, lm);
+                    bucket4_sums(c.w, q, lm);
+                }
+                q2 += q;
+                lm2 += lm;
+            }
+        }
+        q2 = wave_reduce_sum(q2);
+        lm2 = wave_reduce_sum(lm2);
+        if (graph != g) {
+            flush();
+            g = graph;
+        }
+        bal += q2 >> 1;
+        unb += lm2 >> 1;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");  // the slice's reads before the next clear
+    }
+    flush();
+}
+
 // per-vertex output by input vertex id: out[x] = count of x's row
 __global__ void k_pv_out(const u64* __restrict__ pv, const uint32_t* __restrict__ sidx_of, Dims d,
                          u64* __restrict__ out) {
@@ -1640,7 +1855,7 @@ hipError_t launch_pv_out(const u64* pv, const uint32_t* sidx_of, Dims d, u64* ou
 // of hashed pieces redone in k_wedge; per-vertex mode runs every item in
 // k_wedge<true>.
 hipError_t launch_wedge(const Piece* pieces, const uint32_t* order, const uint32_t* items_first,
-                        uint32_t n_heavy, uint32_t n_dense, Piece* redo,
+                        uint32_t n_heavy, uint32_t n_dense, uint32_t n_wave, Piece* redo,
                         uint32_t n_items, const uint4* recs, const uint32_t* col, const uint32_t* tb,
                         Dims d, const uint32_t first_long[2], u64* G, const uint32_t* sw_off,
                         const uint32_t* sw_list, const uint32_t* sw_mid, Control* ctl, u64* gres,
@@ -1667,20 +1882,25 @@ hipError_t launch_wedge(const Piece* pieces, const uint32_t* order, const uint32
     a.gres = gres;
     a.pv = pv;
     a.n_dense = pv ? 0 : n_dense;
+    a.n_wave = pv ? 0 : n_wave;
     a.item0 = pv ? 0 : n_heavy;
     a.redo = pv ? nullptr : redo;
     if (!pv && n_dense > 0) {
         const uint32_t grid = min(num_cus, n_dense);
         hipLaunchKernelGGL(k_wedge_pieces<false>, dim3(grid), dim3(kWedgeThreads), 0, st, a);
     }
-    if (!pv && n_heavy > n_dense) {
-        const uint32_t grid = min(num_cus, n_heavy - n_dense);
+    if (!pv && n_heavy - n_wave > n_dense) {
+        const uint32_t grid = min(num_cus, n_heavy - n_wave - n_dense);
         hipLaunchKernelGGL(k_wedge_pieces<true>, dim3(grid), dim3(kWedgeThreads), 0, st, a);
+    }
+    if (!pv && n_wave > 0) {
+        const uint32_t grid = min(num_cus, (n_wave + kWaves - 1) / kWaves);
+        hipLaunchKernelGGL(k_wedge_wave, dim3(grid), dim3(kWedgeThreads), 0, st, a);
     }
     // light items, and any halves the hashed pieces left
     const uint32_t rest = n_items - a.item0;
     uint32_t grid = num_cus;
-    if (grid > rest && (pv || n_heavy == n_dense)) grid = rest;
+    if (grid > rest && (pv || n_heavy - n_wave == n_dense)) grid = rest;  // (no redo possible)
     if (grid == 0) return hipGetLastError();
     if (pv)
         hipLaunchKernelGGL(k_wedge<true>, dim3(grid), dim3(kWedgeThreads), 0, st, a);
