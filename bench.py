@@ -38,22 +38,25 @@ def log(*a):
 
 
 def wedge_kernel_source_hash() -> str:
+    """Hash of the sources that shape the wedge step's memory traffic (its
+    kernels and the planner that cuts the work into pieces)."""
     h = hashlib.sha256()
-    for f in ("wedge.hip", "bbc_internal.h"):
+    for f in ("wedge.hip", "plan.hip", "bbc_internal.h"):
         h.update(open(os.path.join(ROOT, "paper_2308_07932_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
 
 def measured_traffic(workload: str):
-    """HBM bytes per wedge-kernel launch from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel source; else None."""
+    """HBM bytes of the wedge step (its kernels' launches in one count) from the
+    committed rocprofv3 counter summary, if it was taken on the current
+    sources; else None."""
     p = os.path.join(ROOT, "profiles", f"wedge_{workload}_traffic.json")
     if not os.path.exists(p):
         return None
     d = json.load(open(p))
     if d.get("kernel_source_hash") != wedge_kernel_source_hash():
         return None
-    return d.get("hbm_bytes_per_launch")
+    return d.get("hbm_bytes_per_count")
 
 
 def host_threads() -> int:
@@ -506,7 +509,7 @@ def main():
         f"plan {phase[3]:.3f}, wedge kernel {phase[2]:.3f}; items={st[4]} heavy_pieces={st[7]} "
         f"resplit_pieces={st[5]} active_starts={active}")
 
-    # algorithmic bytes of the wedge kernel: 4 B per wedge (one CSR entry),
+    # algorithmic bytes of the wedge step: 4 B per wedge (one CSR entry),
     # 16 B per middle record, 16 B per active start
     alg_bytes = 4 * W + 16 * m + 16 * active
     achieved = alg_bytes / (phase[2] * 1e-3) / 1e9
@@ -530,9 +533,17 @@ def main():
         "total_count_time_ms": ms,
         "phase_ms": {"prep": phase[1], "plan": phase[3], "wedge_kernel": phase[2],
                      "pipeline": phase[0]},
+        "work": {"work_items": st[4], "heavy_pieces": st[7], "resplit_pieces": st[5],
+                 "tile_pieces": {"dense_32bit": st[8], "dense_16bit_2_tiles": st[9],
+                                 "dense_8bit_4_tiles": st[11], "dense_4bit_8_tiles": st[12],
+                                 "hashed_runs": st[10]},
+                 "one_wave_pieces": st[13]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic, "kernel": "bbc::k_wedge",
+                     "traffic": traffic,
+                     "kernel": "wedge step: bbc::k_wedge_pieces<false> (dense pieces), "
+                               "k_wedge_pieces<true> (hashed), k_wedge_wave (one-wave pieces), "
+                               "k_wedge (light items), one launch each per count",
                      "algorithmic_bytes_per_launch": alg_bytes},
     }
     peaks = lds_atomic_peaks()

@@ -227,6 +227,27 @@ def test_packed_counters_at_their_limits(ctx):
     assert ctx.stats()[11] >= 1, ctx.stats()
 
 
+def test_one_wave_pieces_at_their_limits(ctx):
+    # starts counted by one wave alone: 4-bit halves filled to 15 (4,000 ends
+    # of degree 15), 8-bit halves filled to 255, and 16-bit counters over a
+    # range of exactly one slice (2,048 ends: 2,047 of degree 1 below one of
+    # degree 300, which sets the width)
+    for g in (saturated_graph(4000, 15, 1000), saturated_graph(250, 255, 400)):
+        check(ctx, g)
+        assert ctx.stats()[13] >= 1, ctx.stats()
+    rng = np.random.default_rng(12)
+    eu, ev = [0] * 400, list(range(400))
+    for i in range(1, 2048):
+        eu.append(i)
+        ev.append(i % 400)
+    eu += [2048] * 300
+    ev += list(range(300))
+    g = SignedBipartiteGraph(2049, 400, np.array(eu, np.int32), np.array(ev, np.int32),
+                             rng.choice([1, -1], size=len(eu)).astype(np.int8), "wave16_full")
+    check(ctx, g)
+    assert ctx.stats()[13] >= 1, ctx.stats()
+
+
 def test_tiles_of_degree_one_ends(ctx):
     # A hub adjacent to 2000 middles, each with private leaves of degree 1
     # (80 per middle for the first 100, whose rows are then long, 30 for the
