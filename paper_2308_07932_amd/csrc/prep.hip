@@ -23,11 +23,14 @@ namespace bbc {
 // workgroup takes chunks of kAggChunk edges; the endpoints of one vertex inside
 // a chunk are ranked in an LDS table and reserve their slots with one global
 // returning atomic, so a hub costs one global atomic per chunk instead of one
-// per edge.  Endpoints that find no table slot reserve theirs directly.
-constexpr int kAggThreads = 256;
+// per edge (device-wide atomics are the cost here: on MI355X they retire at a
+// few G/s).  Chunks of 16K edges and a 16K-slot table let every vertex of a
+// small graph of a batch (at most 8192) aggregate within a chunk.  Endpoints
+// that find no table slot reserve theirs directly.
+constexpr int kAggThreads = 1024;
 constexpr int kAggPer = 16;  // edges per thread per chunk
 constexpr uint32_t kAggChunk = kAggThreads * kAggPer;
-constexpr uint32_t kAggLog2 = 12;
+constexpr uint32_t kAggLog2 = 14;
 constexpr uint32_t kAggSlots = 1u << kAggLog2;
 
 __device__ inline bool edge_ok(int32_t u, int32_t v, int8_t s, uint32_t n_u, uint32_t n_v) {
