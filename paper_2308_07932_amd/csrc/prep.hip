@@ -247,8 +247,13 @@ __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ eu,
                                                  const uint2* __restrict__ vx,
                                                  const uint2* __restrict__ rank,
                                                  uint32_t* __restrict__ col) {
-    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
-         e += (uint64_t)gridDim.x * blockDim.x) {
+    // XCD-aware: workgroup b runs on XCD b % 8 (round-robin dispatch); XCD x
+    // takes the x-th eighth of the edges, so the rows a batched graph writes
+    // are written through one L2
+    const uint32_t x = blockIdx.x & 7u, bx = blockIdx.x >> 3, nbx = gridDim.x >> 3;
+    const uint64_t e_lo = m * x / 8, e_hi = m * (x + 1) / 8;
+    for (uint64_t e = e_lo + (uint64_t)bx * blockDim.x + threadIdx.x; e < e_hi;
+         e += (uint64_t)nbx * blockDim.x) {
         const int32_t u = eu[e], v = ev[e];
         const int8_t s = sg[e];
         if (!edge_ok(u, v, s, n_u, n_v)) continue;
@@ -1043,7 +1048,8 @@ hipError_t launch_scatter(const int32_t* eu, const int32_t* ev, const int8_t* sg
     const uint32_t n = n_u + n_v;
     hipLaunchKernelGGL(k_vertex_pack, grid_n(n, 256), dim3(256), 0, st, sidx_of, row_ptr, n, n_u,
                        vx);
-    hipLaunchKernelGGL(k_scatter, grid_n(m, 256), dim3(256), 0, st, eu, ev, sg, m, n_u, n_v,
+    hipLaunchKernelGGL(k_scatter, dim3((grid_n(m, 256).x + 7) & ~7u), dim3(256), 0, st, eu, ev, sg,
+                       m, n_u, n_v,
                        (const uint2*)vx, rank, col);
     return hipGetLastError();
 }
