@@ -93,10 +93,11 @@ __device__ inline uint32_t hash32(uint32_t w) { return w * 0x9E3779B1u; }
 // (l | m << 16).  Returns false if w finds no slot within `lim` probes.
 constexpr uint32_t kHash16Slots = 2 * kHashSlots;
 static_assert(kLightWindow16 + 2 * kLightMax <= kHash16Slots, "a light item's regions fit its table");
-__device__ inline bool bucket_add16(uint32_t* s32, uint32_t lim, uint32_t w, uint32_t inc) {
-    constexpr uint32_t lg = 31u - __builtin_clz(kHash16Slots);
-    const uint32_t h = hash32(w) >> (32 - lg);
-    for (uint32_t i = 0; i < lim; ++i) {
+constexpr uint32_t kHash16Log2 = 31u - __builtin_clz(kHash16Slots);
+__device__ inline bool bucket_add16(uint32_t* s32, uint32_t lim, uint32_t w, uint32_t inc,
+                                    uint32_t i0 = 0) {
+    const uint32_t h = hash32(w) >> (32 - kHash16Log2);
+    for (uint32_t i = i0; i < lim; ++i) {
         const uint32_t s = (h + i) & (kHash16Slots - 1u);
         uint32_t k = s32[s];
         if (k == kEmpty) {
@@ -114,11 +115,12 @@ __device__ inline bool bucket_add16(uint32_t* s32, uint32_t lim, uint32_t w, uin
 // The same table for the light starts of an item: w is hashed into its
 // start's region, probed whole (a region holds more slots than the start has
 // distinct ends, so it never fills).
-__device__ inline bool bucket_add16r(uint32_t* s32, uint32_t region, uint32_t w, uint32_t inc) {
+__device__ inline bool bucket_add16r(uint32_t* s32, uint32_t region, uint32_t w, uint32_t inc,
+                                     uint32_t i0 = 0) {
     const uint32_t rb = region & 0xFFFFu, lg = (region >> 16) & 31u;
     const uint32_t msk = (1u << lg) - 1u;
     const uint32_t h = hash32(w) >> (32 - lg);
-    for (uint32_t i = 0; i <= msk; ++i) {
+    for (uint32_t i = i0; i <= msk; ++i) {
         const uint32_t s = rb + ((h + i) & msk);
         uint32_t k = s32[s];
         if (k == kEmpty) {
@@ -579,12 +581,37 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge(WedgeArgs a) {
                         }
                         ok = __ballot(!lok) == 0;  // the whole wave leaves together
                     } else {  // light starts of an item: regions of the 16-bit-half table
-                        bool lok = true;
-#pragma unroll 1
+                        // The first probes of the step's windows go together (their
+                        // region, key and insert reads wait for LDS once each); an
+                        // entry whose first slot holds another key probes on from
+                        // the second slot.
+                        uint32_t rg[kUnroll], sl[kUnroll], kk[kUnroll];
+#pragma unroll
+                        for (uint32_t u = 0; u < kUnroll; ++u)
+                            rg[u] = s_pc[aux[u] == kEmpty ? 0u : aux[u] >> 2].region;
+#pragma unroll
                         for (uint32_t u = 0; u < kUnroll; ++u) {
-                            if (aux[u] == kEmpty || !lok) continue;
-                            lok = bucket_add16r(s32, s_pc[aux[u] >> 2].region, x[u] >> 1,
-                                                ((x[u] ^ aux[u]) & 1u) ? 0x10000u : 1u);
+                            const uint32_t lg = (rg[u] >> 16) & 31u;
+                            sl[u] = (rg[u] & 0xFFFFu) + (hash32(x[u] >> 1) >> (32 - lg));
+                            kk[u] = s32[sl[u]];
+                        }
+#pragma unroll
+                        for (uint32_t u = 0; u < kUnroll; ++u) {
+                            if (aux[u] != kEmpty && kk[u] == kEmpty) {
+                                const uint32_t o = atomicCAS(&s32[sl[u]], kEmpty, x[u] >> 1);
+                                kk[u] = o == kEmpty ? x[u] >> 1 : o;
+                            }
+                        }
+                        bool lok = true;
+#pragma unroll
+                        for (uint32_t u = 0; u < kUnroll; ++u) {
+                            if (aux[u] == kEmpty) continue;
+                            const uint32_t w = x[u] >> 1;
+                            const uint32_t inc = ((x[u] ^ aux[u]) & 1u) ? 0x10000u : 1u;
+                            if (kk[u] == w)
+                                atomicAdd(&s32[kHash16Slots + sl[u]], inc);
+                            else if (lok)
+                                lok = bucket_add16r(s32, rg[u], w, inc, 1);
                         }
                         ok = __ballot(!lok) == 0;
                     }
@@ -957,6 +984,62 @@ struct DenseGrab {
     uint32_t ta, tb;           // tile offsets of the piece's range (long middles of split starts)
 };
 
+// Where a piece's grabs come from: its records, the grab size, and for a split
+// start the tile tables that give each record's sub-interval of the range
+struct GrabSrc {
+    uint32_t rec0, total, bsz, t0, t1, tstride, flong;
+    bool partial;
+    const uint32_t* tbl;
+};
+
+__device__ inline GrabSrc grab_src(const WedgeArgs& a, uint32_t rec0, uint32_t nrec,
+                                   uint32_t flags, uint32_t t0, uint32_t t1) {
+    GrabSrc g;
+    g.rec0 = rec0;
+    g.total = nrec;
+    g.t0 = t0;
+    g.t1 = t1;
+    g.partial = (flags & kPiecePartial) != 0;
+    const uint32_t ys = (flags & kPieceSideV) ? 0u : 1u;  // side of the middles
+    g.bsz = g.partial ? min(32u, max(4u, (nrec + 15) / 16))
+                      : min(64u, max(8u, (nrec + a.d.grab_div - 1) / a.d.grab_div));
+    g.tbl = g.partial ? a.tb + a.d.tb_off[ys] : nullptr;
+    g.tstride = a.d.ntile[ys ^ 1u] + 1;
+    g.flong = a.first_long[ys];
+    return g;
+}
+
+// Loads below are issued by every lane (inactive lanes read a valid address
+// and drop the value): a load in a per-lane branch makes the compiler wait
+// for all outstanding loads where the branches meet.
+// -- this lane's record of the grab at `base` (total > 0)
+__device__ inline void grab_records(const WedgeArgs& a, const GrabSrc& s, uint32_t base,
+                                    uint32_t lane, DenseGrab& g) {
+    const uint32_t f = base + lane;
+    const bool act = lane < s.bsz && f < s.total;
+    const uint4 rc = a.recs[s.rec0 + (act ? f : 0u)];
+    g.rs = rc.x;
+    g.pos = act ? rc.y >> 1 : 0u;
+    g.s1 = rc.y & 1u;
+    g.vs = rc.z;
+}
+
+// -- the tile offsets of the piece's range in the record's middle row (split
+// starts; each long middle row has a tile table)
+__device__ inline void grab_tiles(const GrabSrc& s, DenseGrab& g) {
+    g.ta = 0;
+    g.tb = g.pos;
+    if (s.partial) {
+        const bool lng = g.pos > 0 && g.vs >= s.flong;
+        const uint32_t* t = s.tbl + (uint64_t)(lng ? g.vs - s.flong : 0u) * s.tstride;
+        const uint32_t a0 = t[s.t0], a1 = t[s.t1];
+        if (lng) {
+            g.ta = a0;
+            g.tb = a1;
+        }
+    }
+}
+
 // 2 (C(l,2) + C(m,2)) and 2 l m of one u32 bucket l | (m << 16), l + m < 2^16:
 // dot products of the two 16-bit halves
 __device__ inline void bucket16_sums(uint32_t c, u64& q2, u64& lm2) {
@@ -968,21 +1051,23 @@ __device__ inline void bucket16_sums(uint32_t c, u64& q2, u64& lm2) {
                                   false);
 }
 
-// The same sums over a word of two 8-bit-half buckets (bytes l0, m0, l1, m1):
-// every byte squared minus every byte, and each byte times its partner
-__device__ inline void bucket8_sums(uint32_t c, uint32_t& q2, uint32_t& lm2) {
-    const uint32_t sw = ((c >> 8) & 0x00FF00FFu) | ((c & 0x00FF00FFu) << 8);
-    q2 += __builtin_amdgcn_udot4(c, c, 0u, false) - __builtin_amdgcn_udot4(c, 0x01010101u, 0u, false);
-    lm2 += __builtin_amdgcn_udot4(c, sw, 0u, false);
+// Sums over a word of two 8-bit-half buckets (bytes l0, m0, l1, m1), kept in
+// the instructions' accumulators: q += every byte squared, s += every byte,
+// lm += l0 m0 + l1 m1; then 2 (C(l,2) + C(m,2)) = q - s over the words
+__device__ inline void bucket8_acc(uint32_t c, uint32_t& q, uint32_t& s, uint32_t& lm) {
+    q = __builtin_amdgcn_udot4(c, c, q, false);
+    s = __builtin_amdgcn_sad_u8(c, 0u, s);
+    lm = __builtin_amdgcn_udot4(c & 0x00FF00FFu, (c >> 8) & 0x00FF00FFu, lm, false);
 }
 
 // ... and over a word of four 4-bit-half buckets (byte i = l_i | m_i << 4,
 // l_i + m_i <= 15): the l and m nibbles split into bytes first
-__device__ inline void bucket4_sums(uint32_t c, uint32_t& q2, uint32_t& lm2) {
+__device__ inline void bucket4_acc(uint32_t c, uint32_t& q, uint32_t& s, uint32_t& lm) {
     const uint32_t l = c & 0x0F0F0F0Fu, m = (c >> 4) & 0x0F0F0F0Fu;
-    q2 += __builtin_amdgcn_udot4(l, l, 0u, false) + __builtin_amdgcn_udot4(m, m, 0u, false) -
-          __builtin_amdgcn_udot4(l + m, 0x01010101u, 0u, false);
-    lm2 += 2u * __builtin_amdgcn_udot4(l, m, 0u, false);
+    q = __builtin_amdgcn_udot4(l, l, q, false);
+    q = __builtin_amdgcn_udot4(m, m, q, false);
+    s = __builtin_amdgcn_sad_u8(l + m, 0u, s);
+    lm = __builtin_amdgcn_udot4(l, m, lm, false);
 }
 
 // dense counter layouts of k_wedge_pieces (log2 of end vertices per u32 word
@@ -1058,14 +1143,9 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge_pieces(WedgeArgs a) {
         // halves by k_wedge); an unsplit one holds at most kHashSlots/2 ends
         const uint32_t lim = (P.flags & kPiecePartial) ? a.d.probe_limit : kHashSlots;
         const bool partial = (P.flags & kPiecePartial) != 0;
-        const uint32_t ys = (P.flags & kPieceSideV) ? 0u : 1u;  // side of the middles
         const uint32_t dlo = P.lo, plo = P.lo, phi = P.hi, dwidth = P.hi - P.lo;
-        const uint32_t total = P.nrec;
-        const uint32_t bsz = partial ? min(32u, max(4u, (total + 31) / 32))
-                                     : min(64u, max(8u, (total + a.d.grab_div - 1) / a.d.grab_div));
-        const uint32_t* tbl = partial ? a.tb + a.d.tb_off[ys] : nullptr;
-        const uint32_t tstride = a.d.ntile[ys ^ 1u] + 1;
-        const uint32_t flong = a.first_long[ys];
+        const GrabSrc src = grab_src(a, P.rec0, P.nrec, P.flags, P.t0, P.t1);
+        const uint32_t total = src.total, bsz = src.bsz, flong = src.flong;
         const uint32_t junk32 = 2 * kDenseW + lane, junk64 = kDenseW + (lane >> 1);
         if (tid == 0) {
             s_batch = kWaves * bsz;  // grabs beyond every wave's first one
@@ -1074,33 +1154,9 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge_pieces(WedgeArgs a) {
             s_done = 0;
             s_abort = 0;
         }
-        // Loads below are issued by every lane (inactive lanes read a valid
-        // address and drop the value): a load in a per-lane branch makes the
-        // compiler wait for all outstanding loads where the branches meet.
-        // -- a grab's records (issued now, used later); total > 0
-        auto load_rec = [&](uint32_t base, DenseGrab& g) {
-            const uint32_t f = base + lane;
-            const bool act = lane < bsz && f < total;
-            const uint4 rc = a.recs[P.rec0 + (act ? f : 0u)];
-            g.rs = rc.x;
-            g.pos = act ? rc.y >> 1 : 0u;
-            g.s1 = rc.y & 1u;
-            g.vs = rc.z;
-        };
-        // tile offsets of the piece's range in the middle's row (split starts)
-        auto load_tiles = [&](DenseGrab& g) {
-            g.ta = 0;
-            g.tb = g.pos;
-            if (partial) {
-                const bool lng = g.pos > 0 && g.vs >= flong;
-                const uint32_t* t = tbl + (uint64_t)(lng ? g.vs - flong : 0u) * tstride;
-                const uint32_t a0 = t[P.t0], a1 = t[P.t1];
-                if (lng) {
-                    g.ta = a0;
-                    g.tb = a1;
-                }
-            }
-        };
+        // a grab's records (issued now, used later), then its tile offsets
+        auto load_rec = [&](uint32_t base, DenseGrab& g) { grab_records(a, src, base, lane, g); };
+        auto load_tiles = [&](DenseGrab& g) { grab_tiles(src, g); };
         // one wedge into the bucket of end vertex w; false when a hashed table
         // has no room for w within the probe limit
         auto add_one = [&](uint32_t w, bool asym) -> bool {
@@ -1289,6 +1345,37 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge_pieces(WedgeArgs a) {
                     return true;
                 }
                 bool lok = true;
+                if (h16) {
+                    // The first probes of the step's windows go together, so
+                    // that their key reads, and then their inserts, wait for
+                    // LDS once; an entry whose first slot holds another key
+                    // probes on from the second slot.  (The sentinel's pad
+                    // entries take no part.)
+                    uint32_t sl[kUnroll], kk[kUnroll];
+#pragma unroll
+                    for (uint32_t u = 0; u < kUnroll; ++u) {
+                        sl[u] = hash32(x[u] >> 1) >> (32 - kHash16Log2);
+                        kk[u] = s32[sl[u]];
+                    }
+#pragma unroll
+                    for (uint32_t u = 0; u < kUnroll; ++u) {
+                        if ((aux[u] & 2u) == 0 && kk[u] == kEmpty) {
+                            const uint32_t o = atomicCAS(&s32[sl[u]], kEmpty, x[u] >> 1);
+                            kk[u] = o == kEmpty ? x[u] >> 1 : o;
+                        }
+                    }
+#pragma unroll
+                    for (uint32_t u = 0; u < kUnroll; ++u) {
+                        if (aux[u] & 2u) continue;
+                        const uint32_t w = x[u] >> 1;
+                        const uint32_t inc = ((x[u] ^ aux[u]) & 1u) ? 0x10000u : 1u;
+                        if (kk[u] == w)
+                            atomicAdd(&s32[kHash16Slots + sl[u]], inc);
+                        else if (lok)
+                            lok = bucket_add16(s32, lim, w, inc, 1);
+                    }
+                    return __ballot(!lok) == 0;
+                }
 #pragma unroll
                 for (uint32_t u = 0; u < kUnroll; ++u) {
                     if ((aux[u] & 2u) || !lok) continue;
@@ -1511,26 +1598,23 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge_pieces(WedgeArgs a) {
             // 4 * 255^2 per word), summed per group of four words into 64 bits
             const uint4* t4 = reinterpret_cast<const uint4*>(s32);
             const uint32_t groups = (((dwidth + (1u << wlog) - 1u) >> wlog) + 3) / 4;
-            u64 q2 = 0, lm2 = 0;
+            uint32_t q = 0, sl = 0, lm = 0;
             for (uint32_t g = tid; g < groups; g += kWedgeThreads) {
                 const uint4 c = t4[g];
-                uint32_t q = 0, lm = 0;
                 if (dk == kD8) {
-                    bucket8_sums(c.x, q, lm);
-                    bucket8_sums(c.y, q, lm);
-                    bucket8_sums(c.z, q, lm);
-                    bucket8_sums(c.w, q, lm);
+                    bucket8_acc(c.x, q, sl, lm);
+                    bucket8_acc(c.y, q, sl, lm);
+                    bucket8_acc(c.z, q, sl, lm);
+                    bucket8_acc(c.w, q, sl, lm);
                 } else {
-                    bucket4_sums(c.x, q, lm);
-                    bucket4_sums(c.y, q, lm);
-                    bucket4_sums(c.z, q, lm);
-                    bucket4_sums(c.w, q, lm);
+                    bucket4_acc(c.x, q, sl, lm);
+                    bucket4_acc(c.y, q, sl, lm);
+                    bucket4_acc(c.z, q, sl, lm);
+                    bucket4_acc(c.w, q, sl, lm);
                 }
-                q2 += q;
-                lm2 += lm;
             }
-            bal = q2 >> 1;
-            unb = lm2 >> 1;
+            bal = (q - sl) >> 1;
+            unb = lm;
         } else if (d16 && !(P.flags & kPieceMerge)) {
             // 2 (C(l,2) + C(m,2)) and 2 l m from dot products of the halves
             // (l + m < 2^16); entries past the range and unreached ones are zero
@@ -1806,20 +1890,20 @@ __global__ __launch_bounds__(kWedgeThreads) void k_wedge_wave(WedgeArgs a) {
                 bucket16_sums(c.z, q2, lm2);
                 bucket16_sums(c.w, q2, lm2);
             } else {
-                uint32_t q = 0, lm = 0;
+                uint32_t q = 0, sl = 0, lm = 0;
                 if (dk == kD8) {
-                    bucket8_sums(c.x, q, lm);
-                    bucket8_sums(c.y, q, lm);
-                    bucket8_sums(c.z, q, lm);
-                    bucket8_sums(c.w, q, lm);
+                    bucket8_acc(c.x, q, sl, lm);
+                    bucket8_acc(c.y, q, sl, lm);
+                    bucket8_acc(c.z, q, sl, lm);
+                    bucket8_acc(c.w, q, sl, lm);
                 } else {
-                    bucket4_sums(c.x, q, lm);
-                    bucket4_sums(c.y, q, lm);
-                    bucket4_sums(c.z, q, lm);
-                    bucket4_sums(c.w, q, lm);
+                    bucket4_acc(c.x, q, sl, lm);
+                    bucket4_acc(c.y, q, sl, lm);
+                    bucket4_acc(c.z, q, sl, lm);
+                    bucket4_acc(c.w, q, sl, lm);
                 }
-                q2 += q;
-                lm2 += lm;
+                q2 += q - sl;
+                lm2 += 2ull * lm;
             }
         }
         q2 = wave_reduce_sum(q2);

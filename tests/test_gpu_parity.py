@@ -248,6 +248,57 @@ def test_one_wave_pieces_at_their_limits(ctx):
     assert ctx.stats()[13] >= 1, ctx.stats()
 
 
+def test_16bit_halves_at_their_limit(ctx):
+    # k = 2^16 - 1 middles, all adjacent to a start s and to ends of the same
+    # degree below it (lower id): w+ with every sign +, w- with every sign -.
+    # With s all +, the bucket (s, w+) holds l = 65535 and (s, w-) m = 65535,
+    # the most a 16-bit half may hold (l + m <= the start's middles < 2^16);
+    # with s mixed, both halves are large.  20,000 ends of degree 1 below them
+    # fill the first end-vertex tile (no piece), so the live tile becomes a
+    # two-tile dense piece with 16-bit halves.  With a single end the start has
+    # W = 65535 wedges and is counted by one wave, with 16-bit halves too.
+    # Expected counts in closed form (Lemma 2 per pair; ends of degree 1 lie
+    # in no butterfly): a pair whose common middles give l symmetric and m
+    # asymmetric wedges holds C(l,2) + C(m,2) balanced and l m unbalanced.
+    k = 65535
+    rng = np.random.default_rng(16)
+
+    def c2(x):
+        return x * (x - 1) // 2
+
+    def graph(n_pad, end_signs, n_plus, name):
+        eu = [np.arange(n_pad, dtype=np.int32)]
+        ev = [rng.integers(0, k, size=n_pad).astype(np.int32)]
+        sg = [rng.choice([1, -1], size=n_pad).astype(np.int8)]
+        s_signs = np.where(np.arange(k) < n_plus, 1, -1).astype(np.int8)
+        for i, sgn in enumerate(end_signs):
+            eu.append(np.full(k, n_pad + i, np.int32))
+            ev.append(np.arange(k, dtype=np.int32))
+            sg.append(np.full(k, sgn, np.int8))
+        eu.append(np.full(k, n_pad + len(end_signs), np.int32))  # the start, highest id
+        ev.append(np.arange(k, dtype=np.int32))
+        sg.append(s_signs)
+        return SignedBipartiteGraph(n_pad + len(end_signs) + 1, k, np.concatenate(eu),
+                                    np.concatenate(ev), np.concatenate(sg), name)
+
+    for n_plus in (k, 40000):
+        p, q = n_plus, k - n_plus
+        g = graph(20000, (1, -1), n_plus, f"halves16_tiles_{n_plus}")
+        got = run(ctx, g)
+        # (s, w+) and (s, w-) each give l, m = p, q (in either order); (w-, w+)
+        # has only asymmetric wedges
+        want = bbc.Result(2 * (c2(p) + c2(q)) + c2(k), 2 * p * q, oracle.wedges(g))
+        assert got == want, (g.name, got, want)
+        assert ctx.stats()[9] >= 1, ctx.stats()
+        assert ctx.stats()[5] == 0, ctx.stats()
+    for sgn in (1, -1):
+        g = graph(0, (sgn,), k, f"halves16_wave_{sgn}")
+        got = run(ctx, g)
+        assert got == bbc.Result(c2(k), 0, k), (g.name, got)
+        assert oracle.wedges(g) == k
+        assert ctx.stats()[13] == 1, ctx.stats()
+
+
 def test_tiles_of_degree_one_ends(ctx):
     # A hub adjacent to 2000 middles, each with private leaves of degree 1
     # (80 per middle for the first 100, whose rows are then long, 30 for the
