@@ -60,18 +60,67 @@ __device__ inline uint32_t cost_key(double wedges, uint32_t nrec, uint32_t group
 // Kinds of the pieces of a split start
 enum : uint32_t { kRunHash = 0, kRunD32, kRunD16, kRunD8, kRunD4 };
 
+// The planner's tile loops read two values at end-vertex tile boundaries h
+// (h = S, or a multiple of kTile below S) of one side: the degree mass below
+// h, row_ptr[base + h], and the degree of the vertex at sidx h - 1.  Both are
+// the same for every start of the side except at h = S, so a workgroup keeps
+// them per tile boundary in LDS (sides of at most kPlanTiles tiles); each
+// step of a loop then waits for LDS rather than for a global load.
+constexpr uint32_t kPlanTiles = 1024;
+struct TileBounds {
+    const uint32_t* mass[2];  // per side: row_ptr at sidx t * kTile, or nullptr
+    const uint32_t* deg[2];   // per side: degree of sidx t * kTile - 1 (t >= 1)
+};
+
+// Fill the workgroup's table (single graphs only; a batch never splits a
+// start into tiles) and wait for it.
+__device__ inline TileBounds load_tile_bounds(const uint32_t* __restrict__ row_ptr, const Dims& d,
+                                              uint32_t (*s_mass)[kPlanTiles],
+                                              uint32_t (*s_deg)[kPlanTiles]) {
+    TileBounds tb = {{nullptr, nullptr}, {nullptr, nullptr}};
+    for (uint32_t side = 0; side < 2 && d.n_graphs == 1; ++side) {
+        const uint32_t n_side = side ? d.n - d.n_u : d.n_u;
+        const uint32_t nt = n_side / kTile + 1;  // boundaries 0, kTile, ... <= n_side
+        if (nt > kPlanTiles) continue;
+        for (uint32_t t = threadIdx.x; t < nt; t += blockDim.x) {
+            const uint32_t h = d.base[side] + t * kTile;
+            s_mass[side][t] = row_ptr[h];
+            s_deg[side][t] = t > 0 ? row_ptr[h] - row_ptr[h - 1] : 0u;
+        }
+        tb.mass[side] = s_mass[side];
+        tb.deg[side] = s_deg[side];
+    }
+    __syncthreads();
+    return tb;
+}
+
+// The boundary values of one start's end-vertex space [0, S)
+struct TileView {
+    const uint32_t* row_ptr;
+    const uint32_t* lmass;  // LDS table of the side, or nullptr
+    const uint32_t* ldeg;
+    uint32_t base, S, mass_S, deg_S;
+    __device__ TileView(const uint32_t* __restrict__ rp, const TileBounds& tb, uint32_t side,
+                        uint32_t b, uint32_t s)
+        : row_ptr(rp), lmass(tb.mass[side]), ldeg(tb.deg[side]), base(b), S(s) {
+        mass_S = rp[b + s];
+        deg_S = s > 0 ? mass_S - rp[b + s - 1] : 0u;
+    }
+    __device__ uint32_t mass(uint32_t h) const {
+        return h == S ? mass_S : lmass ? lmass[h / kTile] : row_ptr[base + h];
+    }
+    __device__ uint32_t deg_last(uint32_t h) const {
+        return h == S ? deg_S : ldeg ? ldeg[h / kTile] : row_ptr[base + h] - row_ptr[base + h - 1];
+    }
+};
+
 // First tile of a start's end-vertex space [0, S) holding an end vertex of
 // degree at least 2: an end w of degree 1 has l + m <= 1, so it lies in no
 // butterfly, and the tiles below (rows are sorted by degree) get no piece.
-__device__ inline uint32_t first_live_tile(const uint32_t* __restrict__ row_ptr, uint32_t base,
-                                           uint32_t S) {
-    const uint32_t T = (S + kTile - 1) / kTile;
+__device__ inline uint32_t first_live_tile(const TileView& tv) {
+    const uint32_t S = tv.S, T = (S + kTile - 1) / kTile;
     uint32_t t = 0;
-    while (t < T) {
-        const uint32_t last = base + min(S, (t + 1) * kTile) - 1;
-        if (row_ptr[last + 1] - row_ptr[last] > 1) break;
-        ++t;
-    }
+    while (t < T && tv.deg_last(min(S, (t + 1) * kTile)) <= 1) ++t;
     return t;
 }
 
@@ -90,22 +139,19 @@ __device__ inline uint32_t first_live_tile(const uint32_t* __restrict__ row_ptr,
 // the target (twice that with 16-bit table halves, k < 2^16).  Runs start at
 // the first live tile.
 template <typename F>
-__device__ uint32_t plan_runs(const uint32_t* __restrict__ row_ptr, uint32_t base, uint32_t S,
-                              u64 W, uint32_t k, uint32_t target, bool pack, F emit) {
+__device__ uint32_t plan_runs(const TileView& tv, uint32_t t_live, u64 W, uint32_t k,
+                              uint32_t target, bool pack, F emit) {
     using u128 = unsigned __int128;
-    const uint32_t T = (S + kTile - 1) / kTile;
-    const u64 tot = row_ptr[base + S] - row_ptr[base];
+    const uint32_t S = tv.S, T = (S + kTile - 1) / kTile;
+    const u64 tot = tv.mass(S) - tv.mass(0);
     const u128 lim = (u128)target * tot;
     const u128 lim_run = k < (1u << 16) ? 2 * lim : lim;
     auto est = [&](u64 x) { return tot > 0 ? (double)x * (double)W / (double)tot : 0.0; };
     // the largest possible count of a bucket whose end vertex is below sidx hi
-    auto bound = [&](uint32_t hi) {
-        const uint32_t dg = row_ptr[base + hi] - row_ptr[base + hi - 1];
-        return min(k, dg);
-    };
+    auto bound = [&](uint32_t hi) { return min(k, tv.deg_last(hi)); };
     uint32_t n = 0, rs = kNoTile;
     u64 rx = 0;  // degree mass of the open run
-    for (uint32_t t = first_live_tile(row_ptr, base, S); t < T;) {
+    for (uint32_t t = t_live; t < T;) {
         uint32_t span = 1, kind = kRunD32;
         if (pack && bound(min(S, (t + 8) * kTile)) <= 15u) {
             span = 8;
@@ -119,7 +165,7 @@ __device__ uint32_t plan_runs(const uint32_t* __restrict__ row_ptr, uint32_t bas
         }
         const uint32_t t1 = min(T, t + span);
         const uint32_t lo = t * kTile;
-        const u64 xs = row_ptr[base + min(S, t1 * kTile)] - row_ptr[base + lo];
+        const u64 xs = tv.mass(min(S, t1 * kTile)) - tv.mass(lo);
         if ((u128)xs * W > lim) {
             if (rs != kNoTile) {
                 emit(rs, t, kRunHash, est(rx));
@@ -131,7 +177,7 @@ __device__ uint32_t plan_runs(const uint32_t* __restrict__ row_ptr, uint32_t bas
             t = t1;
             continue;
         }
-        const u64 x = row_ptr[base + min(S, lo + kTile)] - row_ptr[base + lo];
+        const u64 x = tv.mass(min(S, lo + kTile)) - tv.mass(lo);
         if (rs != kNoTile && (u128)(rx + x) * W > lim_run) {
             emit(rs, t, kRunHash, est(rx));
             ++n;
@@ -182,8 +228,13 @@ __device__ inline u64 chunk_wedges(const Dims& d, const Control* ctl) {
     return c > d.chunk_min ? c : d.chunk_min;
 }
 
-__device__ inline StartPlan plan_start(const uint32_t* __restrict__ row_ptr, const Dims& d,
-                                       uint32_t r, u64 W, uint32_t k, u64 chunk) {
+// The plan of start r.  With TILES, a split start's tile runs are planned
+// here (and tallied by kind in nk); without, a split start only gets its class
+// (the writing pass takes its piece and tile counts from the counting pass).
+template <bool TILES>
+__device__ inline StartPlan plan_start(const uint32_t* __restrict__ row_ptr, const TileBounds& tb,
+                                       const Dims& d, uint32_t r, u64 W, uint32_t k, u64 chunk,
+                                       u64* nk = nullptr) {
     StartPlan sp = {kClassNone, 0, 0, 0, 0, 0, 0};
     const uint32_t side = r >= d.n_u ? 1u : 0u;
     const uint32_t S = r - d.base[side];
@@ -220,10 +271,13 @@ __device__ inline StartPlan plan_start(const uint32_t* __restrict__ row_ptr, con
     const uint32_t T = (S + kTile - 1) / kTile;
     bool whole = false;
     sp.cls = kClassTiles;
-    const uint32_t t_live = first_live_tile(row_ptr, d.base[side], S);
-    sp.pieces = plan_runs(row_ptr, d.base[side], S, W, k, d.hash_target, !d.per_vertex,
+    if (!TILES) return sp;
+    const TileView tv(row_ptr, tb, side, d.base[side], S);
+    const uint32_t t_live = first_live_tile(tv);
+    sp.pieces = plan_runs(tv, t_live, W, k, d.hash_target, !d.per_vertex,
                           [&](uint32_t t0, uint32_t t1, uint32_t kind, double) {
                               whole = whole || (t0 == t_live && t1 == T && kind == kRunHash);
+                              if (nk) ++nk[kind];
                           });
     // One hashed run over everything is left unsplit only when its W wedges
     // cannot fill the table (at most W distinct ends); otherwise it keeps its
@@ -239,19 +293,18 @@ __global__ void k_plan_count(const u64* __restrict__ wu, const u64* __restrict__
                              uint32_t* __restrict__ hp, u64* __restrict__ lr,
                              uint32_t* __restrict__ lf, uint32_t* __restrict__ gs,
                              uint32_t* __restrict__ tc, u64* __restrict__ swc, Control* ctl) {
+    __shared__ uint32_t s_mass[2][kPlanTiles], s_deg[2][kPlanTiles];
+    const TileBounds tb = load_tile_bounds(row_ptr, d, s_mass, s_deg);
     const u64 chunk = chunk_wedges(d, ctl);
     u64 n_wave = 0;
     for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < d.n; r += gridDim.x * blockDim.x) {
         const u64 W = wu[r];
-        const StartPlan sp = plan_start(row_ptr, d, r, W, lowcnt[r], chunk);
+        u64 nk[5] = {0, 0, 0, 0, 0};  // tile pieces by kind
+        const StartPlan sp = plan_start<true>(row_ptr, tb, d, r, W, lowcnt[r], chunk, nk);
         n_wave += sp.cls == kClassWave ? 1u : 0u;
         const uint32_t side = r >= d.n_u ? 1u : 0u;
         if (sp.cls == kClassTiles && d.n_graphs > 1) atomicOr(&ctl->internal_err, 2u);
-        if (sp.cls == kClassTiles) {  // tile pieces by kind
-            u64 nk[5] = {0, 0, 0, 0, 0};  // by kind
-            plan_runs(row_ptr, d.base[side], r - d.base[side], W, lowcnt[r], d.hash_target,
-                      !d.per_vertex,
-                      [&](uint32_t, uint32_t, uint32_t kind, double) { ++nk[kind]; });
+        if (sp.cls == kClassTiles) {
             if (nk[kRunD32]) atomicAdd(&ctl->n_dense, nk[kRunD32]);
             if (nk[kRunD16]) atomicAdd(&ctl->n_dense16, nk[kRunD16]);
             if (nk[kRunD8]) atomicAdd(&ctl->n_dense8, nk[kRunD8]);
@@ -283,12 +336,18 @@ __global__ void k_plan_write(const u64* __restrict__ wu, const uint32_t* __restr
                              Piece* __restrict__ pieces, u64* __restrict__ light_off,
                              uint32_t* __restrict__ hkey, uint32_t* __restrict__ tile_piece,
                              const Control* ctl) {
+    __shared__ uint32_t s_mass[2][kPlanTiles], s_deg[2][kPlanTiles];
+    const TileBounds tb = load_tile_bounds(row_ptr, d, s_mass, s_deg);
     const u64 chunk = chunk_wedges(d, ctl);
     for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < d.n; r += gridDim.x * blockDim.x) {
         const u64 W = wu[r];
         if (W == 0) continue;
         const uint32_t k = lowcnt[r], m0 = mptr[r];
-        const StartPlan sp = plan_start(row_ptr, d, r, W, k, chunk);
+        StartPlan sp = plan_start<false>(row_ptr, tb, d, r, W, k, chunk);
+        if (sp.cls == kClassTiles) {  // as planned by the counting pass
+            sp.pieces = hp_off[r + 1] - hp_off[r];
+            sp.tiles = tc_off[r + 1] - tc_off[r];
+        }
         const uint32_t side = r >= d.n_u ? 1u : 0u;
         const uint32_t S = r - d.base[side];
         const uint32_t sideflag = side ? kPieceSideV : 0u;
@@ -363,11 +422,12 @@ __global__ void k_plan_write(const u64* __restrict__ wu, const uint32_t* __restr
         const bool split = sp.tiles > 0;
         const bool bucketed = split;
         const uint32_t nlong = front[r] - m0;
+        const TileView tv(row_ptr, tb, side, d.base[side], S);
+        const uint32_t t_live = first_live_tile(tv);
         if (split)  // tiles of ends of degree <= 1: no piece
-            for (uint32_t t = 0, t1 = first_live_tile(row_ptr, d.base[side], S); t < t1; ++t)
-                tile_piece[tc_off[r] + t] = kEmpty;
+            for (uint32_t t = 0; t < t_live; ++t) tile_piece[tc_off[r] + t] = kEmpty;
         uint32_t i = 0;
-        plan_runs(row_ptr, d.base[side], S, W, k, d.hash_target, !d.per_vertex,
+        plan_runs(tv, t_live, W, k, d.hash_target, !d.per_vertex,
                   [&](uint32_t t0, uint32_t t1, uint32_t kind, double est) {
             if (i >= h) return;
             const bool dense = kind != kRunHash;
