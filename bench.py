@@ -492,11 +492,11 @@ def main():
     for _ in range(args.warmup):
         r = ctx.count(eu, ev, sg, g.n_u, g.n_v)
     torch.cuda.synchronize()
-    phase = np.zeros(4)
+    phase = np.zeros(5)
     t0 = time.perf_counter()
     for _ in range(args.steps):
         r = ctx.count(eu, ev, sg, g.n_u, g.n_v)
-        for p in range(4):
+        for p in range(5):
             phase[p] += ctx.phase_ms(p)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -532,7 +532,7 @@ def main():
                    "unbalanced": r.unbalanced, "parallelism": "single GPU"},
         "total_count_time_ms": ms,
         "phase_ms": {"prep": phase[1], "plan": phase[3], "wedge_kernel": phase[2],
-                     "pipeline": phase[0]},
+                     "pipeline": phase[0], "short_wedge_lists": phase[4]},
         "work": {"work_items": st[4], "heavy_pieces": st[7], "resplit_pieces": st[5],
                  "tile_pieces": {"dense_32bit": st[8], "dense_16bit_2_tiles": st[9],
                                  "dense_8bit_4_tiles": st[11], "dense_4bit_8_tiles": st[12],
@@ -544,7 +544,12 @@ def main():
                      "kernel": "wedge step: bbc::k_wedge_pieces<false> (dense pieces), "
                                "k_wedge_pieces<true> (hashed), k_wedge_wave (one-wave pieces), "
                                "k_wedge (light items), one launch each per count",
-                     "algorithmic_bytes_per_launch": alg_bytes},
+                     "algorithmic_bytes_per_launch": alg_bytes,
+                     # the planner's bucketing of the wedges through short middle
+                     # rows (k_short_wedges, timed as its own phase) also reads
+                     # wedges: the fraction with its time added to the step's
+                     "frac_with_short_wedge_lists":
+                         alg_bytes / ((phase[2] + phase[4]) * 1e-3) / 1e9 / HBM_PEAK_GBS},
     }
     peaks = lds_atomic_peaks()
     adds = W / (phase[2] * 1e-3)  # one LDS add per wedge

@@ -269,7 +269,10 @@ int bbc_version(void);
  * phase: 0 = whole device pipeline (first kernel to last),
  *        1 = preprocessing (validation, degrees, priority relabel, CSR build),
  *        2 = wedge enumeration and bucket counting (the wedge kernel alone),
- *        3 = planning (work estimate and work-item construction).
+ *        3 = planning (work estimate and work-item construction),
+ *        4 = the part of planning that buckets the wedges through short
+ *            middle rows of split starts by piece (k_short_wedges; 0 when the
+ *            pipeline runs as captured HIP graphs).
  * *ms receives milliseconds.  BBC_ERR_INVALID_ARG for an unknown phase or when
  * timing was off during the last call.
  */

@@ -74,7 +74,9 @@ struct Arena {
     size_t used = 0;
 };
 
-enum { kEvStart, kEvPrepEnd, kEvPlanA, kEvPlanB, kEvPlanC, kEvWedgeA, kEvWedgeB, kEvEnd, kNumEv };
+enum { kEvStart, kEvPrepEnd, kEvPlanA, kEvPlanB, kEvPlanC, kEvWedgeA, kEvWedgeB, kEvEnd,
+       kEvSwA, kEvSwB, kNumEv };
+constexpr int kNumPhases = 5;  // see bbc_last_phase_ms
 
 struct bbc_context {
     int device = 0;
@@ -87,7 +89,7 @@ struct bbc_context {
     hipEvent_t ev[kNumEv] = {};
     bool timing = false;
     bool timing_valid = false;
-    double phase_ms[4] = {0, 0, 0, 0};
+    double phase_ms[kNumPhases] = {0, 0, 0, 0, 0};
     int64_t stats[14] = {0};
     uint32_t hash_target = bbc::kDefaultHashTarget;
     uint32_t probe_limit = bbc::kDefaultProbeLimit;
@@ -493,7 +495,7 @@ bbc_status bbc_get_param(const bbc_context* c, int param, int64_t* value) {
 }
 
 bbc_status bbc_last_phase_ms(const bbc_context* c, int phase, double* ms) {
-    if (!c || !ms || phase < 0 || phase > 3 || !c->timing_valid) return BBC_ERR_INVALID_ARG;
+    if (!c || !ms || phase < 0 || phase >= kNumPhases || !c->timing_valid) return BBC_ERR_INVALID_ARG;
     *ms = c->phase_ms[phase];
     return BBC_OK;
 }
@@ -873,6 +875,7 @@ static bbc_status run_pipeline(bbc_context* c, const RunIn& in, RunOut& ro) {
                                   tile_piece, n_light, n_light_items, items_first, b.ctl, st));
     // bucket the short-middle wedges of split starts by piece
     HIPCHECK(c, fill_u32(sw_cnt, 0, (size_t)n_heavy + 1, st));
+    if (tm) HIPCHECK(c, hipEventRecord(c->ev[kEvSwA], st));
     if (h.tot_sw > 0) {
         HIPCHECK(c, launch_short_wedges(b.recs, (uint32_t)m, b.col, b.cursor, b.tc, b.tc_off,
                                         b.hp_off, tile_piece, nu, sw_cnt, sw_cur, sw_list, sw_mid,
@@ -885,6 +888,7 @@ static bbc_status run_pipeline(bbc_context* c, const RunIn& in, RunOut& ro) {
                                         b.hp_off, tile_piece, nu, sw_cnt, sw_cur, sw_list, sw_mid,
                                         sw_chunk, true, st));
     }
+    if (tm) HIPCHECK(c, hipEventRecord(c->ev[kEvSwB], st));
     uint32_t* order = nullptr;
     if (n_heavy > 0)  // heavy pieces, most expensive first
         HIPCHECK(c, radix_sort_by_key(hkey, n_heavy, 8, ok0, ov0, ok1, ov1, ortmp, ortmp_bytes,
@@ -922,6 +926,7 @@ static bbc_status run_pipeline(bbc_context* c, const RunIn& in, RunOut& ro) {
         c->phase_ms[1] += ev_ms(c, kEvStart, kEvPrepEnd);
         c->phase_ms[2] += ev_ms(c, kEvWedgeA, kEvWedgeB);
         c->phase_ms[3] += ev_ms(c, kEvPrepEnd, kEvPlanA) + ev_ms(c, kEvPlanB, kEvPlanC);
+        c->phase_ms[4] += ev_ms(c, kEvSwA, kEvSwB);
     } else if (tm_out) {  // graph mode: the two replayed segments
         c->phase_ms[0] += ev_ms(c, kEvStart, kEvEnd);
         c->phase_ms[1] += ev_ms(c, kEvStart, kEvPrepEnd);
@@ -1293,10 +1298,10 @@ bbc_status bbc_count_batch(bbc_context* c, int32_t n_graphs, const int32_t* n_u,
             small.push_back((uint32_t)g);
     }
     int64_t stats[14] = {0};
-    double ph[4] = {0, 0, 0, 0};
+    double ph[kNumPhases] = {0, 0, 0, 0, 0};
     auto keep_stats = [&]() {
         for (int i = 0; i < 14; ++i) stats[i] += c->stats[i];
-        for (int i = 0; i < 4; ++i) ph[i] += c->phase_ms[i];
+        for (int i = 0; i < kNumPhases; ++i) ph[i] += c->phase_ms[i];
     };
     // unions: consecutive small graphs up to the size limits
     size_t i = 0;
@@ -1335,7 +1340,7 @@ bbc_status bbc_count_batch(bbc_context* c, int32_t n_graphs, const int32_t* n_u,
         }
     }
     memcpy(c->stats, stats, sizeof(stats));
-    for (int k = 0; k < 4; ++k) c->phase_ms[k] = ph[k];
+    for (int k = 0; k < kNumPhases; ++k) c->phase_ms[k] = ph[k];
     c->timing_valid = c->timing;
     c->err[0] = 0;
     return BBC_OK;

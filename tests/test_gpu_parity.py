@@ -121,6 +121,25 @@ def test_small_powerlaw(ctx):
         check(ctx, g)
 
 
+def test_phase_timing(ctx):
+    # HIP-event phase times: the pipeline holds preprocessing, planning and the
+    # wedge step; the short-wedge bucketing (phase 4) is part of planning
+    g = gen.chung_lu_graph(seed=11, n_u=60000, n_v=20000, n_edges=250000, p_neg=0.25)
+    c = bbc.Context(0)
+    try:
+        c.set_timing(True)
+        r = c.count(g.eu, g.ev, g.sign, g.n_u, g.n_v)
+        assert r == expect(g)
+        ph = [c.phase_ms(p) for p in range(5)]
+        assert all(x >= 0 for x in ph), ph
+        assert ph[1] + ph[2] + ph[3] <= ph[0] * 1.01 + 0.01, ph
+        assert 0 < ph[4] <= ph[3], ph  # this graph has split starts with short middles
+        with pytest.raises(bbc.BBCError):
+            c.phase_ms(5)
+    finally:
+        c.close()
+
+
 def test_resplit_path(ctx):
     # A hub start whose first end-vertex tile holds 16000 degree-2 leaves (each
     # sharing two middles with the hub) while most degree mass sits in 100
