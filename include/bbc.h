@@ -336,6 +336,13 @@ bbc_status bbc_last_stats(const bbc_context* ctx, int64_t* stats, int n);
  *                          (smaller unions: more passes, but each pass's work
  *                          arrays fit the on-package cache).  Default 2^30,
  *                          range [2^16, 2^30].
+ *   BBC_PARAM_WAVE_SHARE   a start whose end vertices fit one wavefront's
+ *                          counters is counted by that wavefront alone when it
+ *                          has at most W / WAVE_SHARE of the count's W wedges
+ *                          (at least 4096, at most 65536), so that no
+ *                          wavefront keeps counting long after the others;
+ *                          0 lifts the W / WAVE_SHARE bound.  Default 2048,
+ *                          range [0, 2^20].
  * bbc_set_param returns BBC_ERR_INVALID_ARG for a NULL context, an unknown
  * parameter or a value out of range (the setting is then unchanged);
  * bbc_get_param writes the current value to *value.
@@ -349,7 +356,8 @@ enum {
     BBC_PARAM_GRAPH_REPLAYS = 6,  /* read only */
     BBC_PARAM_LIGHT_MAX = 7,
     BBC_PARAM_GRAB_DIV = 8,
-    BBC_PARAM_UNION_EDGES = 9
+    BBC_PARAM_UNION_EDGES = 9,
+    BBC_PARAM_WAVE_SHARE = 10
 };
 bbc_status bbc_set_param(bbc_context* ctx, int param, int64_t value);
 bbc_status bbc_get_param(const bbc_context* ctx, int param, int64_t* value);

@@ -49,6 +49,7 @@ PARAM_GRAPH_REPLAYS = 6
 PARAM_LIGHT_MAX = 7
 PARAM_GRAB_DIV = 8
 PARAM_UNION_EDGES = 9
+PARAM_WAVE_SHARE = 10
 
 PHASE_TOTAL, PHASE_PREP, PHASE_WEDGE, PHASE_PLAN = 0, 1, 2, 3
 

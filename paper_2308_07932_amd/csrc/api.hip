@@ -96,6 +96,7 @@ struct bbc_context {
     uint64_t chunk_min = bbc::kRecordChunkWedges;
     uint32_t light_max = bbc::kLightMax;
     uint32_t grab_div = 16;
+    uint32_t wave_share = (uint32_t)bbc::kWaveShare;
     uint64_t union_edges = bbc::kBatchMaxEdges;
     int64_t* pv_host = nullptr;  // pinned staging of per-vertex counts
     size_t pv_host_cap = 0;
@@ -473,6 +474,10 @@ bbc_status bbc_set_param(bbc_context* c, int param, int64_t value) {
         if (value < (1 << 16) || value > (int64_t)bbc::kBatchMaxEdges) return BBC_ERR_INVALID_ARG;
         c->union_edges = (uint64_t)value;
         return BBC_OK;
+    case BBC_PARAM_WAVE_SHARE:
+        if (value < 0 || value > (1 << 20)) return BBC_ERR_INVALID_ARG;
+        c->wave_share = (uint32_t)value;
+        return BBC_OK;
     default:
         return BBC_ERR_INVALID_ARG;
     }
@@ -490,6 +495,7 @@ bbc_status bbc_get_param(const bbc_context* c, int param, int64_t* value) {
     case BBC_PARAM_LIGHT_MAX: *value = c->light_max; return BBC_OK;
     case BBC_PARAM_GRAB_DIV: *value = c->grab_div; return BBC_OK;
     case BBC_PARAM_UNION_EDGES: *value = (int64_t)c->union_edges; return BBC_OK;
+    case BBC_PARAM_WAVE_SHARE: *value = c->wave_share; return BBC_OK;
     default: return BBC_ERR_INVALID_ARG;
     }
 }
@@ -632,6 +638,7 @@ static bbc_status run_pipeline(bbc_context* c, const RunIn& in, RunOut& ro) {
     d.light_window = kLightWindow16;
     d.light_max = c->light_max;
     d.grab_div = c->grab_div;
+    d.wave_share = c->wave_share;
     // rows of side Y with more than kLongDeg entries: at most m / (kLongDeg + 1) per side
     uint64_t maxlong0 = std::min<uint64_t>(nu, m / (kLongDeg + 1));
     uint64_t maxlong1 = std::min<uint64_t>(nv, m / (kLongDeg + 1));
@@ -674,7 +681,8 @@ static bbc_status run_pipeline(bbc_context* c, const RunIn& in, RunOut& ro) {
     if (c->use_graphs)
         keyA = {n, nu, nv, m, (uint64_t)eu, (uint64_t)ev, (uint64_t)sg,
                 (uint64_t)prep_base, tb_total, d.hash_target, d.probe_limit,
-                d.chunk_min, d.per_vertex, bt_on, deg_bits, g_bits, d.light_max, d.grab_div};
+                d.chunk_min, d.per_vertex, bt_on, deg_bits, g_bits, d.light_max, d.grab_div,
+                d.wave_share};
     if (bt && c->use_graphs) {
         for (uint64_t x : {(uint64_t)bt->n_graphs, (uint64_t)bt->blk[0], (uint64_t)bt->blk[1],
                            (uint64_t)bt->gres, (uint64_t)bt->gerr})

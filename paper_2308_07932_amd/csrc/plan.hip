@@ -228,13 +228,20 @@ __device__ inline u64 chunk_wedges(const Dims& d, const Control* ctl) {
     return c > d.chunk_min ? c : d.chunk_min;
 }
 
+// most wedges of a one-wave start
+__device__ inline u64 wave_max_wedges(const Dims& d, const Control* ctl) {
+    if (d.wave_share == 0) return kWaveMaxW;
+    const u64 c = ctl->wedges / d.wave_share;
+    return c < kWaveMinW ? kWaveMinW : c > kWaveMaxW ? kWaveMaxW : c;
+}
+
 // The plan of start r.  With TILES, a split start's tile runs are planned
 // here (and tallied by kind in nk); without, a split start only gets its class
 // (the writing pass takes its piece and tile counts from the counting pass).
 template <bool TILES>
 __device__ inline StartPlan plan_start(const uint32_t* __restrict__ row_ptr, const TileBounds& tb,
                                        const Dims& d, uint32_t r, u64 W, uint32_t k, u64 chunk,
-                                       u64* nk = nullptr) {
+                                       u64 wave_max, u64* nk = nullptr) {
     StartPlan sp = {kClassNone, 0, 0, 0, 0, 0, 0};
     const uint32_t side = r >= d.n_u ? 1u : 0u;
     const uint32_t S = r - d.base[side];
@@ -245,7 +252,7 @@ __device__ inline StartPlan plan_start(const uint32_t* __restrict__ row_ptr, con
     if (W == 0) return sp;
     // a small start whose end range fits one wave's packed counters: one wave
     // counts it alone (no workgroup barriers, no hashing)
-    if (!d.per_vertex && W <= kWaveMaxW) {
+    if (!d.per_vertex && W <= wave_max) {
         const uint32_t wl = wave_layout(row_ptr, d.base[side], sp.lo, S, k);
         if (wl != kEmpty) {
             sp.cls = kClassWave;
@@ -295,12 +302,12 @@ __global__ void k_plan_count(const u64* __restrict__ wu, const u64* __restrict__
                              uint32_t* __restrict__ tc, u64* __restrict__ swc, Control* ctl) {
     __shared__ uint32_t s_mass[2][kPlanTiles], s_deg[2][kPlanTiles];
     const TileBounds tb = load_tile_bounds(row_ptr, d, s_mass, s_deg);
-    const u64 chunk = chunk_wedges(d, ctl);
+    const u64 chunk = chunk_wedges(d, ctl), wave_max = wave_max_wedges(d, ctl);
     u64 n_wave = 0;
     for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < d.n; r += gridDim.x * blockDim.x) {
         const u64 W = wu[r];
         u64 nk[5] = {0, 0, 0, 0, 0};  // tile pieces by kind
-        const StartPlan sp = plan_start<true>(row_ptr, tb, d, r, W, lowcnt[r], chunk, nk);
+        const StartPlan sp = plan_start<true>(row_ptr, tb, d, r, W, lowcnt[r], chunk, wave_max, nk);
         n_wave += sp.cls == kClassWave ? 1u : 0u;
         const uint32_t side = r >= d.n_u ? 1u : 0u;
         if (sp.cls == kClassTiles && d.n_graphs > 1) atomicOr(&ctl->internal_err, 2u);
@@ -338,12 +345,12 @@ __global__ void k_plan_write(const u64* __restrict__ wu, const uint32_t* __restr
                              const Control* ctl) {
     __shared__ uint32_t s_mass[2][kPlanTiles], s_deg[2][kPlanTiles];
     const TileBounds tb = load_tile_bounds(row_ptr, d, s_mass, s_deg);
-    const u64 chunk = chunk_wedges(d, ctl);
+    const u64 chunk = chunk_wedges(d, ctl), wave_max = wave_max_wedges(d, ctl);
     for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < d.n; r += gridDim.x * blockDim.x) {
         const u64 W = wu[r];
         if (W == 0) continue;
         const uint32_t k = lowcnt[r], m0 = mptr[r];
-        StartPlan sp = plan_start<false>(row_ptr, tb, d, r, W, k, chunk);
+        StartPlan sp = plan_start<false>(row_ptr, tb, d, r, W, k, chunk, wave_max);
         if (sp.cls == kClassTiles) {  // as planned by the counting pass
             sp.pieces = hp_off[r + 1] - hp_off[r];
             sp.tiles = tc_off[r + 1] - tc_off[r];

@@ -293,21 +293,24 @@ def test_autotune_keeps_counts(ctx):
 
 
 def test_batch_tunables_never_change_counts(ctx):
-    # the light cut, grab size and union size change how the work is cut,
-    # never a count: extreme settings (many tiny unions, almost no light
-    # starts, one-record grabs) give the same per-graph results
+    # the light cut, grab size, union size and one-wave share change how the
+    # work is cut, never a count: extreme settings (many tiny unions, almost
+    # no light starts, one-record grabs, one-wave starts of any size or of at
+    # most 4096 wedges) give the same per-graph results
     graphs = mixed_graphs(17, 120)
     nu, nv, off, eu, ev, sg = bbc.concat_graphs(graphs)
     want = ctx.count_batch(nu, nv, off, eu, ev, sg)
     tctx = bbc.Context(0)
     try:
-        for lm, gd, ue in ((16, 4, 1 << 16), (2048, 64, 1 << 16), (512, 8, 1 << 20), (1024, 32, 1 << 30)):
+        for lm, gd, ue, ws in ((16, 4, 1 << 16, 0), (2048, 64, 1 << 16, 1 << 20),
+                               (512, 8, 1 << 20, 1), (1024, 32, 1 << 30, 2048)):
             tctx.set_param(bbc.PARAM_LIGHT_MAX, lm)
             tctx.set_param(bbc.PARAM_GRAB_DIV, gd)
             tctx.set_param(bbc.PARAM_UNION_EDGES, ue)
+            tctx.set_param(bbc.PARAM_WAVE_SHARE, ws)
             got = tctx.count_batch(nu, nv, off, eu, ev, sg)
             for a, b in zip(want, got):
-                assert np.array_equal(a, b), (lm, gd, ue)
+                assert np.array_equal(a, b), (lm, gd, ue, ws)
         with pytest.raises(bbc.BBCError):
             tctx.set_param(bbc.PARAM_LIGHT_MAX, 4096)
         with pytest.raises(bbc.BBCError):

@@ -250,21 +250,26 @@ def test_one_wave_pieces_at_their_limits(ctx):
     # starts counted by one wave alone: 4-bit halves filled to 15 (4,000 ends
     # of degree 15), 8-bit halves filled to 255, and 16-bit counters over a
     # range of exactly one slice (2,048 ends: 2,047 of degree 1 below one of
-    # degree 300, which sets the width)
-    for g in (saturated_graph(4000, 15, 1000), saturated_graph(250, 255, 400)):
+    # degree 300, which sets the width).  These graphs are small, so the
+    # bound of a one-wave start by its share of the count is lifted.
+    ctx.set_param(bbc.PARAM_WAVE_SHARE, 0)
+    try:
+        for g in (saturated_graph(4000, 15, 1000), saturated_graph(250, 255, 400)):
+            check(ctx, g)
+            assert ctx.stats()[13] >= 1, ctx.stats()
+        rng = np.random.default_rng(12)
+        eu, ev = [0] * 400, list(range(400))
+        for i in range(1, 2048):
+            eu.append(i)
+            ev.append(i % 400)
+        eu += [2048] * 300
+        ev += list(range(300))
+        g = SignedBipartiteGraph(2049, 400, np.array(eu, np.int32), np.array(ev, np.int32),
+                                 rng.choice([1, -1], size=len(eu)).astype(np.int8), "wave16_full")
         check(ctx, g)
         assert ctx.stats()[13] >= 1, ctx.stats()
-    rng = np.random.default_rng(12)
-    eu, ev = [0] * 400, list(range(400))
-    for i in range(1, 2048):
-        eu.append(i)
-        ev.append(i % 400)
-    eu += [2048] * 300
-    ev += list(range(300))
-    g = SignedBipartiteGraph(2049, 400, np.array(eu, np.int32), np.array(ev, np.int32),
-                             rng.choice([1, -1], size=len(eu)).astype(np.int8), "wave16_full")
-    check(ctx, g)
-    assert ctx.stats()[13] >= 1, ctx.stats()
+    finally:
+        ctx.set_param(bbc.PARAM_WAVE_SHARE, 2048)
 
 
 def test_16bit_halves_at_their_limit(ctx):
@@ -310,12 +315,20 @@ def test_16bit_halves_at_their_limit(ctx):
         assert got == want, (g.name, got, want)
         assert ctx.stats()[9] >= 1, ctx.stats()
         assert ctx.stats()[5] == 0, ctx.stats()
-    for sgn in (1, -1):
-        g = graph(0, (sgn,), k, f"halves16_wave_{sgn}")
-        got = run(ctx, g)
-        assert got == bbc.Result(c2(k), 0, k), (g.name, got)
-        assert oracle.wedges(g) == k
-        assert ctx.stats()[13] == 1, ctx.stats()
+    # the same start alone (W = 65535): counted by one wave when the bound by
+    # its share of the count is lifted, else (W / 2048 < 4096, so at most 4096
+    # wedges) by a workgroup piece; the same counts either way
+    for share, waves in ((0, 1), (2048, 0)):
+        ctx.set_param(bbc.PARAM_WAVE_SHARE, share)
+        try:
+            for sgn in (1, -1):
+                g = graph(0, (sgn,), k, f"halves16_wave_{sgn}_{share}")
+                got = run(ctx, g)
+                assert got == bbc.Result(c2(k), 0, k), (g.name, got)
+                assert oracle.wedges(g) == k
+                assert ctx.stats()[13] == waves, ctx.stats()
+        finally:
+            ctx.set_param(bbc.PARAM_WAVE_SHARE, 2048)
 
 
 def test_tiles_of_degree_one_ends(ctx):
@@ -350,8 +363,10 @@ def test_tiles_of_degree_one_ends(ctx):
 def test_param_checks(ctx):
     assert ctx.get_param(bbc.PARAM_HASH_TARGET) == 4096
     assert ctx.get_param(bbc.PARAM_PROBE_LIMIT) == 256
+    assert ctx.get_param(bbc.PARAM_WAVE_SHARE) == 2048
     for p, v in ((bbc.PARAM_HASH_TARGET, 63), (bbc.PARAM_HASH_TARGET, (1 << 20) + 1),
-                 (bbc.PARAM_PROBE_LIMIT, 0), (bbc.PARAM_PROBE_LIMIT, 8193), (99, 1)):
+                 (bbc.PARAM_PROBE_LIMIT, 0), (bbc.PARAM_PROBE_LIMIT, 8193),
+                 (bbc.PARAM_WAVE_SHARE, -1), (bbc.PARAM_WAVE_SHARE, (1 << 20) + 1), (99, 1)):
         with pytest.raises(bbc.BBCError):
             ctx.set_param(p, v)
     assert ctx.get_param(bbc.PARAM_HASH_TARGET) == 4096
