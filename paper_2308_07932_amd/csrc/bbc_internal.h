@@ -91,14 +91,16 @@ constexpr uint32_t kDensePacked = kPieceDense8 | kPieceDense4;
 constexpr uint32_t kPieceWave = 256u;  // counted by one wave alone (k_wedge_wave)
 // One-wave pieces: each wave of a workgroup owns kWaveWords u32 counters
 // (l | m halves of 16, 8 or 4 bits, so 1, 2 or 4 end vertices per word), and
-// takes starts of at most kWaveMaxW wedges, and at most W / wave_share of a
-// count's W wedges (but at least kWaveMinW; default share kWaveShare): one wave
-// alone counts a start, so a start much larger than a wave's share of the
-// count would leave the wave working long after the others are done
+// takes starts of at most kWaveMaxW wedges whose cost W_u + kWaveRecordCost
+// k_u is at most W / wave_share of a count's W wedges (but at least kWaveMinW;
+// default share kWaveShare): one wave alone counts a start, so a start much
+// larger than a wave's share of the count would leave the wave working long
+// after the others are done
 constexpr uint32_t kWaveWords = 2048;
 constexpr u64 kWaveMaxW = 1u << 16;
 constexpr u64 kWaveMinW = 1u << 12;
 constexpr u64 kWaveShare = 2048;
+constexpr u64 kWaveRecordCost = 8;
 
 // One unit of counting: records [rec0, rec0 + nrec) of one start vertex,
 // restricted to end vertices with sidx in [lo, hi).

@@ -228,11 +228,13 @@ __device__ inline u64 chunk_wedges(const Dims& d, const Control* ctl) {
     return c > d.chunk_min ? c : d.chunk_min;
 }
 
-// most wedges of a one-wave start
-__device__ inline u64 wave_max_wedges(const Dims& d, const Control* ctl) {
-    if (d.wave_share == 0) return kWaveMaxW;
+// a one-wave start's share of the count: its cost W_u + kWaveRecordCost k_u
+// (a wave reads its records 64 at a time, each round a chain of loads) is at
+// most W / wave_share (at least kWaveMinW; no bound for wave_share 0)
+__device__ inline u64 wave_max_cost(const Dims& d, const Control* ctl) {
+    if (d.wave_share == 0) return ~0ull;
     const u64 c = ctl->wedges / d.wave_share;
-    return c < kWaveMinW ? kWaveMinW : c > kWaveMaxW ? kWaveMaxW : c;
+    return c < kWaveMinW ? kWaveMinW : c;
 }
 
 // The plan of start r.  With TILES, a split start's tile runs are planned
@@ -252,7 +254,7 @@ __device__ inline StartPlan plan_start(const uint32_t* __restrict__ row_ptr, con
     if (W == 0) return sp;
     // a small start whose end range fits one wave's packed counters: one wave
     // counts it alone (no workgroup barriers, no hashing)
-    if (!d.per_vertex && W <= wave_max) {
+    if (!d.per_vertex && W <= kWaveMaxW && W + kWaveRecordCost * k <= wave_max) {
         const uint32_t wl = wave_layout(row_ptr, d.base[side], sp.lo, S, k);
         if (wl != kEmpty) {
             sp.cls = kClassWave;
@@ -302,7 +304,7 @@ __global__ void k_plan_count(const u64* __restrict__ wu, const u64* __restrict__
                              uint32_t* __restrict__ tc, u64* __restrict__ swc, Control* ctl) {
     __shared__ uint32_t s_mass[2][kPlanTiles], s_deg[2][kPlanTiles];
     const TileBounds tb = load_tile_bounds(row_ptr, d, s_mass, s_deg);
-    const u64 chunk = chunk_wedges(d, ctl), wave_max = wave_max_wedges(d, ctl);
+    const u64 chunk = chunk_wedges(d, ctl), wave_max = wave_max_cost(d, ctl);
     u64 n_wave = 0;
     for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < d.n; r += gridDim.x * blockDim.x) {
         const u64 W = wu[r];
@@ -345,7 +347,7 @@ __global__ void k_plan_write(const u64* __restrict__ wu, const uint32_t* __restr
                              const Control* ctl) {
     __shared__ uint32_t s_mass[2][kPlanTiles], s_deg[2][kPlanTiles];
     const TileBounds tb = load_tile_bounds(row_ptr, d, s_mass, s_deg);
-    const u64 chunk = chunk_wedges(d, ctl), wave_max = wave_max_wedges(d, ctl);
+    const u64 chunk = chunk_wedges(d, ctl), wave_max = wave_max_cost(d, ctl);
     for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < d.n; r += gridDim.x * blockDim.x) {
         const u64 W = wu[r];
         if (W == 0) continue;

@@ -316,8 +316,8 @@ def test_16bit_halves_at_their_limit(ctx):
         assert ctx.stats()[9] >= 1, ctx.stats()
         assert ctx.stats()[5] == 0, ctx.stats()
     # the same start alone (W = 65535): counted by one wave when the bound by
-    # its share of the count is lifted, else (W / 2048 < 4096, so at most 4096
-    # wedges) by a workgroup piece; the same counts either way
+    # its share of the count is lifted, else (its cost W_u + 8 k_u far above
+    # max(4096, W / 2048)) by a workgroup piece; the same counts either way
     for share, waves in ((0, 1), (2048, 0)):
         ctx.set_param(bbc.PARAM_WAVE_SHARE, share)
         try:
