@@ -340,10 +340,10 @@ bbc_status bbc_last_stats(const bbc_context* ctx, int64_t* stats, int n);
  *                          counters (and with at most 65536 wedges) is counted
  *                          by that wavefront alone when its cost, W_u + 8 k_u
  *                          (wedges plus 8 per middle), is at most W /
- *                          WAVE_SHARE of the count's W wedges (or at most
- *                          4096), so that no wavefront keeps counting long
- *                          after the others; 0 lifts this bound.  Default
- *                          2048, range [0, 2^20].
+ *                          WAVE_SHARE of the count's W wedges (but at least
+ *                          4096 and at most 32768), so that no wavefront
+ *                          keeps counting long after the others; 0 lifts
+ *                          this bound.  Default 2048, range [0, 2^20].
  * bbc_set_param returns BBC_ERR_INVALID_ARG for a NULL context, an unknown
  * parameter or a value out of range (the setting is then unchanged);
  * bbc_get_param writes the current value to *value.

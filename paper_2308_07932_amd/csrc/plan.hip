@@ -230,11 +230,12 @@ __device__ inline u64 chunk_wedges(const Dims& d, const Control* ctl) {
 
 // a one-wave start's share of the count: its cost W_u + kWaveRecordCost k_u
 // (a wave reads its records 64 at a time, each round a chain of loads) is at
-// most W / wave_share (at least kWaveMinW; no bound for wave_share 0)
+// most W / wave_share, at least kWaveMinW and at most kWaveMaxCost, above
+// which a workgroup counts the start faster (no bound for wave_share 0)
 __device__ inline u64 wave_max_cost(const Dims& d, const Control* ctl) {
     if (d.wave_share == 0) return ~0ull;
     const u64 c = ctl->wedges / d.wave_share;
-    return c < kWaveMinW ? kWaveMinW : c;
+    return c < kWaveMinW ? kWaveMinW : c > kWaveMaxCost ? kWaveMaxCost : c;
 }
 
 // The plan of start r.  With TILES, a split start's tile runs are planned
