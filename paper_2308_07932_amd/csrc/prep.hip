@@ -34,8 +34,19 @@ constexpr uint32_t kAggLog2 = 14;
 constexpr uint32_t kAggSlots = 1u << kAggLog2;
 
 __device__ inline bool edge_ok(int32_t u, int32_t v, int8_t s, uint32_t n_u, uint32_t n_v) {
-    return u >= 0 && (uint32_t)u < n_u && v >= 0 && (uint32_t)v < n_v && (s == 1 || s == -1);
+    return (u >= 0) & ((uint32_t)u < n_u) & (v >= 0) & ((uint32_t)v < n_v) & ((s == 1) | (s == -1));
 }
+
+// Per endpoint a thread keeps one word: its table slot with its rank among the
+// slot's endpoints (slot | rank << kAggLog2; a chunk has at most 2 * kAggChunk
+// endpoints, so the word stays below 2^29), or kAggDirect / kAggSkip; the rank
+// of a direct reservation goes to a register of its own, so that its return is
+// waited for once, after the chunk (the loops are unrolled to keep all of it in
+// registers, and the flush issues its returning atomics before it waits).
+constexpr uint32_t kAggDirect = 1u << 30;
+constexpr uint32_t kAggSkip = 1u << 31;  // invalid edge or past the end
+constexpr uint32_t kAggFlush = kAggSlots / kAggThreads;
+static_assert(2 * kAggChunk <= (1u << (30 - kAggLog2)), "slot and rank share a word");
 
 __global__ __launch_bounds__(kAggThreads) void k_degree(const int32_t* __restrict__ eu,
                                                         const int32_t* __restrict__ ev,
@@ -43,7 +54,6 @@ __global__ __launch_bounds__(kAggThreads) void k_degree(const int32_t* __restric
                                                         uint32_t n_u, uint32_t n_v,
                                                         uint32_t* __restrict__ deg,
                                                         uint2* __restrict__ rank, Control* ctl) {
-    constexpr uint32_t kSkip = kEmpty - 1;  // slot mark: invalid edge or past the end
     __shared__ uint32_t keys[kAggSlots];
     __shared__ uint32_t cnt[kAggSlots];  // ranks handed out; after the flush, the reserved base
     const uint32_t tid = threadIdx.x;
@@ -53,39 +63,75 @@ __global__ __launch_bounds__(kAggThreads) void k_degree(const int32_t* __restric
             cnt[i] = 0;
         }
         __syncthreads();
-        uint32_t slot[kAggPer][2], rk[kAggPer][2];
+        // the chunk's edges first: all loads in flight together, and none
+        // pending once the first returning atomic is issued (a later wait for
+        // a load would wait for that atomic too: they complete in order)
+        int32_t eu_k[kAggPer], ev_k[kAggPer];
+        int8_t sg_k[kAggPer];
+#pragma unroll
         for (int k = 0; k < kAggPer; ++k) {
-            slot[k][0] = slot[k][1] = kSkip;
             const uint64_t e = c0 + (uint64_t)k * kAggThreads + tid;
-            if (e >= m) continue;
-            const int32_t u = eu[e], v = ev[e];
-            const int8_t s = sg[e];
-            if (!edge_ok(u, v, s, n_u, n_v)) {
-                const bool range = u < 0 || (uint32_t)u >= n_u || v < 0 || (uint32_t)v >= n_v;
-                atomicMin(&ctl->edge_err, (e << 4) | (range ? kErrRange : kErrSign));
-                continue;
-            }
-            const uint32_t x[2] = {(uint32_t)u, n_u + (uint32_t)v};
+            const uint64_t ec = e < m ? e : m - 1;  // (c0 < m)
+            eu_k[k] = eu[ec];
+            ev_k[k] = ev[ec];
+            sg_k[k] = sg[ec];
+        }
+        uint32_t xk[kAggPer][2];
+        uint32_t okm = 0;     // bit k: edge k of this thread is in range and valid
+        u64 err = ~0ull;      // the first invalid edge of this thread, as edge_err keeps it
+#pragma unroll
+        for (int k = 0; k < kAggPer; ++k) {
+            const uint64_t e = c0 + (uint64_t)k * kAggThreads + tid;
+            const int32_t u = eu_k[k], v = ev_k[k];
+            const bool ok = edge_ok(u, v, sg_k[k], n_u, n_v);
+            const bool range = (u < 0) | ((uint32_t)u >= n_u) | (v < 0) | ((uint32_t)v >= n_v);
+            const u64 code = (e << 4) | (range ? kErrRange : kErrSign);
+            err = (e < m && !ok && code < err) ? code : err;
+            okm |= (e < m && ok ? 1u : 0u) << k;
+            xk[k][0] = (uint32_t)u;
+            xk[k][1] = n_u + (uint32_t)v;
+        }
+        if (err != ~0ull) atomicMin(&ctl->edge_err, err);
+        uint32_t code[kAggPer][2], rg[kAggPer][2];
+#pragma unroll
+        for (int k = 0; k < kAggPer; ++k) {
+            code[k][0] = code[k][1] = kAggSkip;  // (rg is read only where code says direct)
+            if (!((okm >> k) & 1u)) continue;
+#pragma unroll
             for (int t = 0; t < 2; ++t) {
-                const int sl = agg_slot<kAggLog2>(keys, x[t]);
+                const int sl = agg_slot<kAggLog2>(keys, xk[k][t]);
                 if (sl >= 0) {
-                    slot[k][t] = (uint32_t)sl;
-                    rk[k][t] = atomicAdd(&cnt[sl], 1u);
+                    code[k][t] = (uint32_t)sl | (atomicAdd(&cnt[sl], 1u) << kAggLog2);
                 } else {
-                    slot[k][t] = kEmpty;  // slot reserved directly
-                    rk[k][t] = atomicAdd(&deg[x[t]], 1u);
+                    code[k][t] = kAggDirect;
+                    rg[k][t] = atomicAdd(&deg[xk[k][t]], 1u);  // slot reserved directly
                 }
             }
         }
         __syncthreads();
-        for (uint32_t i = tid; i < kAggSlots; i += kAggThreads)
-            if (keys[i] != kEmpty) cnt[i] = atomicAdd(&deg[keys[i]], cnt[i]);
+        {
+            uint32_t fk[kAggFlush], fr[kAggFlush];
+#pragma unroll
+            for (uint32_t j = 0; j < kAggFlush; ++j) {
+                const uint32_t i = j * kAggThreads + tid;
+                fk[j] = keys[i];
+                fr[j] = 0;
+                if (fk[j] != kEmpty) fr[j] = atomicAdd(&deg[fk[j]], cnt[i]);
+            }
+#pragma unroll
+            for (uint32_t j = 0; j < kAggFlush; ++j)
+                if (fk[j] != kEmpty) cnt[j * kAggThreads + tid] = fr[j];
+        }
         __syncthreads();
+#pragma unroll
         for (int k = 0; k < kAggPer; ++k) {
-            if (slot[k][0] == kSkip) continue;
+            if (code[k][0] == kAggSkip) continue;
             uint32_t r[2];
+#pragma unroll
             for (int t = 0; t < 2; ++t)
-                r[t] = slot[k][t] == kEmpty ? rk[k][t] : cnt[slot[k][t]] + rk[k][t];
+                r[t] = code[k][t] == kAggDirect
+                           ? rg[k][t]
+                           : cnt[code[k][t] & (kAggSlots - 1u)] + (code[k][t] >> kAggLog2);
             rank[c0 + (uint64_t)k * kAggThreads + tid] = make_uint2(r[0], r[1]);
         }
         __syncthreads();
