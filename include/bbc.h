@@ -112,7 +112,7 @@ bbc_status bbc_count(bbc_context* ctx, int32_t n_u, int32_t n_v, int64_t n_edges
  *    BBC_NOALLOC_SCRATCH_BYTES per device, which the library holds from its
  *    first use on that device until the process ends; a graph whose workspace
  *    does not fit gets BBC_ERR_TOO_LARGE (bbc_workspace_bytes estimates it;
- *    about 2 million edges fit), with the outputs untouched;
+ *    about 4 million edges fit), with the outputs untouched;
  *  - the call makes no hipMalloc / hipFree / hipHostMalloc and no host heap
  *    allocation; HIP-graph replay (BBC_PARAM_GRAPHS) is not used for it.
  * Every allocation-free call on one device uses the same array, whatever the

@@ -30,11 +30,9 @@ hipError_t launch_scatter(const int32_t*, const int32_t*, const int8_t*, uint64_
 hipError_t launch_row_sort(const uint32_t*, const uint32_t*, const uint32_t*, uint32_t*, Dims,
                            Control*, uint32_t, hipStream_t);
 hipError_t launch_lowcount(const uint32_t*, const uint32_t*, const uint32_t*, uint32_t, uint32_t*,
-                           uint32_t*, hipStream_t);
-hipError_t launch_records_raw(const uint32_t*, const uint32_t*, const uint32_t*, const uint32_t*,
-                              Dims, uint64_t, uint4*, uint32_t*, hipStream_t);
-hipError_t launch_records_gather(const uint4*, const uint32_t*, const uint32_t*, uint64_t, uint4*,
-                                 u64*, u64*, uint32_t*, hipStream_t);
+                           hipStream_t);
+hipError_t launch_records(const uint32_t*, const uint32_t*, const uint32_t*, const uint32_t*, Dims,
+                          uint64_t, uint4*, u64*, u64*, uint32_t*, hipStream_t);
 hipError_t launch_tile_table(const uint32_t*, const uint32_t*, Dims, const Control*, uint32_t*,
                              uint32_t, hipStream_t);
 hipError_t launch_plan_count(const u64*, const u64*, const uint32_t*, const uint32_t*, Dims,
@@ -265,8 +263,7 @@ struct PrepBufs {
     int8_t* sg;
     uint32_t *deg, *k0, *v0, *k1, *v1, *flag, *cnt_u, *sidx_of, *rowdeg, *rowcross, *row_ptr,
         *cursor, *col_in, *col, *lowcnt, *mptr, *tb, *hp, *hp_off, *lf, *lf_off, *gs, *gs_off,
-        *tc, *tc_off, *upcnt, *uptr, *rkey, *rk1, *rv1;
-    uint4* raw;
+        *tc, *tc_off;
     uint2* vx;  // per input vertex: {sidx, row start} (the scatter's lookups)
     u64 *lr, *lr_off, *wu, *wsu, *swc, *swc_off;
     uint4* recs;
@@ -302,12 +299,6 @@ static size_t carve_prep(Carver& cv, PrepBufs& b, uint32_t n, uint64_t m, bool c
     b.lowcnt = cv.take<uint32_t>(n);
     b.mptr = cv.take<uint32_t>(n + 1);
     b.recs = cv.take<uint4>(m);
-    b.raw = cv.take<uint4>(m);
-    b.rkey = cv.take<uint32_t>(m);
-    b.rk1 = cv.take<uint32_t>(m);
-    b.rv1 = cv.take<uint32_t>(m);
-    b.upcnt = cv.take<uint32_t>(n);
-    b.uptr = cv.take<uint32_t>(n + 1);
     b.wu = cv.take<u64>(n);
     b.tb = cv.take<uint32_t>(tb_total);
     b.hp = cv.take<uint32_t>(n);
@@ -323,7 +314,7 @@ static size_t carve_prep(Carver& cv, PrepBufs& b, uint32_t n, uint64_t m, bool c
     b.wsu = cv.take<u64>(n);
     b.swc = cv.take<u64>(n);
     b.swc_off = cv.take<u64>(n + 1);
-    b.rtmp_bytes = radix_tmp_bytes((uint32_t)std::max<uint64_t>(n, m));
+    b.rtmp_bytes = radix_tmp_bytes(n);
     b.rtmp = cv.take<char>(b.rtmp_bytes);
     b.stmp_bytes = scan_tmp_bytes(n + 1);
     b.stmp = cv.take<char>(b.stmp_bytes);
@@ -717,8 +708,8 @@ static bbc_status run_pipeline(bbc_context* c, const RunIn& in, RunOut& ro) {
     // ---- 1. degrees + validation
     HIPCHECK(c, fill_u32(b.deg, 0, n, st));
     HIPCHECK(c, fill_u32(b.col + 2 * m, kColPadValue, kColPad, st));
-    // every edge's slots in its two rows go to b.raw (free until the records)
-    uint2* slots = reinterpret_cast<uint2*>(b.raw);
+    // every edge's slots in its two rows go to b.recs (free until the records)
+    uint2* slots = reinterpret_cast<uint2*>(b.recs);
     HIPCHECK(c, launch_degree(eu, ev, sg, m, nu, nv, b.deg, slots, b.ctl, st));
     // ---- 2. priority order: stable sort of vertex ids by degree (by graph,
     // then degree, for a batch)
@@ -752,27 +743,15 @@ static bbc_status run_pipeline(bbc_context* c, const RunIn& in, RunOut& ro) {
     HIPCHECK(c, launch_row_sort(b.rowdeg, b.row_ptr, b.col_in, b.col, d, b.ctl, c->num_cus, st));
     if (bt) HIPCHECK(c, launch_dup_graphs(b.row_ptr, b.col, d, b.ctl, st));
     // ---- 5. middle counts, 6. records and W_u, 7. tile tables
-    HIPCHECK(c, launch_lowcount(b.row_ptr, b.col, b.rowcross, n, b.lowcnt, b.upcnt, st));
-    {
-        const uint32_t* ins[2] = {b.lowcnt, b.upcnt};
-        uint32_t* outs[2] = {b.mptr, b.uptr};
-        HIPCHECK(c, scan_excl_u32_set(ins, outs, 2, n, b.stmp, b.stmp_bytes, st));
-    }
-    // records in row-v order with their (start, short) keys, sorted by key,
-    // gathered into [mptr[u], mptr[u+1]) per start with the long-middle ones
+    HIPCHECK(c, launch_lowcount(b.row_ptr, b.col, b.rowcross, n, b.lowcnt, st));
+    HIPCHECK(c, scan_excl_u32(b.lowcnt, b.mptr, n, b.stmp, b.stmp_bytes, st));
+    // every start's records in [mptr[u], mptr[u+1]), the long-middle ones
     // first; front[u] (kept in b.cursor) is where u's short ones begin
-    HIPCHECK(c, fill_u32(b.rkey, kEmpty, m, st));
-    HIPCHECK(c, launch_records_raw(b.row_ptr, b.col, b.lowcnt, b.uptr, d, m, b.raw, b.rkey, st));
-    {
-        uint32_t *order = nullptr, *skey = nullptr;
-        // the first ping-pong pair reuses the scatter's input entries (free now)
-        HIPCHECK(c, radix_sort_by_key(b.rkey, (uint32_t)m, bitlen(n) + 1, b.col_in, b.col_in + m,
-                                      b.rk1, b.rv1, b.rtmp, b.rtmp_bytes, &order, st, &skey));
-        HIPCHECK(c, copy_u32(b.mptr + 1, b.cursor, n, st));
-        HIPCHECK(c, fill_u64(b.wu, 0, n, st));
-        HIPCHECK(c, fill_u64(b.wsu, 0, n, st));
-        HIPCHECK(c, launch_records_gather(b.raw, skey, order, m, b.recs, b.wu, b.wsu, b.cursor, st));
-    }
+    HIPCHECK(c, copy_u32(b.mptr + 1, b.cursor, n, st));
+    HIPCHECK(c, fill_u64(b.wu, 0, n, st));
+    HIPCHECK(c, fill_u64(b.wsu, 0, n, st));
+    HIPCHECK(c, launch_records(b.row_ptr, b.col, b.lowcnt, b.mptr, d, m, b.recs, b.wu, b.wsu,
+                               b.cursor, st));
     if (!bt) HIPCHECK(c, launch_tile_table(b.row_ptr, b.col, d, b.ctl, b.tb, c->num_cus, st));
     if (tm) HIPCHECK(c, hipEventRecord(c->ev[kEvPrepEnd], st));
 

@@ -19,25 +19,6 @@
 namespace bbc {
 
 
-// Graph of union edge x, i.e. the last g in [0, nb) with blk[g] <= x, for x
-// uniform over the wave: 64 bounds per round (lane l reads the l-th of 64
-// evenly spaced candidates and a ballot keeps the last one at or below x), so
-// 20,000 graphs take three dependent rounds instead of fifteen.
-__device__ inline uint32_t wave_block_of(const uint32_t* blk, uint32_t nb, uint32_t x) {
-    const uint32_t lane = lane_id();
-    uint32_t lo = 0, n = nb;  // the answer lies in [lo, lo + n)
-    while (n > 1) {
-        const uint32_t step = (n + 63) / 64;
-        const uint32_t c = lo + lane * step;
-        const u64 le = __ballot(c < lo + n && blk[c] <= x);
-        const uint32_t l = le ? 63u - (uint32_t)__clzll(le) : 0u;  // (lane 0 qualifies)
-        const uint32_t end = lo + n;
-        lo += l * step;
-        n = min(step, end - lo);
-    }
-    return lo;
-}
-
 // An edge whose ids are out of range is written with u = -1, so that the
 // degree and scatter passes drop it (their own range check fails) instead of
 // placing it in another graph's id block (a graph with no vertex on a side

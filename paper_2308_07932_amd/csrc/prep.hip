@@ -853,133 +853,182 @@ __global__ __launch_bounds__(kBigThreads) void k_sort_big(const uint32_t* __rest
 // upper entries, each the middle of a record of a higher start)
 __global__ void k_lowcount(const uint32_t* __restrict__ row_ptr, const uint32_t* __restrict__ col,
                            const uint32_t* __restrict__ rowcross, uint32_t n,
-                           uint32_t* __restrict__ lowcnt, uint32_t* __restrict__ upcnt) {
+                           uint32_t* __restrict__ lowcnt) {
     for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
         uint32_t a = row_ptr[r], L = row_ptr[r + 1] - a;
         const uint32_t k = lower_bound_u32(col + a, L, rowcross[r] << 1);
         lowcnt[r] = k;
-        upcnt[r] = L - k;
     }
 }
 
 // ------------------------------------------------------------- records ------
-// Records come from the upper part of every row: in the sorted row of v, the
-// entry at index i >= k_v names a neighbour u of higher priority, and exactly
-// i entries precede it, all of lower priority than u -- so pos_v(u) = i with
-// no search.  The records are first written in row-v order (slot uptr[v] +
-// i - k_v) with the key (row u) << 1 | short, short meaning the middle row v
-// has at most kLongDeg entries; a radix sort of the keys and a gather then
-// place each start's records together, long-middle ones first, in the slots
-// [mptr[u], mptr[u+1]).  No slot is reserved by atomics.  W_u (and Ws_u, the
-// wedges through short middle rows) are sums of pos over the sorted records.
+// One record per edge, at its start u (the end of higher priority).  The first
+// k_u entries of u's sorted row are its neighbours v of lower priority, the
+// middles, in ascending priority; entry j takes the slot mptr[u] + k_u - 1 - j,
+// so u's records run from its highest-priority middle down.  Priority is
+// (degree, id), so the middles with long rows (more than kLongDeg entries)
+// come first and the short ones end the run; front[u] is u's first short
+// record (preset to mptr[u+1]: none).  pos_v(u), the number of entries of v's
+// sorted row before u (exactly v's neighbours of lower priority than u, the
+// wedge ends of Algorithm 2 through v), comes from a binary search for u in
+// v's row, the rows of middles being mostly short.  W_u and Ws_u (the wedges
+// through short middle rows) are sums of pos over u's records, aggregated per
+// workgroup in an LDS table (a hub's records span many threads).
 //   .x = first entry of row v, .y = pos << 1 | neg(u, v), .z = sidx(v), .w = row u
+//
+// A thread takes kRecPer consecutive CSR entries and a wave 64 * kRecPer; the
+// rows of a wave's first and last entry bound those of the others.  The
+// searches of a thread's records step together, so their loads overlap.
 constexpr int kRecPer = 4;  // consecutive entries per thread
 constexpr int kRecThreads = 256;
+constexpr uint32_t kRecLog2 = 10;
+constexpr uint32_t kRecSlots = 1u << kRecLog2;
 
-__global__ __launch_bounds__(kRecThreads) void k_records_raw(
+__global__ __launch_bounds__(kRecThreads) void k_records(
     const uint32_t* __restrict__ row_ptr, const uint32_t* __restrict__ col,
-    const uint32_t* __restrict__ lowcnt, const uint32_t* __restrict__ uptr, Dims d, uint64_t m,
-    uint4* __restrict__ raw, uint32_t* __restrict__ key) {
-    const uint64_t nnz = row_ptr[d.n];  // entries actually placed (invalid edges are not)
-    const uint64_t stride = (uint64_t)gridDim.x * kRecThreads * kRecPer;
-    for (uint64_t e0 = ((uint64_t)blockIdx.x * kRecThreads + threadIdx.x) * kRecPer; e0 < nnz;
-         e0 += stride) {
-        uint32_t lo = 0, hi = d.n;  // row holding entry e0: last r with row_ptr[r] <= e0
-        while (hi - lo > 1) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (row_ptr[mid] <= e0)
-                lo = mid;
-            else
-                hi = mid;
-        }
-        uint32_t r = lo;
-        for (int k = 0; k < kRecPer; ++k) {
-            const uint64_t e = e0 + k;
-            if (e >= nnz) break;
-            while (row_ptr[r + 1] <= e) ++r;
-            const uint32_t rs = row_ptr[r];
-            const uint32_t i = (uint32_t)(e - rs);
-            const uint32_t kv = lowcnt[r];
-            if (i < kv) continue;  // lower entry: v's own middle, not a record here
-            // descending row-v order: after the (stable) sort a start's records
-            // run from its highest-degree middles down, longest intervals first
-            const uint64_t slot = m - 1 - (uptr[r] + (i - kv));
-            const uint32_t side = r >= d.n_u ? 1u : 0u;
-            const uint32_t x = col[e];
-            if ((x >> 1) >= d.size[side ^ 1u] || uptr[r] + (i - kv) >= m) continue;  // a hole
-            const uint32_t urow = d.base[side ^ 1u] + (x >> 1);
-            const bool is_short = row_ptr[r + 1] - rs <= kLongDeg;
-            raw[slot] = make_uint4(rs, (i << 1) | (x & 1u), r - d.base[side], urow);
-            key[slot] = (urow << 1) | (is_short ? 1u : 0u);
-        }
-    }
-}
-
-// recs[j] = raw[order[j]]; W_u and Ws_u summed over each start's run of
-// sorted records, aggregated per workgroup in an LDS table (a hub start's
-// records span many threads); front[u] = the first short record of u (preset
-// to mptr[u+1] for a start without any).
-constexpr uint32_t kGatherLog2 = 10;
-constexpr uint32_t kGatherSlots = 1u << kGatherLog2;
-
-__global__ __launch_bounds__(kRecThreads) void k_records_gather(
-    const uint4* __restrict__ raw, const uint32_t* __restrict__ skey,
-    const uint32_t* __restrict__ order, uint64_t m, uint4* __restrict__ recs,
-    u64* __restrict__ wu, u64* __restrict__ wsu, uint32_t* __restrict__ front) {
-    __shared__ uint32_t keys[kGatherSlots];
-    __shared__ u64 sw[kGatherSlots], ss[kGatherSlots];
-    const uint32_t tid = threadIdx.x;
-    constexpr uint64_t kChunk = (uint64_t)kRecThreads * kRecPer;
-    for (uint64_t c0 = (uint64_t)blockIdx.x * kChunk; c0 < m; c0 += (uint64_t)gridDim.x * kChunk) {
-        for (uint32_t i = tid; i < kGatherSlots; i += kRecThreads) {
+    const uint32_t* __restrict__ lowcnt, const uint32_t* __restrict__ mptr, Dims d, uint64_t m,
+    uint4* __restrict__ recs, u64* __restrict__ wu, u64* __restrict__ wsu,
+    uint32_t* __restrict__ front) {
+    __shared__ uint32_t keys[kRecSlots];
+    __shared__ u64 sw[kRecSlots], ss[kRecSlots];
+    __shared__ uint32_t sf[kRecSlots];
+    const uint32_t tid = threadIdx.x, lane = lane_id();
+    const uint32_t nnz = row_ptr[d.n];  // entries actually placed (invalid edges are not)
+    // slots past the last start's records (invalid edges leave some) hold
+    // harmless empty records
+    for (uint64_t j = (uint64_t)mptr[d.n] + (uint64_t)blockIdx.x * kRecThreads + tid; j < m;
+         j += (uint64_t)gridDim.x * kRecThreads)
+        recs[j] = make_uint4(0, 0, 0, 0);
+    constexpr uint32_t kSpan = 64 * kRecPer;
+    const uint32_t nwaves = gridDim.x * (kRecThreads / 64);
+    for (uint32_t s0 = (blockIdx.x * (kRecThreads / 64) + (tid >> 6)) * kSpan;; s0 += nwaves * kSpan) {
+        // (uniform over the workgroup: its waves' spans are adjacent)
+        const uint32_t blk0 = s0 - (tid >> 6) * kSpan;
+        if (blk0 >= nnz) break;
+        for (uint32_t i = tid; i < kRecSlots; i += kRecThreads) {
             keys[i] = kEmpty;
             sw[i] = 0;
             ss[i] = 0;
+            sf[i] = kEmpty;
         }
         __syncthreads();
-        uint32_t cur = kEmpty;
-        u64 accW = 0, accS = 0;
-        auto flush = [&]() {
-            if (cur == kEmpty || (accW == 0 && accS == 0)) return;
-            const int sl = agg_slot<kGatherLog2>(keys, cur);
-            if (sl >= 0) {
-                if (accW) atomicAdd(&sw[sl], accW);
-                if (accS) atomicAdd(&ss[sl], accS);
-            } else {
-                if (accW) atomicAdd(&wu[cur], accW);
-                if (accS) atomicAdd(&wsu[cur], accS);
+        if (s0 < nnz) {
+            const uint32_t rlo = wave_block_of(row_ptr, d.n, s0);
+            const uint32_t rhi = wave_block_of(row_ptr, d.n, min(s0 + kSpan, nnz) - 1);
+            const uint32_t e0 = s0 + lane * kRecPer;
+            // this thread's entries: row, middle, slot; then the searches
+            uint32_t rs[kRecPer], len[kRecPer], key[kRecPer], slot[kRecPer], urow[kRecPer];
+            uint32_t x[kRecPer], pos[kRecPer];
+            bool rec[kRecPer];  // entry q is a record with its fields set
+#pragma unroll
+            for (int q = 0; q < kRecPer; ++q) rec[q] = false;
+            if (e0 < nnz) {
+                uint32_t r = rlo, hi = rhi + 1;  // row_ptr[r] <= e0 < row_ptr[hi]
+                while (hi - r > 1) {
+                    const uint32_t mid = (r + hi) >> 1;
+                    if (row_ptr[mid] <= e0)
+                        r = mid;
+                    else
+                        hi = mid;
+                }
+                uint32_t ra = row_ptr[r], rb = row_ptr[r + 1], k = lowcnt[r];
+#pragma unroll
+                for (int q = 0; q < kRecPer; ++q) {
+                    const uint32_t e = e0 + q;
+                    if (e >= nnz) continue;
+                    while (rb <= e) {  // (rows without entries are passed over)
+                        ++r;
+                        ra = rb;
+                        rb = row_ptr[r + 1];
+                        k = lowcnt[r];
+                    }
+                    const uint32_t jj = e - ra;
+                    if (jj >= k) continue;  // an upper entry: a record of the other end
+                    const uint32_t side = r >= d.n_u ? 1u : 0u;
+                    x[q] = col[e];
+                    urow[q] = r;
+                    slot[q] = mptr[r] + (k - 1u - jj);
+                    key[q] = (r - d.base[side]) << 1;  // u's entry in v's row, sign cleared
+                    const uint32_t sv = x[q] >> 1;
+                    if (sv >= d.size[side ^ 1u] || slot[q] >= m) {  // only with invalid input
+                        if (slot[q] < m) recs[slot[q]] = make_uint4(0, 0, 0, 0);
+                        continue;
+                    }
+                    const uint32_t vrow = d.base[side ^ 1u] + sv;
+                    rs[q] = row_ptr[vrow];
+                    len[q] = row_ptr[vrow + 1] - rs[q];
+                    rec[q] = true;
+                }
             }
-        };
-        const uint64_t j0 = c0 + (uint64_t)tid * kRecPer;
-        for (int k = 0; k < kRecPer; ++k) {
-            const uint64_t j = j0 + k;
-            if (j >= m) break;
-            const uint32_t key = skey[j];
-            if (key == kEmpty) {  // never written (invalid input): a harmless record
-                recs[j] = make_uint4(0, 0, 0, 0);
-                continue;
+            // lower bounds of key in the rows of the middles, all at once
+            {
+                uint32_t lo[kRecPer], n[kRecPer];
+                bool any = false;
+#pragma unroll
+                for (int q = 0; q < kRecPer; ++q) {
+                    lo[q] = 0;
+                    n[q] = rec[q] ? len[q] : 0u;
+                    any |= n[q] > 0;
+                }
+                while (any) {
+                    any = false;
+#pragma unroll
+                    for (int q = 0; q < kRecPer; ++q) {
+                        if (n[q] == 0) continue;
+                        const uint32_t h = n[q] >> 1;
+                        if (col[rs[q] + lo[q] + h] < key[q]) {
+                            lo[q] += h + 1;
+                            n[q] -= h + 1;
+                        } else {
+                            n[q] = h;
+                        }
+                        any |= n[q] > 0;
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < kRecPer; ++q) pos[q] = lo[q];
             }
-            const uint4 rc = raw[order[j]];
-            recs[j] = rc;
-            const uint32_t u = key >> 1;
-            if (u != cur) {
-                flush();
-                cur = u;
-                accW = accS = 0;
+            // write the records; sums per start, flushed when the start changes
+            uint32_t cur = kEmpty, f = kEmpty;
+            u64 accW = 0, accS = 0;
+            auto flush = [&]() {
+                if (cur == kEmpty) return;
+                const int sl = agg_slot<kRecLog2>(keys, cur);
+                if (sl >= 0) {
+                    if (accW) atomicAdd(&sw[sl], accW);
+                    if (accS) atomicAdd(&ss[sl], accS);
+                    if (f != kEmpty) atomicMin(&sf[sl], f);
+                } else {
+                    if (accW) atomicAdd(&wu[cur], accW);
+                    if (accS) atomicAdd(&wsu[cur], accS);
+                    if (f != kEmpty) atomicMin(&front[cur], f);
+                }
+            };
+#pragma unroll
+            for (int q = 0; q < kRecPer; ++q) {
+                if (!rec[q]) continue;
+                const uint32_t sv = x[q] >> 1;
+                recs[slot[q]] = make_uint4(rs[q], (pos[q] << 1) | (x[q] & 1u), sv, urow[q]);
+                if (urow[q] != cur) {
+                    flush();
+                    cur = urow[q];
+                    accW = accS = 0;
+                    f = kEmpty;
+                }
+                accW += pos[q];
+                if (len[q] <= kLongDeg) {
+                    accS += pos[q];
+                    f = min(f, slot[q]);
+                }
             }
-            const u64 pos = rc.y >> 1;
-            accW += pos;
-            if (key & 1u) {
-                accS += pos;
-                if (j == 0 || skey[j - 1] != key) front[u] = (uint32_t)j;
-            }
+            flush();
         }
-        flush();
         __syncthreads();
-        for (uint32_t i = tid; i < kGatherSlots; i += kRecThreads)
+        for (uint32_t i = tid; i < kRecSlots; i += kRecThreads)
             if (keys[i] != kEmpty) {
                 if (sw[i]) atomicAdd(&wu[keys[i]], sw[i]);
                 if (ss[i]) atomicAdd(&wsu[keys[i]], ss[i]);
+                if (sf[i] != kEmpty) atomicMin(&front[keys[i]], sf[i]);
             }
         __syncthreads();
     }
@@ -1127,25 +1176,17 @@ hipError_t launch_row_sort(const uint32_t* rowdeg, const uint32_t* row_ptr, cons
 }
 
 hipError_t launch_lowcount(const uint32_t* row_ptr, const uint32_t* col, const uint32_t* rowcross,
-                           uint32_t n, uint32_t* lowcnt, uint32_t* upcnt, hipStream_t st) {
+                           uint32_t n, uint32_t* lowcnt, hipStream_t st) {
     hipLaunchKernelGGL(k_lowcount, grid_n(n, 256), dim3(256), 0, st, row_ptr, col, rowcross, n,
-                       lowcnt, upcnt);
+                       lowcnt);
     return hipGetLastError();
 }
 
-hipError_t launch_records_raw(const uint32_t* row_ptr, const uint32_t* col, const uint32_t* lowcnt,
-                              const uint32_t* uptr, Dims d, uint64_t m, uint4* raw, uint32_t* key,
-                              hipStream_t st) {
-    hipLaunchKernelGGL(k_records_raw, grid_n(2 * m, kRecThreads * kRecPer, 8192), dim3(kRecThreads),
-                       0, st, row_ptr, col, lowcnt, uptr, d, m, raw, key);
-    return hipGetLastError();
-}
-
-hipError_t launch_records_gather(const uint4* raw, const uint32_t* skey, const uint32_t* order,
-                                 uint64_t m, uint4* recs, u64* wu, u64* wsu, uint32_t* front,
-                                 hipStream_t st) {
-    hipLaunchKernelGGL(k_records_gather, grid_n(m, kRecThreads * kRecPer, 8192), dim3(kRecThreads),
-                       0, st, raw, skey, order, m, recs, wu, wsu, front);
+hipError_t launch_records(const uint32_t* row_ptr, const uint32_t* col, const uint32_t* lowcnt,
+                          const uint32_t* mptr, Dims d, uint64_t m, uint4* recs, u64* wu, u64* wsu,
+                          uint32_t* front, hipStream_t st) {
+    hipLaunchKernelGGL(k_records, grid_n(2 * m, kRecThreads * kRecPer, 8192), dim3(kRecThreads), 0,
+                       st, row_ptr, col, lowcnt, mptr, d, m, recs, wu, wsu, front);
     return hipGetLastError();
 }
 

@@ -72,7 +72,7 @@ def test_noalloc_raw_abi_and_limits():
                                      bbc.INPUT_ON_DEVICE | bbc.PER_VERTEX, ctypes.byref(sentinel),
                                      pv.ctypes.data) == bbc.INVALID_ARG
         # a graph whose workspace exceeds the scratch: TOO_LARGE, outputs untouched
-        n_u, n_v, m = 100000, 60, 6_000_000
+        n_u, n_v, m = 100000, 120, 12_000_000
         i = torch.arange(m, device="cuda:0", dtype=torch.int64)
         eu = (i % n_u).to(torch.int32)
         ev = (i // n_u).to(torch.int32)
