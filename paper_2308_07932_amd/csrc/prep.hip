@@ -285,7 +285,11 @@ __global__ void k_vertex_pack(const uint32_t* __restrict__ sidx_of,
 }
 
 // Each edge lands in row u (entry sidx(v)) and row v (entry sidx(u)), at the
-// slots the degree pass reserved for it.
+// slots the degree pass reserved for it.  A thread takes kScatterPer edges per
+// round, each round's loads issued together (a batch's union gives a thread
+// about a hundred edges).
+constexpr int kScatterPer = 4;
+
 __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ eu,
                                                  const int32_t* __restrict__ ev,
                                                  const int8_t* __restrict__ sg, uint64_t m,
@@ -296,18 +300,39 @@ __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ eu,
     // XCD-aware: workgroup b runs on XCD b % 8 (round-robin dispatch); XCD x
     // takes the x-th eighth of the edges, so the rows a batched graph writes
     // are written through one L2
+    if (n_u + n_v == 0) return;  // no edge can be valid (and vertex 0 does not exist)
     const uint32_t x = blockIdx.x & 7u, bx = blockIdx.x >> 3, nbx = gridDim.x >> 3;
     const uint64_t e_lo = m * x / 8, e_hi = m * (x + 1) / 8;
-    for (uint64_t e = e_lo + (uint64_t)bx * blockDim.x + threadIdx.x; e < e_hi;
-         e += (uint64_t)nbx * blockDim.x) {
-        const int32_t u = eu[e], v = ev[e];
-        const int8_t s = sg[e];
-        if (!edge_ok(u, v, s, n_u, n_v)) continue;
-        const uint2 pu = vx[u], pv = vx[n_u + (uint32_t)v];  // {sidx, row start}
-        const uint2 r = rank[e];
-        const uint32_t neg = s < 0 ? 1u : 0u;
-        col[pu.y + r.x] = (pv.x << 1) | neg;
-        col[pv.y + r.y] = (pu.x << 1) | neg;
+    const uint64_t span = (uint64_t)nbx * blockDim.x;
+    for (uint64_t e0 = e_lo + (uint64_t)bx * blockDim.x + threadIdx.x; e0 < e_hi;
+         e0 += kScatterPer * span) {
+        int32_t u[kScatterPer], v[kScatterPer];
+        int8_t s[kScatterPer];
+        uint2 r[kScatterPer];
+#pragma unroll
+        for (int q = 0; q < kScatterPer; ++q) {
+            const uint64_t e = e0 + q * span;
+            const uint64_t ec = e < e_hi ? e : e0;  // (e0 < e_hi)
+            u[q] = eu[ec];
+            v[q] = ev[ec];
+            s[q] = sg[ec];
+            r[q] = rank[ec];
+        }
+        bool ok[kScatterPer];
+        uint2 pu[kScatterPer], pv[kScatterPer];  // {sidx, row start}
+#pragma unroll
+        for (int q = 0; q < kScatterPer; ++q) {  // (an edge left out reads vertex 0)
+            ok[q] = e0 + q * span < e_hi && edge_ok(u[q], v[q], s[q], n_u, n_v);
+            pu[q] = vx[ok[q] ? (uint32_t)u[q] : 0u];
+            pv[q] = vx[ok[q] ? n_u + (uint32_t)v[q] : 0u];
+        }
+#pragma unroll
+        for (int q = 0; q < kScatterPer; ++q) {
+            if (!ok[q]) continue;
+            const uint32_t neg = s[q] < 0 ? 1u : 0u;
+            col[pu[q].y + r[q].x] = (pv[q].x << 1) | neg;
+            col[pv[q].y + r[q].y] = (pu[q].x << 1) | neg;
+        }
     }
 }
 
@@ -1143,7 +1168,8 @@ hipError_t launch_scatter(const int32_t* eu, const int32_t* ev, const int8_t* sg
     const uint32_t n = n_u + n_v;
     hipLaunchKernelGGL(k_vertex_pack, grid_n(n, 256), dim3(256), 0, st, sidx_of, row_ptr, n, n_u,
                        vx);
-    hipLaunchKernelGGL(k_scatter, dim3((grid_n(m, 256).x + 7) & ~7u), dim3(256), 0, st, eu, ev, sg,
+    hipLaunchKernelGGL(k_scatter, dim3((grid_n(m, 256 * kScatterPer).x + 7) & ~7u), dim3(256), 0, st,
+                       eu, ev, sg,
                        m, n_u, n_v,
                        (const uint2*)vx, rank, col);
     return hipGetLastError();
