@@ -926,9 +926,11 @@ __global__ __launch_bounds__(kRecThreads) void k_records(
         recs[j] = make_uint4(0, 0, 0, 0);
     constexpr uint32_t kSpan = 64 * kRecPer;
     const uint32_t nwaves = gridDim.x * (kRecThreads / 64);
-    for (uint32_t s0 = (blockIdx.x * (kRecThreads / 64) + (tid >> 6)) * kSpan;; s0 += nwaves * kSpan) {
+    // (64-bit positions: nnz may come within a span of 2^32)
+    for (uint64_t s0 = (uint64_t)(blockIdx.x * (kRecThreads / 64) + (tid >> 6)) * kSpan;;
+         s0 += (uint64_t)nwaves * kSpan) {
         // (uniform over the workgroup: its waves' spans are adjacent)
-        const uint32_t blk0 = s0 - (tid >> 6) * kSpan;
+        const uint64_t blk0 = s0 - (uint64_t)(tid >> 6) * kSpan;
         if (blk0 >= nnz) break;
         for (uint32_t i = tid; i < kRecSlots; i += kRecThreads) {
             keys[i] = kEmpty;
@@ -938,9 +940,10 @@ __global__ __launch_bounds__(kRecThreads) void k_records(
         }
         __syncthreads();
         if (s0 < nnz) {
-            const uint32_t rlo = wave_block_of(row_ptr, d.n, s0);
-            const uint32_t rhi = wave_block_of(row_ptr, d.n, min(s0 + kSpan, nnz) - 1);
-            const uint32_t e0 = s0 + lane * kRecPer;
+            const uint32_t rlo = wave_block_of(row_ptr, d.n, (uint32_t)s0);
+            const uint32_t rhi =
+                wave_block_of(row_ptr, d.n, (uint32_t)(min<uint64_t>(s0 + kSpan, nnz) - 1));
+            const uint64_t e0 = s0 + lane * kRecPer;
             // this thread's entries: row, middle, slot; then the searches
             uint32_t rs[kRecPer], len[kRecPer], key[kRecPer], slot[kRecPer], urow[kRecPer];
             uint32_t x[kRecPer], pos[kRecPer];
@@ -959,7 +962,7 @@ __global__ __launch_bounds__(kRecThreads) void k_records(
                 uint32_t ra = row_ptr[r], rb = row_ptr[r + 1], k = lowcnt[r];
 #pragma unroll
                 for (int q = 0; q < kRecPer; ++q) {
-                    const uint32_t e = e0 + q;
+                    const uint64_t e = e0 + q;
                     if (e >= nnz) continue;
                     while (rb <= e) {  // (rows without entries are passed over)
                         ++r;
@@ -967,7 +970,7 @@ __global__ __launch_bounds__(kRecThreads) void k_records(
                         rb = row_ptr[r + 1];
                         k = lowcnt[r];
                     }
-                    const uint32_t jj = e - ra;
+                    const uint32_t jj = (uint32_t)(e - ra);
                     if (jj >= k) continue;  // an upper entry: a record of the other end
                     const uint32_t side = r >= d.n_u ? 1u : 0u;
                     x[q] = col[e];
