@@ -896,7 +896,7 @@ __global__ void k_lowcount(const uint32_t* __restrict__ row_ptr, const uint32_t*
 // record (preset to mptr[u+1]: none).  pos_v(u), the number of entries of v's
 // sorted row before u (exactly v's neighbours of lower priority than u, the
 // wedge ends of Algorithm 2 through v), comes from a binary search for u in
-// v's row, the rows of middles being mostly short.  W_u and Ws_u (the wedges
+// v's row (a middle has lower priority, so mostly a short row).  W_u and Ws_u (the wedges
 // through short middle rows) are sums of pos over u's records, aggregated per
 // workgroup in an LDS table (a hub's records span many threads).
 //   .x = first entry of row v, .y = pos << 1 | neg(u, v), .z = sidx(v), .w = row u
