@@ -39,7 +39,7 @@ typedef enum bbc_status {
     BBC_ERR_VERTEX_RANGE = -2,    /* an edge names u >= n_u, v >= n_v or a negative id */
     BBC_ERR_BAD_SIGN = -3,        /* an edge sign other than +1 or -1 */
     BBC_ERR_DUPLICATE_EDGE = -4,  /* the same (u, v) pair twice, whatever the signs */
-    BBC_ERR_TOO_LARGE = -5,       /* n_u + n_v >= 2^30 or n_edges >= 2^31 */
+    BBC_ERR_TOO_LARGE = -5,       /* n_u + n_v >= 2^30 or n_edges >= 2^31 - 1024 */
     BBC_ERR_OVERFLOW = -6,        /* a count does not fit in int64_t */
     BBC_ERR_OUT_OF_MEMORY = -7,   /* device workspace could not be allocated or exceeds
                                      the BBC_MAX_DEVICE_BYTES budget */

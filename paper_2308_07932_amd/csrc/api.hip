@@ -14,6 +14,9 @@
 #include "bbc_internal.h"
 
 namespace bbc {
+// edges of one graph: its CSR holds 2m entries and the kColPad pad entries the
+// wedge sweeps read past a grab, all at 32-bit positions
+constexpr uint64_t kMaxEdges = (1ull << 31) - kColPad;
 // launchers defined in prep.hip / plan.hip / wedge.hip
 hipError_t launch_degree(const int32_t*, const int32_t*, const int8_t*, uint64_t, uint32_t, uint32_t,
                          uint32_t*, uint2*, Control*, hipStream_t);
@@ -506,7 +509,7 @@ bbc_status bbc_last_stats(const bbc_context* c, int64_t* stats, int n) {
 int64_t bbc_workspace_bytes(int32_t n_u, int32_t n_v, int64_t n_edges) {
     if (n_u < 0 || n_v < 0 || n_edges < 0) return -1;
     const uint64_t n64 = (uint64_t)n_u + (uint64_t)n_v;
-    if (n64 >= (1ull << 30) || (uint64_t)n_edges >= (1ull << 31)) return -1;
+    if (n64 >= (1ull << 30) || (uint64_t)n_edges >= kMaxEdges) return -1;
     const uint32_t n = (uint32_t)n64;
     const uint64_t m = (uint64_t)n_edges;
     const uint32_t nt0 = ((uint32_t)n_u + kTile - 1) / kTile, nt1 = ((uint32_t)n_v + kTile - 1) / kTile;
@@ -970,8 +973,8 @@ bbc_status bbc_count(bbc_context* c, int32_t n_u, int32_t n_v, int64_t n_edges,
         return fail(c, BBC_ERR_INVALID_ARG, "BBC_PER_VERTEX without per_vertex buffer");
     const uint64_t n64 = (uint64_t)n_u + (uint64_t)n_v;
     if (n64 >= (1ull << 30)) return fail(c, BBC_ERR_TOO_LARGE, "n_u + n_v = %llu >= 2^30", (unsigned long long)n64);
-    if ((uint64_t)n_edges >= (1ull << 31))
-        return fail(c, BBC_ERR_TOO_LARGE, "n_edges = %lld >= 2^31", (long long)n_edges);
+    if ((uint64_t)n_edges >= kMaxEdges)
+        return fail(c, BBC_ERR_TOO_LARGE, "n_edges = %lld >= 2^31 - %u", (long long)n_edges, kColPad);
     if (n_edges == 0) {
         if ((flags & BBC_PER_VERTEX) && pv_on_device && n64 > 0) {
             HIPCHECK(c, hipSetDevice(c->device));

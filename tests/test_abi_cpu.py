@@ -111,6 +111,9 @@ def test_server_argument_checks(lib):
 def test_workspace_estimate():
     assert bbc.workspace_bytes(-1, 5, 5) == -1
     assert bbc.workspace_bytes(1 << 30, 0, 5) == -1
+    # edges: the CSR's 2m entries and its 1024 pad entries keep 32-bit positions
+    assert bbc.workspace_bytes(1000, 1000, (1 << 31) - 1024) == -1
+    assert bbc.workspace_bytes(1000, 1000, (1 << 31) - 1025) > 0
     a = bbc.workspace_bytes(1000, 1000, 10000)
     b = bbc.workspace_bytes(1000, 1000, 100000)
     c = bbc.workspace_bytes(100000, 1000, 100000)
