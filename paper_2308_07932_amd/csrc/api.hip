@@ -150,7 +150,7 @@ static bbc_status arena_reserve(bbc_context* c, Arena& a, size_t bytes) {
     if (a.base) {
         hipError_t e = hipStreamSynchronize(c->stream);
         if (e != hipSuccess) return fail(c, BBC_ERR_DEVICE, "hipStreamSynchronize: %s", hipGetErrorString(e));
-        hipFree(a.base);
+        (void)hipFree(a.base);
         a.base = nullptr;
         a.cap = 0;
     }
@@ -185,13 +185,13 @@ bool context_trim(bbc_context* c) {
         return false;
     }
     for (Arena* a : {&c->prep, &c->plan, &c->batch}) {
-        if (a->base) hipFree(a->base);
+        if (a->base) (void)hipFree(a->base);
         a->base = nullptr;
         a->cap = a->used = 0;
     }
     for (auto& g : c->seg)  // replay graphs point into the freed arenas
         if (g.exec) {
-            hipGraphExecDestroy(g.exec);
+            (void)hipGraphExecDestroy(g.exec);
             g.exec = nullptr;
             g.key.clear();
         }
@@ -415,18 +415,18 @@ bbc_status bbc_create(int device, void* hip_stream, bbc_context** out) {
 
 void bbc_destroy(bbc_context* c) {
     if (!c) return;
-    hipSetDevice(c->device);
-    if (c->stream) hipStreamSynchronize(c->stream);
-    if (c->prep.base) hipFree(c->prep.base);
-    if (c->plan.base) hipFree(c->plan.base);
-    if (c->batch.base) hipFree(c->batch.base);
-    if (c->pv_host) hipHostFree(c->pv_host);
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    if (c->prep.base) (void)hipFree(c->prep.base);
+    if (c->plan.base) (void)hipFree(c->plan.base);
+    if (c->batch.base) (void)hipFree(c->batch.base);
+    if (c->pv_host) (void)hipHostFree(c->pv_host);
     for (auto& g : c->seg)
-        if (g.exec) hipGraphExecDestroy(g.exec);
-    if (c->host_ctl) hipHostFree(c->host_ctl);
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (c->host_ctl) (void)hipHostFree(c->host_ctl);
     for (int i = 0; i < kNumEv; ++i)
-        if (c->ev[i]) hipEventDestroy(c->ev[i]);
-    if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
+        if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     (void)hipGetLastError();
     delete c;
 }
@@ -580,12 +580,12 @@ static bbc_status run_segment(bbc_context* c, int which, const std::vector<uint6
         hipGraph_t g = nullptr;
         const hipError_t e = hipStreamEndCapture(st, &g);
         if (s) {
-            if (g) hipGraphDestroy(g);
+            if (g) (void)hipGraphDestroy(g);
             return s;
         }
         if (e != hipSuccess) return fail(c, BBC_ERR_DEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
         const hipError_t e2 = hipGraphInstantiate(&slot.exec, g, nullptr, nullptr, 0);
-        hipGraphDestroy(g);
+        (void)hipGraphDestroy(g);
         if (e2 != hipSuccess) {
             slot.exec = nullptr;
             return fail(c, BBC_ERR_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e2));
@@ -994,7 +994,7 @@ bbc_status bbc_count(bbc_context* c, int32_t n_u, int32_t n_v, int64_t n_edges,
     if ((flags & BBC_PER_VERTEX) && !pv_on_device) {
         const size_t bytes = 8ull * (size_t)n64;
         if (c->pv_host_cap < bytes) {
-            if (c->pv_host) hipHostFree(c->pv_host);
+            if (c->pv_host) (void)hipHostFree(c->pv_host);
             c->pv_host = nullptr;
             c->pv_host_cap = 0;
             void* hp = nullptr;
